@@ -63,10 +63,10 @@ _SIGS = {
     "or_emit_keys": (None, [_P, _P, _P, _P, _I64, _P, _I, _I, _P, _P, _P]),
     "or_sort_segments": (None, [_P, _P, _P, _I]),
     "or_tile_ranges": (None, [_P, _P, _P, _I, _I, _P]),
-    "or_raster_fwd": (None, [_P, _P, _P, _P, _P, _P, _P, _I64, _P, _I, _I, _P,
+    "or_raster_fwd": (None, [_P, _P, _P, _P, _P, _P, _P, _I64, _P, _I, _I, _P, _P,
                              _P, _P, _P, _P, _P, _P]),
     "or_l1": (_D, [_P, _P, _I64, _D, _P, _P]),
-    "or_raster_bwd": (None, [_P, _P, _P, _P, _P, _P, _P, _P, _I64, _P, _I, _I, _P, _P, _P]),
+    "or_raster_bwd": (None, [_P, _P, _P, _P, _P, _P, _P, _P, _I64, _P, _I, _I, _P, _P, _P, _P]),
     "or_project_bwd": (None, [_P, _P, _P, _P, _P, _I64, _P, _I, _I, _P, _P]),
     "or_adam": (None, [_P, _P, _P, _P, _I64, _P, _D, _D, _D, _I]),
     "or_sh_basis": (None, [_P, _P]),
@@ -203,7 +203,9 @@ class Image:
 
 
 def raster_fwd(proj: Projected, bins: Bins, views, tile: int, double: bool = False,
-               margins=DEFAULT_MARGINS) -> Image:
+               margins=DEFAULT_MARGINS, tile_mask=None) -> Image:
+    """Compositing forward; tile_mask (total tiles, nonzero = render) limits the
+    work to a sample of tiles (other pixels stay zero)."""
     L = lib(double)
     V, n = proj.tiles.shape
     views = np.ascontiguousarray(views)
@@ -214,10 +216,11 @@ def raster_fwd(proj: Projected, bins: Bins, views, tile: int, double: bool = Fal
     mg = np.asarray(margins, np.float64)
     vals = bins.vals if bins.vals.size else np.zeros(1, np.uint32)
     gid = bins.gid if bins.gid.size else np.zeros(1, np.uint32)
+    tm = None if tile_mask is None else np.ascontiguousarray(tile_mask, dtype=np.uint8)
     L.or_raster_fwd(_p(np.ascontiguousarray(proj.xy)), _p(np.ascontiguousarray(proj.conic)),
                     _p(np.ascontiguousarray(proj.opacity)), _p(np.ascontiguousarray(proj.rgb)),
                     _p(bins.ranges), _p(vals), _p(gid), n, _p(views), V, tile, _p(mg),
-                    _p(img.rgb), _p(img.T), _p(img.last), _p(img.fragile),
+                    None if tm is None else _p(tm), _p(img.rgb), _p(img.T), _p(img.last), _p(img.fragile),
                     _p(img.tile_traversed), _p(img.tile_evaluated))
     return img
 
@@ -233,8 +236,9 @@ def l1(image_rgb: np.ndarray, target: np.ndarray, double=False, fragile: np.ndar
 
 
 def raster_bwd(proj: Projected, bins: Bins, views, tile: int, dLdC: np.ndarray,
-               double: bool = False):
-    """Returns (partials [K,9] by unsorted index, grads2d [V,N,9])."""
+               double: bool = False, tile_mask=None):
+    """Returns (partials [K,9] by unsorted index, grads2d [V,N,9]); tile_mask
+    limits the work to a sample of tiles (others contribute nothing)."""
     L = lib(double)
     V, n = proj.tiles.shape
     views = np.ascontiguousarray(views)
@@ -246,6 +250,7 @@ def raster_bwd(proj: Projected, bins: Bins, views, tile: int, dLdC: np.ndarray,
     L.or_raster_bwd(_p(np.ascontiguousarray(proj.xy)), _p(np.ascontiguousarray(proj.conic)),
                     _p(np.ascontiguousarray(proj.opacity)), _p(np.ascontiguousarray(proj.rgb)),
                     _p(bins.ranges), _p(vals), _p(gid), _p(bins.offsets), n, _p(views), V, tile,
+                    None if tile_mask is None else _p(np.ascontiguousarray(tile_mask, dtype=np.uint8)),
                     _p(np.ascontiguousarray(dLdC, dtype=np.float64)), _p(partials), _p(grads2d))
     return partials[:K], grads2d
 

@@ -584,8 +584,8 @@ static int view_of_tile(const or_view* views, int n_views, int tile, int64_t gti
 void or_raster_fwd(const double* xy, const double* conic, const double* opac, const double* rgb,
                    const uint32_t* ranges, const uint32_t* vals, const uint32_t* gid, int64_t n,
                    const or_view* views, int n_views, int tile, const double* margins,
-                   double* image, double* Tfinal, uint32_t* last, uint8_t* fragile,
-                   uint32_t* tile_traversed, uint64_t* tile_evaluated)
+                   const uint8_t* tile_mask, double* image, double* Tfinal, uint32_t* last,
+                   uint8_t* fragile, uint32_t* tile_traversed, uint64_t* tile_evaluated)
 {
     int64_t ntiles = 0;
     for (int vi = 0; vi < n_views; ++vi)
@@ -600,6 +600,7 @@ void or_raster_fwd(const double* xy, const double* conic, const double* opac, co
     }
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t gt = 0; gt < ntiles; ++gt) {
+        if (tile_mask && !tile_mask[gt]) continue;
         int lt = 0;
         int64_t pixbase = 0;
         const int vi = view_of_tile(views, n_views, tile, gt, &lt, &pixbase);
@@ -675,7 +676,7 @@ double or_l1(const double* image, const float* target, int64_t npix, double sign
 void or_raster_bwd(const double* xy, const double* conic, const double* opac, const double* rgb,
                    const uint32_t* ranges, const uint32_t* vals, const uint32_t* gid,
                    const uint32_t* offsets, int64_t n, const or_view* views, int n_views, int tile,
-                   const double* dLdC, double* partials, double* grads2d)
+                   const uint8_t* tile_mask, const double* dLdC, double* partials, double* grads2d)
 {
     int64_t ntiles = 0;
     for (int vi = 0; vi < n_views; ++vi)
@@ -695,6 +696,7 @@ void or_raster_bwd(const double* xy, const double* conic, const double* opac, co
         real* e_dy = NULL;
 #pragma omp for schedule(dynamic, 4)
         for (int64_t gt = 0; gt < ntiles; ++gt) {
+            if (tile_mask && !tile_mask[gt]) continue;
             int lt = 0;
             int64_t pixbase = 0;
             const int vi = view_of_tile(views, n_views, tile, gt, &lt, &pixbase);

@@ -1,0 +1,538 @@
+// Binning and sorting: exclusive scan of tiles touched, 32-bit (tile, depth)
+// key emission, stable LSD radix sort of each view's segment (4 passes of 8
+// bits), per-tile [start, end) ranges.
+//
+// The sort runs over all views at once: each view's segment is cut into
+// chunks of kChunk keys that never straddle two views, and the per-chunk digit
+// histograms are laid out [view][digit][chunk] so one exclusive scan of the
+// whole histogram array yields every scatter destination directly.  Grids are
+// sized from the capacity (an upper bound known on the host); the actual
+// counts are read on the device, so no step needs a host synchronisation.
+#include "gs_internal.h"
+
+namespace gs {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanBlock = kScanThreads * kScanItems;  // 2048 elements per block
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kChunk = kSortThreads * kSortItems;      // 4096 keys per radix chunk
+constexpr int kDigits = 256;
+
+// ---------------------------------------------------------------------------
+// workspace
+// ---------------------------------------------------------------------------
+
+struct Workspace {
+    uint32_t* keys_tmp;
+    uint32_t* vals_tmp;
+    uint32_t* hist;        // kDigits * max_chunks
+    uint64_t* block_sums;  // scan partials
+    uint32_t* table;       // 4 * (GS_MAX_VIEWS + 1)
+    int64_t max_chunks;
+    int64_t max_scan_blocks;
+};
+
+static inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+static int64_t max_chunks_for(int64_t capacity, int n_views) {
+    return (capacity + kChunk - 1) / kChunk + n_views;
+}
+
+static size_t carve(int64_t n, const gs_layout& L, int64_t capacity, char* base, Workspace* w) {
+    const int64_t mc = max_chunks_for(capacity, L.n_views);
+    const int64_t scan_elems = std::max<int64_t>((int64_t)L.n_views * n, kDigits * mc);
+    const int64_t sb = (scan_elems + kScanBlock - 1) / kScanBlock;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base ? base + off : nullptr;
+        off = align_up(off + bytes);
+        return p;
+    };
+    Workspace tmp;
+    tmp.keys_tmp = (uint32_t*)take(sizeof(uint32_t) * (size_t)std::max<int64_t>(capacity, 1));
+    tmp.vals_tmp = (uint32_t*)take(sizeof(uint32_t) * (size_t)std::max<int64_t>(capacity, 1));
+    tmp.hist = (uint32_t*)take(sizeof(uint32_t) * (size_t)(kDigits * mc + 1));  // +1: scan total
+    tmp.block_sums = (uint64_t*)take(sizeof(uint64_t) * (size_t)(sb + 1));
+    tmp.table = (uint32_t*)take(sizeof(uint32_t) * 4 * (GS_MAX_VIEWS + 1));
+    tmp.max_chunks = mc;
+    tmp.max_scan_blocks = sb;
+    if (w) *w = tmp;
+    return off;
+}
+
+size_t bin_sort_workspace(int64_t n, const gs_layout& L, int64_t capacity) {
+    return carve(n, L, capacity, nullptr, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// generic exclusive scan of uint32 -> uint32 (64-bit carries)
+// ---------------------------------------------------------------------------
+
+GS_DEV uint64_t block_reduce_u64(uint64_t v, uint64_t* lds) {
+    // wave reduction with shuffles, then across the 4 waves
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    if (lane == 0) lds[w] = v;
+    __syncthreads();
+    uint64_t t = 0;
+    for (int i = 0; i < (int)(blockDim.x / kWave); ++i) t += lds[i];
+    __syncthreads();
+    return t;
+}
+
+// inclusive scan across the block of one value per thread; returns inclusive
+GS_DEV uint64_t block_scan_u64(uint64_t v, uint64_t* lds, uint64_t* total) {
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    uint64_t x = v;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint64_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == kWave - 1) lds[w] = x;
+    __syncthreads();
+    const int nw = blockDim.x / kWave;
+    uint64_t pre = 0, tot = 0;
+    for (int i = 0; i < nw; ++i) {
+        if (i < w) pre += lds[i];
+        tot += lds[i];
+    }
+    __syncthreads();
+    *total = tot;
+    return x + pre;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __restrict__ in,
+                                                              int64_t len,
+                                                              uint64_t* __restrict__ sums) {
+    __shared__ uint64_t lds[kScanThreads / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock;
+    uint64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t idx = base + (int64_t)i * kScanThreads + threadIdx.x;
+        if (idx < len) s += in[idx];
+    }
+    s = block_reduce_u64(s, lds);
+    if (threadIdx.x == 0) sums[blockIdx.x] = s;
+}
+
+// single workgroup: exclusive scan of nb block sums in place; sums[nb] = total
+__global__ __launch_bounds__(1024) void k_scan_top(uint64_t* __restrict__ sums, int64_t nb,
+                                                   uint32_t* __restrict__ status) {
+    __shared__ uint64_t lds[1024 / kWave];
+    uint64_t carry = 0;
+    for (int64_t b = 0; b < nb; b += 1024) {
+        const int64_t i = b + threadIdx.x;
+        const uint64_t v = i < nb ? sums[i] : 0;
+        uint64_t tot;
+        const uint64_t inc = block_scan_u64(v, lds, &tot);
+        if (i < nb) sums[i] = carry + inc - v;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        sums[nb] = carry;
+        if (status && carry > 0xFFFFFFFFull) atomicOr(status, (uint32_t)GS_STATUS_OVERFLOW);
+    }
+}
+
+// `in` and `out` may be the same array (the radix histograms are scanned in place).
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* in, int64_t len,
+                                                            const uint64_t* __restrict__ sums,
+                                                            int64_t nb, uint32_t* out) {
+    __shared__ uint64_t lds[kScanThreads / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock;
+    // each thread owns kScanItems consecutive elements
+    uint32_t v[kScanItems];
+    uint64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t idx = base + (int64_t)threadIdx.x * kScanItems + i;
+        v[i] = idx < len ? in[idx] : 0u;
+        s += v[i];
+    }
+    uint64_t tot;
+    const uint64_t inc = block_scan_u64(s, lds, &tot);
+    uint64_t run = sums[blockIdx.x] + inc - s;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t idx = base + (int64_t)threadIdx.x * kScanItems + i;
+        if (idx < len) out[idx] = (uint32_t)run;
+        run += v[i];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[len] = (uint32_t)sums[nb];
+}
+
+static int scan_exclusive(const uint32_t* in, int64_t len, uint32_t* out, uint64_t* sums,
+                          uint32_t* status, hipStream_t s) {
+    const int64_t nb = std::max<int64_t>((len + kScanBlock - 1) / kScanBlock, 1);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, len, sums);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, sums, nb, status);
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, len, sums, nb,
+                       out);
+    return check_launch("scan");
+}
+
+// ---------------------------------------------------------------------------
+// per-view segment table
+// ---------------------------------------------------------------------------
+
+__global__ void k_view_table(const uint32_t* __restrict__ offsets, int64_t n, int n_views,
+                             int64_t capacity, uint32_t* __restrict__ table,
+                             uint32_t* __restrict__ status) {
+    if (threadIdx.x != 0) return;
+    uint32_t chunks = 0;
+    const uint64_t cap = (uint64_t)capacity;
+    for (int v = 0; v < n_views; ++v) {
+        uint64_t b = offsets[(int64_t)v * n], e = offsets[(int64_t)(v + 1) * n];
+        b = b < cap ? b : cap;
+        e = e < cap ? e : cap;
+        const uint32_t nc = (uint32_t)((e - b + kChunk - 1) / kChunk);
+        table[4 * v + 0] = (uint32_t)b;
+        table[4 * v + 1] = (uint32_t)e;
+        table[4 * v + 2] = chunks;
+        table[4 * v + 3] = nc;
+        chunks += nc;
+    }
+    table[4 * n_views] = chunks;
+    if ((uint64_t)offsets[(int64_t)n_views * n] > cap) atomicOr(status, (uint32_t)GS_STATUS_CAPACITY);
+}
+
+// ---------------------------------------------------------------------------
+// key emission
+// ---------------------------------------------------------------------------
+
+struct EmitGeom {
+    int32_t tiles_x[GS_MAX_VIEWS];
+    int32_t depth_bits[GS_MAX_VIEWS];
+};
+
+__global__ __launch_bounds__(256) void k_emit(const gs_splats sp, const uint32_t* __restrict__ offsets,
+                                              int64_t n, int n_views, EmitGeom geo, int64_t capacity,
+                                              uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                              uint32_t* __restrict__ gid) {
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= (int64_t)n_views * n) return;
+    const uint32_t cnt = sp.tiles[o];
+    if (cnt == 0) return;
+    const int v = (int)(o / n);
+    const uint32_t g = (uint32_t)(o - (int64_t)v * n);
+    const uint2 rc = reinterpret_cast<const uint2*>(sp.rect)[o];
+    const int x0 = rc.x & 0xFFFF, y0 = rc.x >> 16, x1 = rc.y & 0xFFFF, y1 = rc.y >> 16;
+    const float z = reinterpret_cast<const float4*>(sp.geo2)[o].z;
+    const int D = geo.depth_bits[v];
+    const int gx = geo.tiles_x[v];
+    // depth map z -> (2z + 1) / (z + 1) in (1, 2): only mantissa bits vary
+    const float num = 2.0f * z + 1.0f;
+    const float den = z + 1.0f;
+    const float f = num / den;
+    const uint32_t dk = (__float_as_uint(f) & 0x7FFFFFu) >> (23 - D);
+    uint64_t pos = offsets[o];
+    for (int ty = y0; ty < y1; ++ty)
+        for (int tx = x0; tx < x1; ++tx) {
+            if (pos < (uint64_t)capacity) {
+                keys[pos] = ((uint32_t)(ty * gx + tx) << D) | dk;
+                vals[pos] = (uint32_t)pos;
+                gid[pos] = g;
+            }
+            ++pos;
+        }
+}
+
+// ---------------------------------------------------------------------------
+// radix sort passes
+// ---------------------------------------------------------------------------
+
+// Chunk b -> (view, chunk within view).  Returns false for unused chunks.
+GS_DEV bool chunk_of(const uint32_t* table, int n_views, uint32_t b, int* view, uint32_t* c) {
+    if (b >= table[4 * n_views]) return false;
+    int v = 0;
+    for (int i = 0; i < n_views; ++i)
+        if (table[4 * i + 3] > 0 && b >= table[4 * i + 2]) v = i;
+    *view = v;
+    *c = b - table[4 * v + 2];
+    return true;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __restrict__ keys,
+                                                             const uint32_t* __restrict__ table,
+                                                             int n_views, int shift,
+                                                             uint32_t* __restrict__ hist) {
+    __shared__ uint32_t cnt[kSortThreads / kWave][kDigits];
+    const uint32_t b = blockIdx.x;
+    int v;
+    uint32_t c;
+    if (!chunk_of(table, n_views, b, &v, &c)) {
+        // unused chunk: zero its slot in the tail of the histogram array
+        hist[(int64_t)b * kDigits + threadIdx.x] = 0u;
+        return;
+    }
+    const int w = threadIdx.x / kWave;
+    for (int i = threadIdx.x; i < (kSortThreads / kWave) * kDigits; i += kSortThreads)
+        (&cnt[0][0])[i] = 0u;
+    __syncthreads();
+    const uint32_t seg_b = table[4 * v], seg_e = table[4 * v + 1];
+    const uint32_t start = seg_b + c * kChunk;
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        const uint32_t idx = start + i * kSortThreads + threadIdx.x;
+        if (idx < seg_e) atomicAdd(&cnt[w][(keys[idx] >> shift) & 0xFF], 1u);
+    }
+    __syncthreads();
+    uint32_t tot = 0;
+#pragma unroll
+    for (int i = 0; i < kSortThreads / kWave; ++i) tot += cnt[i][threadIdx.x];
+    const uint32_t nc = table[4 * v + 3], cb = table[4 * v + 2];
+    hist[(int64_t)cb * kDigits + (int64_t)threadIdx.x * nc + c] = tot;
+}
+
+GS_DEV uint64_t lanemask_lt() {
+    const int lane = threadIdx.x % kWave;
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
+    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
+    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
+    const uint32_t* __restrict__ table, int n_views, int shift,
+    const uint32_t* __restrict__ scanned) {
+    constexpr int NW = kSortThreads / kWave;
+    __shared__ uint32_t base[kDigits];
+    __shared__ uint32_t wcnt[NW][kDigits];
+    const uint32_t b = blockIdx.x;
+    int v;
+    uint32_t c;
+    if (!chunk_of(table, n_views, b, &v, &c)) return;
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const uint32_t nc = table[4 * v + 3], cb = table[4 * v + 2];
+    base[threadIdx.x] = scanned[(int64_t)cb * kDigits + (int64_t)threadIdx.x * nc + c];
+    const uint32_t seg_e = table[4 * v + 1];
+    const uint32_t start = table[4 * v] + c * kChunk;
+    uint32_t k[kSortItems], val[kSortItems];
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        const uint32_t idx = start + i * kSortThreads + threadIdx.x;
+        k[i] = idx < seg_e ? keys_in[idx] : 0u;
+        val[i] = idx < seg_e ? vals_in[idx] : 0u;
+    }
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        const uint32_t idx = start + i * kSortThreads + threadIdx.x;
+        const bool valid = idx < seg_e;
+        const uint32_t d = (k[i] >> shift) & 0xFF;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const bool set = (d >> bit) & 1u;
+            const uint64_t m = __ballot(set);
+            peers &= set ? m : ~m;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & lt);
+        const bool leader = valid && (peers & lt) == 0ull;
+        for (int j = threadIdx.x; j < NW * kDigits; j += kSortThreads) (&wcnt[0][0])[j] = 0u;
+        __syncthreads();
+        if (leader) wcnt[w][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = base[d] + rank;
+            for (int j = 0; j < w; ++j) pos += wcnt[j][d];
+            keys_out[pos] = k[i];
+            vals_out[pos] = val[i];
+        }
+        __syncthreads();
+        {
+            uint32_t add = 0;
+#pragma unroll
+            for (int j = 0; j < NW; ++j) add += wcnt[j][threadIdx.x];
+            base[threadIdx.x] += add;
+        }
+        __syncthreads();
+    }
+    (void)lane;
+}
+
+// ---------------------------------------------------------------------------
+// tile ranges
+// ---------------------------------------------------------------------------
+
+struct RangeGeom {
+    int32_t depth_bits[GS_MAX_VIEWS];
+    int32_t tile_base[GS_MAX_VIEWS + 1];
+};
+
+__global__ __launch_bounds__(256) void k_ranges_empty(const uint32_t* __restrict__ table, int n_views,
+                                                      RangeGeom geo, uint32_t* __restrict__ ranges) {
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gt >= geo.tile_base[n_views]) return;
+    int v = 0;
+    for (int i = 1; i < n_views; ++i)
+        if (gt >= geo.tile_base[i]) v = i;
+    const uint32_t b = table[4 * v], e = table[4 * v + 1];
+    if (b == e) reinterpret_cast<uint2*>(ranges)[gt] = make_uint2(b, b);
+}
+
+__global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ keys,
+                                                const uint32_t* __restrict__ table, int n_views,
+                                                RangeGeom geo, int64_t capacity,
+                                                uint32_t* __restrict__ ranges) {
+    const int64_t j64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j64 >= capacity) return;
+    const uint32_t j = (uint32_t)j64;
+    int v = -1;
+    for (int i = 0; i < n_views; ++i)
+        if (j >= table[4 * i] && j < table[4 * i + 1]) v = i;
+    if (v < 0) return;
+    const uint32_t sb = table[4 * v], se = table[4 * v + 1];
+    const int D = geo.depth_bits[v];
+    const int tb = geo.tile_base[v];
+    const int nt = geo.tile_base[v + 1] - tb;
+    uint2* R = reinterpret_cast<uint2*>(ranges) + tb;
+    const int t = min((int)(keys[j] >> D), nt - 1);
+    if (j == sb) {
+        for (int u = 0; u <= t; ++u) R[u].x = j;
+        for (int u = 0; u < t; ++u) R[u].y = j;
+    } else {
+        const int tp = min((int)(keys[j - 1] >> D), nt - 1);
+        if (tp != t) {
+            for (int u = tp + 1; u <= t; ++u) R[u].x = j;
+            for (int u = tp; u < t; ++u) R[u].y = j;
+        }
+    }
+    if (j == se - 1) {
+        for (int u = t; u < nt; ++u) R[u].y = j + 1;
+        for (int u = t + 1; u < nt; ++u) R[u].x = j + 1;
+    }
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = value;
+}
+
+int launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s) {
+    if (count <= 0) return GS_OK;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, value,
+                       count);
+    return check_launch("fill");
+}
+
+// ---------------------------------------------------------------------------
+// stand-alone stable sort of (key, value) pairs, one segment [0, count)
+// ---------------------------------------------------------------------------
+
+__global__ void k_single_table(uint32_t* table, int64_t count) {
+    if (threadIdx.x != 0) return;
+    table[0] = 0u;
+    table[1] = (uint32_t)count;
+    table[2] = 0u;
+    table[3] = (uint32_t)((count + kChunk - 1) / kChunk);
+    table[4] = table[3];
+}
+
+size_t sort_pairs_scratch(int64_t count) {
+    const int64_t mc = (count + kChunk - 1) / kChunk + 1;
+    const int64_t sb = (kDigits * mc + kScanBlock - 1) / kScanBlock;
+    return align_up(8 * (size_t)count) + align_up(4 * (size_t)(kDigits * mc + 1)) +
+           align_up(8 * (size_t)(sb + 1)) + align_up(4 * 8);
+}
+
+int sort_pairs(uint32_t* keys, uint32_t* vals, int64_t count, void* scratch, hipStream_t s) {
+    if (count <= 1) return GS_OK;
+    const int64_t mc = (count + kChunk - 1) / kChunk + 1;
+    const int64_t sb = (kDigits * mc + kScanBlock - 1) / kScanBlock;
+    char* p = (char*)scratch;
+    uint32_t* ktmp = (uint32_t*)p;
+    uint32_t* vtmp = ktmp + count;
+    p += align_up(8 * (size_t)count);
+    uint32_t* hist = (uint32_t*)p;
+    p += align_up(4 * (size_t)(kDigits * mc + 1));
+    uint64_t* sums = (uint64_t*)p;
+    p += align_up(8 * (size_t)(sb + 1));
+    uint32_t* table = (uint32_t*)p;
+    hipLaunchKernelGGL(k_single_table, dim3(1), dim3(64), 0, s, table, count);
+    int rc = check_launch("sort_table");
+    if (rc != GS_OK) return rc;
+    uint32_t *kin = keys, *vin = vals, *kout = ktmp, *vout = vtmp;
+    for (int pass = 0; pass < 4; ++pass) {
+        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)mc), dim3(kSortThreads), 0, s, kin, table, 1,
+                           8 * pass, hist);
+        if ((rc = check_launch("sort_hist")) != GS_OK) return rc;
+        if ((rc = scan_exclusive(hist, kDigits * mc, hist, sums, nullptr, s)) != GS_OK) return rc;
+        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)mc), dim3(kSortThreads), 0, s, kin, vin, kout,
+                           vout, table, 1, 8 * pass, hist);
+        if ((rc = check_launch("sort_scatter")) != GS_OK) return rc;
+        std::swap(kin, kout);
+        std::swap(vin, vout);
+    }
+    return GS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// driver
+// ---------------------------------------------------------------------------
+
+int launch_bin_sort(const gs_splats& sp, int64_t n, const gs_layout& L, const gs_bins& b, void* ws,
+                    size_t ws_bytes, hipStream_t s) {
+    Workspace W;
+    const size_t need = carve(n, L, b.capacity, (char*)ws, &W);
+    if (ws_bytes < need) {
+        set_error("bin_sort: workspace of %zu bytes, %zu needed", ws_bytes, need);
+        return GS_ERR_WORKSPACE;
+    }
+    const int V = L.n_views;
+    const int64_t m = (int64_t)V * n;
+    int rc;
+    if ((rc = launch_fill_u32(b.status, 0u, 1, s)) != GS_OK) return rc;
+    if ((rc = scan_exclusive(sp.tiles, m, b.offsets, W.block_sums, b.status, s)) != GS_OK) return rc;
+    hipLaunchKernelGGL(k_view_table, dim3(1), dim3(64), 0, s, b.offsets, n, V, b.capacity, W.table,
+                       b.status);
+    if ((rc = check_launch("view_table")) != GS_OK) return rc;
+    EmitGeom eg;
+    RangeGeom rg;
+    for (int v = 0; v < GS_MAX_VIEWS; ++v) {
+        eg.tiles_x[v] = v < V ? L.tiles_x[v] : 0;
+        eg.depth_bits[v] = v < V ? L.depth_bits[v] : 0;
+        rg.depth_bits[v] = eg.depth_bits[v];
+    }
+    for (int v = 0; v <= GS_MAX_VIEWS; ++v) rg.tile_base[v] = v <= V ? L.tile_base[v] : L.tile_base[V];
+    if (m > 0) {
+        hipLaunchKernelGGL(k_emit, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, sp, b.offsets,
+                           n, V, eg, b.capacity, b.keys, b.vals, b.gid);
+        if ((rc = check_launch("emit_keys")) != GS_OK) return rc;
+    }
+    // 4 stable LSD passes; even count leaves the result in keys / vals
+    uint32_t* kin = b.keys;
+    uint32_t* vin = b.vals;
+    uint32_t* kout = W.keys_tmp;
+    uint32_t* vout = W.vals_tmp;
+    const unsigned grid = (unsigned)W.max_chunks;
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 8 * pass;
+        hipLaunchKernelGGL(k_radix_hist, dim3(grid), dim3(kSortThreads), 0, s, kin, W.table, V, shift,
+                           W.hist);
+        if ((rc = check_launch("radix_hist")) != GS_OK) return rc;
+        if ((rc = scan_exclusive(W.hist, kDigits * W.max_chunks, W.hist, W.block_sums, nullptr, s)) !=
+            GS_OK)
+            return rc;
+        hipLaunchKernelGGL(k_radix_scatter, dim3(grid), dim3(kSortThreads), 0, s, kin, vin, kout, vout,
+                           W.table, V, shift, W.hist);
+        if ((rc = check_launch("radix_scatter")) != GS_OK) return rc;
+        std::swap(kin, kout);
+        std::swap(vin, vout);
+    }
+    const int64_t nt = L.tile_base[V];
+    hipLaunchKernelGGL(k_ranges_empty, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, W.table, V,
+                       rg, b.ranges);
+    if ((rc = check_launch("ranges_empty")) != GS_OK) return rc;
+    if (b.capacity > 0) {
+        hipLaunchKernelGGL(k_ranges, dim3((unsigned)((b.capacity + 255) / 256)), dim3(256), 0, s,
+                           b.keys, W.table, V, rg, b.capacity, b.ranges);
+        if ((rc = check_launch("ranges")) != GS_OK) return rc;
+    }
+    return GS_OK;
+}
+
+}  // namespace gs

@@ -1,0 +1,64 @@
+// Projection forward: one thread per Gaussian, looping over the views so the
+// 240-byte parameter record is read from HBM once per call.  Loads are float4
+// planes (plane-major SoA), so each wavefront reads 1 KiB contiguous per plane.
+#include "project_math.h"
+
+namespace gs {
+
+struct ViewGrid {
+    int32_t gx[GS_MAX_VIEWS], gy[GS_MAX_VIEWS];
+};
+
+__global__ __launch_bounds__(256) void k_project(const float* __restrict__ params, int64_t n,
+                                                 const gs_view* __restrict__ views, int n_views,
+                                                 int tile, ViewGrid grid, gs_splats out) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    const float4 p0 = ld4(params, 0 * n + g);
+    const float4 p1 = ld4(params, 1 * n + g);
+    const float4 p2 = ld4(params, 2 * n + g);
+    float4 sh[12];
+    bool finite = finite4(p0) && finite4(make_float4(p1.x, p1.y, p1.z, 0.0f)) && finite4(p2);
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+        sh[q] = ld4(params, (3 + q) * n + g);
+        finite = finite && finite4(sh[q]);
+    }
+    for (int v = 0; v < n_views; ++v) {
+        const gs_view vw = views[v];
+        Proj P;
+        P.valid = false;
+        if (finite) project_gaussian<true>(p0, p1, p2, sh, vw, tile, grid.gx[v], grid.gy[v], P);
+        const int64_t o = (int64_t)v * n + g;
+        if (P.valid) {
+            st4(out.geo, o, make_float4(P.u, P.v, P.A, P.B));
+            st4(out.geo2, o, make_float4(P.C, P.o, P.z, P.radius));
+            st4(out.rgb, o, make_float4(P.col[0], P.col[1], P.col[2], 0.0f));
+            reinterpret_cast<uint2*>(out.rect)[o] =
+                make_uint2((uint32_t)P.x0 | ((uint32_t)P.y0 << 16), (uint32_t)P.x1 | ((uint32_t)P.y1 << 16));
+            out.tiles[o] = (uint32_t)((P.x1 - P.x0) * (P.y1 - P.y0));
+        } else {
+            st4(out.geo, o, make_float4(0.f, 0.f, 0.f, 0.f));
+            st4(out.geo2, o, make_float4(0.f, 0.f, 0.f, 0.f));
+            st4(out.rgb, o, make_float4(0.f, 0.f, 0.f, 0.f));
+            reinterpret_cast<uint2*>(out.rect)[o] = make_uint2(0u, 0u);
+            out.tiles[o] = 0u;
+        }
+    }
+}
+
+int launch_project(const float* params, int64_t n, const gs_view* views, const gs_layout& L,
+                   const gs_splats& out, hipStream_t s) {
+    if (n == 0) return GS_OK;
+    ViewGrid grid;
+    for (int v = 0; v < GS_MAX_VIEWS; ++v) {
+        grid.gx[v] = v < L.n_views ? L.tiles_x[v] : 0;
+        grid.gy[v] = v < L.n_views ? L.tiles_y[v] : 0;
+    }
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, s, params, n, views,
+                       L.n_views, L.tile, grid, out);
+    return check_launch("project");
+}
+
+}  // namespace gs

@@ -1,0 +1,511 @@
+// Tile rasteriser: forward alpha compositing and its exact backward.
+//
+// One workgroup renders one T x T tile (one thread per pixel; T = 8, 16, 32 gives
+// 1, 4 or 16 wavefronts).  The tile's sorted Gaussian list is consumed in
+// batches of S records gathered into LDS; every lane then reads the batch
+// with broadcast LDS loads.  The conic is staged pre-scaled by -log2(e)/2 so
+// that a pair costs one v_exp_f32.
+//
+// Backward: transmittance is recomputed front to back with the very same
+// arithmetic as the forward (shared device function, explicit FMAs), so the
+// set of composited pairs is bitwise that of the forward.  Using the forward's
+// output colour, the colour behind entry i is C_out - (colour composited up to
+// and including i), so no per-pair state is stored.  Per-pixel gradient terms
+// are summed over each wavefront with DPP row/broadcast reductions (no
+// atomics), waves whose lanes all skip a Gaussian skip its reduction (ballot),
+// and the per-wave sums are added in a fixed order through LDS: one 48-byte
+// record per (Gaussian, tile) intersection, deterministic.
+//
+// Scheduling: either one workgroup per tile, or a persistent grid popping
+// tiles from a device counter in the order of a permutation (static or
+// learned); the choice changes no output bit.
+#include "gs_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace gs {
+
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kAlphaMax = 0.99f;
+constexpr float kTMin = 1e-4f;
+
+struct RasterArgs {
+    gs_layout L;
+    const float4* geo;
+    const float4* geo2;
+    const float4* rgb;
+    const uint32_t* vals;
+    const uint32_t* gid;
+    const uint2* ranges;
+    const gs_view* views;
+    int64_t n;
+    const uint32_t* order;  // nullable
+    uint32_t* counter;      // nullable: non-null selects the persistent schedule
+    int32_t total_tiles;
+    // forward outputs / backward inputs
+    float* out_rgb;
+    float* out_T;
+    uint32_t* out_last;
+    uint32_t* tile_stats;
+    // backward
+    const float* target;
+    const float* dLdC;
+    float inv_count;
+    float4* partials;
+    float* loss;
+    int64_t capacity;
+};
+
+// Staged splat: (u, v, -A log2e / 2, -B log2e), (-C log2e / 2, o, r, g), b
+GS_DEV void stage_splat(const RasterArgs& a, int view, uint32_t sorted_pos, float4& sg, float4& sh,
+                        float& sb, uint32_t& idx) {
+    idx = a.vals[sorted_pos];
+    const int64_t o = (int64_t)view * a.n + a.gid[idx];
+    const float4 g = a.geo[o];
+    const float4 g2 = a.geo2[o];
+    const float4 c = a.rgb[o];
+    sg = make_float4(g.x, g.y, (-0.5f * kLog2e) * g.z, (-kLog2e) * g.w);
+    sh = make_float4((-0.5f * kLog2e) * g2.x, g2.y, c.x, c.y);
+    sb = c.z;
+}
+
+// power (log2-scaled) at the pixel; false if positive (skipped)
+GS_DEV bool eval_pair(float px, float py, const float4& sg, const float4& sh, float& dx, float& dy,
+                      float& G, float& ag) {
+    dx = px - sg.x;
+    dy = py - sg.y;
+    const float p2 = __builtin_fmaf(sg.z * dx, dx, __builtin_fmaf(sh.x * dy, dy, (sg.w * dx) * dy));
+    if (p2 > 0.0f) return false;
+    G = __builtin_amdgcn_exp2f(p2);
+    ag = sh.y * G;
+    return true;
+}
+
+// Next tile of this workgroup: -1 = no more work, -2 = skip (an order entry
+// outside [0, total tiles) is ignored rather than followed out of bounds).
+GS_DEV int next_tile(const RasterArgs& a, int* s_tile) {
+    if (a.counter == nullptr) {
+        const uint32_t t = a.order ? a.order[blockIdx.x] : blockIdx.x;
+        return t < (uint32_t)a.total_tiles ? (int)t : -2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t k = atomicAdd(a.counter, 1u);
+        int t = -1;
+        if (k < (uint32_t)a.total_tiles) {
+            const uint32_t o = a.order ? a.order[k] : k;
+            t = o < (uint32_t)a.total_tiles ? (int)o : -2;
+        }
+        *s_tile = t;
+    }
+    __syncthreads();
+    return *s_tile;
+}
+
+struct TilePix {
+    int view, ix, iy;
+    bool inside;
+    int64_t pix;
+    uint2 range;
+};
+
+template <int TILE>
+GS_DEV TilePix tile_pixel(const RasterArgs& a, int gt) {
+    TilePix t;
+    t.view = view_of_tile(a.L, gt);
+    const int lt = gt - a.L.tile_base[t.view];
+    const int gx = a.L.tiles_x[t.view];
+    const int tx = lt % gx, ty = lt / gx;
+    t.ix = tx * TILE + (int)(threadIdx.x % TILE);
+    t.iy = ty * TILE + (int)(threadIdx.x / TILE);
+    const int W = a.L.width[t.view], H = a.L.height[t.view];
+    t.inside = t.ix < W && t.iy < H;
+    t.pix = a.L.pixel_base[t.view] + (int64_t)t.iy * W + t.ix;
+    t.range = a.ranges[gt];
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// forward
+// ---------------------------------------------------------------------------
+
+template <int TILE, int S>
+__global__ __launch_bounds__(TILE* TILE) void k_raster_fwd(RasterArgs a) {
+    constexpr int NT = TILE * TILE;
+    __shared__ float4 s_g[S];
+    __shared__ float4 s_h[S];
+    __shared__ float s_b[S];
+    __shared__ int s_tile;
+    __shared__ uint32_t s_max, s_sum, s_comp;
+    for (;;) {
+        const int gt = next_tile(a, &s_tile);
+        if (gt == -1 || (gt == -2 && a.counter == nullptr)) break;
+        if (gt == -2) continue;
+        const TilePix tp = tile_pixel<TILE>(a, gt);
+        const float px = (float)tp.ix + 0.5f, py = (float)tp.iy + 0.5f;
+        const uint32_t start = tp.range.x, end = tp.range.y;
+        float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
+        uint32_t last = 0, examined = 0, composited = 0;
+        bool done = !tp.inside;
+        if (threadIdx.x == 0) { s_max = 0; s_sum = 0; s_comp = 0; }
+        for (uint32_t b0 = start; b0 < end; b0 += S) {
+            if (__syncthreads_count(!done) == 0) break;
+            for (int i = threadIdx.x; i < S; i += NT) {
+                const uint32_t j = b0 + i;
+                if (j < end) {
+                    uint32_t idx;
+                    stage_splat(a, tp.view, j, s_g[i], s_h[i], s_b[i], idx);
+                }
+            }
+            __syncthreads();
+            if (!done) {
+                const int cnt = (int)min((uint32_t)S, end - b0);
+                for (int k = 0; k < cnt; ++k) {
+                    ++examined;
+                    const float4 sg = s_g[k];
+                    const float4 sh = s_h[k];
+                    float dx, dy, G, ag;
+                    if (!eval_pair(px, py, sg, sh, dx, dy, G, ag)) continue;
+                    const float alpha = fminf(kAlphaMax, ag);
+                    if (alpha < kAlphaMin) continue;
+                    const float test_T = T * (1.0f - alpha);
+                    if (test_T < kTMin) {
+                        done = true;
+                        break;
+                    }
+                    const float w = alpha * T;
+                    C0 = __builtin_fmaf(w, sh.z, C0);
+                    C1 = __builtin_fmaf(w, sh.w, C1);
+                    C2 = __builtin_fmaf(w, s_b[k], C2);
+                    T = test_T;
+                    last = b0 - start + (uint32_t)k + 1u;
+                    ++composited;
+                }
+            }
+        }
+        if (tp.inside) {
+            const float* bg = a.views[tp.view].bg;
+            a.out_rgb[3 * tp.pix + 0] = __builtin_fmaf(T, bg[0], C0);
+            a.out_rgb[3 * tp.pix + 1] = __builtin_fmaf(T, bg[1], C1);
+            a.out_rgb[3 * tp.pix + 2] = __builtin_fmaf(T, bg[2], C2);
+            a.out_T[tp.pix] = T;
+            a.out_last[tp.pix] = last;
+        }
+        if (a.tile_stats) {
+            __syncthreads();
+            atomicMax(&s_max, examined);
+            atomicAdd(&s_sum, examined);
+            atomicAdd(&s_comp, composited);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                a.tile_stats[4 * (int64_t)gt + 0] = s_max;
+                a.tile_stats[4 * (int64_t)gt + 1] = s_sum;
+                a.tile_stats[4 * (int64_t)gt + 2] = s_comp;
+                a.tile_stats[4 * (int64_t)gt + 3] = 0u;
+            }
+        }
+        if (a.counter == nullptr) break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// wavefront reduction (DPP): lane 63 receives the sum of all 64 lanes
+// ---------------------------------------------------------------------------
+
+template <int CTRL, int ROW_MASK>
+GS_DEV float dpp(float v) {
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xF, false));
+}
+
+GS_DEV float wave_sum_to_last(float v) {
+    v += dpp<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+    v += dpp<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+    v += dpp<0x141, 0xF>(v);  // row_half_mirror
+    v += dpp<0x140, 0xF>(v);  // row_mirror: every lane holds its row's sum
+    v += dpp<0x142, 0xA>(v);  // row_bcast:15 into rows 1, 3
+    v += dpp<0x143, 0xC>(v);  // row_bcast:31 into rows 2, 3
+    return v;
+}
+
+GS_DEV float lane63(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+
+// ---------------------------------------------------------------------------
+// backward
+// ---------------------------------------------------------------------------
+
+template <int TILE, int S>
+__global__ __launch_bounds__(TILE* TILE) void k_raster_bwd(RasterArgs a) {
+    constexpr int NT = TILE * TILE;
+    constexpr int NW = NT / kWave;
+    constexpr int SUB = 64;  // Gaussians per reduction sub-batch
+    __shared__ float4 s_g[S];
+    __shared__ float4 s_h[S];
+    __shared__ float s_b[S];
+    __shared__ uint32_t s_idx[S];
+    __shared__ float s_red[NW][SUB][9];
+    __shared__ uint64_t s_mask[NW];
+    __shared__ int s_tile;
+    __shared__ uint32_t s_len;
+    __shared__ float s_loss[NW];
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    for (;;) {
+        const int gt = next_tile(a, &s_tile);
+        if (gt == -1 || (gt == -2 && a.counter == nullptr)) break;
+        if (gt == -2) continue;
+        const TilePix tp = tile_pixel<TILE>(a, gt);
+        const float px = (float)tp.ix + 0.5f, py = (float)tp.iy + 0.5f;
+        const uint32_t start = tp.range.x;
+        float Co0 = 0, Co1 = 0, Co2 = 0, g0 = 0, g1 = 0, g2 = 0, l1 = 0;
+        uint32_t lastp = 0;
+        if (tp.inside) {
+            Co0 = a.out_rgb[3 * tp.pix + 0];
+            Co1 = a.out_rgb[3 * tp.pix + 1];
+            Co2 = a.out_rgb[3 * tp.pix + 2];
+            lastp = a.out_last[tp.pix];
+            if (a.target) {
+                const float d0 = Co0 - a.target[3 * tp.pix + 0];
+                const float d1 = Co1 - a.target[3 * tp.pix + 1];
+                const float d2 = Co2 - a.target[3 * tp.pix + 2];
+                g0 = d0 > 0.0f ? a.inv_count : (d0 < 0.0f ? -a.inv_count : 0.0f);
+                g1 = d1 > 0.0f ? a.inv_count : (d1 < 0.0f ? -a.inv_count : 0.0f);
+                g2 = d2 > 0.0f ? a.inv_count : (d2 < 0.0f ? -a.inv_count : 0.0f);
+                l1 = (fabsf(d0) + fabsf(d1)) + fabsf(d2);
+            } else {
+                g0 = a.dLdC[3 * tp.pix + 0];
+                g1 = a.dLdC[3 * tp.pix + 1];
+                g2 = a.dLdC[3 * tp.pix + 2];
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) s_len = 0;
+        if (a.loss) {
+            // per-tile L1 sum, fixed-order reduction
+            float s = l1;
+            for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+            if (lane == 0) s_loss[w] = s;
+        }
+        __syncthreads();
+        atomicMax(&s_len, lastp);
+        if (a.loss && threadIdx.x == 0) {
+            float s = 0.0f;
+            for (int i = 0; i < NW; ++i) s += s_loss[i];
+            a.loss[gt] = s;
+        }
+        __syncthreads();
+        const uint32_t stop = start + s_len;
+        float T = 1.0f, Ca0 = 0.0f, Ca1 = 0.0f, Ca2 = 0.0f;
+        for (uint32_t b0 = start; b0 < stop; b0 += S) {
+            __syncthreads();
+            for (int i = threadIdx.x; i < S; i += NT) {
+                const uint32_t j = b0 + i;
+                if (j < stop) stage_splat(a, tp.view, j, s_g[i], s_h[i], s_b[i], s_idx[i]);
+            }
+            __syncthreads();
+            const int cnt = (int)min((uint32_t)S, stop - b0);
+            for (int sub = 0; sub < cnt; sub += SUB) {
+                const int scnt = min(SUB, cnt - sub);
+                uint64_t used = 0;
+                for (int kk = 0; kk < scnt; ++kk) {
+                    const int k = sub + kk;
+                    const uint32_t pos = b0 - start + (uint32_t)k;
+                    const float4 sg = s_g[k];
+                    const float4 sh = s_h[k];
+                    float dx = 0, dy = 0, G = 0, ag = 0, alpha = 0;
+                    bool contrib = false;
+                    if (pos < lastp && eval_pair(px, py, sg, sh, dx, dy, G, ag)) {
+                        alpha = fminf(kAlphaMax, ag);
+                        contrib = alpha >= kAlphaMin;
+                    }
+                    if (__ballot(contrib) == 0ull) continue;
+                    float v0 = 0, v1 = 0, v2 = 0, v3 = 0, v4 = 0, v5 = 0, v6 = 0, v7 = 0, v8 = 0;
+                    if (contrib) {
+                        const float cb = s_b[k];
+                        const float wgt = alpha * T;
+                        v6 = wgt * g0;
+                        v7 = wgt * g1;
+                        v8 = wgt * g2;
+                        Ca0 = __builtin_fmaf(wgt, sh.z, Ca0);
+                        Ca1 = __builtin_fmaf(wgt, sh.w, Ca1);
+                        Ca2 = __builtin_fmaf(wgt, cb, Ca2);
+                        const float gc = __builtin_fmaf(g2, cb, __builtin_fmaf(g1, sh.w, g0 * sh.z));
+                        const float gS = __builtin_fmaf(g2, Co2 - Ca2,
+                                                        __builtin_fmaf(g1, Co1 - Ca1, g0 * (Co0 - Ca0)));
+                        const float one_m = 1.0f - alpha;
+                        const float dalpha = T * gc - gS / one_m;
+                        const float dpow = ag > kAlphaMax ? 0.0f : alpha * dalpha;
+                        v0 = dpow;
+                        v1 = dpow * dx;
+                        v2 = dpow * dy;
+                        v3 = v1 * dx;
+                        v4 = v1 * dy;
+                        v5 = v2 * dy;
+                        T = T * one_m;
+                    }
+                    v0 = wave_sum_to_last(v0);
+                    v1 = wave_sum_to_last(v1);
+                    v2 = wave_sum_to_last(v2);
+                    v3 = wave_sum_to_last(v3);
+                    v4 = wave_sum_to_last(v4);
+                    v5 = wave_sum_to_last(v5);
+                    v6 = wave_sum_to_last(v6);
+                    v7 = wave_sum_to_last(v7);
+                    v8 = wave_sum_to_last(v8);
+                    if (lane == kWave - 1) {
+                        float* r = s_red[w][kk];
+                        r[0] = v0; r[1] = v1; r[2] = v2; r[3] = v3; r[4] = v4;
+                        r[5] = v5; r[6] = v6; r[7] = v7; r[8] = v8;
+                    }
+                    used |= 1ull << kk;
+                }
+                if (lane == 0) s_mask[w] = used;
+                __syncthreads();
+                if ((int)threadIdx.x < scnt) {
+                    const int kk = threadIdx.x;
+                    float r[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+                    bool any = false;
+                    for (int ww = 0; ww < NW; ++ww) {
+                        if ((s_mask[ww] >> kk) & 1ull) {
+                            any = true;
+#pragma unroll
+                            for (int q = 0; q < 9; ++q) r[q] += s_red[ww][kk][q];
+                        }
+                    }
+                    const uint32_t idx = s_idx[sub + kk];
+                    float4* rec = a.partials + 3 * (int64_t)idx;
+                    if (any) {
+                        // conic and opacity of this Gaussian, unscaled
+                        const int64_t o = (int64_t)tp.view * a.n + a.gid[idx];
+                        const float4 g = a.geo[o];
+                        const float4 g2v = a.geo2[o];
+                        const float A = g.z, B = g.w, C = g2v.x, op = g2v.y;
+                        const float du = A * r[1] + B * r[2];
+                        const float dv = B * r[1] + C * r[2];
+                        rec[0] = make_float4(du, dv, -0.5f * r[3], -r[4]);
+                        rec[1] = make_float4(-0.5f * r[5], r[0] / op, r[6], r[7]);
+                        rec[2] = make_float4(r[8], 0.0f, 0.0f, 0.0f);
+                    } else {
+                        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+                        rec[0] = z; rec[1] = z; rec[2] = z;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        // entries no pixel of the tile reached contribute nothing: zero records
+        {
+            const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+            for (uint32_t j = stop + threadIdx.x; j < tp.range.y; j += NT) {
+                float4* rec = a.partials + 3 * (int64_t)a.vals[j];
+                rec[0] = z; rec[1] = z; rec[2] = z;
+            }
+        }
+        if (a.counter == nullptr) break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+template <int TILE, int S>
+static void launch_fwd_t(const RasterArgs& a, unsigned grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_raster_fwd<TILE, S>), dim3(grid), dim3(TILE * TILE), 0, s, a);
+}
+template <int TILE, int S>
+static void launch_bwd_t(const RasterArgs& a, unsigned grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_raster_bwd<TILE, S>), dim3(grid), dim3(TILE * TILE), 0, s, a);
+}
+
+template <bool FWD, int TILE>
+static int dispatch_s(const RasterArgs& a, int S, unsigned grid, hipStream_t s) {
+    switch (S) {
+        case 32: FWD ? launch_fwd_t<TILE, 32>(a, grid, s) : launch_bwd_t<TILE, 32>(a, grid, s); break;
+        case 64: FWD ? launch_fwd_t<TILE, 64>(a, grid, s) : launch_bwd_t<TILE, 64>(a, grid, s); break;
+        case 128: FWD ? launch_fwd_t<TILE, 128>(a, grid, s) : launch_bwd_t<TILE, 128>(a, grid, s); break;
+        case 256: FWD ? launch_fwd_t<TILE, 256>(a, grid, s) : launch_bwd_t<TILE, 256>(a, grid, s); break;
+        default: set_error("lds_batch must be 32, 64, 128 or 256 (got %d)", S); return GS_ERR_INVALID_ARG;
+    }
+    return check_launch(FWD ? "rasterize_fwd" : "rasterize_bwd");
+}
+
+template <bool FWD>
+static int dispatch(const RasterArgs& a, int S, unsigned grid, hipStream_t s) {
+    switch (a.L.tile) {
+        case 8: return dispatch_s<FWD, 8>(a, S, grid, s);
+        case 16: return dispatch_s<FWD, 16>(a, S, grid, s);
+        case 32: return dispatch_s<FWD, 32>(a, S, grid, s);
+        default: set_error("tile must be 8, 16 or 32"); return GS_ERR_INVALID_ARG;
+    }
+}
+
+static RasterArgs base_args(const gs_splats& sp, int64_t n, const gs_layout& L, const gs_bins& b,
+                            const gs_view* views, const gs_schedule* sched) {
+    RasterArgs a;
+    memset(&a, 0, sizeof(a));
+    a.L = L;
+    a.geo = reinterpret_cast<const float4*>(sp.geo);
+    a.geo2 = reinterpret_cast<const float4*>(sp.geo2);
+    a.rgb = reinterpret_cast<const float4*>(sp.rgb);
+    a.vals = b.vals;
+    a.gid = b.gid;
+    a.ranges = reinterpret_cast<const uint2*>(b.ranges);
+    a.views = views;
+    a.n = n;
+    a.total_tiles = L.tile_base[L.n_views];
+    a.capacity = b.capacity;
+    if (sched) {
+        a.order = sched->order;
+        a.counter = sched->counter;
+    }
+    return a;
+}
+
+static unsigned grid_for(const RasterArgs& a, const gs_schedule* sched) {
+    if (sched && sched->counter) return (unsigned)std::max(1, std::min(sched->n_groups, a.total_tiles));
+    return (unsigned)a.total_tiles;
+}
+
+int launch_raster_fwd(const gs_splats& sp, int64_t n, const gs_layout& L, const gs_bins& b,
+                      const gs_view* views, const gs_image& out, int lds_batch,
+                      const gs_schedule* sched, hipStream_t s) {
+    RasterArgs a = base_args(sp, n, L, b, views, sched);
+    a.out_rgb = out.rgb;
+    a.out_T = out.T;
+    a.out_last = out.last;
+    a.tile_stats = out.tile_stats;
+    if (a.total_tiles == 0) return GS_OK;
+    if (a.counter) {
+        int rc = launch_fill_u32(a.counter, 0u, 1, s);
+        if (rc != GS_OK) return rc;
+    }
+    return dispatch<true>(a, lds_batch, grid_for(a, sched), s);
+}
+
+int launch_raster_bwd(const gs_splats& sp, int64_t n, const gs_layout& L, const gs_bins& b,
+                      const gs_view* views, const gs_image& fwd, const float* target,
+                      const float* dLdC, float* partials, float* loss, int lds_batch,
+                      const gs_schedule* sched, hipStream_t s) {
+    RasterArgs a = base_args(sp, n, L, b, views, sched);
+    a.out_rgb = fwd.rgb;
+    a.out_T = fwd.T;
+    a.out_last = fwd.last;
+    a.target = target;
+    a.dLdC = dLdC;
+    a.loss = target ? loss : nullptr;
+    a.inv_count = 1.0f / (3.0f * (float)L.pixel_base[L.n_views]);
+    a.partials = reinterpret_cast<float4*>(partials);
+    // every intersection record is written by the kernel (zeros where nothing contributed)
+    int rc = GS_OK;
+    if (a.total_tiles == 0) return GS_OK;
+    if (a.counter) {
+        rc = launch_fill_u32(a.counter, 0u, 1, s);
+        if (rc != GS_OK) return rc;
+    }
+    return dispatch<false>(a, lds_batch, grid_for(a, sched), s);
+}
+
+}  // namespace gs

@@ -1,0 +1,229 @@
+"""Buffers and the training step on top of the C ABI.
+
+PyTorch supplies device memory and the stream; all arithmetic of the path is in
+libgs.  Names follow the five stages of the C ABI:
+project -> bin_sort -> rasterize_fwd -> rasterize_bwd -> project_bwd_adam.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as G
+
+PLANES = G.PARAM_PLANES
+
+# canonical per-Gaussian order: mean(3), log-scale(3), quaternion(4), opacity logit(1), SH(48)
+# -> parameter-block (plane, component); the unused slot is plane 1 component 3
+_PLANE_INDEX = np.zeros(59, np.int64)
+for _k in range(59):
+    if _k < 3:
+        _PLANE_INDEX[_k] = 0 * 4 + _k
+    elif _k < 6:
+        _PLANE_INDEX[_k] = 1 * 4 + (_k - 3)
+    elif _k < 10:
+        _PLANE_INDEX[_k] = 2 * 4 + (_k - 6)
+    elif _k == 10:
+        _PLANE_INDEX[_k] = 0 * 4 + 3
+    else:
+        _PLANE_INDEX[_k] = 12 + (_k - 11)
+
+
+def pack_flat(flat, device="cuda") -> torch.Tensor:
+    """[N,59] canonical parameters -> parameter block [15, N, 4] float32."""
+    flat = torch.as_tensor(np.ascontiguousarray(flat, np.float32) if isinstance(flat, np.ndarray) else flat,
+                           dtype=torch.float32)
+    n = flat.shape[0]
+    blk = torch.zeros(n, PLANES * 4, dtype=torch.float32, device=flat.device)
+    blk[:, torch.as_tensor(_PLANE_INDEX, device=flat.device)] = flat
+    return blk.view(n, PLANES, 4).permute(1, 0, 2).contiguous().to(device)
+
+
+def unpack_flat(block: torch.Tensor) -> torch.Tensor:
+    """parameter block [15, N, 4] -> [N, 59] canonical order."""
+    n = block.shape[1]
+    rows = block.permute(1, 0, 2).reshape(n, PLANES * 4)
+    return rows[:, torch.as_tensor(_PLANE_INDEX, device=block.device)]
+
+
+def views_to_device(views: np.ndarray, device="cuda") -> torch.Tensor:
+    """VIEW_DTYPE records -> device bytes (128 per view)."""
+    raw = np.ascontiguousarray(views).view(np.uint8).reshape(-1)
+    return torch.from_numpy(raw.copy()).to(device)
+
+
+def _i(t) -> int:
+    return t.data_ptr()
+
+
+class Frame:
+    """Per-view-set buffers: projected splats, intersection lists, images."""
+
+    def __init__(self, n: int, widths, heights, tile: int = 16, capacity: int = 1 << 16,
+                 device="cuda", tile_stats: bool = False):
+        self.n = int(n)
+        self.device = device
+        self.layout = G.layout_init(widths, heights, tile)
+        self.n_views = len(widths)
+        self.tile = tile
+        V, n = self.n_views, self.n
+        f32 = dict(dtype=torch.float32, device=device)
+        u32 = dict(dtype=torch.int32, device=device)   # torch has no uint32 arithmetic; bits only
+        self.geo = torch.zeros(V * n, 4, **f32)
+        self.geo2 = torch.zeros(V * n, 4, **f32)
+        self.rgb_s = torch.zeros(V * n, 4, **f32)
+        self.rect = torch.zeros(V * n, 2, **u32)
+        self.tiles = torch.zeros(V * n, **u32)
+        self.offsets = torch.zeros(V * n + 1, **u32)
+        self.ranges = torch.zeros(self.layout.total_tiles, 2, **u32)
+        self.status = torch.zeros(1, **u32)
+        P = self.layout.total_pixels
+        self.image = torch.zeros(P, 3, **f32)
+        self.T = torch.zeros(P, **f32)
+        self.last = torch.zeros(P, **u32)
+        self.tile_stats = torch.zeros(self.layout.total_tiles, 4, **u32) if tile_stats else None
+        self.loss_tiles = torch.zeros(self.layout.total_tiles, **f32)
+        self.counter = torch.zeros(1, **u32)
+        self.capacity = 0
+        self.resize(capacity)
+
+    # -- buffers sized by the intersection capacity --
+    def resize(self, capacity: int) -> None:
+        capacity = max(int(capacity), 1)
+        u32 = dict(dtype=torch.int32, device=self.device)
+        self.keys = torch.zeros(capacity, **u32)
+        self.vals = torch.zeros(capacity, **u32)
+        self.gid = torch.zeros(capacity, **u32)
+        self.partials = torch.zeros(capacity, 12, dtype=torch.float32, device=self.device)
+        ws = G.lib.gs_bin_sort_workspace_size(self.n, C.byref(self.layout), capacity)
+        self.workspace = torch.zeros(max(int(ws), 1), dtype=torch.uint8, device=self.device)
+        self.capacity = capacity
+        self._structs()
+
+    def _structs(self) -> None:
+        self.splats = G.GsSplats(_i(self.geo), _i(self.geo2), _i(self.rgb_s), _i(self.rect), _i(self.tiles))
+        self.bins = G.GsBins(_i(self.offsets), _i(self.keys), _i(self.vals), _i(self.gid),
+                             _i(self.ranges), _i(self.status), self.capacity)
+        self.img = G.GsImage(_i(self.image), _i(self.T), _i(self.last),
+                             _i(self.tile_stats) if self.tile_stats is not None else None)
+
+    def intersections(self) -> int:
+        """K (synchronises)."""
+        return int(self.offsets[-1].item()) & 0xFFFFFFFF
+
+    def status_bits(self) -> int:
+        return int(self.status.item())
+
+    def schedule(self, order: torch.Tensor | None = None, n_groups: int | None = None) -> G.GsSchedule:
+        """Persistent work-queue schedule (order: global tile ids, int32 tensor)."""
+        if n_groups is None:
+            n_groups = 256 * 8
+        return G.GsSchedule(_i(order) if order is not None else None, _i(self.counter), int(n_groups))
+
+
+class Model:
+    """Gaussian parameters (parameter block) and Adam state."""
+
+    def __init__(self, flat, device="cuda", lr=1e-3, betas=(0.9, 0.999), eps=1e-15):
+        self.params = pack_flat(flat, device)
+        self.n = self.params.shape[1]
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.step = torch.zeros(1, dtype=torch.int32, device=device)
+        self.scratch = torch.zeros(4, dtype=torch.float32, device=device)
+        lrs = [float(lr)] * 6 if np.isscalar(lr) else [float(x) for x in lr]
+        self.adam = G.GsAdam(_i(self.m), _i(self.v), _i(self.step), _i(self.scratch),
+                             (C.c_float * 6)(*lrs), betas[0], betas[1], eps)
+
+    def flat(self) -> torch.Tensor:
+        return unpack_flat(self.params)
+
+
+# ---------------------------------------------------------------------------
+# the five stages
+# ---------------------------------------------------------------------------
+
+def project(params: torch.Tensor, frame: Frame, views_dev: torch.Tensor, stream=None) -> None:
+    G.check(G.lib.gs_project(_i(params), frame.n, _i(views_dev), C.byref(frame.layout),
+                             C.byref(frame.splats), G.stream_ptr(stream)), "gs_project")
+
+
+def bin_sort(frame: Frame, stream=None) -> None:
+    G.check(G.lib.gs_bin_sort(C.byref(frame.splats), frame.n, C.byref(frame.layout),
+                              C.byref(frame.bins), _i(frame.workspace), frame.workspace.numel(),
+                              G.stream_ptr(stream)), "gs_bin_sort")
+
+
+def rasterize_fwd(frame: Frame, views_dev: torch.Tensor, lds_batch: int = 64, sched=None,
+                  stream=None) -> None:
+    G.check(G.lib.gs_rasterize_fwd(C.byref(frame.splats), frame.n, C.byref(frame.layout),
+                                   C.byref(frame.bins), _i(views_dev), C.byref(frame.img), lds_batch,
+                                   C.byref(sched) if sched is not None else None,
+                                   G.stream_ptr(stream)), "gs_rasterize_fwd")
+
+
+def rasterize_bwd(frame: Frame, views_dev: torch.Tensor, target: torch.Tensor | None = None,
+                  dLdC: torch.Tensor | None = None, lds_batch: int = 64, sched=None,
+                  stream=None) -> None:
+    G.check(G.lib.gs_rasterize_bwd(C.byref(frame.splats), frame.n, C.byref(frame.layout),
+                                   C.byref(frame.bins), _i(views_dev), C.byref(frame.img),
+                                   _i(target) if target is not None else None,
+                                   _i(dLdC) if dLdC is not None else None, _i(frame.partials),
+                                   _i(frame.loss_tiles) if target is not None else None, lds_batch,
+                                   C.byref(sched) if sched is not None else None,
+                                   G.stream_ptr(stream)), "gs_rasterize_bwd")
+
+
+def project_bwd_adam(model: Model, frame: Frame, views_dev: torch.Tensor, adam: bool = True,
+                     grads_out: torch.Tensor | None = None, stream=None) -> None:
+    G.check(G.lib.gs_project_bwd_adam(_i(model.params), frame.n, _i(views_dev), C.byref(frame.layout),
+                                      C.byref(frame.bins), _i(frame.partials),
+                                      C.byref(model.adam) if adam else None,
+                                      _i(grads_out) if grads_out is not None else None,
+                                      G.stream_ptr(stream)), "gs_project_bwd_adam")
+
+
+def fit_capacity(params: torch.Tensor, frame: Frame, views_dev: torch.Tensor, slack: float = 1.25):
+    """Project once and size the intersection buffers for the current K (synchronises)."""
+    project(params, frame, views_dev)
+    K = int(frame.tiles.to(torch.int64).sum().item())
+    if K > frame.capacity:
+        frame.resize(int(math.ceil(K * slack)) + 1024)
+    return K
+
+
+def render(params: torch.Tensor, frame: Frame, views_dev: torch.Tensor, lds_batch: int = 64,
+           sched=None, check: bool = True) -> torch.Tensor:
+    """Forward only; returns the image [pixels, 3] (a view into frame.image)."""
+    project(params, frame, views_dev)
+    bin_sort(frame)
+    if check and frame.status_bits():
+        fit_capacity(params, frame, views_dev)
+        bin_sort(frame)
+    rasterize_fwd(frame, views_dev, lds_batch, sched)
+    return frame.image
+
+
+def train_step(model: Model, frame: Frame, views_dev: torch.Tensor, target: torch.Tensor,
+               lds_batch: int = 64, sched=None, check: bool = True,
+               grads_out: torch.Tensor | None = None, adam: bool = True) -> None:
+    """One L1 training step over the frame's views: 5 stages, gradients summed over views."""
+    project(model.params, frame, views_dev)
+    bin_sort(frame)
+    if check and frame.status_bits():
+        fit_capacity(model.params, frame, views_dev)
+        bin_sort(frame)
+        if frame.status_bits():
+            raise G.GsError(f"intersection status {frame.status_bits()} after resize")
+    rasterize_fwd(frame, views_dev, lds_batch, sched)
+    rasterize_bwd(frame, views_dev, target=target, lds_batch=lds_batch, sched=sched)
+    project_bwd_adam(model, frame, views_dev, adam=adam, grads_out=grads_out)
+
+
+def loss_value(frame: Frame) -> float:
+    """Mean |C - target| of the last train_step (synchronises)."""
+    return float(frame.loss_tiles.double().sum().item()) / (3.0 * frame.layout.total_pixels)

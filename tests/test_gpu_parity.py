@@ -1,0 +1,232 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bars: bit-exact for tile rectangles, counts, offsets, keys, values and ranges;
+pixels within 1e-4 (max abs) outside pixels whose compositing decisions lie at
+a threshold ("fragile", counted); gradients within 1e-3 relative (floored at
+1e-2 of the column maximum); updated parameters within 1e-3 relative, except
+where the oracle's gradient is too small for its sign to be certain (Adam's
+first step moves such parameters by +-lr, so those are held to 2 lr).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synthetic as S
+from gpu_common import note, per_gaussian_2d, rect_from_packed, run_gpu_step
+from helpers import exempt_gaussians, grad_close
+
+pytestmark = pytest.mark.gpu
+
+PIX_TOL = 1e-4
+GRAD_RTOL = 1e-3
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2605_00219_amd import _lib  # noqa: F401  (fails loudly if not built)
+    yield
+
+
+def _workloads():
+    w1 = S.workload_plain_small()
+    # two views of different (ragged) sizes, tile edge not dividing the image
+    scene = S.scene_uniform_cube(3000, 77, log_scale_mean=-3.2)
+    target_scene = S.scene_uniform_cube(3000, 78, log_scale_mean=-3.2)
+    views = S.views_array([S.make_view(200, 150, (0.5, -0.3, -4.0), bg=(0.1, 0.2, 0.05)),
+                           S.make_view(333, 97, (-2.0, 1.0, -3.0))])
+    return {"plain-2k-256": (w1.scene, w1.target_scene, w1.views, 16),
+            "ragged-2view": (scene, target_scene, views, 16)}
+
+
+WL = _workloads()
+
+
+def _oracle_step(scene, target_scene, views, tile, lr=1e-3):
+    target = oracle.render(target_scene, views, tile)
+    return target, oracle.train_step(scene, views, tile, target, lr=lr)
+
+
+@pytest.mark.parametrize("name", list(WL))
+def test_projection_and_binning_bit_exact(name):
+    scene, target_scene, views, tile = WL[name]
+    note(f"projection/binning parity {name}")
+    ref = oracle.train_step(scene, views, tile, oracle.render(target_scene, views, tile), adam_step=False)
+    g = run_gpu_step(scene, views, tile)
+    assert g["status"] == 0
+    np.testing.assert_array_equal(g["tiles"], ref.proj.tiles)
+    vis = ref.proj.tiles > 0
+    assert vis.sum() > 100
+    np.testing.assert_array_equal(rect_from_packed(g["rect"])[vis], ref.proj.rect[vis])
+    # float outputs: same operation order without contraction -> same bits
+    f32 = lambda a: a.astype(np.float32)
+    np.testing.assert_array_equal(g["geo"][..., 0][vis], f32(ref.proj.xy[..., 0])[vis])
+    np.testing.assert_array_equal(g["geo"][..., 1][vis], f32(ref.proj.xy[..., 1])[vis])
+    np.testing.assert_array_equal(g["geo"][..., 2][vis], f32(ref.proj.conic[..., 0])[vis])
+    np.testing.assert_array_equal(g["geo"][..., 3][vis], f32(ref.proj.conic[..., 1])[vis])
+    np.testing.assert_array_equal(g["geo2"][..., 0][vis], f32(ref.proj.conic[..., 2])[vis])
+    np.testing.assert_array_equal(g["geo2"][..., 1][vis], f32(ref.proj.opacity)[vis])
+    np.testing.assert_array_equal(g["geo2"][..., 2][vis], f32(ref.proj.depth)[vis])
+    np.testing.assert_array_equal(g["geo2"][..., 3][vis], f32(ref.proj.radius)[vis])
+    np.testing.assert_array_equal(g["rgb"][..., :3][vis], f32(ref.proj.rgb)[vis])
+    # binning
+    np.testing.assert_array_equal(g["offsets"], ref.bins.offsets)
+    np.testing.assert_array_equal(g["keys"], ref.bins.keys)
+    np.testing.assert_array_equal(g["vals"], ref.bins.vals)
+    np.testing.assert_array_equal(g["gid"], ref.bins.gid)
+    np.testing.assert_array_equal(g["ranges"], ref.bins.ranges)
+
+
+@pytest.mark.parametrize("name", list(WL))
+@pytest.mark.parametrize("lds_batch", [32, 64, 256])
+def test_forward_pixels(name, lds_batch):
+    scene, target_scene, views, tile = WL[name]
+    note(f"forward parity {name} S={lds_batch}")
+    ref = oracle.train_step(scene, views, tile, oracle.render(target_scene, views, tile), adam_step=False)
+    g = run_gpu_step(scene, views, tile, lds_batch=lds_batch)
+    ok = ref.image.fragile == 0
+    assert ok.mean() > 0.995, f"fragile fraction {1 - ok.mean():.4f}"
+    err = np.abs(g["image"] - ref.image.rgb).max(axis=1)
+    assert err[ok].max() <= PIX_TOL, err[ok].max()
+    assert np.abs(g["T"] - ref.image.T)[ok].max() <= PIX_TOL
+    np.testing.assert_array_equal(g["last"][ok], ref.image.last[ok])
+    note(f"  max pixel err {err[ok].max():.2e}, fragile {int((~ok).sum())} px, "
+         f"last mismatches at fragile {int((g['last'] != ref.image.last).sum())}")
+
+
+@pytest.mark.parametrize("name", list(WL))
+def test_training_step(name):
+    scene, target_scene, views, tile = WL[name]
+    note(f"training-step parity {name}")
+    target, ref = _oracle_step(scene, target_scene, views, tile)
+    g = run_gpu_step(scene, views, tile, target=target)
+    V, n = len(views), scene.n
+    ex = exempt_gaussians(ref.bins.ranges, ref.bins.vals, ref.bins.gid, views, tile, ref.fragile, n)
+    ex_any = ex.any(axis=0)
+    # loss
+    loss_gpu = g["loss_tiles"].astype(np.float64).sum() / (3 * sum(oracle.n_pixels(views)))
+    assert abs(loss_gpu - ref.loss) <= 1e-4 * ref.loss
+    # per-Gaussian 2D gradients (sums of the intersection records)
+    g2 = per_gaussian_2d(g["partials"], g["offsets"], V, n)
+    ok2 = grad_close(g2.reshape(-1, 9), ref.grads2d.reshape(-1, 9), GRAD_RTOL).reshape(V, n, 9)
+    bad = ~ok2.all(axis=2) & ~ex
+    assert not bad.any(), np.argwhere(bad)[:5]
+    # parameter gradients
+    okg = grad_close(g["grads"], ref.grads, GRAD_RTOL)
+    badg = ~okg.all(axis=1) & ~ex_any
+    assert not badg.any(), (np.argwhere(~okg & ~ex_any[:, None])[:5])
+    assert (~okg.all(axis=1)).mean() < 0.02
+    # updated parameters after one Adam step
+    p0 = scene.flat()
+    lr = 1e-3
+    gmax = np.abs(ref.grads).max(axis=0, keepdims=True)
+    certain = np.abs(ref.grads) >= 1e-3 * gmax
+    diff = np.abs(g["params"] - ref.params)
+    tol = np.where(certain, 1e-3 * np.abs(ref.params) + 1e-6, 2 * lr + 1e-6)
+    badp = (diff > tol) & ~ex_any[:, None]
+    assert not badp.any(), np.argwhere(badp)[:5]
+    # every parameter moved by about lr (Adam step 1 with eps = 1e-15)
+    moved = np.abs(g["params"] - p0)
+    assert np.median(moved[np.abs(ref.grads) > 0]) == pytest.approx(lr, rel=1e-3)
+    note(f"  exempt {int(ex_any.sum())}/{n} Gaussians; sign-uncertain {int((~certain).sum())} elems")
+
+
+def test_deterministic_bitwise():
+    scene, target_scene, views, tile = WL["plain-2k-256"]
+    note("determinism")
+    target = oracle.render(target_scene, views, tile)
+    a = run_gpu_step(scene, views, tile, target=target)
+    b = run_gpu_step(scene, views, tile, target=target)
+    for k in ("image", "partials", "grads", "params", "keys", "vals"):
+        np.testing.assert_array_equal(a[k], b[k])
+
+
+def test_persistent_and_permuted_schedules_change_no_bit():
+    scene, target_scene, views, tile = WL["ragged-2view"]
+    note("schedule invariance")
+    target = oracle.render(target_scene, views, tile)
+    base = run_gpu_step(scene, views, tile, target=target)
+    nt = sum(oracle.n_tiles(views, tile))
+    perm = np.random.default_rng(3).permutation(nt).astype(np.int32)
+    for kw in (dict(persistent=True), dict(sched_order=perm), dict(sched_order=perm, persistent=True)):
+        other = run_gpu_step(scene, views, tile, target=target, **kw)
+        for k in ("image", "T", "last", "partials", "grads", "params"):
+            np.testing.assert_array_equal(base[k], other[k], err_msg=str(kw))
+
+
+@pytest.mark.parametrize("tile", [8, 32])
+def test_other_tile_sizes(tile):
+    scene, target_scene, views, _ = WL["ragged-2view"]
+    note(f"tile {tile}")
+    target, ref = _oracle_step(scene, target_scene, views, tile)
+    g = run_gpu_step(scene, views, tile, target=target, lds_batch=128)
+    np.testing.assert_array_equal(g["keys"], ref.bins.keys)
+    np.testing.assert_array_equal(g["ranges"], ref.bins.ranges)
+    ok = ref.image.fragile == 0
+    assert np.abs(g["image"] - ref.image.rgb).max(axis=1)[ok].max() <= PIX_TOL
+    ex_any = exempt_gaussians(ref.bins.ranges, ref.bins.vals, ref.bins.gid, views, tile, ref.fragile,
+                              scene.n).any(axis=0)
+    okg = grad_close(g["grads"], ref.grads, GRAD_RTOL)
+    assert not (~okg.all(axis=1) & ~ex_any).any()
+
+
+def test_empty_scene_and_culled_gaussians():
+    note("edge: nothing visible")
+    scene = S.scene_uniform_cube(500, 5)
+    scene.means[:] = scene.means + np.float32([0, 0, -10])   # all behind the camera at z=-4
+    scene.means[:7, 2] = np.float32(0)                        # a few visible
+    scene.quats[3] = 0                                         # zero quaternion: culled
+    scene.sh[5, 2, 1] = np.float32("nan")                      # non-finite: culled
+    views = S.views_array([S.make_view(64, 48, (0, 0, -4.0))])
+    target = S.random_image(48, 64, 1)
+    ref = oracle.train_step(scene, views, 16, target)
+    g = run_gpu_step(scene, views, 16, target=target)
+    np.testing.assert_array_equal(g["tiles"], ref.proj.tiles)
+    assert g["tiles"][0, 3] == 0 and g["tiles"][0, 5] == 0
+    assert np.abs(g["image"] - ref.image.rgb).max() <= PIX_TOL
+    okg = grad_close(g["grads"], ref.grads, GRAD_RTOL)
+    assert okg.all()
+    # a scene with no visible Gaussian at all
+    scene.means[:, 2] = np.float32(-10)
+    ref = oracle.train_step(scene, views, 16, target)
+    g = run_gpu_step(scene, views, 16, target=target)
+    assert g["K"] == 0 and ref.bins.offsets[-1] == 0
+    np.testing.assert_array_equal(g["ranges"], ref.bins.ranges)
+    assert np.all(g["image"] == 0) and np.all(g["T"] == 1)
+    assert np.all(g["grads"] == 0)
+
+
+def test_capacity_overflow_is_reported_and_recovered():
+    import torch
+    from paper_2605_00219_amd import pipeline as P
+    scene, target_scene, views, tile = WL["plain-2k-256"]
+    note("edge: capacity overflow")
+    model = P.Model(scene.flat())
+    frame = P.Frame(scene.n, [256], [256], 16, capacity=1000)
+    vd = P.views_to_device(views)
+    P.project(model.params, frame, vd)
+    P.bin_sort(frame)
+    torch.cuda.synchronize()
+    assert frame.status_bits() & 1
+    ref = oracle.train_step(scene, views, tile, oracle.render(target_scene, views, tile), adam_step=False)
+    assert frame.intersections() == int(ref.bins.offsets[-1]) > 1000
+    # the step grows the buffers and succeeds
+    target = torch.as_tensor(oracle.render(target_scene, views, tile), device="cuda")
+    P.train_step(model, frame, vd, target)
+    torch.cuda.synchronize()
+    assert frame.status_bits() == 0 and frame.capacity >= frame.intersections()
+
+
+def test_invalid_arguments_raise():
+    from paper_2605_00219_amd import _lib as G
+    from paper_2605_00219_amd import pipeline as P
+    scene, _, views, _ = WL["plain-2k-256"]
+    frame = P.Frame(scene.n, [256], [256], 16)
+    vd = P.views_to_device(views)
+    with pytest.raises(G.GsError, match="lds_batch"):
+        P.rasterize_fwd(frame, vd, lds_batch=48)
+    with pytest.raises(G.GsError, match="exactly one"):
+        P.rasterize_bwd(frame, vd, target=None, dLdC=None)

@@ -1,0 +1,248 @@
+"""Training-step throughput of the 3DGS hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps 100] [--warmup 10]
+
+Default workload: 300k Gaussians (means ~N(0,1)^3, log-scales ~N(-4,0.7)),
+1280x720, 50 cameras on a radius-5 sphere, one view per L1 training step,
+16x16 tiles (targets rendered from a held-out 300k-Gaussian scene outside the
+timed region).  A step is the whole hot path: project -> bin_sort ->
+rasterize_fwd -> rasterize_bwd (fused L1 gradient) -> project_bwd_adam.
+
+Prints one JSON line.  `roofline` describes the kernel with the largest share
+of the step; `cpu_baseline` times the CPU oracle on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "train iters/sec + rasterize_bwd HBM GB/s (% peak), batched/learned vs plain"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+
+# algorithmic work of rasterize_bwd ("Roofline accounting")
+BWD_BYTES_TRAVERSED = 76     # Gaussian id 4 + splat 36 read, gradient record 36 written
+BWD_BYTES_PIXEL = 28         # C 12 + target 12 + last 4
+BWD_BYTES_TILE = 16          # range 8 + loss 4 + traversal stop 4
+BWD_FLOP_EVAL = 14           # recompute of power, G, alpha, thresholds per evaluated pair
+BWD_FLOP_CONTRIB = 44        # gradient terms and their sums per composited pair
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--lds-batch", type=int, default=64)
+    ap.add_argument("--n", type=int, default=300_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-replay", action="store_true", help="skip the work-counting replay")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 1 GiB device copy (for HBM counter scaling)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; multi-GPU runs are not "
+                          "supported (see DESIGN.md for how the path would shard)",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synthetic as S
+    from paper_2605_00219_amd import pipeline as P
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log("generating workload")
+    w = S.workload_plain_300k(n=args.n)
+    n = w.scene.n
+    W, H = int(w.views[0]["width"]), int(w.views[0]["height"])
+    ncam = len(w.views)
+    views_all = P.views_to_device(w.views)           # ncam x 128 bytes
+    vptr = lambda i: views_all[128 * i:128 * (i + 1)]
+
+    # targets: rendered by the GPU forward from the held-out scene (not timed)
+    log("rendering targets")
+    tgt_model = P.Model(w.target_scene.flat())
+    tframe = P.Frame(n, [W], [H], 16)
+    targets = torch.empty(ncam, H * W, 3, device=dev)
+    for i in range(ncam):
+        P.fit_capacity(tgt_model.params, tframe, vptr(i))
+        targets[i].copy_(P.render(tgt_model.params, tframe, vptr(i)))
+    del tgt_model, tframe
+
+    model = P.Model(w.scene.flat(), lr=w.lr)
+    frame = P.Frame(n, [W], [H], 16)
+    kmax = 0
+    for i in range(ncam):
+        kmax = max(kmax, P.fit_capacity(model.params, frame, vptr(i)))
+    frame.resize(int(kmax * 1.3) + 4096)
+    order = [int(x) for x in w.view_order]
+
+    def step(i, ev=None):
+        vi = order[i % ncam]
+        vd = vptr(vi)
+        if ev is not None:
+            ev[0].record()
+        P.project(model.params, frame, vd)
+        if ev is not None:
+            ev[1].record()
+        P.bin_sort(frame)
+        if ev is not None:
+            ev[2].record()
+        P.rasterize_fwd(frame, vd, args.lds_batch)
+        if ev is not None:
+            ev[3].record()
+        P.rasterize_bwd(frame, vd, target=targets[vi], lds_batch=args.lds_batch)
+        if ev is not None:
+            ev[4].record()
+        P.project_bwd_adam(model, frame, vd)
+        if ev is not None:
+            ev[5].record()
+
+    log(f"warmup {args.warmup} steps (N={n}, {W}x{H}, K<={kmax})")
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    if frame.status_bits():
+        raise RuntimeError("intersection capacity exceeded during warmup")
+    state0 = [t.clone() for t in (model.params, model.m, model.v, model.step)]
+
+    # timed region: plain single-view steps
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(args.warmup + i, evs[i])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    if frame.status_bits():
+        raise RuntimeError("intersection capacity exceeded in the timed region")
+    wall = t1 - t0
+    stages = ["project", "bin_sort", "rasterize_fwd", "rasterize_bwd", "project_bwd_adam"]
+    stage_ms = {s: float(np.mean([evs[i][k].elapsed_time(evs[i][k + 1]) for i in range(args.steps)]))
+                for k, s in enumerate(stages)}
+    ips = args.steps / wall
+    log(f"plain: {ips:.1f} iters/s, {1e3 * wall / args.steps:.3f} ms/step; stages {stage_ms}")
+
+    # replay of the timed steps (deterministic) counting the work each kernel did
+    counts = None
+    if not args.no_replay:
+        for t, s0 in zip((model.params, model.m, model.v, model.step), state0):
+            t.copy_(s0)
+        rframe = P.Frame(n, [W], [H], 16, capacity=frame.capacity, tile_stats=True)
+        gx = (W + 15) // 16
+        tile_of_px = torch.arange(H * W, device=dev)
+        tile_of_px = (tile_of_px // W // 16) * gx + (tile_of_px % W) // 16
+        acc = dict(K=0, trav_bwd=0, eval_bwd=0, contrib=0, eval_fwd=0, trav_fwd=0)
+        for i in range(args.steps):
+            vi = order[(args.warmup + i) % ncam]
+            vd = vptr(vi)
+            P.project(model.params, rframe, vd)
+            P.bin_sort(rframe)
+            P.rasterize_fwd(rframe, vd, args.lds_batch)
+            last = rframe.last.to(torch.int64)
+            per_tile = torch.zeros(rframe.layout.total_tiles, dtype=torch.int64, device=dev)
+            per_tile.scatter_reduce_(0, tile_of_px, last, reduce="amax")
+            ts = rframe.tile_stats.to(torch.int64)
+            acc["K"] += rframe.intersections()
+            acc["trav_bwd"] += int(per_tile.sum().item())
+            acc["eval_bwd"] += int(last.sum().item())
+            acc["contrib"] += int(ts[:, 2].sum().item())
+            acc["eval_fwd"] += int(ts[:, 1].sum().item())
+            acc["trav_fwd"] += int(ts[:, 0].sum().item())
+            P.rasterize_bwd(rframe, vd, target=targets[vi], lds_batch=args.lds_batch)
+            P.project_bwd_adam(model, rframe, vd)
+        torch.cuda.synchronize()
+        counts = {k: v / args.steps for k, v in acc.items()}
+        log(f"per-step work: {counts}")
+
+    # roofline of the dominant kernel
+    dom = max(stage_ms, key=stage_ms.get)
+    roof = None
+    extra = {}
+    P_px = H * W
+    ntiles = frame.layout.total_tiles
+    if counts is not None:
+        bwd_bytes = (BWD_BYTES_TRAVERSED * counts["trav_bwd"]
+                     + BWD_BYTES_PIXEL * P_px + BWD_BYTES_TILE * ntiles)
+        bwd_flop = BWD_FLOP_EVAL * counts["eval_bwd"] + BWD_FLOP_CONTRIB * counts["contrib"]
+        t_bwd = stage_ms["rasterize_bwd"] * 1e-3
+        bwd_gbs = bwd_bytes / t_bwd / 1e9
+        bwd_tflops = bwd_flop / t_bwd / 1e12
+        extra["rasterize_bwd"] = {
+            "ms": stage_ms["rasterize_bwd"], "algorithmic_bytes": bwd_bytes,
+            "hbm_gbs": bwd_gbs, "hbm_frac": bwd_gbs / HBM_PEAK_GBS,
+            "algorithmic_flop": bwd_flop, "tflops": bwd_tflops,
+            "alu_frac": bwd_tflops / FP32_PEAK_TFLOPS,
+            "intersections": counts["K"], "traversed": counts["trav_bwd"],
+            "pairs_evaluated": counts["eval_bwd"], "pairs_composited": counts["contrib"]}
+        if dom == "rasterize_bwd":
+            roof = {"bound": "alu", "achieved": bwd_tflops, "peak": FP32_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": bwd_tflops / FP32_PEAK_TFLOPS, "traffic": None,
+                    "kernel": "rasterize_bwd"}
+    if roof is None:
+        roof = {"bound": "unknown", "achieved": None, "peak": None, "unit": None, "frac": None,
+                "traffic": None, "kernel": dom}
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, order)
+
+    out = {
+        "metric": METRIC, "value": ips, "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"plain-{n // 1000}k-{W}x{H}", "gaussians": n, "width": W,
+                   "height": H, "views_per_step": 1, "cameras": ncam, "tile": 16,
+                   "lds_batch": args.lds_batch, "loss": "L1", "lr": w.lr},
+        "stage_ms": stage_ms,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        **extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(w, order, n_steps=3):
+    """The CPU oracle, as it stands, on 3 full training steps of the same
+    workload (one view each, the first 3 views of the step sequence); its
+    targets are rendered by the oracle itself, outside the timed region."""
+    import oracle
+    log(f"cpu baseline: oracle, {n_steps} full steps, {oracle.threads()} threads")
+    vis = [order[i] for i in range(n_steps)]
+    tg = {vi: oracle.render(w.target_scene, w.views[vi:vi + 1], 16) for vi in vis}
+    t0 = time.perf_counter()
+    for vi in vis:
+        oracle.train_step(w.scene, w.views[vi:vi + 1], 16, tg[vi], lr=w.lr)
+    dt = time.perf_counter() - t0
+    return {"value": n_steps / dt, "unit": "iters/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{n_steps} full L1 training steps (300k Gaussians, 1280x720, one view each)",
+            "seconds": dt}
+
+
+if __name__ == "__main__":
+    main()

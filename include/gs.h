@@ -106,26 +106,42 @@ typedef struct gs_layout {
 /* Per-view projection outputs, each an array of n_views * n entries indexed
  * [view * n + g]. */
 typedef struct gs_splats {
-    float* geo;       /* float4 (u, v, A, B): mean in pixels, conic A, B */
-    float* geo2;      /* float4 (C, opacity, depth z, radius in pixels) */
-    float* rgb;       /* float4 (r, g, b, 0) after the +0.5 shift and clamp at 0 */
-    uint32_t* rect;   /* uint32 x2: (x0 | y0 << 16, x1 | y1 << 16), tiles [x0,x1) x [y0,y1) */
+    float* rec;       /* 16 floats (64 bytes, one cache line) per entry:
+                           (u, v, A, B)   mean in pixels, conic A, B
+                           (C, o, r, g)   conic C, opacity, colour r, g
+                           (b, z, radius, 0)  colour b, depth, radius in pixels
+                           (rect0, rect1, 0, 0) tile rectangle bits as uint32:
+                               rect0 = x0 | y0 << 16, rect1 = x1 | y1 << 16,
+                               tiles [x0, x1) x [y0, y1)
+                         colour is after the +0.5 shift and the clamp at 0;
+                         entries of culled Gaussians are all zero */
     uint32_t* tiles;  /* tiles touched, 0 for culled Gaussians */
 } gs_splats;
 
 /* Intersection buffers.  Intersections of view v occupy the contiguous
- * segment [offsets[v*n], offsets[(v+1)*n]); within it Gaussian g owns
- * [offsets[v*n+g], offsets[v*n+g+1]) ("unsorted index", emission order: rows
- * of its tile rectangle outer, columns inner). */
+ * segment [offsets[v*n], offsets[(v+1)*n]); within it Gaussian g owns the
+ * "unsorted indices" [offsets[v*n+g], offsets[v*n+g+1]), one per tile of its
+ * rectangle in emission order (rows outer, columns inner). */
 typedef struct gs_bins {
     uint32_t* offsets;   /* n_views*n + 1: exclusive scan of tiles; [n_views*n] = K */
     uint32_t* keys;      /* capacity: (tile << D) | depth bits, sorted per view */
-    uint32_t* vals;      /* capacity: unsorted index of each sorted key */
-    uint32_t* gid;       /* capacity: Gaussian id by unsorted index */
+    uint32_t* vals;      /* capacity: Gaussian id of each sorted key */
+    uint32_t* inv;       /* capacity: sorted position of each unsorted index */
     uint32_t* ranges;    /* 2 * total tiles: [start, end) of each tile in sorted order */
     uint32_t* status;    /* 1 word, device status bits (GS_STATUS_*), cleared by gs_bin_sort */
-    int64_t capacity;    /* entries in keys / vals / gid, and records in the partials buffer */
+    int64_t capacity;    /* entries in keys / vals / inv and records in gs_grads2d */
 } gs_bins;
+
+/* Screen-space gradients written by gs_rasterize_bwd and read by
+ * gs_project_bwd_adam: one record per intersection that the backward
+ * traversed, at its sorted position. */
+typedef struct gs_grads2d {
+    float* rec;           /* capacity records of 12 floats: (d u, d v, d A, d B, d C,
+                             d opacity, d r, d g, d b, 0, 0, 0) */
+    uint32_t* tile_stop;  /* total tiles: records exist at sorted positions
+                             [ranges[t].start, tile_stop[t]) of each tile t;
+                             the intersections after that contribute nothing */
+} gs_grads2d;
 
 /* Rasterisation outputs, indexed by global pixel (views concatenated). */
 typedef struct gs_image {
@@ -196,10 +212,11 @@ int gs_project(const float* params, int64_t n, const gs_view* views, const gs_la
  * offsets = exclusive scan of splats->tiles over (view, g); K = offsets[V*n].
  * For each Gaussian, one key per touched tile at its unsorted index:
  * key = (tile << D) | (mantissa(f) >> (23 - D)) with f = (2z+1)/(z+1) in
- * float32, value = the unsorted index, gid = g.  Keys of each view are sorted
- * ascending by a stable LSD radix sort (ties keep emission order), then
- * ranges[t] = [lower_bound(t << D), lower_bound((t+1) << D)) in the view's
- * segment, as global positions.  If K > capacity only the first `capacity`
+ * float32, value = g.  Keys of each view are sorted ascending by a stable LSD
+ * radix sort (ties keep emission order), then ranges[t] =
+ * [lower_bound(t << D), lower_bound((t+1) << D)) in the view's segment, as
+ * global positions, and inv maps each unsorted index to its sorted position.
+ * If K > capacity only the first `capacity`
  * intersections are written and GS_STATUS_CAPACITY is set; the caller reads
  * offsets[V*n] to size a retry.
  *   workspace  device scratch of gs_bin_sort_workspace_size bytes */
@@ -226,19 +243,19 @@ int gs_rasterize_fwd(const gs_splats* splats, int64_t n, const gs_layout* layout
  * (pixels * 3) or, if `target` (pixels * 3) is given, from the fused L1 loss
  * mean|C - target| over all channels of all pixels: g = sign(C - target) /
  * (3 * pixels).  Per-pixel contributions are summed over each tile with
- * wavefront reductions (no atomics) into one record per intersection (every
- * intersection's record is written, zeros where nothing contributed):
- *   partials  device, capacity records of 12 floats at the unsorted index:
- *             (d u, d v, d A, d B, d C, d opacity, d r, d g, d b, 0, 0, 0)
+ * wavefront reductions (no atomics) into one record per traversed
+ * intersection (see gs_grads2d); a tile's traversal ends at the last entry any
+ * of its pixels composited.
  *   loss      nullable device, total tiles floats: per-tile sum |C - target|
  *             (only with `target`) */
 int gs_rasterize_bwd(const gs_splats* splats, int64_t n, const gs_layout* layout,
                      const gs_bins* bins, const gs_view* views, const gs_image* fwd,
-                     const float* target, const float* dL_dC, float* partials, float* loss,
-                     int lds_batch, const gs_schedule* sched, void* stream);
+                     const float* target, const float* dL_dC, const gs_grads2d* grads,
+                     float* loss, int lds_batch, const gs_schedule* sched, void* stream);
 
 /* Projection backward fused with Adam (Sec. 4.3).  For each Gaussian, sums its
- * intersection records of every view (in unsorted-index order), applies the
+ * traversed intersection records of every view (in unsorted-index order, found
+ * through bins->inv and grads->tile_stop), applies the
  * chain rule back through colour (SH basis, clamp, view direction), opacity
  * (sigmoid), conic (inverse), 2D covariance (J R Sigma R^T J^T), the pinhole
  * Jacobian and mean projection, scales (exp) and the quaternion normalisation,
@@ -247,7 +264,7 @@ int gs_rasterize_bwd(const gs_splats* splats, int64_t n, const gs_layout* layout
  * gradients are also written there (parameter-block layout).  At least one of
  * adam, grads_out must be non-NULL. */
 int gs_project_bwd_adam(float* params, int64_t n, const gs_view* views, const gs_layout* layout,
-                        const gs_bins* bins, const float* partials, const gs_adam* adam,
+                        const gs_bins* bins, const gs_grads2d* grads, const gs_adam* adam,
                         float* grads_out, void* stream);
 
 /* ---- learned tile schedule (per-tile cost model) --------------------------- */

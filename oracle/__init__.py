@@ -30,8 +30,10 @@ _loaded: dict = {}
 
 # relative margins around the compositing thresholds inside which a decision
 # taken in float32 may legitimately differ between two float32 implementations
-# (alpha vs 1/255, o*G vs 0.99, T(1-alpha) vs 1e-4, the quadratic form vs 0)
-DEFAULT_MARGINS = (2e-5, 2e-5, 2e-4, 1e-5)
+# (alpha vs 1/255, o*G vs 0.99, T(1-alpha) vs 1e-4, the quadratic form vs 0),
+# and the float32 error of the quadratic form per unit of its absolute terms
+# (a few roundings of 2^-24 each, doubled for safety)
+DEFAULT_MARGINS = (2e-5, 2e-5, 2e-4, 1e-5, 5e-7)
 L1_SIGN_MARGIN = 1e-5
 
 

@@ -525,36 +525,49 @@ typedef struct {
     double margin_clamp;  /* relative distance of o*G to 0.99 */
     double margin_stop;   /* relative distance of T(1-alpha) to 1e-4 */
     double margin_power;  /* |quadratic form| relative to its terms */
+    double form_eps;      /* float32 error of the quadratic form per unit of its
+                             absolute terms (rounding of products and sums) */
 } or_margins;
 
 /* One compositing step, float precision (the paper's).  Returns 0 = skipped,
  * 1 = composited, 2 = stop (not composited).  Sets *fragile when a decision
- * lies within the margins of its threshold. */
+ * lies within reach of its threshold for a different but equally valid
+ * float32 evaluation: the quadratic form d^T Q d carries an absolute rounding
+ * error proportional to the sum of its absolute terms (large for elongated
+ * Gaussians, where the terms cancel), which moves alpha by that much
+ * relatively; transmittance accumulates the alpha errors of the pairs
+ * composited before (*terr, relative, in/out). */
 static int composite_step(real px, real py, real u, real v, real A, real B, real C, real o,
                           real T, real* alpha_out, real* G_out, real* ag_out, real* dx_out,
-                          real* dy_out, const or_margins* mg, int* fragile)
+                          real* dy_out, const or_margins* mg, int* fragile, double* terr)
 {
     const real dx = px - u, dy = py - v;
     const real qa = (A * dx) * dx, qc = (C * dy) * dy, qb = (B * dx) * dy;
     const real power = (real)(-0.5) * (qa + qc) - qb;
     *dx_out = dx; *dy_out = dy;
+    double ea = 0.0;
     if (mg) {
         const double form = (double)qa + (double)qc + 2.0 * (double)qb;
         const double mag = fabs((double)qa) + fabs((double)qc) + 2.0 * fabs((double)qb);
         if (fabs(form) <= mg->margin_power * mag) *fragile = 1;
+        ea = 0.5 * mg->form_eps * mag;   /* relative error of alpha */
     }
     if (power > (real)0) return 0;
     const real G = REXP(power);
     const real ag = o * G;
     const real alpha = RMIN((real)0.99, ag);
     if (mg) {
-        if (fabs((double)ag - 1.0 / 255.0) <= mg->margin_alpha * (1.0 / 255.0)) *fragile = 1;
-        if (fabs((double)ag - 0.99) <= mg->margin_clamp * 0.99) *fragile = 1;
+        if (fabs((double)ag - 1.0 / 255.0) <= (mg->margin_alpha + ea) * (1.0 / 255.0)) *fragile = 1;
+        if (fabs((double)ag - 0.99) <= (mg->margin_clamp + ea) * 0.99) *fragile = 1;
     }
     *G_out = G; *ag_out = ag; *alpha_out = alpha;
     if (alpha < (real)(1.0 / 255.0)) return 0;
     const real test_T = T * ((real)1 - alpha);
-    if (mg && fabs((double)test_T - 1e-4) <= mg->margin_stop * 1e-4) *fragile = 1;
+    if (mg) {
+        const double et = *terr + (ea + mg->margin_alpha) * (double)alpha / (1.0 - (double)alpha);
+        if (fabs((double)test_T - 1e-4) <= (mg->margin_stop + et) * 1e-4) *fragile = 1;
+        *terr = et;
+    }
     if (test_T < (real)1e-4) return 2;
     return 1;
 }
@@ -596,6 +609,7 @@ void or_raster_fwd(const double* xy, const double* conic, const double* opac, co
     if (margins) {
         mg.margin_alpha = margins[0]; mg.margin_clamp = margins[1];
         mg.margin_stop = margins[2]; mg.margin_power = margins[3];
+        mg.form_eps = margins[4];
         pm = &mg;
     }
 #pragma omp parallel for schedule(dynamic, 4)
@@ -617,6 +631,7 @@ void or_raster_fwd(const double* xy, const double* conic, const double* opac, co
                 acc Cacc[3] = {0, 0, 0};
                 uint32_t lst = 0, examined = 0;
                 int frag = 0;
+                double terr = 0.0;
                 for (uint32_t e = start; e < end; ++e) {
                     const int64_t g = (int64_t)vi * n + gid[vals[e]];
                     real alpha = 0, G = 0, ag = 0, dx, dy;
@@ -624,7 +639,7 @@ void or_raster_fwd(const double* xy, const double* conic, const double* opac, co
                     const int st = composite_step(px, py, (real)xy[2 * g], (real)xy[2 * g + 1],
                                                   (real)conic[3 * g], (real)conic[3 * g + 1],
                                                   (real)conic[3 * g + 2], (real)opac[g], T, &alpha,
-                                                  &G, &ag, &dx, &dy, pm, &frag);
+                                                  &G, &ag, &dx, &dy, pm, &frag, &terr);
                     if (st == 2) break;
                     if (st == 0) continue;
                     for (int k = 0; k < 3; ++k)
@@ -726,7 +741,7 @@ void or_raster_bwd(const double* xy, const double* conic, const double* opac, co
                         const int st = composite_step(px, py, (real)xy[2 * g], (real)xy[2 * g + 1],
                                                       (real)conic[3 * g], (real)conic[3 * g + 1],
                                                       (real)conic[3 * g + 2], (real)opac[g], T,
-                                                      &alpha, &G, &ag, &dx, &dy, NULL, &frag);
+                                                      &alpha, &G, &ag, &dx, &dy, NULL, &frag, NULL);
                         if (st == 2) break;
                         if (st == 0) continue;
                         e_idx[m] = e; e_alpha[m] = alpha; e_T[m] = T; e_G[m] = G; e_ag[m] = ag;

@@ -1,0 +1,111 @@
+"""Autotuner for the batched, persistent, graph-captured training step.
+
+Searches tile edge T in {8, 16, 32} and Gaussians-per-LDS-batch S in
+{32, 64, 128, 256}.  Every candidate runs the same iterations from the same
+optimiser state (restored between candidates), each as a captured HIP graph;
+the candidate with the lowest mean step time wins.  Results are cached in a
+JSON file keyed by GPU architecture, the view-set resolutions and the
+Gaussian count; an unreadable cache entry is ignored and the search reruns.
+
+The paper chooses S per tile as ceil(sqrt(N P)) rounded to a wave multiple
+and capped at 128 from a latency model (Sec. 4.2); here S is one value per
+launch, chosen by measurement, and the model only orders the candidates.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+
+import torch
+
+from . import pipeline as P
+from .batched import BatchedStep, ViewSet
+
+TILES = (8, 16, 32)
+BATCHES = (32, 64, 128, 256)
+
+
+def cache_key(resolutions, n: int) -> str:
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    res = "_".join(f"{w}x{h}" for w, h in resolutions)
+    return f"{arch}|{res}|n{int(round(math.log2(max(n, 1))))}"
+
+
+def load_cache(path: str) -> dict:
+    try:
+        with open(path) as f:
+            data = json.load(f)
+        return data if isinstance(data, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def save_cache(path: str, data: dict) -> None:
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def capacity_for(model: P.Model, n: int, viewset: ViewSet, view_rows, iters, slack=1.15) -> int:
+    """Largest intersection count over the given iterations (synchronises)."""
+    f = P.Frame(n, viewset.widths, viewset.heights, viewset.tile, capacity=1)
+    kmax = 0
+    for i in iters:
+        P.project(model.params, f, view_rows(i).reshape(-1))
+        kmax = max(kmax, int(f.tiles.to(torch.int64).sum().item()))
+    del f
+    return int(kmax * slack) + 4096
+
+
+def time_candidate(model: P.Model, n: int, resolutions, tile: int, lds: int, view_rows, targets,
+                   iters, capacity: int) -> float:
+    saved = [t.clone() for t in (model.params, model.m, model.v, model.step)]
+    vs = ViewSet(resolutions, tile)
+    step = BatchedStep(model, n, vs, capacity, lds_batch=lds, persistent=True)
+    step.load(view_rows(iters[0]), targets(iters[0]))
+    step.capture()
+    for i in iters[:2]:                        # warm replays
+        step.load(view_rows(i), targets(i))
+        step.run()
+    torch.cuda.synchronize()
+    for t, s0 in zip((model.params, model.m, model.v, model.step), saved):
+        t.copy_(s0)
+    t0 = time.perf_counter()
+    for i in iters:
+        step.load(view_rows(i), targets(i))
+        step.run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / len(iters)
+    if step.status():
+        dt = float("inf")                      # capacity exceeded: not a valid candidate
+    for t, s0 in zip((model.params, model.m, model.v, model.step), saved):
+        t.copy_(s0)
+    del step
+    torch.cuda.empty_cache()
+    return dt
+
+
+def autotune(model: P.Model, n: int, resolutions, view_rows, targets, iters, cache_path=None,
+             tiles=TILES, batches=BATCHES, log=print) -> dict:
+    key = cache_key(resolutions, n)
+    cache = load_cache(cache_path) if cache_path else {}
+    hit = cache.get(key)
+    if isinstance(hit, dict) and hit.get("tile") in tiles and hit.get("lds_batch") in batches:
+        return dict(hit, cached=True)
+    table = {}
+    for T in tiles:
+        cap = capacity_for(model, n, ViewSet(resolutions, T), view_rows, iters)
+        for S in batches:
+            dt = time_candidate(model, n, resolutions, T, S, view_rows, targets, iters, cap)
+            table[f"T{T}_S{S}"] = dt * 1e3
+            log(f"autotune T={T} S={S}: {dt * 1e3:.3f} ms/step")
+    best = min(table, key=table.get)
+    T, S = (int(x[1:]) for x in best.split("_"))
+    res = {"tile": T, "lds_batch": S, "ms": table[best], "table_ms": table, "cached": False}
+    if cache_path:
+        cache[key] = {k: v for k, v in res.items() if k != "cached"}
+        save_cache(cache_path, cache)
+    return res

@@ -1,6 +1,7 @@
 // Projection backward fused with Adam: one thread per Gaussian streams its
-// parameter record, both Adam moments and its intersection records once, and
-// writes parameters and moments once.  No per-parameter gradient buffer exists
+// parameter record and both Adam moments once, gathers the screen-space
+// gradient records of the intersections the rasteriser traversed (through the
+// inverse sort permutation), and writes parameters and moments once.  No per-parameter gradient buffer exists
 // unless the caller asks for one (grads_out).  Log-scales and opacity logits
 // are optimised as stored: the chain rule through exp and the sigmoid is part
 // of this kernel.
@@ -19,8 +20,11 @@ struct AdamArgs {
     int n_views;
     int tile;
     int32_t gx[GS_MAX_VIEWS], gy[GS_MAX_VIEWS];
+    int32_t tile_base[GS_MAX_VIEWS];
     const uint32_t* offsets;
-    const float4* partials;
+    const uint32_t* inv;
+    const float4* grec;
+    const uint32_t* tile_stop;
     int64_t capacity;
     float4* m;
     float4* v;
@@ -90,18 +94,27 @@ __global__ __launch_bounds__(256) void k_project_bwd_adam(AdamArgs a) {
         uint64_t e = a.offsets[o + 1];
         if (e == b) continue;
         if (e > (uint64_t)a.capacity) e = (uint64_t)a.capacity;
-        float d[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-        for (uint64_t i = b; i < e; ++i) {
-            const float4 r0 = a.partials[3 * i + 0];
-            const float4 r1 = a.partials[3 * i + 1];
-            const float4 r2 = a.partials[3 * i + 2];
-            d[0] += r0.x; d[1] += r0.y; d[2] += r0.z; d[3] += r0.w;
-            d[4] += r1.x; d[5] += r1.y; d[6] += r1.z; d[7] += r1.w; d[8] += r2.x;
-        }
         const gs_view vw = a.views[vi];
         Proj P;
         project_gaussian<true>(p0, p1, p2, sh, vw, a.tile, a.gx[vi], a.gy[vi], P);
         if (!P.valid) continue;
+        // sum the records of this Gaussian's traversed intersections, in
+        // unsorted-index order (tile = its rectangle, row major)
+        float d[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        const uint32_t w = (uint32_t)(P.x1 - P.x0);
+        const int tbase = a.tile_base[vi] + P.y0 * a.gx[vi] + P.x0;
+        uint32_t kx = 0, ky = 0;
+        for (uint64_t i = b; i < e; ++i) {
+            const uint32_t j = a.inv[i];
+            if (j < a.tile_stop[tbase + (int)(ky * (uint32_t)a.gx[vi] + kx)]) {
+                const float4 r0 = a.grec[3 * (int64_t)j + 0];
+                const float4 r1 = a.grec[3 * (int64_t)j + 1];
+                const float4 r2 = a.grec[3 * (int64_t)j + 2];
+                d[0] += r0.x; d[1] += r0.y; d[2] += r0.z; d[3] += r0.w;
+                d[4] += r1.x; d[5] += r1.y; d[6] += r1.z; d[7] += r1.w; d[8] += r2.x;
+            }
+            if (++kx == w) { kx = 0; ++ky; }
+        }
 
         float dmean[3] = {0.f, 0.f, 0.f};
         // colour: c = max(0, raw + 1/2), raw = sum_m sh[m] Y_m(dir)
@@ -276,7 +289,7 @@ __global__ void k_adam_tick(int32_t* step, float* bias, float beta1, float beta2
 }
 
 int launch_project_bwd_adam(float* params, int64_t n, const gs_view* views, const gs_layout& L,
-                            const gs_bins& b, const float* partials, const gs_adam* adam,
+                            const gs_bins& b, const gs_grads2d& grads, const gs_adam* adam,
                             float* grads_out, hipStream_t s) {
     if (n == 0) return GS_OK;
     AdamArgs a;
@@ -289,9 +302,12 @@ int launch_project_bwd_adam(float* params, int64_t n, const gs_view* views, cons
     for (int v = 0; v < GS_MAX_VIEWS; ++v) {
         a.gx[v] = v < L.n_views ? L.tiles_x[v] : 0;
         a.gy[v] = v < L.n_views ? L.tiles_y[v] : 0;
+        a.tile_base[v] = v < L.n_views ? L.tile_base[v] : 0;
     }
     a.offsets = b.offsets;
-    a.partials = reinterpret_cast<const float4*>(partials);
+    a.inv = b.inv;
+    a.grec = reinterpret_cast<const float4*>(grads.rec);
+    a.tile_stop = grads.tile_stop;
     a.capacity = b.capacity;
     a.grads_out = reinterpret_cast<float4*>(grads_out);
     if (adam) {

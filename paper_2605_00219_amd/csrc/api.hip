@@ -99,8 +99,7 @@ int gs_project(const float* params, int64_t n, const gs_view* views, const gs_la
     REQUIRE(layout_ok(layout), "gs_project: invalid layout");
     REQUIRE(n >= 0 && n < (int64_t(1) << 32), "gs_project: n = %lld out of range", (long long)n);
     REQUIRE(out && views && (n == 0 || params), "gs_project: null pointer");
-    REQUIRE(n == 0 || (out->geo && out->geo2 && out->rgb && out->rect && out->tiles),
-            "gs_project: null output buffer");
+    REQUIRE(n == 0 || (out->rec && out->tiles), "gs_project: null output buffer");
     return launch_project(params, n, views, *layout, *out, (hipStream_t)stream);
 }
 
@@ -112,7 +111,7 @@ int gs_bin_sort(const gs_splats* splats, int64_t n, const gs_layout* layout, con
     REQUIRE(bins->capacity >= 0 && bins->capacity < (int64_t(1) << 32) - 1,
             "gs_bin_sort: capacity out of range");
     REQUIRE(bins->offsets && bins->ranges && bins->status && (bins->capacity == 0 ||
-            (bins->keys && bins->vals && bins->gid)), "gs_bin_sort: null bins buffer");
+            (bins->keys && bins->vals && bins->inv)), "gs_bin_sort: null bins buffer");
     REQUIRE(workspace || workspace_bytes == 0, "gs_bin_sort: null workspace");
     return launch_bin_sort(*splats, n, *layout, *bins, workspace, workspace_bytes, (hipStream_t)stream);
 }
@@ -139,31 +138,33 @@ int gs_rasterize_fwd(const gs_splats* splats, int64_t n, const gs_layout* layout
 
 int gs_rasterize_bwd(const gs_splats* splats, int64_t n, const gs_layout* layout,
                      const gs_bins* bins, const gs_view* views, const gs_image* fwd,
-                     const float* target, const float* dL_dC, float* partials, float* loss,
-                     int lds_batch, const gs_schedule* sched, void* stream) {
+                     const float* target, const float* dL_dC, const gs_grads2d* grads,
+                     float* loss, int lds_batch, const gs_schedule* sched, void* stream) {
     REQUIRE(layout_ok(layout), "gs_rasterize_bwd: invalid layout");
     REQUIRE(splats && bins && views && fwd && fwd->rgb && fwd->last, "gs_rasterize_bwd: null pointer");
     REQUIRE((target != nullptr) != (dL_dC != nullptr),
             "gs_rasterize_bwd: give exactly one of target (fused L1) and dL_dC");
-    REQUIRE(partials || bins->capacity == 0, "gs_rasterize_bwd: null partials");
+    REQUIRE(grads && grads->tile_stop && (grads->rec || bins->capacity == 0),
+            "gs_rasterize_bwd: null gradient buffers");
     REQUIRE(lds_batch == 32 || lds_batch == 64 || lds_batch == 128 || lds_batch == 256,
             "gs_rasterize_bwd: lds_batch %d not in {32, 64, 128, 256}", lds_batch);
     int rc = check_sched(sched);
     if (rc != GS_OK) return rc;
-    return launch_raster_bwd(*splats, n, *layout, *bins, views, *fwd, target, dL_dC, partials, loss,
+    return launch_raster_bwd(*splats, n, *layout, *bins, views, *fwd, target, dL_dC, *grads, loss,
                              lds_batch, sched, (hipStream_t)stream);
 }
 
 int gs_project_bwd_adam(float* params, int64_t n, const gs_view* views, const gs_layout* layout,
-                        const gs_bins* bins, const float* partials, const gs_adam* adam,
+                        const gs_bins* bins, const gs_grads2d* grads, const gs_adam* adam,
                         float* grads_out, void* stream) {
     REQUIRE(layout_ok(layout), "gs_project_bwd_adam: invalid layout");
     REQUIRE(views && bins && bins->offsets && (n == 0 || params), "gs_project_bwd_adam: null pointer");
     REQUIRE(adam || grads_out, "gs_project_bwd_adam: need adam state or grads_out");
     REQUIRE(!adam || (adam->m && adam->v && adam->step && adam->scratch),
             "gs_project_bwd_adam: incomplete adam state");
-    REQUIRE(partials || bins->capacity == 0, "gs_project_bwd_adam: null partials");
-    return launch_project_bwd_adam(params, n, views, *layout, *bins, partials, adam, grads_out,
+    REQUIRE(grads && grads->tile_stop && (grads->rec || bins->capacity == 0) &&
+            (bins->inv || bins->capacity == 0), "gs_project_bwd_adam: null gradient buffers");
+    return launch_project_bwd_adam(params, n, views, *layout, *bins, *grads, adam, grads_out,
                                    (hipStream_t)stream);
 }
 

@@ -1,6 +1,7 @@
 // Binning and sorting: exclusive scan of tiles touched, 32-bit (tile, depth)
 // key emission, stable LSD radix sort of each view's segment (4 passes of 8
-// bits), per-tile [start, end) ranges.
+// bits) carrying the Gaussian id, per-tile [start, end) ranges and the
+// inverse permutation (unsorted index -> sorted position).
 //
 // The sort runs over all views at once: each view's segment is cut into
 // chunks of kChunk keys that never straddle two views, and the per-chunk digit
@@ -201,7 +202,7 @@ __global__ void k_view_table(const uint32_t* __restrict__ offsets, int64_t n, in
 }
 
 // ---------------------------------------------------------------------------
-// key emission
+// key emission: one thread per intersection
 // ---------------------------------------------------------------------------
 
 struct EmitGeom {
@@ -209,36 +210,63 @@ struct EmitGeom {
     int32_t depth_bits[GS_MAX_VIEWS];
 };
 
-__global__ __launch_bounds__(256) void k_emit(const gs_splats sp, const uint32_t* __restrict__ offsets,
-                                              int64_t n, int n_views, EmitGeom geo, int64_t capacity,
-                                              uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                                              uint32_t* __restrict__ gid) {
-    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= (int64_t)n_views * n) return;
-    const uint32_t cnt = sp.tiles[o];
-    if (cnt == 0) return;
-    const int v = (int)(o / n);
-    const uint32_t g = (uint32_t)(o - (int64_t)v * n);
-    const uint2 rc = reinterpret_cast<const uint2*>(sp.rect)[o];
-    const int x0 = rc.x & 0xFFFF, y0 = rc.x >> 16, x1 = rc.y & 0xFFFF, y1 = rc.y >> 16;
-    const float z = reinterpret_cast<const float4*>(sp.geo2)[o].z;
-    const int D = geo.depth_bits[v];
-    const int gx = geo.tiles_x[v];
-    // depth map z -> (2z + 1) / (z + 1) in (1, 2): only mantissa bits vary
-    const float num = 2.0f * z + 1.0f;
-    const float den = z + 1.0f;
-    const float f = num / den;
-    const uint32_t dk = (__float_as_uint(f) & 0x7FFFFFu) >> (23 - D);
-    uint64_t pos = offsets[o];
-    for (int ty = y0; ty < y1; ++ty)
-        for (int tx = x0; tx < x1; ++tx) {
-            if (pos < (uint64_t)capacity) {
-                keys[pos] = ((uint32_t)(ty * gx + tx) << D) | dk;
-                vals[pos] = (uint32_t)pos;
-                gid[pos] = g;
-            }
-            ++pos;
+constexpr int kEmitG = 256;  // Gaussians per workgroup
+
+// A workgroup owns kEmitG consecutive (view, Gaussian) entries.  Their
+// rectangles and depth keys are staged in LDS; the workgroup's intersections
+// [offsets[o0], offsets[o0 + kEmitG]) are then written by consecutive threads
+// (coalesced, balanced however unequal the rectangles are), each finding its
+// Gaussian by binary search over the staged offsets.
+__global__ __launch_bounds__(kEmitG) void k_emit(const float4* __restrict__ rec,
+                                                 const uint32_t* __restrict__ tiles,
+                                                 const uint32_t* __restrict__ offsets, int64_t n,
+                                                 int n_views, EmitGeom geo, int64_t capacity,
+                                                 uint32_t* __restrict__ keys,
+                                                 uint32_t* __restrict__ vals) {
+    __shared__ uint32_t s_off[kEmitG + 1];
+    __shared__ uint32_t s_xy[kEmitG];
+    __shared__ uint32_t s_w[kEmitG];
+    __shared__ uint32_t s_dk[kEmitG];
+    __shared__ uint32_t s_view[kEmitG];
+    const int64_t m = (int64_t)n_views * n;
+    const int64_t o0 = (int64_t)blockIdx.x * kEmitG;
+    const int t = threadIdx.x;
+    const int64_t o = o0 + t;
+    s_off[t] = offsets[o < m ? o : m];
+    if (t == 0) s_off[kEmitG] = offsets[o0 + kEmitG < m ? o0 + kEmitG : m];
+    if (o < m && tiles[o] > 0) {
+        const int v = (int)(o / n);
+        const float4 q2 = rec[4 * o + 2];
+        const float4 q3 = rec[4 * o + 3];
+        const uint32_t r0 = __float_as_uint(q3.x), r1 = __float_as_uint(q3.y);
+        const int D = geo.depth_bits[v];
+        // depth map z -> (2z + 1) / (z + 1) in (1, 2): only mantissa bits vary
+        const float z = q2.y;
+        const float num = 2.0f * z + 1.0f;
+        const float den = z + 1.0f;
+        const float f = num / den;
+        s_xy[t] = r0;
+        s_w[t] = (r1 & 0xFFFF) - (r0 & 0xFFFF);
+        s_dk[t] = (__float_as_uint(f) & 0x7FFFFFu) >> (23 - D);
+        s_view[t] = (uint32_t)v;
+    }
+    __syncthreads();
+    const uint32_t begin = s_off[0], end = s_off[kEmitG];
+    for (uint64_t i = (uint64_t)begin + t; i < end; i += kEmitG) {
+        int lo = 0, hi = kEmitG - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] <= i) lo = mid; else hi = mid - 1;
         }
+        const uint32_t k = (uint32_t)(i - s_off[lo]);
+        const uint32_t w = s_w[lo], xy = s_xy[lo];
+        const uint32_t tx = (xy & 0xFFFF) + k % w, ty = (xy >> 16) + k / w;
+        const int v = (int)s_view[lo];
+        if (i < (uint64_t)capacity) {
+            keys[i] = ((ty * (uint32_t)geo.tiles_x[v] + tx) << geo.depth_bits[v]) | s_dk[lo];
+            vals[i] = (uint32_t)(o0 + lo - (int64_t)v * n);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -360,6 +388,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
 
 struct RangeGeom {
     int32_t depth_bits[GS_MAX_VIEWS];
+    int32_t tiles_x[GS_MAX_VIEWS];
     int32_t tile_base[GS_MAX_VIEWS + 1];
 };
 
@@ -374,10 +403,18 @@ __global__ __launch_bounds__(256) void k_ranges_empty(const uint32_t* __restrict
     if (b == e) reinterpret_cast<uint2*>(ranges)[gt] = make_uint2(b, b);
 }
 
+// One thread per sorted position j: tile boundaries -> ranges (lower-bound
+// semantics, empty tiles get start = end = insertion point), and the inverse
+// permutation inv[unsorted index] = j.  The unsorted index of (tile, Gaussian)
+// follows from the Gaussian's rectangle: offsets[v*n+g] + row * width + column.
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ keys,
+                                                const uint32_t* __restrict__ vals,
                                                 const uint32_t* __restrict__ table, int n_views,
                                                 RangeGeom geo, int64_t capacity,
-                                                uint32_t* __restrict__ ranges) {
+                                                const float4* __restrict__ rec,
+                                                const uint32_t* __restrict__ offsets, int64_t n,
+                                                uint32_t* __restrict__ ranges,
+                                                uint32_t* __restrict__ inv) {
     const int64_t j64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j64 >= capacity) return;
     const uint32_t j = (uint32_t)j64;
@@ -405,6 +442,15 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key
         for (int u = t; u < nt; ++u) R[u].y = j + 1;
         for (int u = t + 1; u < nt; ++u) R[u].x = j + 1;
     }
+    // inverse permutation
+    const int64_t o = (int64_t)v * n + vals[j];
+    const float4 q3 = rec[4 * o + 3];
+    const uint32_t r0 = __float_as_uint(q3.x), r1 = __float_as_uint(q3.y);
+    const uint32_t x0 = r0 & 0xFFFF, y0 = r0 >> 16, w = (r1 & 0xFFFF) - x0;
+    const uint32_t gx = (uint32_t)geo.tiles_x[v];
+    const uint32_t tx = (uint32_t)t % gx, ty = (uint32_t)t / gx;
+    const uint64_t i = (uint64_t)offsets[o] + (uint64_t)(ty - y0) * w + (tx - x0);
+    if (i < (uint64_t)capacity) inv[i] = j;
 }
 
 __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, int64_t count) {
@@ -496,11 +542,13 @@ int launch_bin_sort(const gs_splats& sp, int64_t n, const gs_layout& L, const gs
         eg.tiles_x[v] = v < V ? L.tiles_x[v] : 0;
         eg.depth_bits[v] = v < V ? L.depth_bits[v] : 0;
         rg.depth_bits[v] = eg.depth_bits[v];
+        rg.tiles_x[v] = eg.tiles_x[v];
     }
     for (int v = 0; v <= GS_MAX_VIEWS; ++v) rg.tile_base[v] = v <= V ? L.tile_base[v] : L.tile_base[V];
+    const float4* rec = reinterpret_cast<const float4*>(sp.rec);
     if (m > 0) {
-        hipLaunchKernelGGL(k_emit, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, sp, b.offsets,
-                           n, V, eg, b.capacity, b.keys, b.vals, b.gid);
+        hipLaunchKernelGGL(k_emit, dim3((unsigned)((m + kEmitG - 1) / kEmitG)), dim3(kEmitG), 0, s, rec,
+                           sp.tiles, b.offsets, n, V, eg, b.capacity, b.keys, b.vals);
         if ((rc = check_launch("emit_keys")) != GS_OK) return rc;
     }
     // 4 stable LSD passes; even count leaves the result in keys / vals
@@ -529,7 +577,8 @@ int launch_bin_sort(const gs_splats& sp, int64_t n, const gs_layout& L, const gs
     if ((rc = check_launch("ranges_empty")) != GS_OK) return rc;
     if (b.capacity > 0) {
         hipLaunchKernelGGL(k_ranges, dim3((unsigned)((b.capacity + 255) / 256)), dim3(256), 0, s,
-                           b.keys, W.table, V, rg, b.capacity, b.ranges);
+                           b.keys, b.vals, W.table, V, rg, b.capacity, rec, b.offsets, n, b.ranges,
+                           b.inv);
         if ((rc = check_launch("ranges")) != GS_OK) return rc;
     }
     return GS_OK;

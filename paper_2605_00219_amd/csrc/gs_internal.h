@@ -32,14 +32,6 @@ GS_DEV int view_of_tile(const gs_layout& L, int gt) {
 GS_DEV float4 ld4(const float* p, int64_t i) { return reinterpret_cast<const float4*>(p)[i]; }
 GS_DEV void st4(float* p, int64_t i, float4 v) { reinterpret_cast<float4*>(p)[i] = v; }
 
-// Per-view geometry passed by value to the binning kernels.
-struct ViewSeg {
-    // device table written by the scan step: for view v,
-    // [4v+0] segment begin, [4v+1] segment end (clamped to capacity),
-    // [4v+2] first radix chunk, [4v+3] number of radix chunks; [4V] total chunks.
-    uint32_t* table;
-};
-
 // ---- launchers (host) ---------------------------------------------------------
 int launch_project(const float* params, int64_t n, const gs_view* views, const gs_layout& L,
                    const gs_splats& out, hipStream_t s);
@@ -51,10 +43,10 @@ int launch_raster_fwd(const gs_splats& sp, int64_t n, const gs_layout& L, const 
                       const gs_schedule* sched, hipStream_t s);
 int launch_raster_bwd(const gs_splats& sp, int64_t n, const gs_layout& L, const gs_bins& b,
                       const gs_view* views, const gs_image& fwd, const float* target,
-                      const float* dLdC, float* partials, float* loss, int lds_batch,
+                      const float* dLdC, const gs_grads2d& grads, float* loss, int lds_batch,
                       const gs_schedule* sched, hipStream_t s);
 int launch_project_bwd_adam(float* params, int64_t n, const gs_view* views, const gs_layout& L,
-                            const gs_bins& b, const float* partials, const gs_adam* adam,
+                            const gs_bins& b, const gs_grads2d& grads, const gs_adam* adam,
                             float* grads_out, hipStream_t s);
 int launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
 int launch_tile_features(const gs_splats& sp, int64_t n, const gs_layout& L, const gs_bins& b,

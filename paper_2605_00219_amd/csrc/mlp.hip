@@ -16,9 +16,8 @@ static_assert(kOffB3 + 1 == GS_MLP_PARAMS, "weight layout");
 // tile features
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(64) void k_tile_features(const float4* __restrict__ geo2,
+__global__ __launch_bounds__(64) void k_tile_features(const float4* __restrict__ rec,
                                                       const uint32_t* __restrict__ vals,
-                                                      const uint32_t* __restrict__ gid,
                                                       const uint2* __restrict__ ranges, int64_t n,
                                                       gs_layout L, float* __restrict__ feat) {
     const int gt = blockIdx.x;
@@ -26,12 +25,14 @@ __global__ __launch_bounds__(64) void k_tile_features(const float4* __restrict__
     const uint2 r = ranges[gt];
     float so = 0.f, mo = 0.f, sz = 0.f, mz = 3.4e38f, sr = 0.f;
     for (uint32_t j = r.x + threadIdx.x; j < r.y; j += 64) {
-        const float4 g2 = geo2[(int64_t)v * n + gid[vals[j]]];
-        so += g2.y;
-        mo = fmaxf(mo, g2.y);
-        sz += g2.z;
-        mz = fminf(mz, g2.z);
-        sr += g2.w;
+        const float4* r = rec + 4 * ((int64_t)v * n + vals[j]);
+        const float o = r[1].y;
+        const float4 q2 = r[2];
+        so += o;
+        mo = fmaxf(mo, o);
+        sz += q2.y;
+        mz = fminf(mz, q2.y);
+        sr += q2.z;
     }
     for (int off = 32; off > 0; off >>= 1) {
         so += __shfl_xor(so, off);
@@ -62,7 +63,7 @@ int launch_tile_features(const gs_splats& sp, int64_t n, const gs_layout& L, con
     const int total = L.tile_base[L.n_views];
     if (total == 0) return GS_OK;
     hipLaunchKernelGGL(k_tile_features, dim3(total), dim3(64), 0, s,
-                       reinterpret_cast<const float4*>(sp.geo2), b.vals, b.gid,
+                       reinterpret_cast<const float4*>(sp.rec), b.vals,
                        reinterpret_cast<const uint2*>(b.ranges), n, L, features);
     return check_launch("tile_features");
 }

@@ -1,6 +1,8 @@
 // Projection forward: one thread per Gaussian, looping over the views so the
 // 240-byte parameter record is read from HBM once per call.  Loads are float4
 // planes (plane-major SoA), so each wavefront reads 1 KiB contiguous per plane.
+// Each output entry is one 64-byte record (one cache line), so the tile
+// rasteriser gathers everything it needs about a Gaussian with one line fetch.
 #include "project_math.h"
 
 namespace gs {
@@ -30,18 +32,17 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ param
         P.valid = false;
         if (finite) project_gaussian<true>(p0, p1, p2, sh, vw, tile, grid.gx[v], grid.gy[v], P);
         const int64_t o = (int64_t)v * n + g;
+        float4* rec = reinterpret_cast<float4*>(out.rec) + 4 * o;
         if (P.valid) {
-            st4(out.geo, o, make_float4(P.u, P.v, P.A, P.B));
-            st4(out.geo2, o, make_float4(P.C, P.o, P.z, P.radius));
-            st4(out.rgb, o, make_float4(P.col[0], P.col[1], P.col[2], 0.0f));
-            reinterpret_cast<uint2*>(out.rect)[o] =
-                make_uint2((uint32_t)P.x0 | ((uint32_t)P.y0 << 16), (uint32_t)P.x1 | ((uint32_t)P.y1 << 16));
+            rec[0] = make_float4(P.u, P.v, P.A, P.B);
+            rec[1] = make_float4(P.C, P.o, P.col[0], P.col[1]);
+            rec[2] = make_float4(P.col[2], P.z, P.radius, 0.0f);
+            rec[3] = make_float4(__uint_as_float((uint32_t)P.x0 | ((uint32_t)P.y0 << 16)),
+                                 __uint_as_float((uint32_t)P.x1 | ((uint32_t)P.y1 << 16)), 0.0f, 0.0f);
             out.tiles[o] = (uint32_t)((P.x1 - P.x0) * (P.y1 - P.y0));
         } else {
-            st4(out.geo, o, make_float4(0.f, 0.f, 0.f, 0.f));
-            st4(out.geo2, o, make_float4(0.f, 0.f, 0.f, 0.f));
-            st4(out.rgb, o, make_float4(0.f, 0.f, 0.f, 0.f));
-            reinterpret_cast<uint2*>(out.rect)[o] = make_uint2(0u, 0u);
+            const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+            rec[0] = z; rec[1] = z; rec[2] = z; rec[3] = z;
             out.tiles[o] = 0u;
         }
     }

@@ -14,7 +14,9 @@
 // are summed over each wavefront with DPP row/broadcast reductions (no
 // atomics), waves whose lanes all skip a Gaussian skip its reduction (ballot),
 // and the per-wave sums are added in a fixed order through LDS: one 48-byte
-// record per (Gaussian, tile) intersection, deterministic.
+// record per traversed (Gaussian, tile) intersection, written at its sorted
+// position (contiguous per tile), deterministic.  A tile stops at the last
+// entry any of its pixels composited; its stop position is recorded.
 //
 // Scheduling: either one workgroup per tile, or a persistent grid popping
 // tiles from a device counter in the order of a permutation (static or
@@ -32,11 +34,8 @@ constexpr float kTMin = 1e-4f;
 
 struct RasterArgs {
     gs_layout L;
-    const float4* geo;
-    const float4* geo2;
-    const float4* rgb;
-    const uint32_t* vals;
-    const uint32_t* gid;
+    const float4* rec;      // 4 float4 per (view, Gaussian)
+    const uint32_t* vals;   // Gaussian id per sorted position
     const uint2* ranges;
     const gs_view* views;
     int64_t n;
@@ -52,34 +51,36 @@ struct RasterArgs {
     const float* target;
     const float* dLdC;
     float inv_count;
-    float4* partials;
+    float4* grec;           // 3 float4 per sorted position
+    uint32_t* tile_stop;
     float* loss;
     int64_t capacity;
 };
 
 // Staged splat: (u, v, -A log2e / 2, -B log2e), (-C log2e / 2, o, r, g), b
 GS_DEV void stage_splat(const RasterArgs& a, int view, uint32_t sorted_pos, float4& sg, float4& sh,
-                        float& sb, uint32_t& idx) {
-    idx = a.vals[sorted_pos];
-    const int64_t o = (int64_t)view * a.n + a.gid[idx];
-    const float4 g = a.geo[o];
-    const float4 g2 = a.geo2[o];
-    const float4 c = a.rgb[o];
-    sg = make_float4(g.x, g.y, (-0.5f * kLog2e) * g.z, (-kLog2e) * g.w);
-    sh = make_float4((-0.5f * kLog2e) * g2.x, g2.y, c.x, c.y);
-    sb = c.z;
+                        float& sb, uint32_t& gid) {
+    gid = a.vals[sorted_pos];
+    const float4* r = a.rec + 4 * ((int64_t)view * a.n + gid);
+    const float4 q0 = r[0];
+    const float4 q1 = r[1];
+    const float4 q2 = r[2];
+    sg = make_float4(q0.x, q0.y, (-0.5f * kLog2e) * q0.z, (-kLog2e) * q0.w);
+    sh = make_float4((-0.5f * kLog2e) * q1.x, q1.y, q1.z, q1.w);
+    sb = q2.x;
 }
 
-// power (log2-scaled) at the pixel; false if positive (skipped)
+// Quadratic form (log2-scaled power) at the pixel, G = 2^power and o*G.
+// Returns false when the power is positive (the pair is skipped); G and o*G
+// are computed either way so callers can select instead of branching.
 GS_DEV bool eval_pair(float px, float py, const float4& sg, const float4& sh, float& dx, float& dy,
                       float& G, float& ag) {
     dx = px - sg.x;
     dy = py - sg.y;
     const float p2 = __builtin_fmaf(sg.z * dx, dx, __builtin_fmaf(sh.x * dy, dy, (sg.w * dx) * dy));
-    if (p2 > 0.0f) return false;
     G = __builtin_amdgcn_exp2f(p2);
     ag = sh.y * G;
-    return true;
+    return !(p2 > 0.0f);
 }
 
 // Next tile of this workgroup: -1 = no more work, -2 = skip (an order entry
@@ -147,40 +148,45 @@ __global__ __launch_bounds__(TILE* TILE) void k_raster_fwd(RasterArgs a) {
         const uint32_t start = tp.range.x, end = tp.range.y;
         float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
         uint32_t last = 0, examined = 0, composited = 0;
-        bool done = !tp.inside;
+        bool active = tp.inside;
         if (threadIdx.x == 0) { s_max = 0; s_sum = 0; s_comp = 0; }
         for (uint32_t b0 = start; b0 < end; b0 += S) {
-            if (__syncthreads_count(!done) == 0) break;
+            if (__syncthreads_count(active) == 0) break;
             for (int i = threadIdx.x; i < S; i += NT) {
                 const uint32_t j = b0 + i;
                 if (j < end) {
-                    uint32_t idx;
-                    stage_splat(a, tp.view, j, s_g[i], s_h[i], s_b[i], idx);
+                    uint32_t gid;
+                    stage_splat(a, tp.view, j, s_g[i], s_h[i], s_b[i], gid);
                 }
             }
             __syncthreads();
-            if (!done) {
+            // branch-free inner loop: every lane evaluates every staged Gaussian and
+            // the decisions select what is accumulated; a wavefront whose lanes
+            // have all stopped leaves the batch
+            if (__ballot(active) != 0ull) {
                 const int cnt = (int)min((uint32_t)S, end - b0);
+                const uint32_t base = b0 - start + 1u;
                 for (int k = 0; k < cnt; ++k) {
-                    ++examined;
                     const float4 sg = s_g[k];
                     const float4 sh = s_h[k];
+                    const float cb = s_b[k];
                     float dx, dy, G, ag;
-                    if (!eval_pair(px, py, sg, sh, dx, dy, G, ag)) continue;
+                    const bool inside = eval_pair(px, py, sg, sh, dx, dy, G, ag);
                     const float alpha = fminf(kAlphaMax, ag);
-                    if (alpha < kAlphaMin) continue;
+                    const bool ok = active && inside && alpha >= kAlphaMin;
                     const float test_T = T * (1.0f - alpha);
-                    if (test_T < kTMin) {
-                        done = true;
-                        break;
-                    }
-                    const float w = alpha * T;
+                    const bool stop = ok && test_T < kTMin;
+                    const bool comp = ok && !stop;
+                    examined += active ? 1u : 0u;
+                    active = active && !stop;
+                    const float w = comp ? alpha * T : 0.0f;
                     C0 = __builtin_fmaf(w, sh.z, C0);
                     C1 = __builtin_fmaf(w, sh.w, C1);
-                    C2 = __builtin_fmaf(w, s_b[k], C2);
-                    T = test_T;
-                    last = b0 - start + (uint32_t)k + 1u;
-                    ++composited;
+                    C2 = __builtin_fmaf(w, cb, C2);
+                    T = comp ? test_T : T;
+                    last = comp ? base + (uint32_t)k : last;
+                    composited += comp ? 1u : 0u;
+                    if (__ballot(active) == 0ull) break;
                 }
             }
         }
@@ -245,7 +251,7 @@ __global__ __launch_bounds__(TILE* TILE) void k_raster_bwd(RasterArgs a) {
     __shared__ float4 s_g[S];
     __shared__ float4 s_h[S];
     __shared__ float s_b[S];
-    __shared__ uint32_t s_idx[S];
+    __shared__ uint32_t s_gid[S];
     __shared__ float s_red[NW][SUB][9];
     __shared__ uint64_t s_mask[NW];
     __shared__ int s_tile;
@@ -302,7 +308,7 @@ __global__ __launch_bounds__(TILE* TILE) void k_raster_bwd(RasterArgs a) {
             __syncthreads();
             for (int i = threadIdx.x; i < S; i += NT) {
                 const uint32_t j = b0 + i;
-                if (j < stop) stage_splat(a, tp.view, j, s_g[i], s_h[i], s_b[i], s_idx[i]);
+                if (j < stop) stage_splat(a, tp.view, j, s_g[i], s_h[i], s_b[i], s_gid[i]);
             }
             __syncthreads();
             const int cnt = (int)min((uint32_t)S, stop - b0);
@@ -314,37 +320,33 @@ __global__ __launch_bounds__(TILE* TILE) void k_raster_bwd(RasterArgs a) {
                     const uint32_t pos = b0 - start + (uint32_t)k;
                     const float4 sg = s_g[k];
                     const float4 sh = s_h[k];
-                    float dx = 0, dy = 0, G = 0, ag = 0, alpha = 0;
-                    bool contrib = false;
-                    if (pos < lastp && eval_pair(px, py, sg, sh, dx, dy, G, ag)) {
-                        alpha = fminf(kAlphaMax, ag);
-                        contrib = alpha >= kAlphaMin;
-                    }
+                    const float cb = s_b[k];
+                    float dx, dy, G, ag;
+                    const bool inside = eval_pair(px, py, sg, sh, dx, dy, G, ag);
+                    const float alpha = fminf(kAlphaMax, ag);
+                    const bool contrib = pos < lastp && inside && alpha >= kAlphaMin;
                     if (__ballot(contrib) == 0ull) continue;
-                    float v0 = 0, v1 = 0, v2 = 0, v3 = 0, v4 = 0, v5 = 0, v6 = 0, v7 = 0, v8 = 0;
-                    if (contrib) {
-                        const float cb = s_b[k];
-                        const float wgt = alpha * T;
-                        v6 = wgt * g0;
-                        v7 = wgt * g1;
-                        v8 = wgt * g2;
-                        Ca0 = __builtin_fmaf(wgt, sh.z, Ca0);
-                        Ca1 = __builtin_fmaf(wgt, sh.w, Ca1);
-                        Ca2 = __builtin_fmaf(wgt, cb, Ca2);
-                        const float gc = __builtin_fmaf(g2, cb, __builtin_fmaf(g1, sh.w, g0 * sh.z));
-                        const float gS = __builtin_fmaf(g2, Co2 - Ca2,
-                                                        __builtin_fmaf(g1, Co1 - Ca1, g0 * (Co0 - Ca0)));
-                        const float one_m = 1.0f - alpha;
-                        const float dalpha = T * gc - gS / one_m;
-                        const float dpow = ag > kAlphaMax ? 0.0f : alpha * dalpha;
-                        v0 = dpow;
-                        v1 = dpow * dx;
-                        v2 = dpow * dy;
-                        v3 = v1 * dx;
-                        v4 = v1 * dy;
-                        v5 = v2 * dy;
-                        T = T * one_m;
-                    }
+                    // lanes that do not composite this Gaussian select zeros
+                    const float wgt = contrib ? alpha * T : 0.0f;
+                    float v6 = wgt * g0;
+                    float v7 = wgt * g1;
+                    float v8 = wgt * g2;
+                    Ca0 = __builtin_fmaf(wgt, sh.z, Ca0);
+                    Ca1 = __builtin_fmaf(wgt, sh.w, Ca1);
+                    Ca2 = __builtin_fmaf(wgt, cb, Ca2);
+                    const float gc = __builtin_fmaf(g2, cb, __builtin_fmaf(g1, sh.w, g0 * sh.z));
+                    const float gS = __builtin_fmaf(g2, Co2 - Ca2,
+                                                    __builtin_fmaf(g1, Co1 - Ca1, g0 * (Co0 - Ca0)));
+                    const float one_m = 1.0f - alpha;
+                    const float dalpha = T * gc - gS / one_m;
+                    const float dpow = (contrib && !(ag > kAlphaMax)) ? alpha * dalpha : 0.0f;
+                    float v0 = dpow;
+                    float v1 = dpow * dx;
+                    float v2 = dpow * dy;
+                    float v3 = v1 * dx;
+                    float v4 = v1 * dy;
+                    float v5 = v2 * dy;
+                    T = contrib ? T * one_m : T;
                     v0 = wave_sum_to_last(v0);
                     v1 = wave_sum_to_last(v1);
                     v2 = wave_sum_to_last(v2);
@@ -365,28 +367,28 @@ __global__ __launch_bounds__(TILE* TILE) void k_raster_bwd(RasterArgs a) {
                 __syncthreads();
                 if ((int)threadIdx.x < scnt) {
                     const int kk = threadIdx.x;
-                    float r[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+                    float r0 = 0, r1 = 0, r2 = 0, r3 = 0, r4 = 0, r5 = 0, r6 = 0, r7 = 0, r8 = 0;
                     bool any = false;
                     for (int ww = 0; ww < NW; ++ww) {
                         if ((s_mask[ww] >> kk) & 1ull) {
                             any = true;
-#pragma unroll
-                            for (int q = 0; q < 9; ++q) r[q] += s_red[ww][kk][q];
+                            const float* q = s_red[ww][kk];
+                            r0 += q[0]; r1 += q[1]; r2 += q[2]; r3 += q[3]; r4 += q[4];
+                            r5 += q[5]; r6 += q[6]; r7 += q[7]; r8 += q[8];
                         }
                     }
-                    const uint32_t idx = s_idx[sub + kk];
-                    float4* rec = a.partials + 3 * (int64_t)idx;
+                    float4* rec = a.grec + 3 * (int64_t)(b0 + (uint32_t)(sub + kk));
                     if (any) {
                         // conic and opacity of this Gaussian, unscaled
-                        const int64_t o = (int64_t)tp.view * a.n + a.gid[idx];
-                        const float4 g = a.geo[o];
-                        const float4 g2v = a.geo2[o];
-                        const float A = g.z, B = g.w, C = g2v.x, op = g2v.y;
-                        const float du = A * r[1] + B * r[2];
-                        const float dv = B * r[1] + C * r[2];
-                        rec[0] = make_float4(du, dv, -0.5f * r[3], -r[4]);
-                        rec[1] = make_float4(-0.5f * r[5], r[0] / op, r[6], r[7]);
-                        rec[2] = make_float4(r[8], 0.0f, 0.0f, 0.0f);
+                        const float4* r = a.rec + 4 * ((int64_t)tp.view * a.n + s_gid[sub + kk]);
+                        const float4 q0 = r[0];
+                        const float4 q1 = r[1];
+                        const float A = q0.z, B = q0.w, C = q1.x, op = q1.y;
+                        const float du = A * r1 + B * r2;
+                        const float dv = B * r1 + C * r2;
+                        rec[0] = make_float4(du, dv, -0.5f * r3, -r4);
+                        rec[1] = make_float4(-0.5f * r5, r0 / op, r6, r7);
+                        rec[2] = make_float4(r8, 0.0f, 0.0f, 0.0f);
                     } else {
                         const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
                         rec[0] = z; rec[1] = z; rec[2] = z;
@@ -395,14 +397,8 @@ __global__ __launch_bounds__(TILE* TILE) void k_raster_bwd(RasterArgs a) {
                 __syncthreads();
             }
         }
-        // entries no pixel of the tile reached contribute nothing: zero records
-        {
-            const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-            for (uint32_t j = stop + threadIdx.x; j < tp.range.y; j += NT) {
-                float4* rec = a.partials + 3 * (int64_t)a.vals[j];
-                rec[0] = z; rec[1] = z; rec[2] = z;
-            }
-        }
+        // records exist for [start, stop); later entries contribute nothing
+        if (threadIdx.x == 0) a.tile_stop[gt] = stop;
         if (a.counter == nullptr) break;
     }
 }
@@ -447,11 +443,8 @@ static RasterArgs base_args(const gs_splats& sp, int64_t n, const gs_layout& L, 
     RasterArgs a;
     memset(&a, 0, sizeof(a));
     a.L = L;
-    a.geo = reinterpret_cast<const float4*>(sp.geo);
-    a.geo2 = reinterpret_cast<const float4*>(sp.geo2);
-    a.rgb = reinterpret_cast<const float4*>(sp.rgb);
+    a.rec = reinterpret_cast<const float4*>(sp.rec);
     a.vals = b.vals;
-    a.gid = b.gid;
     a.ranges = reinterpret_cast<const uint2*>(b.ranges);
     a.views = views;
     a.n = n;
@@ -487,7 +480,7 @@ int launch_raster_fwd(const gs_splats& sp, int64_t n, const gs_layout& L, const 
 
 int launch_raster_bwd(const gs_splats& sp, int64_t n, const gs_layout& L, const gs_bins& b,
                       const gs_view* views, const gs_image& fwd, const float* target,
-                      const float* dLdC, float* partials, float* loss, int lds_batch,
+                      const float* dLdC, const gs_grads2d& grads, float* loss, int lds_batch,
                       const gs_schedule* sched, hipStream_t s) {
     RasterArgs a = base_args(sp, n, L, b, views, sched);
     a.out_rgb = fwd.rgb;
@@ -497,8 +490,8 @@ int launch_raster_bwd(const gs_splats& sp, int64_t n, const gs_layout& L, const 
     a.dLdC = dLdC;
     a.loss = target ? loss : nullptr;
     a.inv_count = 1.0f / (3.0f * (float)L.pixel_base[L.n_views]);
-    a.partials = reinterpret_cast<float4*>(partials);
-    // every intersection record is written by the kernel (zeros where nothing contributed)
+    a.grec = reinterpret_cast<float4*>(grads.rec);
+    a.tile_stop = grads.tile_stop;
     int rc = GS_OK;
     if (a.total_tiles == 0) return GS_OK;
     if (a.counter) {

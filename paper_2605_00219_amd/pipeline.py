@@ -73,10 +73,7 @@ class Frame:
         V, n = self.n_views, self.n
         f32 = dict(dtype=torch.float32, device=device)
         u32 = dict(dtype=torch.int32, device=device)   # torch has no uint32 arithmetic; bits only
-        self.geo = torch.zeros(V * n, 4, **f32)
-        self.geo2 = torch.zeros(V * n, 4, **f32)
-        self.rgb_s = torch.zeros(V * n, 4, **f32)
-        self.rect = torch.zeros(V * n, 2, **u32)
+        self.rec = torch.zeros(V * n, 16, **f32)    # 64-byte projected records
         self.tiles = torch.zeros(V * n, **u32)
         self.offsets = torch.zeros(V * n + 1, **u32)
         self.ranges = torch.zeros(self.layout.total_tiles, 2, **u32)
@@ -87,6 +84,7 @@ class Frame:
         self.last = torch.zeros(P, **u32)
         self.tile_stats = torch.zeros(self.layout.total_tiles, 4, **u32) if tile_stats else None
         self.loss_tiles = torch.zeros(self.layout.total_tiles, **f32)
+        self.tile_stop = torch.zeros(self.layout.total_tiles, **u32)
         self.counter = torch.zeros(1, **u32)
         self.capacity = 0
         self.resize(capacity)
@@ -97,17 +95,18 @@ class Frame:
         u32 = dict(dtype=torch.int32, device=self.device)
         self.keys = torch.zeros(capacity, **u32)
         self.vals = torch.zeros(capacity, **u32)
-        self.gid = torch.zeros(capacity, **u32)
-        self.partials = torch.zeros(capacity, 12, dtype=torch.float32, device=self.device)
+        self.inv = torch.zeros(capacity, **u32)
+        self.grec = torch.zeros(capacity, 12, dtype=torch.float32, device=self.device)
         ws = G.lib.gs_bin_sort_workspace_size(self.n, C.byref(self.layout), capacity)
         self.workspace = torch.zeros(max(int(ws), 1), dtype=torch.uint8, device=self.device)
         self.capacity = capacity
         self._structs()
 
     def _structs(self) -> None:
-        self.splats = G.GsSplats(_i(self.geo), _i(self.geo2), _i(self.rgb_s), _i(self.rect), _i(self.tiles))
-        self.bins = G.GsBins(_i(self.offsets), _i(self.keys), _i(self.vals), _i(self.gid),
+        self.splats = G.GsSplats(_i(self.rec), _i(self.tiles))
+        self.bins = G.GsBins(_i(self.offsets), _i(self.keys), _i(self.vals), _i(self.inv),
                              _i(self.ranges), _i(self.status), self.capacity)
+        self.grads2d = G.GsGrads2d(_i(self.grec), _i(self.tile_stop))
         self.img = G.GsImage(_i(self.image), _i(self.T), _i(self.last),
                              _i(self.tile_stats) if self.tile_stats is not None else None)
 
@@ -172,7 +171,7 @@ def rasterize_bwd(frame: Frame, views_dev: torch.Tensor, target: torch.Tensor | 
     G.check(G.lib.gs_rasterize_bwd(C.byref(frame.splats), frame.n, C.byref(frame.layout),
                                    C.byref(frame.bins), _i(views_dev), C.byref(frame.img),
                                    _i(target) if target is not None else None,
-                                   _i(dLdC) if dLdC is not None else None, _i(frame.partials),
+                                   _i(dLdC) if dLdC is not None else None, C.byref(frame.grads2d),
                                    _i(frame.loss_tiles) if target is not None else None, lds_batch,
                                    C.byref(sched) if sched is not None else None,
                                    G.stream_ptr(stream)), "gs_rasterize_bwd")
@@ -181,7 +180,7 @@ def rasterize_bwd(frame: Frame, views_dev: torch.Tensor, target: torch.Tensor | 
 def project_bwd_adam(model: Model, frame: Frame, views_dev: torch.Tensor, adam: bool = True,
                      grads_out: torch.Tensor | None = None, stream=None) -> None:
     G.check(G.lib.gs_project_bwd_adam(_i(model.params), frame.n, _i(views_dev), C.byref(frame.layout),
-                                      C.byref(frame.bins), _i(frame.partials),
+                                      C.byref(frame.bins), C.byref(frame.grads2d),
                                       C.byref(model.adam) if adam else None,
                                       _i(grads_out) if grads_out is not None else None,
                                       G.stream_ptr(stream)), "gs_project_bwd_adam")

@@ -43,24 +43,24 @@ def run_gpu_step(scene, views, tile, target=None, lds_batch=64, lr=1e-3, adam=Tr
     out = dict(frame=frame, model=model)
     out["status"] = frame.status_bits()
     out["tiles"] = u32(frame.tiles).reshape(len(views), n)
-    out["rect"] = u32(frame.rect).reshape(len(views), n, 2)
-    out["geo"] = frame.geo.cpu().numpy().reshape(len(views), n, 4)
-    out["geo2"] = frame.geo2.cpu().numpy().reshape(len(views), n, 4)
-    out["rgb"] = frame.rgb_s.cpu().numpy().reshape(len(views), n, 4)
+    rec = frame.rec.cpu().numpy().reshape(len(views), n, 16)
+    out["rec"] = rec
+    out["rect"] = rec[..., 12:14].copy().view(np.uint32)
     out["offsets"] = u32(frame.offsets)
     K = int(out["offsets"][-1])
     out["K"] = K
     out["keys"] = u32(frame.keys)[:K]
     out["vals"] = u32(frame.vals)[:K]
-    out["gid"] = u32(frame.gid)[:K]
+    out["inv"] = u32(frame.inv)[:K]
     out["ranges"] = u32(frame.ranges)
+    out["tile_stop"] = u32(frame.tile_stop)
     out["image"] = frame.image.cpu().numpy()
     out["T"] = frame.T.cpu().numpy()
     out["last"] = u32(frame.last)
     if tile_stats:
         out["tile_stats"] = u32(frame.tile_stats)
     if tgt is not None:
-        out["partials"] = frame.partials.cpu().numpy()[:K]
+        out["grec"] = frame.grec.cpu().numpy()[:K]
         out["loss_tiles"] = frame.loss_tiles.cpu().numpy()
         out["params"] = P.unpack_flat(model.params).cpu().numpy()
         out["m"] = P.unpack_flat(model.m).cpu().numpy()
@@ -70,14 +70,17 @@ def run_gpu_step(scene, views, tile, target=None, lds_batch=64, lr=1e-3, adam=Tr
     return out
 
 
-def per_gaussian_2d(partials, offsets, V, n):
-    """Sum each Gaussian's intersection records: [V, N, 9]."""
-    out = np.zeros((V * n, 9))
-    rec = partials[:, :9].astype(np.float64)
-    cs = np.concatenate([np.zeros((1, 9)), np.cumsum(rec, axis=0)])
-    o = offsets.astype(np.int64)
-    out[:] = cs[o[1:]] - cs[o[:-1]]
-    return out.reshape(V, n, 9)
+def per_gaussian_2d(grec, vals, ranges, tile_stop, tile_base, n):
+    """Sum the traversed records of each (view, Gaussian): [V, N, 9].
+    tile_base: global tile base of each view plus the total."""
+    V = len(tile_base) - 1
+    out = np.zeros((V, n, 9))
+    for v in range(V):
+        for t in range(tile_base[v], tile_base[v + 1]):
+            s, e = int(ranges[t, 0]), int(tile_stop[t])
+            if e > s:
+                np.add.at(out[v], vals[s:e], grec[s:e, :9].astype(np.float64))
+    return out
 
 
 def rect_from_packed(r):

@@ -63,20 +63,20 @@ def test_projection_and_binning_bit_exact(name):
     np.testing.assert_array_equal(rect_from_packed(g["rect"])[vis], ref.proj.rect[vis])
     # float outputs: same operation order without contraction -> same bits
     f32 = lambda a: a.astype(np.float32)
-    np.testing.assert_array_equal(g["geo"][..., 0][vis], f32(ref.proj.xy[..., 0])[vis])
-    np.testing.assert_array_equal(g["geo"][..., 1][vis], f32(ref.proj.xy[..., 1])[vis])
-    np.testing.assert_array_equal(g["geo"][..., 2][vis], f32(ref.proj.conic[..., 0])[vis])
-    np.testing.assert_array_equal(g["geo"][..., 3][vis], f32(ref.proj.conic[..., 1])[vis])
-    np.testing.assert_array_equal(g["geo2"][..., 0][vis], f32(ref.proj.conic[..., 2])[vis])
-    np.testing.assert_array_equal(g["geo2"][..., 1][vis], f32(ref.proj.opacity)[vis])
-    np.testing.assert_array_equal(g["geo2"][..., 2][vis], f32(ref.proj.depth)[vis])
-    np.testing.assert_array_equal(g["geo2"][..., 3][vis], f32(ref.proj.radius)[vis])
-    np.testing.assert_array_equal(g["rgb"][..., :3][vis], f32(ref.proj.rgb)[vis])
-    # binning
+    rec = g["rec"]
+    fields = {0: ref.proj.xy[..., 0], 1: ref.proj.xy[..., 1], 2: ref.proj.conic[..., 0],
+              3: ref.proj.conic[..., 1], 4: ref.proj.conic[..., 2], 5: ref.proj.opacity,
+              6: ref.proj.rgb[..., 0], 7: ref.proj.rgb[..., 1], 8: ref.proj.rgb[..., 2],
+              9: ref.proj.depth, 10: ref.proj.radius}
+    for k, want in fields.items():
+        np.testing.assert_array_equal(rec[..., k][vis], f32(want)[vis], err_msg=f"record field {k}")
+    # binning: keys, the Gaussian id carried by the sort, inverse permutation, ranges
     np.testing.assert_array_equal(g["offsets"], ref.bins.offsets)
     np.testing.assert_array_equal(g["keys"], ref.bins.keys)
-    np.testing.assert_array_equal(g["vals"], ref.bins.vals)
-    np.testing.assert_array_equal(g["gid"], ref.bins.gid)
+    np.testing.assert_array_equal(g["vals"], ref.bins.gid[ref.bins.vals])
+    inv = np.empty_like(ref.bins.vals)
+    inv[ref.bins.vals] = np.arange(ref.bins.vals.size, dtype=np.uint32)
+    np.testing.assert_array_equal(g["inv"], inv)
     np.testing.assert_array_equal(g["ranges"], ref.bins.ranges)
 
 
@@ -110,7 +110,10 @@ def test_training_step(name):
     loss_gpu = g["loss_tiles"].astype(np.float64).sum() / (3 * sum(oracle.n_pixels(views)))
     assert abs(loss_gpu - ref.loss) <= 1e-4 * ref.loss
     # per-Gaussian 2D gradients (sums of the intersection records)
-    g2 = per_gaussian_2d(g["partials"], g["offsets"], V, n)
+    tb = np.cumsum([0] + oracle.n_tiles(views, tile))
+    g2 = per_gaussian_2d(g["grec"], g["vals"], g["ranges"], g["tile_stop"], tb, n)
+    # traversal stops are within the ranges
+    assert np.all(g["tile_stop"] >= g["ranges"][:, 0]) and np.all(g["tile_stop"] <= g["ranges"][:, 1])
     ok2 = grad_close(g2.reshape(-1, 9), ref.grads2d.reshape(-1, 9), GRAD_RTOL).reshape(V, n, 9)
     bad = ~ok2.all(axis=2) & ~ex
     assert not bad.any(), np.argwhere(bad)[:5]
@@ -140,7 +143,7 @@ def test_deterministic_bitwise():
     target = oracle.render(target_scene, views, tile)
     a = run_gpu_step(scene, views, tile, target=target)
     b = run_gpu_step(scene, views, tile, target=target)
-    for k in ("image", "partials", "grads", "params", "keys", "vals"):
+    for k in ("image", "grec", "tile_stop", "grads", "params", "keys", "vals", "inv"):
         np.testing.assert_array_equal(a[k], b[k])
 
 
@@ -153,7 +156,7 @@ def test_persistent_and_permuted_schedules_change_no_bit():
     perm = np.random.default_rng(3).permutation(nt).astype(np.int32)
     for kw in (dict(persistent=True), dict(sched_order=perm), dict(sched_order=perm, persistent=True)):
         other = run_gpu_step(scene, views, tile, target=target, **kw)
-        for k in ("image", "T", "last", "partials", "grads", "params"):
+        for k in ("image", "T", "last", "grec", "tile_stop", "grads", "params"):
             np.testing.assert_array_equal(base[k], other[k], err_msg=str(kw))
 
 

@@ -1,0 +1,162 @@
+"""Learned tile schedule: tile features, the cost MLP's forward / gradient /
+Adam kernels against the CPU oracle, ordering by predicted cost, bit-identical
+images under the learned order, and what the learned order gains in the
+scheduling objective (longest-first makespan of the measured tile costs)."""
+import numpy as np
+import pytest
+
+import oracle
+import synthetic as S
+from gpu_common import note, run_gpu_step, u32
+from oracle import mlp as MO
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mods():
+    import torch
+    from paper_2605_00219_amd import _lib as G
+    from paper_2605_00219_amd import pipeline as P
+    from paper_2605_00219_amd import schedule as SC
+    return torch, G, P, SC
+
+
+def _rand_mlp(seed):
+    rng = np.random.default_rng(seed)
+    w = rng.normal(0, 0.3, size=MO.N_PARAMS).astype(np.float32)
+    norm = np.r_[rng.normal(0, 1, 8), rng.uniform(0.5, 2, 8)].astype(np.float32)
+    x = rng.normal(0, 2, size=(3000, 8)).astype(np.float32)
+    t = rng.normal(0, 1, size=3000).astype(np.float32)
+    return w, norm, x, t
+
+
+def test_mlp_forward_matches_oracle(mods):
+    torch, G, P, SC = mods
+    note("mlp forward")
+    w, norm, x, _ = _rand_mlp(1)
+    cm = SC.CostModel()
+    cm.w = torch.tensor(w, device="cuda")
+    cm.norm = torch.tensor(norm, device="cuda")
+    got = cm.predict(torch.tensor(x, device="cuda")).cpu().numpy()
+    ref = MO.forward(w, norm, x).numpy()
+    np.testing.assert_allclose(got, ref, rtol=1e-4, atol=1e-4 * np.abs(ref).max())
+
+
+def test_mlp_gradient_and_adam_step_match_oracle(mods):
+    torch, G, P, SC = mods
+    note("mlp gradient + adam")
+    w, norm, x, t = _rand_mlp(2)
+    cm = SC.CostModel()
+    cm.w = torch.tensor(w, device="cuda")
+    cm.norm = torch.tensor(norm, device="cuda")
+    lr = 1e-3
+    cm.train_step(torch.tensor(x, device="cuda"), torch.tensor(t, device="cuda"), lr)
+    torch.cuda.synchronize()
+    part = cm.scratch[:G.MLP_GROUPS * (G.MLP_PARAMS + 1)].view(G.MLP_GROUPS, G.MLP_PARAMS + 1)
+    grad = part[:, :G.MLP_PARAMS].double().sum(0).cpu().numpy()
+    loss_gpu = float(cm.loss.item())
+    loss, gref = MO.mse_and_grad(w, norm, x, t)
+    assert loss_gpu == pytest.approx(loss, rel=1e-4)
+    np.testing.assert_allclose(grad, gref, rtol=1e-3, atol=1e-4 * np.abs(gref).max())
+    w1, _, _ = MO.adam(w.astype(np.float64), 0.0, 0.0, gref, 1, lr)
+    got = cm.w.cpu().numpy()
+    certain = np.abs(gref) > 1e-3 * np.abs(gref).max()
+    np.testing.assert_allclose(got[certain], w1[certain], rtol=1e-5, atol=1e-6)
+    assert np.all(np.abs(got - w1)[~certain] <= 2 * lr + 1e-6)
+
+
+def test_order_by_cost_is_stable_descending_with_fallback(mods):
+    torch, G, P, SC = mods
+    note("order by cost")
+    rng = np.random.default_rng(3)
+    p = rng.normal(size=10007).astype(np.float32)
+    p[::7] = np.float32(0.5)        # ties
+    p[5] = np.float32(-0.0)
+    order = SC.order_by_cost(torch.tensor(p, device="cuda")).cpu().numpy()
+    np.testing.assert_array_equal(order, np.argsort(-p.astype(np.float64), kind="stable"))
+    p[100] = np.float32("nan")
+    order = SC.order_by_cost(torch.tensor(p, device="cuda")).cpu().numpy()
+    np.testing.assert_array_equal(order, np.arange(p.size))
+
+
+def test_tile_features_match_oracle_bins(mods):
+    torch, G, P, SC = mods
+    note("tile features")
+    w = S.workload_plain_small()
+    g = run_gpu_step(w.scene, w.views, 16)
+    feats = SC.tile_features(g["frame"]).cpu().numpy()
+    pr = oracle.project(w.scene, w.views, 16)
+    bins = oracle.bin_sort(pr, w.views, 16)
+    for t in range(256):
+        s, e = bins.ranges[t]
+        ids = bins.gid[bins.vals[s:e]]
+        ref = np.zeros(8)
+        ref[0] = np.log1p(e - s)
+        if e > s:
+            o, z, r = pr.opacity[0, ids], pr.depth[0, ids], pr.radius[0, ids]
+            ref[1:6] = [o.mean(), o.max(), z.mean(), z.min(), r.mean()]
+        ref[6] = ((t % 16) + 0.5) / 16
+        ref[7] = ((t // 16) + 0.5) / 16
+        np.testing.assert_allclose(feats[t], ref, rtol=2e-5, atol=1e-5)
+
+
+def makespan(costs, order, workers):
+    """Greedy list scheduling: each tile, in the given order, goes to the
+    worker that frees up first; returns the finishing time of the last one."""
+    import heapq
+    h = [0.0] * workers
+    for t in order:
+        f = heapq.heappop(h)
+        heapq.heappush(h, f + costs[t])
+    return max(h)
+
+
+def test_learned_order_bit_identical_and_shorter_makespan(mods):
+    torch, G, P, SC = mods
+    note("learned schedule: train on anisotropic scenes, apply to a normal scene")
+    feats, targs = [], []
+    for seed in range(3):
+        sc = S.scene_anisotropic(60_000, 3100 + seed)
+        views = S.views_array([S.make_view(640, 480, c) for c in S.fibonacci_sphere(6, 5.0)[seed::3]])
+        g = run_gpu_step(sc, views, 16, tile_stats=True)
+        feats.append(SC.tile_features(g["frame"]))
+        targs.append(SC.traversal_target(g["frame"]))
+    X = torch.cat(feats)
+    Y = torch.cat(targs)
+    cm = SC.CostModel(seed=0)
+    cm.set_normalisation(X)
+    loss0 = float(torch.mean((cm.predict(X) - Y) ** 2).item())
+    loss = cm.fit(X, Y, epochs=300, lr=3e-3)
+    assert loss < 0.5 * loss0
+    # apply on a differently distributed scene (means ~N(0,1), isotropic scales)
+    scene = S.scene_normal(80_000, 3200, log_scale_mean=-3.5)
+    target_scene = S.scene_normal(80_000, 3201, log_scale_mean=-3.5)
+    views = S.views_array([S.make_view(800, 600, c) for c in S.fibonacci_sphere(4, 5.0)[:2]])
+    g = run_gpu_step(scene, views, 16, tile_stats=True)
+    fr = g["frame"]
+    pred = cm.predict(SC.tile_features(fr))
+    meas = SC.traversal_target(fr)
+    q = SC.prediction_quality(pred, meas)
+    order = SC.order_by_cost(pred).cpu().numpy()
+    assert sorted(order.tolist()) == list(range(fr.layout.total_tiles))
+    # bit-identical training step under the learned order (persistent queue)
+    target = oracle.render(target_scene, views, 16)
+    base = run_gpu_step(scene, views, 16, target=target)
+    lrn = run_gpu_step(scene, views, 16, target=target, sched_order=order, persistent=True)
+    for k in ("image", "T", "last", "grec", "grads", "params"):
+        np.testing.assert_array_equal(base[k], lrn[k])
+    # scheduling objective with the measured per-tile costs
+    costs = np.expm1(meas.cpu().numpy()) + 1.0
+    workers = 2048
+    ms_static = makespan(costs, np.arange(costs.size), workers)
+    ms_learned = makespan(costs, order, workers)
+    ms_oracle = makespan(costs, np.argsort(-costs, kind="stable"), workers)
+    note(f"  MAPE {q['mape']:.3f} Spearman {q['spearman']:.3f}; makespan static {ms_static:.0f} "
+         f"learned {ms_learned:.0f} measured-LPT {ms_oracle:.0f}")
+    assert q["spearman"] > 0.5
+    assert ms_learned < ms_static
+    # fallback: non-finite weights give the static order
+    cm.w[-1] = float("nan")   # output bias: every prediction is NaN
+    fb = SC.order_by_cost(cm.predict(SC.tile_features(fr))).cpu().numpy()
+    np.testing.assert_array_equal(fb, np.arange(fr.layout.total_tiles))

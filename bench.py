@@ -38,6 +38,27 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def source_sha(rel: str) -> str:
+    import hashlib
+    with open(os.path.join(ROOT, rel), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def recorded_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` measured by rocprofv3 counters
+    (profiles/hbm_traffic.json), or None if absent or if the kernel's source
+    has changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f).get(kernel)
+        if rec and rec.get("source_sha") == source_sha(rec["source"]):
+            return rec
+    except (OSError, ValueError, KeyError):
+        pass
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -49,6 +70,11 @@ def parse():
     ap.add_argument("--no-replay", action="store_true", help="skip the work-counting replay")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (for HBM counter scaling)")
+    ap.add_argument("--variants", default="batched,learned",
+                    help="comma list of extra measurements: batched, learned ('' for none)")
+    ap.add_argument("--batched-steps", type=int, default=200)
+    ap.add_argument("--batched-plain-steps", type=int, default=25)
+    ap.add_argument("--learned-steps", type=int, default=10)
     return ap.parse_args()
 
 
@@ -192,9 +218,15 @@ def main():
             "alu_frac": bwd_tflops / FP32_PEAK_TFLOPS,
             "intersections": counts["K"], "traversed": counts["trav_bwd"],
             "pairs_evaluated": counts["eval_bwd"], "pairs_composited": counts["contrib"]}
+        tr = recorded_traffic("rasterize_bwd")
+        if tr is not None:
+            extra["rasterize_bwd"]["measured_hbm_bytes"] = tr["bytes_per_launch"]
+            extra["rasterize_bwd"]["measured_hbm_gbs"] = tr["bytes_per_launch"] / t_bwd / 1e9
+            extra["rasterize_bwd"]["measured_hbm_frac"] = tr["bytes_per_launch"] / t_bwd / 1e9 / HBM_PEAK_GBS
         if dom == "rasterize_bwd":
             roof = {"bound": "alu", "achieved": bwd_tflops, "peak": FP32_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": bwd_tflops / FP32_PEAK_TFLOPS, "traffic": None,
+                    "unit": "TFLOP/s", "frac": bwd_tflops / FP32_PEAK_TFLOPS,
+                    "traffic": tr["bytes_per_launch"] if tr else None,
                     "kernel": "rasterize_bwd"}
     if roof is None:
         roof = {"bound": "unknown", "achieved": None, "peak": None, "unit": None, "frac": None,
@@ -207,6 +239,33 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+
+    variants = [v for v in args.variants.split(",") if v]
+    model = frame = targets = state0 = evs = None      # free the plain workload's buffers
+    if counts is not None:
+        rframe = None
+    torch.cuda.empty_cache()
+    if "batched" in variants:
+        from paper_2605_00219_amd import experiments as X
+        log("batched variant: 3M Gaussians, 8 uneven views per step")
+        wb = S.workload_batched()
+        cams, res = wb.extra["cameras"], wb.extra["resolutions"]
+        extra["batched"] = X.run_batched(wb, lambda i: S.batched_views(cams, res, i),
+                                         steps=args.batched_steps,
+                                         plain_steps=args.batched_plain_steps, log=log)
+        del wb
+        torch.cuda.empty_cache()
+    if "learned" in variants:
+        from paper_2605_00219_amd import experiments as X
+        log("learned-schedule variant: 6M Gaussians, 4 x 1920x1080 per step")
+        wl = S.workload_learned()
+        train_cams = S.fibonacci_sphere(50, 5.0)
+        train_sets = [(S.scene_anisotropic(1_000_000, 3000 + 10 * k),
+                       S.views_array([S.make_view(1920, 1080, train_cams[(7 * k + j) % 50])
+                                      for j in range(4)])) for k in range(2)]
+        extra["learned"] = X.run_learned(wl, train_sets, steps=args.learned_steps, log=log)
+        del wl, train_sets
+        torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu_baseline:

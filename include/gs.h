@@ -87,6 +87,9 @@ typedef struct gs_view {
 typedef struct gs_layout {
     int32_t n_views;
     int32_t tile;                          /* tile edge T in pixels: 8, 16 or 32 */
+    int32_t pixels_per_lane;               /* rasteriser lanes per tile = T*T / this; 1 for
+                                              T = 8, 1, 2 or 4 otherwise (default 4 for
+                                              T = 16, 2 for T = 32) */
     int32_t width[GS_MAX_VIEWS], height[GS_MAX_VIEWS];
     int32_t tiles_x[GS_MAX_VIEWS], tiles_y[GS_MAX_VIEWS];
     int32_t depth_bits[GS_MAX_VIEWS];      /* D = min(23, 32 - B), B = ceil(log2 #tiles), B >= 1 */

@@ -24,7 +24,7 @@ STATUS_CAPACITY, STATUS_OVERFLOW = 1, 2
 
 
 class GsLayout(C.Structure):
-    _fields_ = [("n_views", C.c_int32), ("tile", C.c_int32),
+    _fields_ = [("n_views", C.c_int32), ("tile", C.c_int32), ("pixels_per_lane", C.c_int32),
                 ("width", C.c_int32 * MAX_VIEWS), ("height", C.c_int32 * MAX_VIEWS),
                 ("tiles_x", C.c_int32 * MAX_VIEWS), ("tiles_y", C.c_int32 * MAX_VIEWS),
                 ("depth_bits", C.c_int32 * MAX_VIEWS),
@@ -136,10 +136,12 @@ def stream_ptr(stream=None) -> int:
     return s.cuda_stream
 
 
-def layout_init(widths, heights, tile: int) -> GsLayout:
+def layout_init(widths, heights, tile: int, pixels_per_lane: int | None = None) -> GsLayout:
     n = len(widths)
     W = (C.c_int32 * n)(*[int(w) for w in widths])
     H = (C.c_int32 * n)(*[int(h) for h in heights])
     L = GsLayout()
     check(lib.gs_layout_init(W, H, n, int(tile), C.byref(L)), "gs_layout_init")
+    if pixels_per_lane is not None:
+        L.pixels_per_lane = int(pixels_per_lane)
     return L

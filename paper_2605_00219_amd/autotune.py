@@ -1,7 +1,8 @@
 """Autotuner for the batched, persistent, graph-captured training step.
 
-Searches tile edge T in {8, 16, 32} and Gaussians-per-LDS-batch S in
-{32, 64, 128, 256}.  Every candidate runs the same iterations from the same
+Searches tile edge T in {8, 16, 32}, Gaussians-per-LDS-batch S in
+{32, 64, 128, 256} and, for T = 16 and 32, pixels per lane P in {1, 2, 4}
+(one lane renders P pixels of its tile, so a tile takes T*T/P lanes).  Every candidate runs the same iterations from the same
 optimiser state (restored between candidates), each as a captured HIP graph;
 the candidate with the lowest mean step time wins.  Results are cached in a
 JSON file keyed by GPU architecture, the view-set resolutions and the
@@ -25,6 +26,7 @@ from .batched import BatchedStep, ViewSet
 
 TILES = (8, 16, 32)
 BATCHES = (32, 64, 128, 256)
+LANE_PIXELS = (1, 2, 4)
 
 
 def cache_key(resolutions, n: int) -> str:
@@ -61,9 +63,9 @@ def capacity_for(model: P.Model, n: int, viewset: ViewSet, view_rows, iters, sla
 
 
 def time_candidate(model: P.Model, n: int, resolutions, tile: int, lds: int, view_rows, targets,
-                   iters, capacity: int) -> float:
+                   iters, capacity: int, ppl: int | None = None) -> float:
     saved = [t.clone() for t in (model.params, model.m, model.v, model.step)]
-    vs = ViewSet(resolutions, tile)
+    vs = ViewSet(resolutions, tile, ppl)
     step = BatchedStep(model, n, vs, capacity, lds_batch=lds, persistent=True)
     step.load(view_rows(iters[0]), targets(iters[0]))
     step.capture()
@@ -89,22 +91,25 @@ def time_candidate(model: P.Model, n: int, resolutions, tile: int, lds: int, vie
 
 
 def autotune(model: P.Model, n: int, resolutions, view_rows, targets, iters, cache_path=None,
-             tiles=TILES, batches=BATCHES, log=print) -> dict:
+             tiles=TILES, batches=BATCHES, lane_pixels=LANE_PIXELS, log=print) -> dict:
     key = cache_key(resolutions, n)
     cache = load_cache(cache_path) if cache_path else {}
     hit = cache.get(key)
-    if isinstance(hit, dict) and hit.get("tile") in tiles and hit.get("lds_batch") in batches:
+    if (isinstance(hit, dict) and hit.get("tile") in tiles and hit.get("lds_batch") in batches
+            and hit.get("pixels_per_lane") in lane_pixels + (1,)):
         return dict(hit, cached=True)
     table = {}
     for T in tiles:
         cap = capacity_for(model, n, ViewSet(resolutions, T), view_rows, iters)
-        for S in batches:
-            dt = time_candidate(model, n, resolutions, T, S, view_rows, targets, iters, cap)
-            table[f"T{T}_S{S}"] = dt * 1e3
-            log(f"autotune T={T} S={S}: {dt * 1e3:.3f} ms/step")
+        for ppl in ((1,) if T == 8 else lane_pixels):
+            for S in batches:
+                dt = time_candidate(model, n, resolutions, T, S, view_rows, targets, iters, cap, ppl)
+                table[f"T{T}_S{S}_P{ppl}"] = dt * 1e3
+                log(f"autotune T={T} S={S} P={ppl}: {dt * 1e3:.3f} ms/step")
     best = min(table, key=table.get)
-    T, S = (int(x[1:]) for x in best.split("_"))
-    res = {"tile": T, "lds_batch": S, "ms": table[best], "table_ms": table, "cached": False}
+    T, S, ppl = (int(x[1:]) for x in best.split("_"))
+    res = {"tile": T, "lds_batch": S, "pixels_per_lane": ppl, "ms": table[best], "table_ms": table,
+           "cached": False}
     if cache_path:
         cache[key] = {k: v for k, v in res.items() if k != "cached"}
         save_cache(cache_path, cache)

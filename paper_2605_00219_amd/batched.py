@@ -22,11 +22,12 @@ from . import pipeline as P
 class ViewSet:
     """Fixed slot resolutions; per iteration a camera goes into each slot."""
 
-    def __init__(self, resolutions, tile: int):
+    def __init__(self, resolutions, tile: int, pixels_per_lane: int | None = None):
         self.resolutions = list(resolutions)
         self.widths = [w for w, _ in self.resolutions]
         self.heights = [h for _, h in self.resolutions]
         self.tile = tile
+        self.pixels_per_lane = pixels_per_lane
         self.pixels = sum(w * h for w, h in self.resolutions)
 
 
@@ -41,7 +42,8 @@ class BatchedStep:
                  n_groups: int | None = None, graph: bool = True):
         self.model = model
         self.viewset = viewset
-        self.frame = P.Frame(n, viewset.widths, viewset.heights, viewset.tile, capacity=capacity)
+        self.frame = P.Frame(n, viewset.widths, viewset.heights, viewset.tile, capacity=capacity,
+                             pixels_per_lane=viewset.pixels_per_lane)
         self.views_buf = torch.zeros(128 * len(viewset.resolutions), dtype=torch.uint8, device="cuda")
         self.target_buf = torch.zeros(viewset.pixels, 3, dtype=torch.float32, device="cuda")
         self.lds_batch = lds_batch

@@ -29,6 +29,9 @@ int check_launch(const char* what) {
 static bool layout_ok(const gs_layout* L) {
     if (!L || L->n_views < 1 || L->n_views > GS_MAX_VIEWS) return false;
     if (L->tile != 8 && L->tile != 16 && L->tile != 32) return false;
+    if (L->tile == 8 && L->pixels_per_lane != 1) return false;
+    if (L->tile != 8 && L->pixels_per_lane != 1 && L->pixels_per_lane != 2 && L->pixels_per_lane != 4)
+        return false;
     return true;
 }
 
@@ -60,6 +63,7 @@ int gs_layout_init(const int32_t* widths, const int32_t* heights, int n_views, i
     memset(&L, 0, sizeof(L));
     L.n_views = n_views;
     L.tile = tile;
+    L.pixels_per_lane = tile == 8 ? 1 : (tile == 16 ? 4 : 2);
     int64_t tb = 0, pb = 0;
     for (int v = 0; v < n_views; ++v) {
         REQUIRE(widths[v] >= 1 && heights[v] >= 1 && widths[v] <= (1 << 20) && heights[v] <= (1 << 20),

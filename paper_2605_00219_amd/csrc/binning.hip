@@ -321,23 +321,42 @@ GS_DEV uint64_t lanemask_lt() {
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
+// Stable scatter of one radix pass.  The chunk's keys are first ranked and
+// placed in LDS in digit order (chunk-local counting sort, ranks from
+// wavefront match masks built with 8 ballots), then written out from LDS so
+// that consecutive lanes write consecutive addresses of each digit's run.
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
     const uint32_t* __restrict__ table, int n_views, int shift,
     const uint32_t* __restrict__ scanned) {
     constexpr int NW = kSortThreads / kWave;
-    __shared__ uint32_t base[kDigits];
+    __shared__ uint32_t gbase[kDigits];   // global destination of the chunk's first key of digit d
+    __shared__ uint32_t lstart[kDigits];  // chunk-local start of digit d
+    __shared__ uint32_t lrun[kDigits];    // keys of digit d placed so far
     __shared__ uint32_t wcnt[NW][kDigits];
+    __shared__ uint32_t s_k[kChunk];
+    __shared__ uint32_t s_v[kChunk];
+    __shared__ uint64_t s_scan[NW];
     const uint32_t b = blockIdx.x;
     int v;
     uint32_t c;
     if (!chunk_of(table, n_views, b, &v, &c)) return;
-    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int w = threadIdx.x / kWave;
     const uint32_t nc = table[4 * v + 3], cb = table[4 * v + 2];
-    base[threadIdx.x] = scanned[(int64_t)cb * kDigits + (int64_t)threadIdx.x * nc + c];
+    const int64_t hi = (int64_t)cb * kDigits + (int64_t)threadIdx.x * nc + c;
+    const uint32_t g0 = scanned[hi];
+    const uint32_t cnt = scanned[hi + 1] - g0;   // exclusive scan: next minus this
+    gbase[threadIdx.x] = g0;
+    {
+        uint64_t tot;
+        const uint64_t inc = block_scan_u64(cnt, s_scan, &tot);
+        lstart[threadIdx.x] = (uint32_t)(inc - cnt);
+    }
+    lrun[threadIdx.x] = 0u;
     const uint32_t seg_e = table[4 * v + 1];
     const uint32_t start = table[4 * v] + c * kChunk;
+    const uint32_t n_here = min((uint32_t)kChunk, seg_e - start);
     uint32_t k[kSortItems], val[kSortItems];
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
@@ -346,6 +365,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
         val[i] = idx < seg_e ? vals_in[idx] : 0u;
     }
     const uint64_t lt = lanemask_lt();
+    __syncthreads();
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
         const uint32_t idx = start + i * kSortThreads + threadIdx.x;
@@ -365,21 +385,27 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
         if (leader) wcnt[w][d] = (uint32_t)__popcll(peers);
         __syncthreads();
         if (valid) {
-            uint32_t pos = base[d] + rank;
+            uint32_t pos = lstart[d] + lrun[d] + rank;
             for (int j = 0; j < w; ++j) pos += wcnt[j][d];
-            keys_out[pos] = k[i];
-            vals_out[pos] = val[i];
+            s_k[pos] = k[i];
+            s_v[pos] = val[i];
         }
         __syncthreads();
         {
             uint32_t add = 0;
 #pragma unroll
             for (int j = 0; j < NW; ++j) add += wcnt[j][threadIdx.x];
-            base[threadIdx.x] += add;
+            lrun[threadIdx.x] += add;
         }
         __syncthreads();
     }
-    (void)lane;
+    for (uint32_t j = threadIdx.x; j < n_here; j += kSortThreads) {
+        const uint32_t key = s_k[j];
+        const uint32_t d = (key >> shift) & 0xFF;
+        const uint32_t dst = gbase[d] + (j - lstart[d]);
+        keys_out[dst] = key;
+        vals_out[dst] = s_v[j];
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -1,7 +1,8 @@
 // Tile rasteriser: forward alpha compositing and its exact backward.
 //
-// One workgroup renders one T x T tile (one thread per pixel; T = 8, 16, 32 gives
-// 1, 4 or 16 wavefronts).  The tile's sorted Gaussian list is consumed in
+// One workgroup renders one T x T tile (T = 8, 16, 32: one pixel per lane for
+// T = 8, four pixels per lane otherwise, so 1, 1 or 4 wavefronts per tile).
+// The tile's sorted Gaussian list is consumed in
 // batches of S records gathered into LDS; every lane then reads the batch
 // with broadcast LDS loads.  The conic is staged pre-scaled by -log2(e)/2 so
 // that a pair costs one v_exp_f32.
@@ -104,25 +105,35 @@ GS_DEV int next_tile(const RasterArgs& a, int* s_tile) {
     return *s_tile;
 }
 
-struct TilePix {
-    int view, ix, iy;
-    bool inside;
-    int64_t pix;
+// Pixels per lane: a T x T tile is covered by T*T/PPT lanes, lane t holding
+// the pixels t, t + NT, t + 2 NT, ... of the tile (row major).  With 16x16
+// tiles and PPT = 4 one wavefront renders a whole tile: each staged Gaussian
+// is read from LDS once per four pixels, the four transmittance chains give
+// independent work to interleave, and the backward's per-Gaussian wavefront
+// reduction is shared by four pixels per lane.
+template <int TILE, int PPT_>
+struct Geo {
+    static constexpr int PPT = PPT_;
+    static constexpr int NT = TILE * TILE / PPT;
+    static constexpr int NW = NT / kWave;
+};
+
+struct TileInfo {
+    int view, tx, ty, W, H;
+    int64_t pix_base;
     uint2 range;
 };
 
-template <int TILE>
-GS_DEV TilePix tile_pixel(const RasterArgs& a, int gt) {
-    TilePix t;
+GS_DEV TileInfo tile_info(const RasterArgs& a, int gt) {
+    TileInfo t;
     t.view = view_of_tile(a.L, gt);
     const int lt = gt - a.L.tile_base[t.view];
     const int gx = a.L.tiles_x[t.view];
-    const int tx = lt % gx, ty = lt / gx;
-    t.ix = tx * TILE + (int)(threadIdx.x % TILE);
-    t.iy = ty * TILE + (int)(threadIdx.x / TILE);
-    const int W = a.L.width[t.view], H = a.L.height[t.view];
-    t.inside = t.ix < W && t.iy < H;
-    t.pix = a.L.pixel_base[t.view] + (int64_t)t.iy * W + t.ix;
+    t.tx = lt % gx;
+    t.ty = lt / gx;
+    t.W = a.L.width[t.view];
+    t.H = a.L.height[t.view];
+    t.pix_base = a.L.pixel_base[t.view];
     t.range = a.ranges[gt];
     return t;
 }
@@ -131,9 +142,9 @@ GS_DEV TilePix tile_pixel(const RasterArgs& a, int gt) {
 // forward
 // ---------------------------------------------------------------------------
 
-template <int TILE, int S>
-__global__ __launch_bounds__(TILE* TILE) void k_raster_fwd(RasterArgs a) {
-    constexpr int NT = TILE * TILE;
+template <int TILE, int S, int PPT_, bool STATS>
+__global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_fwd(RasterArgs a) {
+    constexpr int PPT = PPT_, NT = Geo<TILE, PPT_>::NT;
     __shared__ float4 s_g[S];
     __shared__ float4 s_h[S];
     __shared__ float s_b[S];
@@ -143,66 +154,96 @@ __global__ __launch_bounds__(TILE* TILE) void k_raster_fwd(RasterArgs a) {
         const int gt = next_tile(a, &s_tile);
         if (gt == -1 || (gt == -2 && a.counter == nullptr)) break;
         if (gt == -2) continue;
-        const TilePix tp = tile_pixel<TILE>(a, gt);
-        const float px = (float)tp.ix + 0.5f, py = (float)tp.iy + 0.5f;
-        const uint32_t start = tp.range.x, end = tp.range.y;
-        float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-        uint32_t last = 0, examined = 0, composited = 0;
-        bool active = tp.inside;
-        if (threadIdx.x == 0) { s_max = 0; s_sum = 0; s_comp = 0; }
+        const TileInfo ti = tile_info(a, gt);
+        const uint32_t start = ti.range.x, end = ti.range.y;
+        float px[PPT], py[PPT], T[PPT], C0[PPT], C1[PPT], C2[PPT];
+        uint32_t last[PPT], examined[PPT], composited[PPT];
+        bool active[PPT], inside[PPT];
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            const int p = (int)threadIdx.x + q * NT;
+            const int ix = ti.tx * TILE + p % TILE, iy = ti.ty * TILE + p / TILE;
+            px[q] = (float)ix + 0.5f;
+            py[q] = (float)iy + 0.5f;
+            inside[q] = ix < ti.W && iy < ti.H;
+            active[q] = inside[q];
+            T[q] = 1.0f; C0[q] = 0.0f; C1[q] = 0.0f; C2[q] = 0.0f;
+            last[q] = 0; examined[q] = 0; composited[q] = 0;
+        }
+        if (STATS && threadIdx.x == 0) { s_max = 0; s_sum = 0; s_comp = 0; }
         for (uint32_t b0 = start; b0 < end; b0 += S) {
-            if (__syncthreads_count(active) == 0) break;
+            bool any = false;
+#pragma unroll
+            for (int q = 0; q < PPT; ++q) any = any || active[q];
+            if (__syncthreads_count(any) == 0) break;
             for (int i = threadIdx.x; i < S; i += NT) {
                 const uint32_t j = b0 + i;
                 if (j < end) {
                     uint32_t gid;
-                    stage_splat(a, tp.view, j, s_g[i], s_h[i], s_b[i], gid);
+                    stage_splat(a, ti.view, j, s_g[i], s_h[i], s_b[i], gid);
                 }
             }
             __syncthreads();
-            // branch-free inner loop: every lane evaluates every staged Gaussian and
-            // the decisions select what is accumulated; a wavefront whose lanes
-            // have all stopped leaves the batch
-            if (__ballot(active) != 0ull) {
+            // branch-free inner loop: every lane evaluates every staged Gaussian
+            // for each of its pixels and the decisions select what accumulates;
+            // a wavefront whose pixels have all stopped leaves the batch
+            if (__ballot(any) != 0ull) {
                 const int cnt = (int)min((uint32_t)S, end - b0);
                 const uint32_t base = b0 - start + 1u;
                 for (int k = 0; k < cnt; ++k) {
                     const float4 sg = s_g[k];
                     const float4 sh = s_h[k];
                     const float cb = s_b[k];
-                    float dx, dy, G, ag;
-                    const bool inside = eval_pair(px, py, sg, sh, dx, dy, G, ag);
-                    const float alpha = fminf(kAlphaMax, ag);
-                    const bool ok = active && inside && alpha >= kAlphaMin;
-                    const float test_T = T * (1.0f - alpha);
-                    const bool stop = ok && test_T < kTMin;
-                    const bool comp = ok && !stop;
-                    examined += active ? 1u : 0u;
-                    active = active && !stop;
-                    const float w = comp ? alpha * T : 0.0f;
-                    C0 = __builtin_fmaf(w, sh.z, C0);
-                    C1 = __builtin_fmaf(w, sh.w, C1);
-                    C2 = __builtin_fmaf(w, cb, C2);
-                    T = comp ? test_T : T;
-                    last = comp ? base + (uint32_t)k : last;
-                    composited += comp ? 1u : 0u;
-                    if (__ballot(active) == 0ull) break;
+                    bool still = false;
+#pragma unroll
+                    for (int q = 0; q < PPT; ++q) {
+                        float dx, dy, G, ag;
+                        const bool in = eval_pair(px[q], py[q], sg, sh, dx, dy, G, ag);
+                        const float alpha = fminf(kAlphaMax, ag);
+                        const bool ok = active[q] && in && alpha >= kAlphaMin;
+                        const float test_T = T[q] * (1.0f - alpha);
+                        const bool stop = ok && test_T < kTMin;
+                        const bool comp = ok && !stop;
+                        if (STATS) examined[q] += active[q] ? 1u : 0u;
+                        active[q] = active[q] && !stop;
+                        const float w = comp ? alpha * T[q] : 0.0f;
+                        C0[q] = __builtin_fmaf(w, sh.z, C0[q]);
+                        C1[q] = __builtin_fmaf(w, sh.w, C1[q]);
+                        C2[q] = __builtin_fmaf(w, cb, C2[q]);
+                        T[q] = comp ? test_T : T[q];
+                        last[q] = comp ? base + (uint32_t)k : last[q];
+                        if (STATS) composited[q] += comp ? 1u : 0u;
+                        still = still || active[q];
+                    }
+                    if (__ballot(still) == 0ull) break;
                 }
             }
         }
-        if (tp.inside) {
-            const float* bg = a.views[tp.view].bg;
-            a.out_rgb[3 * tp.pix + 0] = __builtin_fmaf(T, bg[0], C0);
-            a.out_rgb[3 * tp.pix + 1] = __builtin_fmaf(T, bg[1], C1);
-            a.out_rgb[3 * tp.pix + 2] = __builtin_fmaf(T, bg[2], C2);
-            a.out_T[tp.pix] = T;
-            a.out_last[tp.pix] = last;
+        const float* bg = a.views[ti.view].bg;
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            if (!inside[q]) continue;
+            const int p = (int)threadIdx.x + q * NT;
+            const int64_t pix = ti.pix_base + (int64_t)(ti.ty * TILE + p / TILE) * ti.W +
+                                ti.tx * TILE + p % TILE;
+            a.out_rgb[3 * pix + 0] = __builtin_fmaf(T[q], bg[0], C0[q]);
+            a.out_rgb[3 * pix + 1] = __builtin_fmaf(T[q], bg[1], C1[q]);
+            a.out_rgb[3 * pix + 2] = __builtin_fmaf(T[q], bg[2], C2[q]);
+            a.out_T[pix] = T[q];
+            a.out_last[pix] = last[q];
         }
-        if (a.tile_stats) {
+        if (STATS) {
+            uint32_t mx = 0, sm = 0, cp = 0;
+#pragma unroll
+            for (int q = 0; q < PPT; ++q) {
+                mx = max(mx, examined[q]);
+                sm += examined[q];
+                cp += composited[q];
+            }
             __syncthreads();
-            atomicMax(&s_max, examined);
-            atomicAdd(&s_sum, examined);
-            atomicAdd(&s_comp, composited);
+            atomicMax(&s_max, mx);
+            atomicAdd(&s_sum, sm);
+            atomicAdd(&s_comp, cp);
             __syncthreads();
             if (threadIdx.x == 0) {
                 a.tile_stats[4 * (int64_t)gt + 0] = s_max;
@@ -235,18 +276,13 @@ GS_DEV float wave_sum_to_last(float v) {
     return v;
 }
 
-GS_DEV float lane63(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
-}
-
 // ---------------------------------------------------------------------------
 // backward
 // ---------------------------------------------------------------------------
 
-template <int TILE, int S>
-__global__ __launch_bounds__(TILE* TILE) void k_raster_bwd(RasterArgs a) {
-    constexpr int NT = TILE * TILE;
-    constexpr int NW = NT / kWave;
+template <int TILE, int S, int PPT_>
+__global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd(RasterArgs a) {
+    constexpr int PPT = PPT_, NT = Geo<TILE, PPT_>::NT, NW = Geo<TILE, PPT_>::NW;
     constexpr int SUB = 64;  // Gaussians per reduction sub-batch
     __shared__ float4 s_g[S];
     __shared__ float4 s_h[S];
@@ -262,53 +298,66 @@ __global__ __launch_bounds__(TILE* TILE) void k_raster_bwd(RasterArgs a) {
         const int gt = next_tile(a, &s_tile);
         if (gt == -1 || (gt == -2 && a.counter == nullptr)) break;
         if (gt == -2) continue;
-        const TilePix tp = tile_pixel<TILE>(a, gt);
-        const float px = (float)tp.ix + 0.5f, py = (float)tp.iy + 0.5f;
-        const uint32_t start = tp.range.x;
-        float Co0 = 0, Co1 = 0, Co2 = 0, g0 = 0, g1 = 0, g2 = 0, l1 = 0;
-        uint32_t lastp = 0;
-        if (tp.inside) {
-            Co0 = a.out_rgb[3 * tp.pix + 0];
-            Co1 = a.out_rgb[3 * tp.pix + 1];
-            Co2 = a.out_rgb[3 * tp.pix + 2];
-            lastp = a.out_last[tp.pix];
-            if (a.target) {
-                const float d0 = Co0 - a.target[3 * tp.pix + 0];
-                const float d1 = Co1 - a.target[3 * tp.pix + 1];
-                const float d2 = Co2 - a.target[3 * tp.pix + 2];
-                g0 = d0 > 0.0f ? a.inv_count : (d0 < 0.0f ? -a.inv_count : 0.0f);
-                g1 = d1 > 0.0f ? a.inv_count : (d1 < 0.0f ? -a.inv_count : 0.0f);
-                g2 = d2 > 0.0f ? a.inv_count : (d2 < 0.0f ? -a.inv_count : 0.0f);
-                l1 = (fabsf(d0) + fabsf(d1)) + fabsf(d2);
-            } else {
-                g0 = a.dLdC[3 * tp.pix + 0];
-                g1 = a.dLdC[3 * tp.pix + 1];
-                g2 = a.dLdC[3 * tp.pix + 2];
+        const TileInfo ti = tile_info(a, gt);
+        const uint32_t start = ti.range.x;
+        float px[PPT], py[PPT], Co0[PPT], Co1[PPT], Co2[PPT], g0[PPT], g1[PPT], g2[PPT];
+        float T[PPT], Ca0[PPT], Ca1[PPT], Ca2[PPT];
+        uint32_t lastp[PPT];
+        float l1 = 0.0f;
+        uint32_t mylen = 0;
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            const int p = (int)threadIdx.x + q * NT;
+            const int ix = ti.tx * TILE + p % TILE, iy = ti.ty * TILE + p / TILE;
+            px[q] = (float)ix + 0.5f;
+            py[q] = (float)iy + 0.5f;
+            Co0[q] = Co1[q] = Co2[q] = g0[q] = g1[q] = g2[q] = 0.0f;
+            T[q] = 1.0f; Ca0[q] = Ca1[q] = Ca2[q] = 0.0f;
+            lastp[q] = 0;
+            if (ix < ti.W && iy < ti.H) {
+                const int64_t pix = ti.pix_base + (int64_t)iy * ti.W + ix;
+                Co0[q] = a.out_rgb[3 * pix + 0];
+                Co1[q] = a.out_rgb[3 * pix + 1];
+                Co2[q] = a.out_rgb[3 * pix + 2];
+                lastp[q] = a.out_last[pix];
+                if (a.target) {
+                    const float d0 = Co0[q] - a.target[3 * pix + 0];
+                    const float d1 = Co1[q] - a.target[3 * pix + 1];
+                    const float d2 = Co2[q] - a.target[3 * pix + 2];
+                    g0[q] = d0 > 0.0f ? a.inv_count : (d0 < 0.0f ? -a.inv_count : 0.0f);
+                    g1[q] = d1 > 0.0f ? a.inv_count : (d1 < 0.0f ? -a.inv_count : 0.0f);
+                    g2[q] = d2 > 0.0f ? a.inv_count : (d2 < 0.0f ? -a.inv_count : 0.0f);
+                    l1 += (fabsf(d0) + fabsf(d1)) + fabsf(d2);
+                } else {
+                    g0[q] = a.dLdC[3 * pix + 0];
+                    g1[q] = a.dLdC[3 * pix + 1];
+                    g2[q] = a.dLdC[3 * pix + 2];
+                }
             }
+            mylen = max(mylen, lastp[q]);
         }
         __syncthreads();
         if (threadIdx.x == 0) s_len = 0;
         if (a.loss) {
             // per-tile L1 sum, fixed-order reduction
-            float s = l1;
-            for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-            if (lane == 0) s_loss[w] = s;
+            float sl = l1;
+            for (int off = 32; off > 0; off >>= 1) sl += __shfl_xor(sl, off);
+            if (lane == 0) s_loss[w] = sl;
         }
         __syncthreads();
-        atomicMax(&s_len, lastp);
+        atomicMax(&s_len, mylen);
         if (a.loss && threadIdx.x == 0) {
-            float s = 0.0f;
-            for (int i = 0; i < NW; ++i) s += s_loss[i];
-            a.loss[gt] = s;
+            float sl = 0.0f;
+            for (int i = 0; i < NW; ++i) sl += s_loss[i];
+            a.loss[gt] = sl;
         }
         __syncthreads();
         const uint32_t stop = start + s_len;
-        float T = 1.0f, Ca0 = 0.0f, Ca1 = 0.0f, Ca2 = 0.0f;
         for (uint32_t b0 = start; b0 < stop; b0 += S) {
             __syncthreads();
             for (int i = threadIdx.x; i < S; i += NT) {
                 const uint32_t j = b0 + i;
-                if (j < stop) stage_splat(a, tp.view, j, s_g[i], s_h[i], s_b[i], s_gid[i]);
+                if (j < stop) stage_splat(a, ti.view, j, s_g[i], s_h[i], s_b[i], s_gid[i]);
             }
             __syncthreads();
             const int cnt = (int)min((uint32_t)S, stop - b0);
@@ -321,32 +370,50 @@ __global__ __launch_bounds__(TILE* TILE) void k_raster_bwd(RasterArgs a) {
                     const float4 sg = s_g[k];
                     const float4 sh = s_h[k];
                     const float cb = s_b[k];
-                    float dx, dy, G, ag;
-                    const bool inside = eval_pair(px, py, sg, sh, dx, dy, G, ag);
-                    const float alpha = fminf(kAlphaMax, ag);
-                    const bool contrib = pos < lastp && inside && alpha >= kAlphaMin;
-                    if (__ballot(contrib) == 0ull) continue;
-                    // lanes that do not composite this Gaussian select zeros
-                    const float wgt = contrib ? alpha * T : 0.0f;
-                    float v6 = wgt * g0;
-                    float v7 = wgt * g1;
-                    float v8 = wgt * g2;
-                    Ca0 = __builtin_fmaf(wgt, sh.z, Ca0);
-                    Ca1 = __builtin_fmaf(wgt, sh.w, Ca1);
-                    Ca2 = __builtin_fmaf(wgt, cb, Ca2);
-                    const float gc = __builtin_fmaf(g2, cb, __builtin_fmaf(g1, sh.w, g0 * sh.z));
-                    const float gS = __builtin_fmaf(g2, Co2 - Ca2,
-                                                    __builtin_fmaf(g1, Co1 - Ca1, g0 * (Co0 - Ca0)));
-                    const float one_m = 1.0f - alpha;
-                    const float dalpha = T * gc - gS / one_m;
-                    const float dpow = (contrib && !(ag > kAlphaMax)) ? alpha * dalpha : 0.0f;
-                    float v0 = dpow;
-                    float v1 = dpow * dx;
-                    float v2 = dpow * dy;
-                    float v3 = v1 * dx;
-                    float v4 = v1 * dy;
-                    float v5 = v2 * dy;
-                    T = contrib ? T * one_m : T;
+                    // evaluate the pixels first; a wavefront none of whose pixels
+                    // composite this Gaussian skips the gradient terms entirely
+                    float dxq[PPT], dyq[PPT], agq[PPT], alq[PPT];
+                    bool cq[PPT];
+                    bool any = false;
+#pragma unroll
+                    for (int q = 0; q < PPT; ++q) {
+                        float G;
+                        const bool in = eval_pair(px[q], py[q], sg, sh, dxq[q], dyq[q], G, agq[q]);
+                        alq[q] = fminf(kAlphaMax, agq[q]);
+                        cq[q] = pos < lastp[q] && in && alq[q] >= kAlphaMin;
+                        any = any || cq[q];
+                    }
+                    if (__ballot(any) == 0ull) continue;
+                    float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f, v4 = 0.f, v5 = 0.f, v6 = 0.f,
+                          v7 = 0.f, v8 = 0.f;
+#pragma unroll
+                    for (int q = 0; q < PPT; ++q) {
+                        const bool contrib = cq[q];
+                        const float alpha = alq[q], dx = dxq[q], dy = dyq[q];
+                        // pixels that do not composite this Gaussian select zeros
+                        const float wgt = contrib ? alpha * T[q] : 0.0f;
+                        v6 = __builtin_fmaf(wgt, g0[q], v6);
+                        v7 = __builtin_fmaf(wgt, g1[q], v7);
+                        v8 = __builtin_fmaf(wgt, g2[q], v8);
+                        Ca0[q] = __builtin_fmaf(wgt, sh.z, Ca0[q]);
+                        Ca1[q] = __builtin_fmaf(wgt, sh.w, Ca1[q]);
+                        Ca2[q] = __builtin_fmaf(wgt, cb, Ca2[q]);
+                        const float gc = __builtin_fmaf(g2[q], cb, __builtin_fmaf(g1[q], sh.w, g0[q] * sh.z));
+                        const float gS = __builtin_fmaf(g2[q], Co2[q] - Ca2[q],
+                                                        __builtin_fmaf(g1[q], Co1[q] - Ca1[q],
+                                                                       g0[q] * (Co0[q] - Ca0[q])));
+                        const float one_m = 1.0f - alpha;
+                        const float dalpha = T[q] * gc - gS / one_m;
+                        const float dpow = (contrib && !(agq[q] > kAlphaMax)) ? alpha * dalpha : 0.0f;
+                        const float ddx = dpow * dx, ddy = dpow * dy;
+                        v0 += dpow;
+                        v1 += ddx;
+                        v2 += ddy;
+                        v3 = __builtin_fmaf(ddx, dx, v3);
+                        v4 = __builtin_fmaf(ddx, dy, v4);
+                        v5 = __builtin_fmaf(ddy, dy, v5);
+                        T[q] = contrib ? T[q] * one_m : T[q];
+                    }
                     v0 = wave_sum_to_last(v0);
                     v1 = wave_sum_to_last(v1);
                     v2 = wave_sum_to_last(v2);
@@ -365,24 +432,23 @@ __global__ __launch_bounds__(TILE* TILE) void k_raster_bwd(RasterArgs a) {
                 }
                 if (lane == 0) s_mask[w] = used;
                 __syncthreads();
-                if ((int)threadIdx.x < scnt) {
-                    const int kk = threadIdx.x;
+                for (int kk = threadIdx.x; kk < scnt; kk += NT) {
                     float r0 = 0, r1 = 0, r2 = 0, r3 = 0, r4 = 0, r5 = 0, r6 = 0, r7 = 0, r8 = 0;
-                    bool any = false;
+                    bool anyw = false;
                     for (int ww = 0; ww < NW; ++ww) {
                         if ((s_mask[ww] >> kk) & 1ull) {
-                            any = true;
+                            anyw = true;
                             const float* q = s_red[ww][kk];
                             r0 += q[0]; r1 += q[1]; r2 += q[2]; r3 += q[3]; r4 += q[4];
                             r5 += q[5]; r6 += q[6]; r7 += q[7]; r8 += q[8];
                         }
                     }
                     float4* rec = a.grec + 3 * (int64_t)(b0 + (uint32_t)(sub + kk));
-                    if (any) {
+                    if (anyw) {
                         // conic and opacity of this Gaussian, unscaled
-                        const float4* r = a.rec + 4 * ((int64_t)tp.view * a.n + s_gid[sub + kk]);
-                        const float4 q0 = r[0];
-                        const float4 q1 = r[1];
+                        const float4* rr = a.rec + 4 * ((int64_t)ti.view * a.n + s_gid[sub + kk]);
+                        const float4 q0 = rr[0];
+                        const float4 q1 = rr[1];
                         const float A = q0.z, B = q0.w, C = q1.x, op = q1.y;
                         const float du = A * r1 + B * r2;
                         const float dv = B * r1 + C * r2;
@@ -407,22 +473,26 @@ __global__ __launch_bounds__(TILE* TILE) void k_raster_bwd(RasterArgs a) {
 // launchers
 // ---------------------------------------------------------------------------
 
-template <int TILE, int S>
+template <int TILE, int S, int PPT>
 static void launch_fwd_t(const RasterArgs& a, unsigned grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_raster_fwd<TILE, S>), dim3(grid), dim3(TILE * TILE), 0, s, a);
+    constexpr int NT = Geo<TILE, PPT>::NT;
+    if (a.tile_stats)
+        hipLaunchKernelGGL((k_raster_fwd<TILE, S, PPT, true>), dim3(grid), dim3(NT), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_raster_fwd<TILE, S, PPT, false>), dim3(grid), dim3(NT), 0, s, a);
 }
-template <int TILE, int S>
+template <int TILE, int S, int PPT>
 static void launch_bwd_t(const RasterArgs& a, unsigned grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_raster_bwd<TILE, S>), dim3(grid), dim3(TILE * TILE), 0, s, a);
+    hipLaunchKernelGGL((k_raster_bwd<TILE, S, PPT>), dim3(grid), dim3(Geo<TILE, PPT>::NT), 0, s, a);
 }
 
-template <bool FWD, int TILE>
+template <bool FWD, int TILE, int PPT>
 static int dispatch_s(const RasterArgs& a, int S, unsigned grid, hipStream_t s) {
     switch (S) {
-        case 32: FWD ? launch_fwd_t<TILE, 32>(a, grid, s) : launch_bwd_t<TILE, 32>(a, grid, s); break;
-        case 64: FWD ? launch_fwd_t<TILE, 64>(a, grid, s) : launch_bwd_t<TILE, 64>(a, grid, s); break;
-        case 128: FWD ? launch_fwd_t<TILE, 128>(a, grid, s) : launch_bwd_t<TILE, 128>(a, grid, s); break;
-        case 256: FWD ? launch_fwd_t<TILE, 256>(a, grid, s) : launch_bwd_t<TILE, 256>(a, grid, s); break;
+        case 32: FWD ? launch_fwd_t<TILE, 32, PPT>(a, grid, s) : launch_bwd_t<TILE, 32, PPT>(a, grid, s); break;
+        case 64: FWD ? launch_fwd_t<TILE, 64, PPT>(a, grid, s) : launch_bwd_t<TILE, 64, PPT>(a, grid, s); break;
+        case 128: FWD ? launch_fwd_t<TILE, 128, PPT>(a, grid, s) : launch_bwd_t<TILE, 128, PPT>(a, grid, s); break;
+        case 256: FWD ? launch_fwd_t<TILE, 256, PPT>(a, grid, s) : launch_bwd_t<TILE, 256, PPT>(a, grid, s); break;
         default: set_error("lds_batch must be 32, 64, 128 or 256 (got %d)", S); return GS_ERR_INVALID_ARG;
     }
     return check_launch(FWD ? "rasterize_fwd" : "rasterize_bwd");
@@ -430,10 +500,17 @@ static int dispatch_s(const RasterArgs& a, int S, unsigned grid, hipStream_t s) 
 
 template <bool FWD>
 static int dispatch(const RasterArgs& a, int S, unsigned grid, hipStream_t s) {
+    const int ppt = a.L.pixels_per_lane;
     switch (a.L.tile) {
-        case 8: return dispatch_s<FWD, 8>(a, S, grid, s);
-        case 16: return dispatch_s<FWD, 16>(a, S, grid, s);
-        case 32: return dispatch_s<FWD, 32>(a, S, grid, s);
+        case 8: return dispatch_s<FWD, 8, 1>(a, S, grid, s);
+        case 16:
+            return ppt == 1 ? dispatch_s<FWD, 16, 1>(a, S, grid, s)
+                 : ppt == 2 ? dispatch_s<FWD, 16, 2>(a, S, grid, s)
+                            : dispatch_s<FWD, 16, 4>(a, S, grid, s);
+        case 32:
+            return ppt == 1 ? dispatch_s<FWD, 32, 1>(a, S, grid, s)
+                 : ppt == 2 ? dispatch_s<FWD, 32, 2>(a, S, grid, s)
+                            : dispatch_s<FWD, 32, 4>(a, S, grid, s);
         default: set_error("tile must be 8, 16 or 32"); return GS_ERR_INVALID_ARG;
     }
 }

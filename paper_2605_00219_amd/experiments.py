@@ -1,0 +1,212 @@
+"""Benchmark drivers for the batched (several uneven views per step) and the
+learned-schedule variants.  All work runs through the C ABI; these functions
+only arrange buffers, iterations and timing."""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import torch
+
+from . import pipeline as P
+from .autotune import autotune, capacity_for
+from .batched import BatchedStep, ViewSet
+from . import schedule as SC
+
+
+def _render_targets(target_params, n, resolutions, tile, views_per_step):
+    """GPU-rendered target images, one concatenated [pixels, 3] tensor per step."""
+    out = []
+    f = None
+    for vd in views_per_step:
+        if f is None:
+            f = P.Frame(n, [w for w, _ in resolutions], [h for _, h in resolutions], tile)
+        P.fit_capacity(target_params, f, vd)
+        out.append(P.render(target_params, f, vd).clone())
+    del f
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_batched(workload, make_views, steps: int = 200, plain_steps: int = 25, log=print,
+                tune_iters=3, cache_path=None) -> dict:
+    """Batched + persistent + graph + autotuned step vs plain single-view steps."""
+    w = workload
+    res = w.extra["resolutions"]
+    n = w.scene.n
+    period = 25
+    vrows = [P.views_to_device(make_views(i)) for i in range(period)]
+    log(f"batched: rendering {period} target sets")
+    tparams = P.pack_flat(w.target_scene.flat())
+    targets = _render_targets(tparams, n, res, 16, vrows)
+    del tparams
+    model = P.Model(w.scene.flat(), lr=w.lr)
+    view_rows = lambda i: vrows[i % period]
+    tgt = lambda i: targets[i % period]
+    log("batched: autotuning tile edge and LDS batch")
+    tune = autotune(model, n, res, view_rows, tgt, list(range(tune_iters)), cache_path=cache_path,
+                    log=log)
+    T, S, ppl = tune["tile"], tune["lds_batch"], tune.get("pixels_per_lane")
+    cap = capacity_for(model, n, ViewSet(res, T), view_rows, list(range(period)))
+    step = BatchedStep(model, n, ViewSet(res, T, ppl), cap, lds_batch=S, persistent=True)
+    step.load(view_rows(0), tgt(0))
+    step.capture()
+    for i in range(3):                       # warm replays
+        step.load(view_rows(i), tgt(i))
+        step.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step.load(view_rows(i), tgt(i))
+        step.run()
+    torch.cuda.synchronize()
+    dt_b = (time.perf_counter() - t0) / steps
+    status = step.status()
+    del step
+    torch.cuda.empty_cache()
+    # plain: each view its own single-view step (one workgroup per tile, T = 16, S = 64)
+    frames = [P.Frame(n, [wd], [ht], 16) for wd, ht in res]
+    for k, f in enumerate(frames):
+        kmax = 0
+        for i in range(period):
+            kmax = max(kmax, P.fit_capacity(model.params, f, view_rows(i)[128 * k:128 * (k + 1)]))
+        f.resize(int(kmax * 1.15) + 4096)
+    pix_base = np.cumsum([0] + [wd * ht for wd, ht in res])
+
+    def plain_iter(i):
+        vr = view_rows(i)
+        for k, f in enumerate(frames):
+            vd = vr[128 * k:128 * (k + 1)]
+            P.train_step(model, f, vd, tgt(i)[pix_base[k]:pix_base[k + 1]], check=False)
+
+    plain_iter(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(plain_steps):
+        plain_iter(i)
+    torch.cuda.synchronize()
+    dt_p = (time.perf_counter() - t0) / plain_steps
+    st_p = max(f.status_bits() for f in frames)
+    del frames
+    torch.cuda.empty_cache()
+    V = len(res)
+    mpix = sum(wd * ht for wd, ht in res) / 1e6
+    return {
+        "workload": w.name, "gaussians": n, "views_per_step": V,
+        "resolutions": [f"{wd}x{ht}" for wd, ht in res],
+        "autotune": {k: v for k, v in tune.items() if k != "cached"},
+        "batched": {"iters_per_s": 1.0 / dt_b, "ms_per_step": 1e3 * dt_b, "views_per_s": V / dt_b,
+                    "mpix_per_s": mpix / dt_b, "steps": steps, "tile": T, "lds_batch": S,
+                    "pixels_per_lane": ppl,
+                    "graph": True, "persistent": True, "status": status},
+        "plain": {"iters_per_s": 1.0 / dt_p, "ms_per_step": 1e3 * dt_p, "views_per_s": V / dt_p,
+                  "mpix_per_s": mpix / dt_p, "steps": plain_steps, "tile": 16, "lds_batch": 64,
+                  "note": "8 sequential single-view steps per iteration", "status": st_p},
+        "speedup_views_per_s": dt_p / dt_b,
+    }
+
+
+def collect_cost_data(scenes_views, tile=16, log=print):
+    """Per-tile features and log(1 + traversal) targets from forward passes."""
+    X, Y = [], []
+    for scene, views in scenes_views:
+        n = scene.n
+        f = P.Frame(n, [int(v["width"]) for v in views], [int(v["height"]) for v in views], tile,
+                    tile_stats=True)
+        params = P.pack_flat(scene.flat())
+        vd = P.views_to_device(views)
+        P.render(params, f, vd)
+        X.append(SC.tile_features(f))
+        Y.append(SC.traversal_target(f))
+        del f, params
+    torch.cuda.empty_cache()
+    return torch.cat(X), torch.cat(Y)
+
+
+def run_learned(workload, train_sets, steps: int = 10, log=print, epochs: int = 400) -> dict:
+    """Persistent raster with static, list-length and learned tile orders.
+    Each order runs the same steps from the same optimiser state."""
+    w = workload
+    res = w.extra["resolutions"]
+    cams = w.extra["cameras"]
+    n = w.scene.n
+    V = len(res)
+    import synthetic as S
+    log("learned: collecting training data")
+    X, Y = collect_cost_data(train_sets, log=log)
+    cm = SC.CostModel(seed=0)
+    cm.set_normalisation(X)
+    perm = torch.randperm(X.shape[0], generator=torch.Generator().manual_seed(0)).cuda()
+    ntr = int(0.8 * X.shape[0])
+    tr, va = perm[:ntr], perm[ntr:]
+    t0 = time.perf_counter()
+    loss = cm.fit(X[tr].contiguous(), Y[tr].contiguous(), epochs=epochs, lr=3e-3)
+    t_train = time.perf_counter() - t0
+    q_val = SC.prediction_quality(cm.predict(X[va].contiguous()), Y[va])
+    log(f"learned: trained {epochs} epochs in {t_train:.2f}s, loss {loss:.4f}, held-out {q_val}")
+    views = [S.views_array([S.make_view(wd, ht, cams[(V * i + k) % len(cams)])
+                            for k, (wd, ht) in enumerate(res)]) for i in range(steps)]
+    vrows = [P.views_to_device(v) for v in views]
+    tparams = P.pack_flat(w.target_scene.flat())
+    targets = _render_targets(tparams, n, res, 16, vrows)
+    del tparams
+    model = P.Model(w.scene.flat(), lr=w.lr)
+    frame = P.Frame(n, [wd for wd, _ in res], [ht for _, ht in res], 16, tile_stats=False)
+    kmax = 0
+    for vd in vrows:
+        kmax = max(kmax, P.fit_capacity(model.params, frame, vd))
+    frame.resize(int(kmax * 1.1) + 4096)
+    saved = [t.clone() for t in (model.params, model.m, model.v, model.step)]
+    nt = frame.layout.total_tiles
+    results = {}
+    images = {}
+    for mode in ("static", "length", "learned"):
+        for t, s0 in zip((model.params, model.m, model.v, model.step), saved):
+            t.copy_(s0)
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            vd = vrows[i]
+            P.project(model.params, frame, vd)
+            P.bin_sort(frame)
+            ev[i][0].record()
+            if mode == "static":
+                order = None
+            else:
+                feats = SC.tile_features(frame)
+                pred = feats[:, 0].contiguous() if mode == "length" else cm.predict(feats)
+                order = SC.order_by_cost(pred)
+            sched = frame.schedule(order)
+            ev[i][1].record()
+            P.rasterize_fwd(frame, vd, 64, sched)
+            ev[i][2].record()
+            P.rasterize_bwd(frame, vd, target=targets[i], lds_batch=64, sched=sched)
+            ev[i][3].record()
+            P.project_bwd_adam(model, frame, vd)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        results[mode] = {
+            "iters_per_s": 1.0 / wall, "ms_per_step": 1e3 * wall,
+            "order_ms": float(np.mean([e[0].elapsed_time(e[1]) for e in ev])),
+            "raster_fwd_ms": float(np.mean([e[1].elapsed_time(e[2]) for e in ev])),
+            "raster_bwd_ms": float(np.mean([e[2].elapsed_time(e[3]) for e in ev])),
+        }
+        images[mode] = (frame.image.clone(), model.params.clone())
+        log(f"learned: {mode}: {results[mode]}")
+    same = all(torch.equal(images[m][0], images["static"][0]) and
+               torch.equal(images[m][1], images["static"][1]) for m in images)
+    # prediction quality on the benchmark scene's own tiles (never trained on)
+    fr = P.Frame(n, [wd for wd, _ in res], [ht for _, ht in res], 16, capacity=frame.capacity,
+                 tile_stats=True)
+    for t, s0 in zip((model.params,), saved[:1]):
+        t.copy_(s0)
+    P.render(model.params, fr, vrows[0])
+    q_bench = SC.prediction_quality(cm.predict(SC.tile_features(fr)), SC.traversal_target(fr))
+    del fr, frame
+    torch.cuda.empty_cache()
+    return {"workload": w.name, "gaussians": n, "views_per_step": V, "tiles_per_step": nt,
+            "steps": steps, "mlp": {"epochs": epochs, "train_s": t_train, "train_loss": loss,
+                                    "heldout": q_val, "bench_scene": q_bench},
+            "orders": results, "bitwise_identical": bool(same),
+            "speedup_learned_vs_static": results["static"]["ms_per_step"] / results["learned"]["ms_per_step"]}

@@ -64,10 +64,10 @@ class Frame:
     """Per-view-set buffers: projected splats, intersection lists, images."""
 
     def __init__(self, n: int, widths, heights, tile: int = 16, capacity: int = 1 << 16,
-                 device="cuda", tile_stats: bool = False):
+                 device="cuda", tile_stats: bool = False, pixels_per_lane: int | None = None):
         self.n = int(n)
         self.device = device
-        self.layout = G.layout_init(widths, heights, tile)
+        self.layout = G.layout_init(widths, heights, tile, pixels_per_lane)
         self.n_views = len(widths)
         self.tile = tile
         V, n = self.n_views, self.n

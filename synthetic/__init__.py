@@ -242,30 +242,35 @@ BATCH_RESOLUTIONS = [(640, 480), (800, 600), (1024, 768), (1280, 720), (1280, 72
 
 def workload_batched(n: int = 3_000_000, resolutions=None, steps: int = 200,
                      seed_base: int = 4000) -> Workload:
-    """Config-2 distributions; 8 views of uneven resolution per launch; views
-    of step i use cameras (8i + k) mod 50."""
+    """300k-workload distributions at 3M Gaussians; 8 views of uneven
+    resolution per step; slot k of step i holds camera (8i + k) mod 50 at the
+    slot's resolution (`batched_views`)."""
     res = resolutions or BATCH_RESOLUTIONS
     scene = scene_normal(n, seed_base)
     target = scene_normal(n, seed_base + 1)
     cams = fibonacci_sphere(50, 5.0)
-    views = []
-    for i in range(50):
-        w, h = res[i % len(res)]
-        views.append(make_view(w, h, cams[i]))
     return Workload(f"batched-{n // 1000}k-{len(res)}views", scene, target,
-                    views_array(views), tile=16, steps=steps,
-                    extra={"resolutions": res})
+                    views_array([make_view(w, h, cams[k]) for k, (w, h) in enumerate(res)]),
+                    tile=16, steps=steps, extra={"resolutions": res, "cameras": cams})
+
+
+def batched_views(cams, resolutions, step: int) -> np.ndarray:
+    """Views of one step: camera (k*step + s) mod len(cams) in slot s."""
+    k = len(resolutions)
+    return views_array([make_view(w, h, cams[(k * step + s) % len(cams)])
+                        for s, (w, h) in enumerate(resolutions)])
 
 
 def workload_learned(n: int = 6_000_000, n_views: int = 4, width: int = 1920,
                      height: int = 1080, seed_base: int = 5000) -> Workload:
-    """Config-2 distributions, 4 x 1080p views per launch."""
+    """300k-workload distributions at 6M Gaussians, 4 x 1080p views per launch."""
     scene = scene_normal(n, seed_base)
     target = scene_normal(n, seed_base + 1)
     cams = fibonacci_sphere(50, 5.0)
-    views = views_array([make_view(width, height, c) for c in cams])
     return Workload(f"learned-{n // 1000}k-{n_views}x{width}x{height}", scene, target,
-                    views, tile=16, extra={"views_per_launch": n_views})
+                    views_array([make_view(width, height, c) for c in cams[:n_views]]), tile=16,
+                    extra={"views_per_launch": n_views, "cameras": cams,
+                           "resolutions": [(width, height)] * n_views})
 
 
 def random_image(height: int, width: int, seed: int) -> np.ndarray:

@@ -88,14 +88,14 @@ def test_autotune_picks_a_candidate_and_caches(setup, tmp_path):
     p0 = model.params.clone()
     cache = str(tmp_path / "autotune.json")
     res = AT.autotune(model, d["scene"].n, RES, lambda i: vrows[i], lambda i: tg[i], iters,
-                      cache_path=cache, tiles=(8, 16), batches=(32, 64), log=note)
+                      cache_path=cache, tiles=(8, 16), batches=(32, 64), lane_pixels=(2, 4), log=note)
     assert res["tile"] in (8, 16) and res["lds_batch"] in (32, 64) and not res["cached"]
-    assert len(res["table_ms"]) == 4 and all(np.isfinite(v) for v in res["table_ms"].values())
+    assert len(res["table_ms"]) == 6 and all(np.isfinite(v) for v in res["table_ms"].values())
     # optimiser state restored after tuning
     np.testing.assert_array_equal(model.params.cpu().numpy(), p0.cpu().numpy())
     assert int(model.step.item()) == 0
     again = AT.autotune(model, d["scene"].n, RES, lambda i: vrows[i], lambda i: tg[i], iters,
-                        cache_path=cache, tiles=(8, 16), batches=(32, 64), log=note)
+                        cache_path=cache, tiles=(8, 16), batches=(32, 64), lane_pixels=(2, 4), log=note)
     assert again["cached"] and again["tile"] == res["tile"]
     # a corrupt cache is ignored
     with open(cache, "w") as f:

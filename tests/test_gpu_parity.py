@@ -81,12 +81,12 @@ def test_projection_and_binning_bit_exact(name):
 
 
 @pytest.mark.parametrize("name", list(WL))
-@pytest.mark.parametrize("lds_batch", [32, 64, 256])
-def test_forward_pixels(name, lds_batch):
+@pytest.mark.parametrize("lds_batch,ppl", [(32, 4), (64, 1), (64, 2), (256, 4)])
+def test_forward_pixels(name, lds_batch, ppl):
     scene, target_scene, views, tile = WL[name]
-    note(f"forward parity {name} S={lds_batch}")
+    note(f"forward parity {name} S={lds_batch} pixels/lane={ppl}")
     ref = oracle.train_step(scene, views, tile, oracle.render(target_scene, views, tile), adam_step=False)
-    g = run_gpu_step(scene, views, tile, lds_batch=lds_batch)
+    g = run_gpu_step(scene, views, tile, lds_batch=lds_batch, pixels_per_lane=ppl)
     ok = ref.image.fragile == 0
     assert ok.mean() > 0.995, f"fragile fraction {1 - ok.mean():.4f}"
     err = np.abs(g["image"] - ref.image.rgb).max(axis=1)
@@ -98,11 +98,12 @@ def test_forward_pixels(name, lds_batch):
 
 
 @pytest.mark.parametrize("name", list(WL))
-def test_training_step(name):
+@pytest.mark.parametrize("ppl", [1, 2, 4])
+def test_training_step(name, ppl):
     scene, target_scene, views, tile = WL[name]
-    note(f"training-step parity {name}")
+    note(f"training-step parity {name} pixels/lane={ppl}")
     target, ref = _oracle_step(scene, target_scene, views, tile)
-    g = run_gpu_step(scene, views, tile, target=target)
+    g = run_gpu_step(scene, views, tile, target=target, pixels_per_lane=ppl)
     V, n = len(views), scene.n
     ex = exempt_gaussians(ref.bins.ranges, ref.bins.vals, ref.bins.gid, views, tile, ref.fragile, n)
     ex_any = ex.any(axis=0)
@@ -160,12 +161,12 @@ def test_persistent_and_permuted_schedules_change_no_bit():
             np.testing.assert_array_equal(base[k], other[k], err_msg=str(kw))
 
 
-@pytest.mark.parametrize("tile", [8, 32])
-def test_other_tile_sizes(tile):
+@pytest.mark.parametrize("tile,ppl", [(8, 1), (32, 1), (32, 2), (32, 4)])
+def test_other_tile_sizes(tile, ppl):
     scene, target_scene, views, _ = WL["ragged-2view"]
-    note(f"tile {tile}")
+    note(f"tile {tile} pixels/lane {ppl}")
     target, ref = _oracle_step(scene, target_scene, views, tile)
-    g = run_gpu_step(scene, views, tile, target=target, lds_batch=128)
+    g = run_gpu_step(scene, views, tile, target=target, lds_batch=128, pixels_per_lane=ppl)
     np.testing.assert_array_equal(g["keys"], ref.bins.keys)
     np.testing.assert_array_equal(g["ranges"], ref.bins.ranges)
     ok = ref.image.fragile == 0

@@ -113,9 +113,11 @@ typedef struct gs_splats {
                            (u, v, A, B)   mean in pixels, conic A, B
                            (C, o, r, g)   conic C, opacity, colour r, g
                            (b, z, radius, 0)  colour b, depth, radius in pixels
-                           (rect0, rect1, 0, 0) tile rectangle bits as uint32:
+                           (rect0, rect1, dcode, 0) uint32 bits:
                                rect0 = x0 | y0 << 16, rect1 = x1 | y1 << 16,
-                               tiles [x0, x1) x [y0, y1)
+                               tiles [x0, x1) x [y0, y1);
+                               dcode = the 23 mantissa bits of the float32
+                               (2z + 1) / (z + 1) (the depth part of the keys)
                          colour is after the +0.5 shift and the clamp at 0;
                          entries of culled Gaussians are all zero */
     uint32_t* tiles;  /* tiles touched, 0 for culled Gaussians */
@@ -129,21 +131,29 @@ typedef struct gs_bins {
     uint32_t* offsets;   /* n_views*n + 1: exclusive scan of tiles; [n_views*n] = K */
     uint32_t* keys;      /* capacity: (tile << D) | depth bits, sorted per view */
     uint32_t* vals;      /* capacity: Gaussian id of each sorted key */
-    uint32_t* inv;       /* capacity: sorted position of each unsorted index */
     uint32_t* ranges;    /* 2 * total tiles: [start, end) of each tile in sorted order */
     uint32_t* status;    /* 1 word, device status bits (GS_STATUS_*), cleared by gs_bin_sort */
-    int64_t capacity;    /* entries in keys / vals / inv and records in gs_grads2d */
+    int64_t capacity;    /* entries in keys / vals and records in gs_grads2d */
 } gs_bins;
 
 /* Screen-space gradients written by gs_rasterize_bwd and read by
  * gs_project_bwd_adam: one record per intersection that the backward
- * traversed, at its sorted position. */
+ * traversed, at its unsorted index, so that each (view, Gaussian) finds its
+ * records in its own contiguous index range.  Which intersections were
+ * traversed follows from the tile's stop entry: the sorted order within a
+ * tile is ascending (key, unsorted index), and the traversal covers exactly
+ * the entries before the first one it did not reach. */
 typedef struct gs_grads2d {
     float* rec;           /* capacity records of 12 floats: (d u, d v, d A, d B, d C,
-                             d opacity, d r, d g, d b, 0, 0, 0) */
-    uint32_t* tile_stop;  /* total tiles: records exist at sorted positions
-                             [ranges[t].start, tile_stop[t]) of each tile t;
-                             the intersections after that contribute nothing */
+                             d opacity, d r, d g, d b, 0, 0, 0); records of entries
+                             not traversed are left as they were */
+    uint32_t* tile_stop;  /* 4 words per tile t: (stop, key, index, 0).  Entries at
+                             sorted positions [ranges[t].start, stop) were traversed;
+                             (key, index) are the key and unsorted index of the entry
+                             at `stop`, or (0xFFFFFFFF, 0xFFFFFFFF) if stop = end */
+    float* sums;          /* 9 planes of n_views * n floats, plane c at c * n_views * n:
+                             per (view, Gaussian) sum of its traversed records
+                             (components 0..8), written by gs_project_bwd_adam */
 } gs_grads2d;
 
 /* Rasterisation outputs, indexed by global pixel (views concatenated). */
@@ -218,8 +228,8 @@ int gs_project(const float* params, int64_t n, const gs_view* views, const gs_la
  * float32, value = g.  Keys of each view are sorted ascending by a stable LSD
  * radix sort (ties keep emission order), then ranges[t] =
  * [lower_bound(t << D), lower_bound((t+1) << D)) in the view's segment, as
- * global positions, and inv maps each unsorted index to its sorted position.
- * If K > capacity only the first `capacity`
+ * global positions.  Unsorted index of Gaussian g's entry for tile (tx, ty):
+ * offsets[v*n+g] + (ty - y0) * (x1 - x0) + (tx - x0).  If K > capacity only the first `capacity`
  * intersections are written and GS_STATUS_CAPACITY is set; the caller reads
  * offsets[V*n] to size a retry.
  *   workspace  device scratch of gs_bin_sort_workspace_size bytes */
@@ -247,8 +257,8 @@ int gs_rasterize_fwd(const gs_splats* splats, int64_t n, const gs_layout* layout
  * mean|C - target| over all channels of all pixels: g = sign(C - target) /
  * (3 * pixels).  Per-pixel contributions are summed over each tile with
  * wavefront reductions (no atomics) into one record per traversed
- * intersection (see gs_grads2d); a tile's traversal ends at the last entry any
- * of its pixels composited.
+ * intersection, written at its unsorted index (see gs_grads2d); a tile's
+ * traversal ends at the last entry any of its pixels composited.
  *   loss      nullable device, total tiles floats: per-tile sum |C - target|
  *             (only with `target`) */
 int gs_rasterize_bwd(const gs_splats* splats, int64_t n, const gs_layout* layout,
@@ -256,9 +266,9 @@ int gs_rasterize_bwd(const gs_splats* splats, int64_t n, const gs_layout* layout
                      const float* target, const float* dL_dC, const gs_grads2d* grads,
                      float* loss, int lds_batch, const gs_schedule* sched, void* stream);
 
-/* Projection backward fused with Adam (Sec. 4.3).  For each Gaussian, sums its
- * traversed intersection records of every view (in unsorted-index order, found
- * through bins->inv and grads->tile_stop), applies the
+/* Projection backward fused with Adam (Sec. 4.3).  First pass: for each
+ * (view, Gaussian), the sum of its traversed intersection records in
+ * unsorted-index order, into grads->sums.  Second pass, per Gaussian: applies the
  * chain rule back through colour (SH basis, clamp, view direction), opacity
  * (sigmoid), conic (inverse), 2D covariance (J R Sigma R^T J^T), the pinhole
  * Jacobian and mean projection, scales (exp) and the quaternion normalisation,
@@ -267,8 +277,8 @@ int gs_rasterize_bwd(const gs_splats* splats, int64_t n, const gs_layout* layout
  * gradients are also written there (parameter-block layout).  At least one of
  * adam, grads_out must be non-NULL. */
 int gs_project_bwd_adam(float* params, int64_t n, const gs_view* views, const gs_layout* layout,
-                        const gs_bins* bins, const gs_grads2d* grads, const gs_adam* adam,
-                        float* grads_out, void* stream);
+                        const gs_splats* splats, const gs_bins* bins, const gs_grads2d* grads,
+                        const gs_adam* adam, float* grads_out, void* stream);
 
 /* ---- learned tile schedule (per-tile cost model) --------------------------- */
 

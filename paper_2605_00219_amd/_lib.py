@@ -46,12 +46,11 @@ class GsSplats(C.Structure):
 
 class GsBins(C.Structure):
     _fields_ = [("offsets", C.c_void_p), ("keys", C.c_void_p), ("vals", C.c_void_p),
-                ("inv", C.c_void_p), ("ranges", C.c_void_p), ("status", C.c_void_p),
-                ("capacity", C.c_int64)]
+                ("ranges", C.c_void_p), ("status", C.c_void_p), ("capacity", C.c_int64)]
 
 
 class GsGrads2d(C.Structure):
-    _fields_ = [("rec", C.c_void_p), ("tile_stop", C.c_void_p)]
+    _fields_ = [("rec", C.c_void_p), ("tile_stop", C.c_void_p), ("sums", C.c_void_p)]
 
 
 class GsImage(C.Structure):
@@ -83,8 +82,9 @@ _SIGS = {
     "gs_rasterize_bwd": (C.c_int, [C.POINTER(GsSplats), C.c_int64, C.POINTER(GsLayout),
                                    C.POINTER(GsBins), _P, C.POINTER(GsImage), _P, _P,
                                    C.POINTER(GsGrads2d), _P, C.c_int, C.POINTER(GsSchedule), _P]),
-    "gs_project_bwd_adam": (C.c_int, [_P, C.c_int64, _P, C.POINTER(GsLayout), C.POINTER(GsBins),
-                                      C.POINTER(GsGrads2d), C.POINTER(GsAdam), _P, _P]),
+    "gs_project_bwd_adam": (C.c_int, [_P, C.c_int64, _P, C.POINTER(GsLayout), C.POINTER(GsSplats),
+                                      C.POINTER(GsBins), C.POINTER(GsGrads2d), C.POINTER(GsAdam),
+                                      _P, _P]),
     "gs_tile_features": (C.c_int, [C.POINTER(GsSplats), C.c_int64, C.POINTER(GsLayout),
                                    C.POINTER(GsBins), _P, _P]),
     "gs_mlp_forward": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P]),

@@ -1,7 +1,15 @@
-// Projection backward fused with Adam: one thread per Gaussian streams its
-// parameter record and both Adam moments once, gathers the screen-space
-// gradient records of the intersections the rasteriser traversed (through the
-// inverse sort permutation), and writes parameters and moments once.  No per-parameter gradient buffer exists
+// Projection backward fused with Adam, in two passes.
+//
+// Gather: per (view, Gaussian), the sum of the screen-space gradient records
+// of its traversed intersections.  The backward rasteriser wrote them at
+// their unsorted indices, so a Gaussian's records are one contiguous range;
+// whether an entry was traversed follows from its tile's stop entry (sorted
+// order within a tile is ascending (key, unsorted index)).  The sums go to a
+// dense [9][views * n] array.
+//
+// Chain rule + Adam: one thread per Gaussian streams its parameter record and
+// both Adam moments once, reads its per-view sums (coalesced), and writes
+// parameters and moments once.  No per-parameter gradient buffer exists
 // unless the caller asks for one (grads_out).  Log-scales and opacity logits
 // are optimised as stored: the chain rule through exp and the sigmoid is part
 // of this kernel.
@@ -13,6 +21,102 @@
 
 namespace gs {
 
+struct GatherArgs {
+    const float4* rec;
+    const uint32_t* offsets;
+    const uint4* stop;
+    const float4* grec;
+    int64_t n;
+    int64_t capacity;
+    int32_t gx[GS_MAX_VIEWS];
+    int32_t tile_base[GS_MAX_VIEWS];
+    int32_t depth_bits[GS_MAX_VIEWS];
+    int n_views;
+    float* sums;
+};
+
+constexpr int kGatherG = 256;   // (view, Gaussian) entries per workgroup = threads
+
+// A workgroup owns kGatherG consecutive (view, Gaussian) entries; their
+// intersections form the contiguous index range [offsets[o0], offsets[o0 +
+// kGatherG]), swept kGatherG indices at a time.  In each sweep thread t takes
+// index i = begin + t (coalesced record loads), finds its Gaussian by binary
+// search over the staged offsets, tests traversal against its tile's stop
+// entry and parks the record (or zeros) in LDS; then the thread owning each
+// Gaussian adds the slice of the sweep that belongs to it, in index order.
+// Long lists therefore cost one LDS pass per sweep instead of serialising
+// one thread on dependent global loads.  grid: ceil(views * n / kGatherG).
+__global__ __launch_bounds__(kGatherG) void k_gather2d(GatherArgs a) {
+    __shared__ uint32_t s_off[kGatherG + 1];
+    __shared__ uint32_t s_xy[kGatherG];
+    __shared__ uint32_t s_w[kGatherG];
+    __shared__ uint32_t s_key[kGatherG];   // depth code >> (23 - D)
+    __shared__ uint32_t s_view[kGatherG];
+    __shared__ float s_rec[kGatherG][9];
+    const int64_t vn = (int64_t)a.n_views * a.n;
+    const int64_t o0 = (int64_t)blockIdx.x * kGatherG;
+    const int t = threadIdx.x;
+    const int64_t o = o0 + t;
+    const int64_t oc = o < vn ? o : vn;
+    s_off[t] = (uint32_t)min((uint64_t)a.offsets[oc], (uint64_t)a.capacity);
+    if (t == 0) {
+        const int64_t oe = o0 + kGatherG < vn ? o0 + kGatherG : vn;
+        s_off[kGatherG] = (uint32_t)min((uint64_t)a.offsets[oe], (uint64_t)a.capacity);
+    }
+    s_xy[t] = 0u; s_w[t] = 1u; s_key[t] = 0u; s_view[t] = 0u;
+    if (o < vn && a.offsets[o + 1] > a.offsets[o]) {
+        const int v = (int)(o / a.n);
+        const float4 q3 = a.rec[4 * o + 3];
+        const uint32_t r0 = __float_as_uint(q3.x), r1 = __float_as_uint(q3.y);
+        s_xy[t] = r0;
+        s_w[t] = (r1 & 0xFFFF) - (r0 & 0xFFFF);
+        s_key[t] = __float_as_uint(q3.z) >> (23 - a.depth_bits[v]);
+        s_view[t] = (uint32_t)v;
+    }
+    __syncthreads();
+    float d[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const uint32_t begin = s_off[0], end = s_off[kGatherG];
+    const uint32_t my_b = s_off[t], my_e = s_off[t + 1];
+    for (uint32_t pb = begin; pb < end; pb += kGatherG) {
+        const uint32_t i = pb + (uint32_t)t;
+        float r[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (i < end) {
+            int lo = 0, hi = kGatherG - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_off[mid] <= i) lo = mid; else hi = mid - 1;
+            }
+            const uint32_t k = i - s_off[lo];
+            const uint32_t w = s_w[lo], xy = s_xy[lo];
+            const int v = (int)s_view[lo];
+            const uint32_t tile = ((xy >> 16) + k / w) * (uint32_t)a.gx[v] + (xy & 0xFFFF) + k % w;
+            const uint4 st = a.stop[a.tile_base[v] + (int)tile];
+            const uint32_t key = (tile << a.depth_bits[v]) | s_key[lo];
+            if (key < st.y || (key == st.y && i < st.z)) {
+                const float4* g = a.grec + 3 * (int64_t)i;
+                const float4 q0 = g[0], q1 = g[1], q2 = g[2];
+                r[0] = q0.x; r[1] = q0.y; r[2] = q0.z; r[3] = q0.w;
+                r[4] = q1.x; r[5] = q1.y; r[6] = q1.z; r[7] = q1.w; r[8] = q2.x;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 9; ++c) s_rec[t][c] = r[c];
+        __syncthreads();
+        const uint32_t pe = min(end, pb + (uint32_t)kGatherG);
+        const uint32_t sb = max(my_b, pb), se = min(my_e, pe);
+        for (uint32_t j = sb; j < se; ++j) {
+            const float* q = s_rec[j - pb];
+#pragma unroll
+            for (int c = 0; c < 9; ++c) d[c] += q[c];
+        }
+    }
+    if (o < vn) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) a.sums[c * vn + o] = d[c];
+    }
+}
+
 struct AdamArgs {
     float4* params;
     int64_t n;
@@ -20,12 +124,8 @@ struct AdamArgs {
     int n_views;
     int tile;
     int32_t gx[GS_MAX_VIEWS], gy[GS_MAX_VIEWS];
-    int32_t tile_base[GS_MAX_VIEWS];
     const uint32_t* offsets;
-    const uint32_t* inv;
-    const float4* grec;
-    const uint32_t* tile_stop;
-    int64_t capacity;
+    const float* sums;
     float4* m;
     float4* v;
     const float* bias;  // [0] = 1 - beta1^t, [1] = sqrt(1 - beta2^t)
@@ -88,33 +188,19 @@ __global__ __launch_bounds__(256) void k_project_bwd_adam(AdamArgs a) {
 #pragma unroll
     for (int i = 0; i < 48; ++i) gsh[i] = 0.f;
 
+    const int64_t vn = (int64_t)a.n_views * n;
     for (int vi = 0; vi < a.n_views && finite; ++vi) {
         const int64_t o = (int64_t)vi * n + g;
-        const uint64_t b = a.offsets[o];
-        uint64_t e = a.offsets[o + 1];
+        const uint32_t b = a.offsets[o];
+        const uint32_t e = a.offsets[o + 1];
         if (e == b) continue;
-        if (e > (uint64_t)a.capacity) e = (uint64_t)a.capacity;
         const gs_view vw = a.views[vi];
         Proj P;
         project_gaussian<true>(p0, p1, p2, sh, vw, a.tile, a.gx[vi], a.gy[vi], P);
         if (!P.valid) continue;
-        // sum the records of this Gaussian's traversed intersections, in
-        // unsorted-index order (tile = its rectangle, row major)
-        float d[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-        const uint32_t w = (uint32_t)(P.x1 - P.x0);
-        const int tbase = a.tile_base[vi] + P.y0 * a.gx[vi] + P.x0;
-        uint32_t kx = 0, ky = 0;
-        for (uint64_t i = b; i < e; ++i) {
-            const uint32_t j = a.inv[i];
-            if (j < a.tile_stop[tbase + (int)(ky * (uint32_t)a.gx[vi] + kx)]) {
-                const float4 r0 = a.grec[3 * (int64_t)j + 0];
-                const float4 r1 = a.grec[3 * (int64_t)j + 1];
-                const float4 r2 = a.grec[3 * (int64_t)j + 2];
-                d[0] += r0.x; d[1] += r0.y; d[2] += r0.z; d[3] += r0.w;
-                d[4] += r1.x; d[5] += r1.y; d[6] += r1.z; d[7] += r1.w; d[8] += r2.x;
-            }
-            if (++kx == w) { kx = 0; ++ky; }
-        }
+        float d[9];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) d[c] = a.sums[c * vn + o];
 
         float dmean[3] = {0.f, 0.f, 0.f};
         // colour: c = max(0, raw + 1/2), raw = sum_m sh[m] Y_m(dir)
@@ -289,9 +375,20 @@ __global__ void k_adam_tick(int32_t* step, float* bias, float beta1, float beta2
 }
 
 int launch_project_bwd_adam(float* params, int64_t n, const gs_view* views, const gs_layout& L,
-                            const gs_bins& b, const gs_grads2d& grads, const gs_adam* adam,
-                            float* grads_out, hipStream_t s) {
+                            const gs_splats& splats, const gs_bins& b, const gs_grads2d& grads,
+                            const gs_adam* adam, float* grads_out, hipStream_t s) {
     if (n == 0) return GS_OK;
+    int rc = GS_OK;
+    GatherArgs ga;
+    memset(&ga, 0, sizeof(ga));
+    ga.rec = reinterpret_cast<const float4*>(splats.rec);
+    ga.offsets = b.offsets;
+    ga.stop = reinterpret_cast<const uint4*>(grads.tile_stop);
+    ga.grec = reinterpret_cast<const float4*>(grads.rec);
+    ga.n = n;
+    ga.capacity = b.capacity;
+    ga.n_views = L.n_views;
+    ga.sums = grads.sums;
     AdamArgs a;
     memset(&a, 0, sizeof(a));
     a.params = reinterpret_cast<float4*>(params);
@@ -302,13 +399,12 @@ int launch_project_bwd_adam(float* params, int64_t n, const gs_view* views, cons
     for (int v = 0; v < GS_MAX_VIEWS; ++v) {
         a.gx[v] = v < L.n_views ? L.tiles_x[v] : 0;
         a.gy[v] = v < L.n_views ? L.tiles_y[v] : 0;
-        a.tile_base[v] = v < L.n_views ? L.tile_base[v] : 0;
+        ga.gx[v] = a.gx[v];
+        ga.tile_base[v] = v < L.n_views ? L.tile_base[v] : 0;
+        ga.depth_bits[v] = v < L.n_views ? L.depth_bits[v] : 0;
     }
     a.offsets = b.offsets;
-    a.inv = b.inv;
-    a.grec = reinterpret_cast<const float4*>(grads.rec);
-    a.tile_stop = grads.tile_stop;
-    a.capacity = b.capacity;
+    a.sums = grads.sums;
     a.grads_out = reinterpret_cast<float4*>(grads_out);
     if (adam) {
         a.m = reinterpret_cast<float4*>(adam->m);
@@ -320,9 +416,14 @@ int launch_project_bwd_adam(float* params, int64_t n, const gs_view* views, cons
         a.eps = adam->eps;
         hipLaunchKernelGGL(k_adam_tick, dim3(1), dim3(64), 0, s, adam->step, adam->scratch, adam->beta1,
                            adam->beta2);
-        int rc = check_launch("adam_tick");
+        rc = check_launch("adam_tick");
         if (rc != GS_OK) return rc;
     }
+    const int64_t vn = (int64_t)L.n_views * n;
+    hipLaunchKernelGGL(k_gather2d, dim3((unsigned)((vn + kGatherG - 1) / kGatherG)), dim3(kGatherG), 0,
+                       s, ga);
+    rc = check_launch("gather2d");
+    if (rc != GS_OK) return rc;
     hipLaunchKernelGGL(k_project_bwd_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
     return check_launch("project_bwd_adam");
 }

@@ -115,7 +115,7 @@ int gs_bin_sort(const gs_splats* splats, int64_t n, const gs_layout* layout, con
     REQUIRE(bins->capacity >= 0 && bins->capacity < (int64_t(1) << 32) - 1,
             "gs_bin_sort: capacity out of range");
     REQUIRE(bins->offsets && bins->ranges && bins->status && (bins->capacity == 0 ||
-            (bins->keys && bins->vals && bins->inv)), "gs_bin_sort: null bins buffer");
+            (bins->keys && bins->vals)), "gs_bin_sort: null bins buffer");
     REQUIRE(workspace || workspace_bytes == 0, "gs_bin_sort: null workspace");
     return launch_bin_sort(*splats, n, *layout, *bins, workspace, workspace_bytes, (hipStream_t)stream);
 }
@@ -159,16 +159,17 @@ int gs_rasterize_bwd(const gs_splats* splats, int64_t n, const gs_layout* layout
 }
 
 int gs_project_bwd_adam(float* params, int64_t n, const gs_view* views, const gs_layout* layout,
-                        const gs_bins* bins, const gs_grads2d* grads, const gs_adam* adam,
-                        float* grads_out, void* stream) {
+                        const gs_splats* splats, const gs_bins* bins, const gs_grads2d* grads,
+                        const gs_adam* adam, float* grads_out, void* stream) {
     REQUIRE(layout_ok(layout), "gs_project_bwd_adam: invalid layout");
     REQUIRE(views && bins && bins->offsets && (n == 0 || params), "gs_project_bwd_adam: null pointer");
     REQUIRE(adam || grads_out, "gs_project_bwd_adam: need adam state or grads_out");
     REQUIRE(!adam || (adam->m && adam->v && adam->step && adam->scratch),
             "gs_project_bwd_adam: incomplete adam state");
-    REQUIRE(grads && grads->tile_stop && (grads->rec || bins->capacity == 0) &&
-            (bins->inv || bins->capacity == 0), "gs_project_bwd_adam: null gradient buffers");
-    return launch_project_bwd_adam(params, n, views, *layout, *bins, *grads, adam, grads_out,
+    REQUIRE(splats && (n == 0 || splats->rec), "gs_project_bwd_adam: null splat records");
+    REQUIRE(grads && grads->tile_stop && (grads->sums || n == 0) && (grads->rec || bins->capacity == 0),
+            "gs_project_bwd_adam: null gradient buffers");
+    return launch_project_bwd_adam(params, n, views, *layout, *splats, *bins, *grads, adam, grads_out,
                                    (hipStream_t)stream);
 }
 

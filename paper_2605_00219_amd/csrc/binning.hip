@@ -1,7 +1,7 @@
 // Binning and sorting: exclusive scan of tiles touched, 32-bit (tile, depth)
 // key emission, stable LSD radix sort of each view's segment (4 passes of 8
-// bits) carrying the Gaussian id, per-tile [start, end) ranges and the
-// inverse permutation (unsorted index -> sorted position).
+// bits) carrying the Gaussian id, and per-tile [start, end) ranges.  The
+// depth part of each key comes precomputed from the projection record.
 //
 // The sort runs over all views at once: each view's segment is cut into
 // chunks of kChunk keys that never straddle two views, and the per-chunk digit
@@ -236,18 +236,12 @@ __global__ __launch_bounds__(kEmitG) void k_emit(const float4* __restrict__ rec,
     if (t == 0) s_off[kEmitG] = offsets[o0 + kEmitG < m ? o0 + kEmitG : m];
     if (o < m && tiles[o] > 0) {
         const int v = (int)(o / n);
-        const float4 q2 = rec[4 * o + 2];
         const float4 q3 = rec[4 * o + 3];
         const uint32_t r0 = __float_as_uint(q3.x), r1 = __float_as_uint(q3.y);
         const int D = geo.depth_bits[v];
-        // depth map z -> (2z + 1) / (z + 1) in (1, 2): only mantissa bits vary
-        const float z = q2.y;
-        const float num = 2.0f * z + 1.0f;
-        const float den = z + 1.0f;
-        const float f = num / den;
         s_xy[t] = r0;
         s_w[t] = (r1 & 0xFFFF) - (r0 & 0xFFFF);
-        s_dk[t] = (__float_as_uint(f) & 0x7FFFFFu) >> (23 - D);
+        s_dk[t] = __float_as_uint(q3.z) >> (23 - D);
         s_view[t] = (uint32_t)v;
     }
     __syncthreads();
@@ -430,17 +424,11 @@ __global__ __launch_bounds__(256) void k_ranges_empty(const uint32_t* __restrict
 }
 
 // One thread per sorted position j: tile boundaries -> ranges (lower-bound
-// semantics, empty tiles get start = end = insertion point), and the inverse
-// permutation inv[unsorted index] = j.  The unsorted index of (tile, Gaussian)
-// follows from the Gaussian's rectangle: offsets[v*n+g] + row * width + column.
+// semantics, empty tiles get start = end = insertion point).
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ keys,
-                                                const uint32_t* __restrict__ vals,
                                                 const uint32_t* __restrict__ table, int n_views,
                                                 RangeGeom geo, int64_t capacity,
-                                                const float4* __restrict__ rec,
-                                                const uint32_t* __restrict__ offsets, int64_t n,
-                                                uint32_t* __restrict__ ranges,
-                                                uint32_t* __restrict__ inv) {
+                                                uint32_t* __restrict__ ranges) {
     const int64_t j64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j64 >= capacity) return;
     const uint32_t j = (uint32_t)j64;
@@ -468,15 +456,6 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key
         for (int u = t; u < nt; ++u) R[u].y = j + 1;
         for (int u = t + 1; u < nt; ++u) R[u].x = j + 1;
     }
-    // inverse permutation
-    const int64_t o = (int64_t)v * n + vals[j];
-    const float4 q3 = rec[4 * o + 3];
-    const uint32_t r0 = __float_as_uint(q3.x), r1 = __float_as_uint(q3.y);
-    const uint32_t x0 = r0 & 0xFFFF, y0 = r0 >> 16, w = (r1 & 0xFFFF) - x0;
-    const uint32_t gx = (uint32_t)geo.tiles_x[v];
-    const uint32_t tx = (uint32_t)t % gx, ty = (uint32_t)t / gx;
-    const uint64_t i = (uint64_t)offsets[o] + (uint64_t)(ty - y0) * w + (tx - x0);
-    if (i < (uint64_t)capacity) inv[i] = j;
 }
 
 __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, int64_t count) {
@@ -603,8 +582,7 @@ int launch_bin_sort(const gs_splats& sp, int64_t n, const gs_layout& L, const gs
     if ((rc = check_launch("ranges_empty")) != GS_OK) return rc;
     if (b.capacity > 0) {
         hipLaunchKernelGGL(k_ranges, dim3((unsigned)((b.capacity + 255) / 256)), dim3(256), 0, s,
-                           b.keys, b.vals, W.table, V, rg, b.capacity, rec, b.offsets, n, b.ranges,
-                           b.inv);
+                           b.keys, W.table, V, rg, b.capacity, b.ranges);
         if ((rc = check_launch("ranges")) != GS_OK) return rc;
     }
     return GS_OK;

@@ -37,8 +37,12 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ param
             rec[0] = make_float4(P.u, P.v, P.A, P.B);
             rec[1] = make_float4(P.C, P.o, P.col[0], P.col[1]);
             rec[2] = make_float4(P.col[2], P.z, P.radius, 0.0f);
+            // depth map z -> (2z + 1) / (z + 1) in (1, 2): only mantissa bits vary
+            const float f = (2.0f * P.z + 1.0f) / (P.z + 1.0f);
+            const uint32_t dcode = __float_as_uint(f) & 0x7FFFFFu;
             rec[3] = make_float4(__uint_as_float((uint32_t)P.x0 | ((uint32_t)P.y0 << 16)),
-                                 __uint_as_float((uint32_t)P.x1 | ((uint32_t)P.y1 << 16)), 0.0f, 0.0f);
+                                 __uint_as_float((uint32_t)P.x1 | ((uint32_t)P.y1 << 16)),
+                                 __uint_as_float(dcode), 0.0f);
             out.tiles[o] = (uint32_t)((P.x1 - P.x0) * (P.y1 - P.y0));
         } else {
             const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);

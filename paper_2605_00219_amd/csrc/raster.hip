@@ -15,9 +15,11 @@
 // are summed over each wavefront with DPP row/broadcast reductions (no
 // atomics), waves whose lanes all skip a Gaussian skip its reduction (ballot),
 // and the per-wave sums are added in a fixed order through LDS: one 48-byte
-// record per traversed (Gaussian, tile) intersection, written at its sorted
-// position (contiguous per tile), deterministic.  A tile stops at the last
-// entry any of its pixels composited; its stop position is recorded.
+// record per traversed (Gaussian, tile) intersection, written at its unsorted
+// index (so each Gaussian's records are contiguous for the gather that
+// follows), deterministic.  A tile stops at the last entry any of its pixels
+// composited; the stop position and the (key, index) of the first entry not
+// traversed are recorded.
 //
 // Scheduling: either one workgroup per tile, or a persistent grid popping
 // tiles from a device counter in the order of a permutation (static or
@@ -52,8 +54,10 @@ struct RasterArgs {
     const float* target;
     const float* dLdC;
     float inv_count;
-    float4* grec;           // 3 float4 per sorted position
-    uint32_t* tile_stop;
+    float4* grec;           // 3 float4 per unsorted index
+    uint4* tile_stop;       // (stop, key, unsorted index, 0) per tile
+    const uint32_t* keys;   // sorted keys
+    const uint32_t* offsets;
     float* loss;
     int64_t capacity;
 };
@@ -69,6 +73,15 @@ GS_DEV void stage_splat(const RasterArgs& a, int view, uint32_t sorted_pos, floa
     sg = make_float4(q0.x, q0.y, (-0.5f * kLog2e) * q0.z, (-kLog2e) * q0.w);
     sh = make_float4((-0.5f * kLog2e) * q1.x, q1.y, q1.z, q1.w);
     sb = q2.x;
+}
+
+// Unsorted index of (tile (tx, ty), Gaussian gid) in view `view`: the
+// Gaussian's first index plus the tile's row-major position in its rectangle.
+GS_DEV uint32_t unsorted_index(const RasterArgs& a, int view, uint32_t gid, int tx, int ty) {
+    const int64_t o = (int64_t)view * a.n + gid;
+    const uint32_t r0 = __float_as_uint(a.rec[4 * o + 3].x), r1 = __float_as_uint(a.rec[4 * o + 3].y);
+    const uint32_t x0 = r0 & 0xFFFF, y0 = r0 >> 16, w = (r1 & 0xFFFF) - x0;
+    return a.offsets[o] + ((uint32_t)ty - y0) * w + ((uint32_t)tx - x0);
 }
 
 // Quadratic form (log2-scaled power) at the pixel, G = 2^power and o*G.
@@ -288,6 +301,7 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd(RasterArgs a)
     __shared__ float4 s_h[S];
     __shared__ float s_b[S];
     __shared__ uint32_t s_gid[S];
+    __shared__ uint32_t s_idx[S];
     __shared__ float s_red[NW][SUB][9];
     __shared__ uint64_t s_mask[NW];
     __shared__ int s_tile;
@@ -357,7 +371,12 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd(RasterArgs a)
             __syncthreads();
             for (int i = threadIdx.x; i < S; i += NT) {
                 const uint32_t j = b0 + i;
-                if (j < stop) stage_splat(a, ti.view, j, s_g[i], s_h[i], s_b[i], s_gid[i]);
+                if (j < stop) {
+                    uint32_t gid;
+                    stage_splat(a, ti.view, j, s_g[i], s_h[i], s_b[i], gid);
+                    s_gid[i] = gid;
+                    s_idx[i] = unsorted_index(a, ti.view, gid, ti.tx, ti.ty);
+                }
             }
             __syncthreads();
             const int cnt = (int)min((uint32_t)S, stop - b0);
@@ -443,7 +462,9 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd(RasterArgs a)
                             r5 += q[5]; r6 += q[6]; r7 += q[7]; r8 += q[8];
                         }
                     }
-                    float4* rec = a.grec + 3 * (int64_t)(b0 + (uint32_t)(sub + kk));
+                    const uint32_t idx = s_idx[sub + kk];
+                    if ((int64_t)idx >= a.capacity) continue;   // only after a capacity overflow
+                    float4* rec = a.grec + 3 * (int64_t)idx;
                     if (anyw) {
                         // conic and opacity of this Gaussian, unscaled
                         const float4* rr = a.rec + 4 * ((int64_t)ti.view * a.n + s_gid[sub + kk]);
@@ -463,8 +484,16 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd(RasterArgs a)
                 __syncthreads();
             }
         }
-        // records exist for [start, stop); later entries contribute nothing
-        if (threadIdx.x == 0) a.tile_stop[gt] = stop;
+        // records exist for [start, stop); the first entry not traversed is
+        // identified by its (key, unsorted index) for the per-Gaussian gather
+        if (threadIdx.x == 0) {
+            uint4 st = make_uint4(stop, 0xFFFFFFFFu, 0xFFFFFFFFu, 0u);
+            if (stop < ti.range.y) {
+                st.y = a.keys[stop];
+                st.z = unsorted_index(a, ti.view, a.vals[stop], ti.tx, ti.ty);
+            }
+            a.tile_stop[gt] = st;
+        }
         if (a.counter == nullptr) break;
     }
 }
@@ -568,7 +597,9 @@ int launch_raster_bwd(const gs_splats& sp, int64_t n, const gs_layout& L, const 
     a.loss = target ? loss : nullptr;
     a.inv_count = 1.0f / (3.0f * (float)L.pixel_base[L.n_views]);
     a.grec = reinterpret_cast<float4*>(grads.rec);
-    a.tile_stop = grads.tile_stop;
+    a.tile_stop = reinterpret_cast<uint4*>(grads.tile_stop);
+    a.keys = b.keys;
+    a.offsets = b.offsets;
     int rc = GS_OK;
     if (a.total_tiles == 0) return GS_OK;
     if (a.counter) {

@@ -84,7 +84,8 @@ class Frame:
         self.last = torch.zeros(P, **u32)
         self.tile_stats = torch.zeros(self.layout.total_tiles, 4, **u32) if tile_stats else None
         self.loss_tiles = torch.zeros(self.layout.total_tiles, **f32)
-        self.tile_stop = torch.zeros(self.layout.total_tiles, **u32)
+        self.tile_stop = torch.zeros(self.layout.total_tiles, 4, **u32)   # (stop, key, index, 0)
+        self.sums = torch.zeros(9, V * n, **f32)      # per (view, Gaussian) screen-space gradient
         self.counter = torch.zeros(1, **u32)
         self.capacity = 0
         self.resize(capacity)
@@ -95,7 +96,6 @@ class Frame:
         u32 = dict(dtype=torch.int32, device=self.device)
         self.keys = torch.zeros(capacity, **u32)
         self.vals = torch.zeros(capacity, **u32)
-        self.inv = torch.zeros(capacity, **u32)
         self.grec = torch.zeros(capacity, 12, dtype=torch.float32, device=self.device)
         ws = G.lib.gs_bin_sort_workspace_size(self.n, C.byref(self.layout), capacity)
         self.workspace = torch.zeros(max(int(ws), 1), dtype=torch.uint8, device=self.device)
@@ -104,9 +104,9 @@ class Frame:
 
     def _structs(self) -> None:
         self.splats = G.GsSplats(_i(self.rec), _i(self.tiles))
-        self.bins = G.GsBins(_i(self.offsets), _i(self.keys), _i(self.vals), _i(self.inv),
-                             _i(self.ranges), _i(self.status), self.capacity)
-        self.grads2d = G.GsGrads2d(_i(self.grec), _i(self.tile_stop))
+        self.bins = G.GsBins(_i(self.offsets), _i(self.keys), _i(self.vals), _i(self.ranges),
+                             _i(self.status), self.capacity)
+        self.grads2d = G.GsGrads2d(_i(self.grec), _i(self.tile_stop), _i(self.sums))
         self.img = G.GsImage(_i(self.image), _i(self.T), _i(self.last),
                              _i(self.tile_stats) if self.tile_stats is not None else None)
 
@@ -180,7 +180,8 @@ def rasterize_bwd(frame: Frame, views_dev: torch.Tensor, target: torch.Tensor | 
 def project_bwd_adam(model: Model, frame: Frame, views_dev: torch.Tensor, adam: bool = True,
                      grads_out: torch.Tensor | None = None, stream=None) -> None:
     G.check(G.lib.gs_project_bwd_adam(_i(model.params), frame.n, _i(views_dev), C.byref(frame.layout),
-                                      C.byref(frame.bins), C.byref(frame.grads2d),
+                                      C.byref(frame.splats), C.byref(frame.bins),
+                                      C.byref(frame.grads2d),
                                       C.byref(model.adam) if adam else None,
                                       _i(grads_out) if grads_out is not None else None,
                                       G.stream_ptr(stream)), "gs_project_bwd_adam")

@@ -52,9 +52,9 @@ def run_gpu_step(scene, views, tile, target=None, lds_batch=64, lr=1e-3, adam=Tr
     out["K"] = K
     out["keys"] = u32(frame.keys)[:K]
     out["vals"] = u32(frame.vals)[:K]
-    out["inv"] = u32(frame.inv)[:K]
     out["ranges"] = u32(frame.ranges)
-    out["tile_stop"] = u32(frame.tile_stop)
+    out["tile_stop"] = u32(frame.tile_stop)[:, 0].copy()
+    out["stop_entry"] = u32(frame.tile_stop)
     out["image"] = frame.image.cpu().numpy()
     out["T"] = frame.T.cpu().numpy()
     out["last"] = u32(frame.last)
@@ -62,6 +62,7 @@ def run_gpu_step(scene, views, tile, target=None, lds_batch=64, lr=1e-3, adam=Tr
         out["tile_stats"] = u32(frame.tile_stats)
     if tgt is not None:
         out["grec"] = frame.grec.cpu().numpy()[:K]
+        out["sums"] = frame.sums.cpu().numpy().reshape(9, len(views), n).transpose(1, 2, 0)
         out["loss_tiles"] = frame.loss_tiles.cpu().numpy()
         out["params"] = P.unpack_flat(model.params).cpu().numpy()
         out["m"] = P.unpack_flat(model.m).cpu().numpy()
@@ -71,16 +72,18 @@ def run_gpu_step(scene, views, tile, target=None, lds_batch=64, lr=1e-3, adam=Tr
     return out
 
 
-def per_gaussian_2d(grec, vals, ranges, tile_stop, tile_base, n):
-    """Sum the traversed records of each (view, Gaussian): [V, N, 9].
-    tile_base: global tile base of each view plus the total."""
+def per_gaussian_2d(grec, sorted_to_unsorted, vals, ranges, tile_stop, tile_base, n):
+    """Sum the traversed records (stored at unsorted indices) of each
+    (view, Gaussian): [V, N, 9].  tile_base: global tile base of each view
+    plus the total."""
     V = len(tile_base) - 1
     out = np.zeros((V, n, 9))
     for v in range(V):
         for t in range(tile_base[v], tile_base[v + 1]):
             s, e = int(ranges[t, 0]), int(tile_stop[t])
             if e > s:
-                np.add.at(out[v], vals[s:e], grec[s:e, :9].astype(np.float64))
+                idx = sorted_to_unsorted[s:e]
+                np.add.at(out[v], vals[s:e], grec[idx, :9].astype(np.float64))
     return out
 
 

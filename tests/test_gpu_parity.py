@@ -70,13 +70,14 @@ def test_projection_and_binning_bit_exact(name):
               9: ref.proj.depth, 10: ref.proj.radius}
     for k, want in fields.items():
         np.testing.assert_array_equal(rec[..., k][vis], f32(want)[vis], err_msg=f"record field {k}")
-    # binning: keys, the Gaussian id carried by the sort, inverse permutation, ranges
+    # depth code: mantissa of the float32 (2z + 1) / (z + 1)
+    z = f32(ref.proj.depth)
+    fz = (np.float32(2) * z + np.float32(1)) / (z + np.float32(1))
+    np.testing.assert_array_equal(rec[..., 14].view(np.uint32)[vis], (fz.view(np.uint32) & 0x7FFFFF)[vis])
+    # binning: keys, the Gaussian id carried by the sort, ranges
     np.testing.assert_array_equal(g["offsets"], ref.bins.offsets)
     np.testing.assert_array_equal(g["keys"], ref.bins.keys)
     np.testing.assert_array_equal(g["vals"], ref.bins.gid[ref.bins.vals])
-    inv = np.empty_like(ref.bins.vals)
-    inv[ref.bins.vals] = np.arange(ref.bins.vals.size, dtype=np.uint32)
-    np.testing.assert_array_equal(g["inv"], inv)
     np.testing.assert_array_equal(g["ranges"], ref.bins.ranges)
 
 
@@ -112,12 +113,31 @@ def test_training_step(name, ppl):
     assert abs(loss_gpu - ref.loss) <= 1e-4 * ref.loss
     # per-Gaussian 2D gradients (sums of the intersection records)
     tb = np.cumsum([0] + oracle.n_tiles(views, tile))
-    g2 = per_gaussian_2d(g["grec"], g["vals"], g["ranges"], g["tile_stop"], tb, n)
-    # traversal stops are within the ranges
-    assert np.all(g["tile_stop"] >= g["ranges"][:, 0]) and np.all(g["tile_stop"] <= g["ranges"][:, 1])
+    g2 = per_gaussian_2d(g["grec"], ref.bins.vals, g["vals"], g["ranges"], g["tile_stop"], tb, n)
+    # traversal stops are within the ranges; the stop entry names the first
+    # entry not traversed by its key and unsorted index
+    stop, st = g["tile_stop"], g["stop_entry"]
+    assert np.all(stop >= g["ranges"][:, 0]) and np.all(stop <= g["ranges"][:, 1])
+    inner = stop < g["ranges"][:, 1]
+    assert inner.any() and not inner.all()
+    np.testing.assert_array_equal(st[inner, 1], g["keys"][stop[inner]])
+    np.testing.assert_array_equal(st[inner, 2], ref.bins.vals[stop[inner]])
+    assert np.all(st[~inner, 1:3] == 0xFFFFFFFF)
+    # records of traversed entries match the oracle's partials at the same unsorted index
+    pos = [np.arange(int(g["ranges"][t, 0]), int(stop[t])) for t in range(len(stop))]
+    pview = np.concatenate([np.full(len(p_), np.searchsorted(tb, t, side="right") - 1) for t, p_ in
+                            enumerate(pos)]).astype(np.int64)
+    pos = np.concatenate(pos).astype(np.int64)
+    trav = ref.bins.vals[pos]
+    okr = grad_close(g["grec"][trav, :9], ref.partials[trav], GRAD_RTOL).all(axis=1)
+    badr = ~okr & ~ex[pview, g["vals"][pos]]
+    assert not badr.any(), (pos[badr][:5], trav[badr][:5])
     ok2 = grad_close(g2.reshape(-1, 9), ref.grads2d.reshape(-1, 9), GRAD_RTOL).reshape(V, n, 9)
     bad = ~ok2.all(axis=2) & ~ex
     assert not bad.any(), np.argwhere(bad)[:5]
+    # the gather's per-(view, Gaussian) sums equal the sums of the records
+    oks = grad_close(g["sums"].reshape(-1, 9), g2.reshape(-1, 9), 1e-5)
+    assert oks.all(), np.argwhere(~oks)[:5]
     # parameter gradients
     okg = grad_close(g["grads"], ref.grads, GRAD_RTOL)
     badg = ~okg.all(axis=1) & ~ex_any
@@ -144,7 +164,7 @@ def test_deterministic_bitwise():
     target = oracle.render(target_scene, views, tile)
     a = run_gpu_step(scene, views, tile, target=target)
     b = run_gpu_step(scene, views, tile, target=target)
-    for k in ("image", "grec", "tile_stop", "grads", "params", "keys", "vals", "inv"):
+    for k in ("image", "grec", "stop_entry", "sums", "grads", "params", "keys", "vals"):
         np.testing.assert_array_equal(a[k], b[k])
 
 
@@ -157,7 +177,7 @@ def test_persistent_and_permuted_schedules_change_no_bit():
     perm = np.random.default_rng(3).permutation(nt).astype(np.int32)
     for kw in (dict(persistent=True), dict(sched_order=perm), dict(sched_order=perm, persistent=True)):
         other = run_gpu_step(scene, views, tile, target=target, **kw)
-        for k in ("image", "T", "last", "grec", "tile_stop", "grads", "params"):
+        for k in ("image", "T", "last", "grec", "stop_entry", "sums", "grads", "params"):
             np.testing.assert_array_equal(base[k], other[k], err_msg=str(kw))
 
 

@@ -26,12 +26,20 @@ METRIC = "train iters/sec + rasterize_bwd HBM GB/s (% peak), batched/learned vs 
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 
-# algorithmic work of rasterize_bwd ("Roofline accounting")
-BWD_BYTES_TRAVERSED = 76     # Gaussian id 4 + splat 36 read, gradient record 36 written
+# Algorithmic work per unit of each stage (the same figures are derived in the
+# design notes): bytes that must cross HBM, or flops that must be executed.
+PROJ_BYTES_G = 308           # parameters 240 read; splat record 64 + tile count 4 written
+SORT_BYTES_G = 28            # counts, offsets, rectangle/depth word per (view, Gaussian)
+SORT_BYTES_K = 92            # emit 8 w; 4 passes x (8 r + 8 w + 4 histogram r); ranges 4 r
+FWD_FLOP_EVAL = 14           # power, G, alpha, thresholds per evaluated pixel-Gaussian pair
+FWD_FLOP_COMP = 9            # colour and transmittance update per composited pair
+BWD_BYTES_TRAVERSED = 88     # Gaussian id 4 + splat 36 + index 12 read, gradient record 36 written
 BWD_BYTES_PIXEL = 28         # C 12 + target 12 + last 4
-BWD_BYTES_TILE = 16          # range 8 + loss 4 + traversal stop 4
+BWD_BYTES_TILE = 32          # range 8 + loss 4 + stop entry 16 + key 4
 BWD_FLOP_EVAL = 14           # recompute of power, G, alpha, thresholds per evaluated pair
 BWD_FLOP_CONTRIB = 44        # gradient terms and their sums per composited pair
+ADAM_BYTES_G = 1516          # params, m, v 720 r + 720 w; offsets 4; per-view sums 36 w + 36 r
+ADAM_BYTES_TRAVERSED = 48    # one gradient record per traversed intersection
 
 
 def log(msg):
@@ -175,7 +183,7 @@ def main():
         gx = (W + 15) // 16
         tile_of_px = torch.arange(H * W, device=dev)
         tile_of_px = (tile_of_px // W // 16) * gx + (tile_of_px % W) // 16
-        acc = dict(K=0, trav_bwd=0, eval_bwd=0, contrib=0, eval_fwd=0, trav_fwd=0)
+        acc = dict(K=0, trav_bwd=0, eval_bwd=0, contrib=0, eval_fwd=0, trav_fwd=0, visible=0)
         for i in range(args.steps):
             vi = order[(args.warmup + i) % ncam]
             vd = vptr(vi)
@@ -187,6 +195,7 @@ def main():
             per_tile.scatter_reduce_(0, tile_of_px, last, reduce="amax")
             ts = rframe.tile_stats.to(torch.int64)
             acc["K"] += rframe.intersections()
+            acc["visible"] += int((rframe.tiles != 0).sum().item())
             acc["trav_bwd"] += int(per_tile.sum().item())
             acc["eval_bwd"] += int(last.sum().item())
             acc["contrib"] += int(ts[:, 2].sum().item())
@@ -198,36 +207,64 @@ def main():
         counts = {k: v / args.steps for k, v in acc.items()}
         log(f"per-step work: {counts}")
 
-    # roofline of the dominant kernel
+    # roofline of the dominant stage (every stage's figure is reported)
     dom = max(stage_ms, key=stage_ms.get)
     roof = None
     extra = {}
     P_px = H * W
     ntiles = frame.layout.total_tiles
     if counts is not None:
-        bwd_bytes = (BWD_BYTES_TRAVERSED * counts["trav_bwd"]
-                     + BWD_BYTES_PIXEL * P_px + BWD_BYTES_TILE * ntiles)
-        bwd_flop = BWD_FLOP_EVAL * counts["eval_bwd"] + BWD_FLOP_CONTRIB * counts["contrib"]
-        t_bwd = stage_ms["rasterize_bwd"] * 1e-3
-        bwd_gbs = bwd_bytes / t_bwd / 1e9
-        bwd_tflops = bwd_flop / t_bwd / 1e12
+        def hbm(name, nbytes, kernel):
+            t = stage_ms[name] * 1e-3
+            gbs = nbytes / t / 1e9
+            tr = recorded_traffic(kernel)
+            return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": gbs / HBM_PEAK_GBS, "traffic": tr["bytes_per_launch"] if tr else None,
+                    "kernel": kernel, "algorithmic_bytes": nbytes, "ms": stage_ms[name]}
+
+        def alu(name, flop, nbytes, kernel):
+            t = stage_ms[name] * 1e-3
+            tf = flop / t / 1e12
+            tr = recorded_traffic(kernel)
+            return {"bound": "alu", "achieved": tf, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": tf / FP32_PEAK_TFLOPS, "traffic": tr["bytes_per_launch"] if tr else None,
+                    "kernel": kernel, "algorithmic_flop": flop, "algorithmic_bytes": nbytes,
+                    "hbm_gbs": nbytes / t / 1e9, "hbm_frac": nbytes / t / 1e9 / HBM_PEAK_GBS,
+                    "ms": stage_ms[name]}
+
+        vis = counts["visible"]
+        per_stage = {
+            "project": hbm("project", PROJ_BYTES_G * n, "project"),
+            "bin_sort": hbm("bin_sort", SORT_BYTES_G * n + SORT_BYTES_K * counts["K"], "bin_sort"),
+            "rasterize_fwd": alu("rasterize_fwd",
+                                 FWD_FLOP_EVAL * counts["eval_fwd"] + FWD_FLOP_COMP * counts["contrib"],
+                                 68 * counts["trav_fwd"] + 20 * P_px + 8 * ntiles, "rasterize_fwd"),
+            "rasterize_bwd": alu("rasterize_bwd",
+                                 BWD_FLOP_EVAL * counts["eval_bwd"] + BWD_FLOP_CONTRIB * counts["contrib"],
+                                 BWD_BYTES_TRAVERSED * counts["trav_bwd"] + BWD_BYTES_PIXEL * P_px
+                                 + BWD_BYTES_TILE * ntiles, "rasterize_bwd"),
+            "project_bwd_adam": hbm("project_bwd_adam",
+                                    ADAM_BYTES_G * n + ADAM_BYTES_TRAVERSED * counts["trav_bwd"],
+                                    "project_bwd_adam"),
+        }
+        rb = per_stage["rasterize_bwd"]
         extra["rasterize_bwd"] = {
-            "ms": stage_ms["rasterize_bwd"], "algorithmic_bytes": bwd_bytes,
-            "hbm_gbs": bwd_gbs, "hbm_frac": bwd_gbs / HBM_PEAK_GBS,
-            "algorithmic_flop": bwd_flop, "tflops": bwd_tflops,
-            "alu_frac": bwd_tflops / FP32_PEAK_TFLOPS,
+            "ms": rb["ms"], "algorithmic_bytes": rb["algorithmic_bytes"], "hbm_gbs": rb["hbm_gbs"],
+            "hbm_frac": rb["hbm_frac"], "algorithmic_flop": rb["algorithmic_flop"],
+            "tflops": rb["achieved"], "alu_frac": rb["frac"],
             "intersections": counts["K"], "traversed": counts["trav_bwd"],
-            "pairs_evaluated": counts["eval_bwd"], "pairs_composited": counts["contrib"]}
+            "pairs_evaluated": counts["eval_bwd"], "pairs_composited": counts["contrib"],
+            "visible_gaussians": vis}
         tr = recorded_traffic("rasterize_bwd")
         if tr is not None:
+            t_bwd = rb["ms"] * 1e-3
             extra["rasterize_bwd"]["measured_hbm_bytes"] = tr["bytes_per_launch"]
             extra["rasterize_bwd"]["measured_hbm_gbs"] = tr["bytes_per_launch"] / t_bwd / 1e9
             extra["rasterize_bwd"]["measured_hbm_frac"] = tr["bytes_per_launch"] / t_bwd / 1e9 / HBM_PEAK_GBS
-        if dom == "rasterize_bwd":
-            roof = {"bound": "alu", "achieved": bwd_tflops, "peak": FP32_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": bwd_tflops / FP32_PEAK_TFLOPS,
-                    "traffic": tr["bytes_per_launch"] if tr else None,
-                    "kernel": "rasterize_bwd"}
+        extra["stage_roofline"] = {k: {kk: v[kk] for kk in ("bound", "achieved", "unit", "frac")}
+                                   for k, v in per_stage.items()}
+        roof = {k: per_stage[dom][k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic",
+                                              "kernel")}
     if roof is None:
         roof = {"bound": "unknown", "achieved": None, "peak": None, "unit": None, "frac": None,
                 "traffic": None, "kernel": dom}

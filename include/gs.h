@@ -154,6 +154,8 @@ typedef struct gs_grads2d {
     float* sums;          /* 9 planes of n_views * n floats, plane c at c * n_views * n:
                              per (view, Gaussian) sum of its traversed records
                              (components 0..8), written by gs_project_bwd_adam */
+    void* workspace;      /* device scratch of gs_grads2d_workspace_size(capacity) bytes
+                             for gs_project_bwd_adam */
 } gs_grads2d;
 
 /* Rasterisation outputs, indexed by global pixel (views concatenated). */
@@ -201,6 +203,11 @@ int gs_layout_init(const int32_t* widths, const int32_t* heights, int n_views, i
 /* Bytes of scratch that gs_bin_sort needs for n Gaussians, the layout and the
  * given intersection capacity. */
 size_t gs_bin_sort_workspace_size(int64_t n, const gs_layout* layout, int64_t capacity);
+
+/* Bytes of scratch (gs_grads2d.workspace) that gs_project_bwd_adam needs for
+ * the given intersection capacity: per 1024 intersection indices, one owner
+ * word and two partial sums of 9 floats. */
+size_t gs_grads2d_workspace_size(int64_t capacity);
 
 /* ---- the five stages ------------------------------------------------------ */
 

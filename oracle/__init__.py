@@ -57,23 +57,26 @@ _I = C.c_int
 _D = C.c_double
 
 _SIGS = {
-    "or_project": (None, [_P, _P, _P, _P, _P, _I64, _P, _I, _I, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "or_project": (None, [_P, _P, _P, _P, _P, _I64, _P, _I, _I, _I, _P, _P, _P, _P, _P, _P, _P, _P,
+                          _P]),
     "or_scan": (_I, [_P, _I64, _P]),
     "or_tile_bits": (_I, [_I]),
     "or_depth_bits": (_I, [_I]),
     "or_depth_key": (C.c_uint32, [C.c_float, _I]),
-    "or_emit_keys": (None, [_P, _P, _P, _P, _I64, _P, _I, _I, _P, _P, _P]),
+    "or_emit_keys": (None, [_P, _P, _P, _P, _P, _P, _I, _P, _I64, _P, _I, _I, _P, _P, _P]),
     "or_sort_segments": (None, [_P, _P, _P, _I]),
     "or_tile_ranges": (None, [_P, _P, _P, _I, _I, _P]),
     "or_raster_fwd": (None, [_P, _P, _P, _P, _P, _P, _P, _I64, _P, _I, _I, _P, _P,
                              _P, _P, _P, _P, _P, _P]),
     "or_l1": (_D, [_P, _P, _I64, _D, _P, _P]),
     "or_raster_bwd": (None, [_P, _P, _P, _P, _P, _P, _P, _P, _I64, _P, _I, _I, _P, _P, _P, _P]),
-    "or_project_bwd": (None, [_P, _P, _P, _P, _P, _I64, _P, _I, _I, _P, _P]),
+    "or_project_bwd": (None, [_P, _P, _P, _P, _P, _I64, _P, _I, _I, _I, _P, _P]),
     "or_adam": (None, [_P, _P, _P, _P, _I64, _P, _D, _D, _D, _I]),
     "or_sh_basis": (None, [_P, _P]),
     "or_cov3d": (_I, [_P, _P, _P, _P]),
     "or_exp_param": (_D, [_D]),
+    "or_log_spec": (_D, [_D]),
+    "or_ellipse_tiles": (_I, [_D, _D, _D, _D, _D, _D, _I, _I, _I, _P]),
     "or_sigmoid": (_D, [_D]),
     "or_threads": (_I, []),
     "or_is_double": (_I, []),
@@ -135,11 +138,15 @@ class Projected:
     depth: np.ndarray    # [V, N]
     radius: np.ndarray   # [V, N]
     cov2d: np.ndarray    # [V, N, 3]  (a, b, c)
-    rect: np.ndarray     # [V, N, 4]  (x0, y0, x1, y1) int32
+    rect: np.ndarray     # [V, N, 4]  (x0, y0, x1, y1) int32: bounding tile box
     tiles: np.ndarray    # [V, N] uint32
+    cull: int = 0        # 0: 3-sigma rectangle; 1: exact opacity-ellipse culling
 
 
-def project(scene, views, tile: int, double: bool = False) -> Projected:
+CULL_RECT, CULL_ELLIPSE = 0, 1
+
+
+def project(scene, views, tile: int, double: bool = False, cull: int = CULL_RECT) -> Projected:
     L = lib(double)
     means, ls, q, lo, sh = (_pin(a, double) for a in scene.arrays())
     n = means.shape[0]
@@ -147,8 +154,8 @@ def project(scene, views, tile: int, double: bool = False) -> Projected:
     views = np.ascontiguousarray(views)
     out = Projected(np.zeros((V, n, 2)), np.zeros((V, n, 3)), np.zeros((V, n)), np.zeros((V, n, 3)),
                     np.zeros((V, n)), np.zeros((V, n)), np.zeros((V, n, 3)),
-                    np.zeros((V, n, 4), np.int32), np.zeros((V, n), np.uint32))
-    L.or_project(_p(means), _p(ls), _p(q), _p(lo), _p(sh), n, _p(views), V, tile, _p(out.xy),
+                    np.zeros((V, n, 4), np.int32), np.zeros((V, n), np.uint32), int(cull))
+    L.or_project(_p(means), _p(ls), _p(q), _p(lo), _p(sh), n, _p(views), V, tile, int(cull), _p(out.xy),
                  _p(out.conic), _p(out.opacity), _p(out.rgb), _p(out.depth), _p(out.radius),
                  _p(out.cov2d), _p(out.rect), _p(out.tiles))
     return out
@@ -185,7 +192,9 @@ def bin_sort(proj: Projected, views, tile: int, double: bool = False) -> Bins:
     gid = np.zeros(max(K, 1), np.uint32)
     depth = np.ascontiguousarray(proj.depth)
     L.or_emit_keys(_p(np.ascontiguousarray(proj.rect)), _p(np.ascontiguousarray(proj.tiles)),
-                   _p(depth), _p(offsets), n, _p(views), V, tile, _p(keys), _p(vals), _p(gid))
+                   _p(depth), _p(np.ascontiguousarray(proj.xy)), _p(np.ascontiguousarray(proj.conic)),
+                   _p(np.ascontiguousarray(proj.opacity)), int(proj.cull), _p(offsets), n, _p(views),
+                   V, tile, _p(keys), _p(vals), _p(gid))
     keys_unsorted = keys[:K].copy()
     seg = np.array([offsets[v * n] for v in range(V)] + [K], np.uint32)
     L.or_sort_segments(_p(keys), _p(vals), _p(seg), V)
@@ -257,7 +266,8 @@ def raster_bwd(proj: Projected, bins: Bins, views, tile: int, dLdC: np.ndarray,
     return partials[:K], grads2d
 
 
-def project_bwd(scene, views, tile: int, grads2d: np.ndarray, double: bool = False) -> np.ndarray:
+def project_bwd(scene, views, tile: int, grads2d: np.ndarray, double: bool = False,
+                cull: int = CULL_RECT) -> np.ndarray:
     """Returns grads [N, 59] in the canonical parameter order."""
     L = lib(double)
     means, ls, q, lo, sh = (_pin(a, double) for a in scene.arrays())
@@ -265,7 +275,7 @@ def project_bwd(scene, views, tile: int, grads2d: np.ndarray, double: bool = Fal
     views = np.ascontiguousarray(views)
     grads = np.zeros((n, 59))
     L.or_project_bwd(_p(means), _p(ls), _p(q), _p(lo), _p(sh), n, _p(views), len(views), tile,
-                     _p(np.ascontiguousarray(grads2d, dtype=np.float64)), _p(grads))
+                     int(cull), _p(np.ascontiguousarray(grads2d, dtype=np.float64)), _p(grads))
     return grads
 
 
@@ -308,6 +318,18 @@ def sigmoid(x: float, double=False) -> float:
     return float(lib(double).or_sigmoid(float(x)))
 
 
+def log_spec(x: float, double=False) -> float:
+    return float(lib(double).or_log_spec(float(x)))
+
+
+def ellipse_tiles(u, v, A, B, C, o, tile, gx, gy, double=False) -> np.ndarray:
+    """Tile mask [gy, gx] (uint8) of one screen-space Gaussian under exact culling."""
+    mask = np.zeros(gx * gy, np.uint8)
+    lib(double).or_ellipse_tiles(float(u), float(v), float(A), float(B), float(C), float(o), int(tile),
+                                 int(gx), int(gy), _p(mask))
+    return mask.reshape(gy, gx)
+
+
 def threads(double=False) -> int:
     return int(lib(double).or_threads())
 
@@ -333,15 +355,15 @@ class StepResult:
 
 
 def train_step(scene, views, tile: int, target: np.ndarray, lr=1e-3, step: int = 1, m=None, v=None,
-               double: bool = False, adam_step: bool = True) -> StepResult:
+               double: bool = False, adam_step: bool = True, cull: int = CULL_RECT) -> StepResult:
     """One L1 training step over all given views (gradients summed over views)."""
-    proj = project(scene, views, tile, double)
+    proj = project(scene, views, tile, double, cull)
     bins = bin_sort(proj, views, tile, double)
     img = raster_fwd(proj, bins, views, tile, double)
     fragile = img.fragile.copy()
     loss, dLdC = l1(img.rgb, target, double, fragile)
     partials, grads2d = raster_bwd(proj, bins, views, tile, dLdC, double)
-    grads = project_bwd(scene, views, tile, grads2d, double)
+    grads = project_bwd(scene, views, tile, grads2d, double, cull)
     params = mm = vv = None
     if adam_step:
         params = scene.flat()
@@ -352,8 +374,8 @@ def train_step(scene, views, tile: int, target: np.ndarray, lr=1e-3, step: int =
     return StepResult(proj, bins, img, loss, dLdC, partials, grads2d, grads, params, mm, vv, fragile)
 
 
-def render(scene, views, tile: int, double: bool = False) -> np.ndarray:
+def render(scene, views, tile: int, double: bool = False, cull: int = CULL_RECT) -> np.ndarray:
     """Forward only: the composited image [P,3] float32 (views concatenated)."""
-    proj = project(scene, views, tile, double)
+    proj = project(scene, views, tile, double, cull)
     bins = bin_sort(proj, views, tile, double)
     return raster_fwd(proj, bins, views, tile, double).rgb.astype(np.float32)

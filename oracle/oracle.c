@@ -110,6 +110,106 @@ static real exp_param(real x)
 
 static real sigmoid_param(real x) { return (real)1 / ((real)1 + exp_param(-x)); }
 
+/* ln x for x > 0, for the opacity threshold of exact tile culling.  Float
+ * build: x = m 2^k with m in [1/sqrt 2, sqrt 2) (exact), then
+ * ln m = 2 atanh(s) with s = (m - 1)/(m + 1), summed as the odd series
+ * s (2 + z (2/3 + z (2/5 + ... + z 2/13))), z = s^2, in Horner form, and
+ * ln x = k ln2_hi + (k ln2_lo + ln m); every step one IEEE float operation,
+ * coefficients the float32 values nearest 2/(2j+1). */
+static real log_spec(real x)
+{
+#ifdef OR_DOUBLE
+    return log(x);
+#else
+    int k;
+    float m = frexpf(x, &k);                       /* x = m 2^k, m in [0.5, 1) */
+    if (m < 0.70710676908493042f) { m = m * 2.0f; k = k - 1; }
+    const float s = (m - 1.0f) / (m + 1.0f);
+    const float z = s * s;
+    float p = 0.15384615957736969f;                /* 2/13 */
+    p = p * z + 0.18181818723678589f;              /* 2/11 */
+    p = p * z + 0.22222222387790680f;              /* 2/9 */
+    p = p * z + 0.28571429848670959f;              /* 2/7 */
+    p = p * z + 0.40000000596046448f;              /* 2/5 */
+    p = p * z + 0.66666668653488159f;              /* 2/3 */
+    p = p * z + 2.0f;
+    const float lm = s * p;
+    const float fk = (float)k;
+    return fk * 0.693145751953125f + (fk * 1.4286067653301870e-06f + lm);
+#endif
+}
+
+/* ------------------------------------------------------------------------- */
+/* Tile sets (Sec. 4.1)                                                       */
+/* ------------------------------------------------------------------------- */
+
+/* Exact culling: the tiles of a Gaussian are those whose square meets the
+ * ellipse where it can reach alpha >= 1/255, i.e. the points d (offset from
+ * the 2D mean) with A dx^2 + 2 B dx dy + C dy^2 <= tau, tau = 2 ln(255 o).
+ * Tile rows are those meeting [v - hy, v + hy]; in each row band
+ * [ya, yb] (clipped to the ellipse) the ellipse's x-extent is either its
+ * global extreme (when the extreme point's y lies in the band) or the
+ * boundary at one of the band's edges, and the column range is that extent
+ * rounded outwards to tile boundaries.  Everything is float arithmetic in a
+ * fixed order. */
+typedef struct {
+    real u, v, A, B, C, tau, dQ, hx, hy, ys;
+} or_ellipse;
+
+static int ellipse_setup(real u, real v, real A, real B, real C, real o, or_ellipse* e)
+{
+    const real x = (real)255 * o;
+    if (!(x > (real)1)) return 0;                   /* alpha never reaches 1/255 */
+    e->u = u; e->v = v; e->A = A; e->B = B; e->C = C;
+    e->tau = (real)2 * log_spec(x);
+    e->dQ = A * C - B * B;
+    if (!(e->dQ > 0) || !(A > 0) || !(C > 0)) return 0;
+    e->hx = RSQRT((e->tau * C) / e->dQ);
+    e->hy = RSQRT((e->tau * A) / e->dQ);
+    e->ys = -((B * e->hx) / C);                     /* dy of the rightmost point */
+    return 1;
+}
+
+/* boundary x-offsets of the ellipse at height dy: (-B dy +- sqrt(A tau - dQ dy^2)) / A */
+static real ellipse_xp(const or_ellipse* e, real dy)
+{
+    real w = e->A * e->tau - e->dQ * (dy * dy);
+    w = RMAX(w, (real)0);
+    return (RSQRT(w) - e->B * dy) / e->A;
+}
+static real ellipse_xm(const or_ellipse* e, real dy)
+{
+    real w = e->A * e->tau - e->dQ * (dy * dy);
+    w = RMAX(w, (real)0);
+    return (-RSQRT(w) - e->B * dy) / e->A;
+}
+
+/* rows [*y0, *y1) of tiles that meet the ellipse */
+static void ellipse_rows(const or_ellipse* e, int tile, int gy, int* y0, int* y1)
+{
+    const real invT = (real)1 / (real)tile;
+    const real fgy = (real)gy;
+    *y0 = (int)RMIN(RMAX(RFLOOR((e->v - e->hy) * invT), (real)0), fgy);
+    *y1 = (int)RMIN(RMAX(RFLOOR((e->v + e->hy) * invT) + (real)1, (real)0), fgy);
+}
+
+/* column range [*xa, *xb) of tile row ty (empty if *xb <= *xa) */
+static void ellipse_span(const or_ellipse* e, int tile, int gx, int ty, int* xa, int* xb)
+{
+    const real invT = (real)1 / (real)tile;
+    const real fgx = (real)gx;
+    real ya = (real)(ty * tile) - e->v;
+    real yb = (real)((ty + 1) * tile) - e->v;
+    ya = RMAX(ya, -e->hy);
+    yb = RMIN(yb, e->hy);
+    const real xmax = (ya <= e->ys && e->ys <= yb) ? e->hx
+                                                   : RMAX(ellipse_xp(e, ya), ellipse_xp(e, yb));
+    const real xmin = (ya <= -e->ys && -e->ys <= yb) ? -e->hx
+                                                     : RMIN(ellipse_xm(e, ya), ellipse_xm(e, yb));
+    *xa = (int)RMIN(RMAX(RFLOOR((e->u + xmin) * invT), (real)0), fgx);
+    *xb = (int)RMIN(RMAX(RFLOOR((e->u + xmax) * invT) + (real)1, (real)0), fgx);
+}
+
 /* Real spherical harmonics up to degree 3, orthonormal on the unit sphere,
  * in the sign convention common to 3DGS trainers. */
 static const double SH_C0 = 0.28209479177387814;  /* 1/(2 sqrt(pi)) */
@@ -249,7 +349,7 @@ static int covariance3d(const real* lsc, const real* quat, or_proj* P)
 }
 
 static void project_one(const real* mean, const real* lsc, const real* quat, real logit,
-                        const real* sh, const or_view* vw, int tile, or_proj* P)
+                        const real* sh, const or_view* vw, int tile, int cull, or_proj* P)
 {
     memset(P, 0, sizeof(*P));
     if (!finite_all(mean, 3) || !finite_all(lsc, 3) || !finite_all(quat, 4) || !isfinite(logit) ||
@@ -326,10 +426,27 @@ static void project_one(const real* mean, const real* lsc, const real* quat, rea
     const real fy1 = RMIN(RMAX(RFLOOR((P->v + r) * invT) + (real)1, (real)0), fgy);
     P->x0 = (int32_t)fx0; P->x1 = (int32_t)fx1;
     P->y0 = (int32_t)fy0; P->y1 = (int32_t)fy1;
-    if (!(P->x1 > P->x0 && P->y1 > P->y0)) return;
+    uint32_t count = (uint32_t)((P->x1 - P->x0) * (P->y1 - P->y0));
 
     /* opacity */
     P->o = sigmoid_param((real)logit);
+
+    if (cull == 1) {
+        /* exact culling: rows of the opacity-threshold ellipse, column spans per row;
+         * the rectangle becomes the ellipse's bounding tile box */
+        or_ellipse e;
+        if (!ellipse_setup(P->u, P->v, P->A, P->B, P->C, P->o, &e)) return;
+        ellipse_rows(&e, tile, gy, &P->y0, &P->y1);
+        P->x0 = (int32_t)RMIN(RMAX(RFLOOR((e.u - e.hx) * invT), (real)0), fgx);
+        P->x1 = (int32_t)RMIN(RMAX(RFLOOR((e.u + e.hx) * invT) + (real)1, (real)0), fgx);
+        count = 0;
+        for (int ty = P->y0; ty < P->y1; ++ty) {
+            int xa, xb;
+            ellipse_span(&e, tile, gx, ty, &xa, &xb);
+            if (xb > xa) count += (uint32_t)(xb - xa);
+        }
+    }
+    if (!(P->x1 > P->x0 && P->y1 > P->y0) || count == 0) return;
 
     /* view-dependent colour: SH degree 3 along the camera-to-mean direction */
     real dv[3];
@@ -347,7 +464,7 @@ static void project_one(const real* mean, const real* lsc, const real* quat, rea
         P->col[k] = RMAX(s + (real)0.5, (real)0);
     }
 
-    P->tiles = (uint32_t)((P->x1 - P->x0) * (P->y1 - P->y0));
+    P->tiles = count;
     P->valid = 1;
 }
 
@@ -355,15 +472,15 @@ static void project_one(const real* mean, const real* lsc, const real* quat, rea
  * [view][gaussian]; float outputs are widened to double for the caller. */
 void or_project(const real* means, const real* log_scales, const real* quats,
                 const real* logits, const real* sh, int64_t n, const or_view* views, int n_views,
-                int tile, double* xy, double* conic, double* opac, double* rgb, double* depth,
-                double* radius, double* cov2d, int32_t* rect, uint32_t* tiles)
+                int tile, int cull, double* xy, double* conic, double* opac, double* rgb,
+                double* depth, double* radius, double* cov2d, int32_t* rect, uint32_t* tiles)
 {
     for (int vi = 0; vi < n_views; ++vi) {
 #pragma omp parallel for schedule(static)
         for (int64_t g = 0; g < n; ++g) {
             or_proj P;
             project_one(means + 3 * g, log_scales + 3 * g, quats + 4 * g, logits[g], sh + 48 * g,
-                        views + vi, tile, &P);
+                        views + vi, tile, cull, &P);
             const int64_t o = (int64_t)vi * n + g;
             xy[2 * o + 0] = P.u; xy[2 * o + 1] = P.v;
             conic[3 * o + 0] = P.A; conic[3 * o + 1] = P.B; conic[3 * o + 2] = P.C;
@@ -424,10 +541,12 @@ uint32_t or_depth_key(float z, int D)
 }
 
 /* For each view v and Gaussian g, write one (key, value) per touched tile:
- * rows y0..y1-1 outer, columns x0..x1-1 inner, at positions starting at
- * offsets[v*n+g].  key = (tile << D) | depth bits; value = the position itself
- * (the unsorted intersection index); gid = g. */
+ * rows y0..y1-1 outer, columns inner (x0..x1-1 for the 3-sigma rectangle,
+ * the row's span for exact culling), at positions starting at offsets[v*n+g].
+ * key = (tile << D) | depth bits; value = the position itself (the unsorted
+ * intersection index); gid = g. */
 void or_emit_keys(const int32_t* rect, const uint32_t* tiles, const double* depth,
+                  const double* xy, const double* conic, const double* opac, int cull,
                   const uint32_t* offsets, int64_t n, const or_view* views, int n_views, int tile,
                   uint32_t* keys, uint32_t* vals, uint32_t* gid)
 {
@@ -441,14 +560,21 @@ void or_emit_keys(const int32_t* rect, const uint32_t* tiles, const double* dept
             if (tiles[o] == 0) continue;
             uint32_t pos = offsets[o];
             const uint32_t dk = or_depth_key((float)depth[o], D);
-            for (int ty = rect[4 * o + 1]; ty < rect[4 * o + 3]; ++ty)
-                for (int tx = rect[4 * o + 0]; tx < rect[4 * o + 2]; ++tx) {
+            or_ellipse e;
+            if (cull == 1)
+                ellipse_setup((real)xy[2 * o], (real)xy[2 * o + 1], (real)conic[3 * o],
+                              (real)conic[3 * o + 1], (real)conic[3 * o + 2], (real)opac[o], &e);
+            for (int ty = rect[4 * o + 1]; ty < rect[4 * o + 3]; ++ty) {
+                int xa = rect[4 * o + 0], xb = rect[4 * o + 2];
+                if (cull == 1) ellipse_span(&e, tile, gx, ty, &xa, &xb);
+                for (int tx = xa; tx < xb; ++tx) {
                     const uint32_t t = (uint32_t)(ty * gx + tx);
                     keys[pos] = (t << D) | dk;
                     vals[pos] = pos;
                     gid[pos] = (uint32_t)g;
                     ++pos;
                 }
+            }
         }
     }
 }
@@ -799,7 +925,7 @@ void or_raster_bwd(const double* xy, const double* conic, const double* opac, co
  * opacity logit(1), SH coefficient m*3+k (48).  Sums over views. */
 void or_project_bwd(const real* means, const real* log_scales, const real* quats,
                     const real* logits, const real* sh, int64_t n, const or_view* views,
-                    int n_views, int tile, const double* grads2d, double* grads)
+                    int n_views, int tile, int cull, const double* grads2d, double* grads)
 {
 #pragma omp parallel for schedule(static)
     for (int64_t g = 0; g < n; ++g) {
@@ -808,7 +934,7 @@ void or_project_bwd(const real* means, const real* log_scales, const real* quats
         for (int vi = 0; vi < n_views; ++vi) {
             or_proj P;
             project_one(means + 3 * g, log_scales + 3 * g, quats + 4 * g, logits[g], sh + 48 * g,
-                        views + vi, tile, &P);
+                        views + vi, tile, cull, &P);
             if (!P.valid) continue;
             const acc* d2 = grads2d + 9 * ((int64_t)vi * n + g);
             const acc du = d2[0], dv = d2[1], dA = d2[2], dB = d2[3], dC = d2[4], dop = d2[5];
@@ -1003,6 +1129,25 @@ void or_sh_basis(const double* dir, double* Y)
 }
 
 double or_exp_param(double x) { return (double)exp_param((real)x); }
+double or_log_spec(double x) { return (double)log_spec((real)x); }
+
+/* Tile set of one screen-space Gaussian under exact culling, for tests:
+ * writes 1 into mask[ty * gx + tx] for each listed tile; returns the count
+ * (0 if the Gaussian is culled). */
+int or_ellipse_tiles(double u, double v, double A, double B, double C, double o, int tile, int gx,
+                     int gy, uint8_t* mask)
+{
+    or_ellipse e;
+    if (!ellipse_setup((real)u, (real)v, (real)A, (real)B, (real)C, (real)o, &e)) return 0;
+    int y0, y1, count = 0;
+    ellipse_rows(&e, tile, gy, &y0, &y1);
+    for (int ty = y0; ty < y1; ++ty) {
+        int xa, xb;
+        ellipse_span(&e, tile, gx, ty, &xa, &xb);
+        for (int tx = xa; tx < xb; ++tx) { mask[ty * gx + tx] = 1; ++count; }
+    }
+    return count;
+}
 double or_sigmoid(double x) { return (double)sigmoid_param((real)x); }
 
 int or_threads(void)

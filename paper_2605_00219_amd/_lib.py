@@ -50,7 +50,8 @@ class GsBins(C.Structure):
 
 
 class GsGrads2d(C.Structure):
-    _fields_ = [("rec", C.c_void_p), ("tile_stop", C.c_void_p), ("sums", C.c_void_p)]
+    _fields_ = [("rec", C.c_void_p), ("tile_stop", C.c_void_p), ("sums", C.c_void_p),
+                ("workspace", C.c_void_p)]
 
 
 class GsImage(C.Structure):
@@ -73,6 +74,7 @@ _SIGS = {
     "gs_last_error": (C.c_char_p, []),
     "gs_layout_init": (C.c_int, [_P, _P, C.c_int, C.c_int, C.POINTER(GsLayout)]),
     "gs_bin_sort_workspace_size": (C.c_size_t, [C.c_int64, C.POINTER(GsLayout), C.c_int64]),
+    "gs_grads2d_workspace_size": (C.c_size_t, [C.c_int64]),
     "gs_project": (C.c_int, [_P, C.c_int64, _P, C.POINTER(GsLayout), C.POINTER(GsSplats), _P]),
     "gs_bin_sort": (C.c_int, [C.POINTER(GsSplats), C.c_int64, C.POINTER(GsLayout), C.POINTER(GsBins),
                               _P, C.c_size_t, _P]),

@@ -33,65 +33,87 @@ struct GatherArgs {
     int32_t depth_bits[GS_MAX_VIEWS];
     int n_views;
     float* sums;
+    uint32_t* block_first;  // per block: the (view, Gaussian) owning its first index
+    float* part_first;      // per block, 9 floats: sum of its first run if that run
+                            // belongs to a Gaussian that started in an earlier block
+    float* part_last;       // per block, 9 floats: sum of its last run if that run's
+                            // Gaussian started in this block and continues after it
 };
 
-constexpr int kGatherG = 256;   // (view, Gaussian) entries per workgroup = threads
+constexpr int kGatherThreads = 256;
+constexpr int kGatherE = 1024;   // intersection indices per workgroup
 
-// A workgroup owns kGatherG consecutive (view, Gaussian) entries; their
-// intersections form the contiguous index range [offsets[o0], offsets[o0 +
-// kGatherG]), swept kGatherG indices at a time.  In each sweep thread t takes
-// index i = begin + t (coalesced record loads), finds its Gaussian by binary
-// search over the staged offsets, tests traversal against its tile's stop
-// entry and parks the record (or zeros) in LDS; then the thread owning each
-// Gaussian adds the slice of the sweep that belongs to it, in index order.
-// Long lists therefore cost one LDS pass per sweep instead of serialising
-// one thread on dependent global loads.  grid: ceil(views * n / kGatherG).
-__global__ __launch_bounds__(kGatherG) void k_gather2d(GatherArgs a) {
-    __shared__ uint32_t s_off[kGatherG + 1];
-    __shared__ uint32_t s_xy[kGatherG];
-    __shared__ uint32_t s_w[kGatherG];
-    __shared__ uint32_t s_key[kGatherG];   // depth code >> (23 - D)
-    __shared__ uint32_t s_view[kGatherG];
-    __shared__ float s_rec[kGatherG][9];
+size_t gather_workspace(int64_t capacity) {
+    const size_t nb = (size_t)((capacity + kGatherE - 1) / kGatherE) + 1;
+    auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+    return up(4 * (nb + 1)) + 2 * up(4 * 9 * nb);
+}
+
+static void carve_gather(void* ws, int64_t capacity, GatherArgs& g) {
+    const size_t nb = (size_t)((capacity + kGatherE - 1) / kGatherE) + 1;
+    auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+    char* p = static_cast<char*>(ws);
+    g.block_first = reinterpret_cast<uint32_t*>(p);
+    p += up(4 * (nb + 1));
+    g.part_first = reinterpret_cast<float*>(p);
+    p += up(4 * 9 * nb);
+    g.part_last = reinterpret_cast<float*>(p);
+}
+
+// block_first[b] = the (view, Gaussian) whose index range holds index b * E.
+__global__ __launch_bounds__(256) void k_gather_index(const uint32_t* __restrict__ offsets, int64_t vn,
+                                                      int64_t capacity, uint32_t* __restrict__ block_first) {
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= vn) return;
+    const uint64_t b = min((uint64_t)offsets[o], (uint64_t)capacity);
+    const uint64_t e = min((uint64_t)offsets[o + 1], (uint64_t)capacity);
+    for (uint64_t blk = (b + kGatherE - 1) / kGatherE; blk * kGatherE < e; ++blk)
+        block_first[blk] = (uint32_t)o;
+}
+
+// Gather: workgroup b owns the intersection indices [b E, (b+1) E).  Each
+// index finds its (view, Gaussian) by binary search over the offsets
+// (bounded by the owners of this block's and the next block's first index),
+// tests traversal against its tile's stop entry and parks its record (or
+// zeros) in LDS, with coalesced record loads.  Then the first index of every
+// run of equal owner adds up its run in index order: a run that is the whole
+// of its Gaussian's range is written to sums directly; the block's first and
+// last runs, if their Gaussian extends past the block, go to per-block
+// partials that the chain-rule kernel adds in block order.  No workgroup
+// handles more than E indices, however long one Gaussian's list is.
+__global__ __launch_bounds__(kGatherThreads) void k_gather2d(GatherArgs a) {
+    __shared__ float s_rec[kGatherE][9];
+    __shared__ uint32_t s_own[kGatherE];
     const int64_t vn = (int64_t)a.n_views * a.n;
-    const int64_t o0 = (int64_t)blockIdx.x * kGatherG;
+    const uint64_t kc = min((uint64_t)a.offsets[vn], (uint64_t)a.capacity);
+    const uint64_t e0 = (uint64_t)blockIdx.x * kGatherE;
+    if (e0 >= kc) return;
+    const uint64_t e1 = min(e0 + (uint64_t)kGatherE, kc);
+    const uint32_t nblk = (uint32_t)((kc + kGatherE - 1) / kGatherE);
+    const uint32_t oa = a.block_first[blockIdx.x];
+    const uint32_t oz = blockIdx.x + 1 < nblk ? a.block_first[blockIdx.x + 1] : (uint32_t)(vn - 1);
     const int t = threadIdx.x;
-    const int64_t o = o0 + t;
-    const int64_t oc = o < vn ? o : vn;
-    s_off[t] = (uint32_t)min((uint64_t)a.offsets[oc], (uint64_t)a.capacity);
-    if (t == 0) {
-        const int64_t oe = o0 + kGatherG < vn ? o0 + kGatherG : vn;
-        s_off[kGatherG] = (uint32_t)min((uint64_t)a.offsets[oe], (uint64_t)a.capacity);
-    }
-    s_xy[t] = 0u; s_w[t] = 1u; s_key[t] = 0u; s_view[t] = 0u;
-    if (o < vn && a.offsets[o + 1] > a.offsets[o]) {
-        const int v = (int)(o / a.n);
-        const float4 q3 = a.rec[4 * o + 3];
-        const uint32_t r0 = __float_as_uint(q3.x), r1 = __float_as_uint(q3.y);
-        s_xy[t] = r0;
-        s_w[t] = (r1 & 0xFFFF) - (r0 & 0xFFFF);
-        s_key[t] = __float_as_uint(q3.z) >> (23 - a.depth_bits[v]);
-        s_view[t] = (uint32_t)v;
-    }
-    __syncthreads();
-    float d[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    const uint32_t begin = s_off[0], end = s_off[kGatherG];
-    const uint32_t my_b = s_off[t], my_e = s_off[t + 1];
-    for (uint32_t pb = begin; pb < end; pb += kGatherG) {
-        const uint32_t i = pb + (uint32_t)t;
+    const int cnt = (int)(e1 - e0);
+    for (int j = t; j < kGatherE; j += kGatherThreads) {
         float r[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        if (i < end) {
-            int lo = 0, hi = kGatherG - 1;
+        uint32_t own = 0xFFFFFFFFu;
+        if (j < cnt) {
+            const uint32_t i = (uint32_t)(e0 + (uint64_t)j);
+            uint32_t lo = oa, hi = oz;
             while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (s_off[mid] <= i) lo = mid; else hi = mid - 1;
+                const uint32_t mid = lo + ((hi - lo + 1) >> 1);
+                if (a.offsets[mid] <= i) lo = mid; else hi = mid - 1;
             }
-            const uint32_t k = i - s_off[lo];
-            const uint32_t w = s_w[lo], xy = s_xy[lo];
-            const int v = (int)s_view[lo];
-            const uint32_t tile = ((xy >> 16) + k / w) * (uint32_t)a.gx[v] + (xy & 0xFFFF) + k % w;
+            own = lo;
+            const int v = (int)((int64_t)lo / a.n);
+            const float4 q3 = a.rec[4 * (int64_t)lo + 3];
+            const uint32_t r0 = __float_as_uint(q3.x), r1 = __float_as_uint(q3.y);
+            const uint32_t w = (r1 & 0xFFFF) - (r0 & 0xFFFF);
+            const uint32_t k = i - a.offsets[lo];
+            const uint32_t tile = ((r0 >> 16) + k / w) * (uint32_t)a.gx[v] + (r0 & 0xFFFF) + k % w;
             const uint4 st = a.stop[a.tile_base[v] + (int)tile];
-            const uint32_t key = (tile << a.depth_bits[v]) | s_key[lo];
+            const int D = a.depth_bits[v];
+            const uint32_t key = (tile << D) | (__float_as_uint(q3.z) >> (23 - D));
             if (key < st.y || (key == st.y && i < st.z)) {
                 const float4* g = a.grec + 3 * (int64_t)i;
                 const float4 q0 = g[0], q1 = g[1], q2 = g[2];
@@ -99,22 +121,59 @@ __global__ __launch_bounds__(kGatherG) void k_gather2d(GatherArgs a) {
                 r[4] = q1.x; r[5] = q1.y; r[6] = q1.z; r[7] = q1.w; r[8] = q2.x;
             }
         }
-        __syncthreads();
 #pragma unroll
-        for (int c = 0; c < 9; ++c) s_rec[t][c] = r[c];
-        __syncthreads();
-        const uint32_t pe = min(end, pb + (uint32_t)kGatherG);
-        const uint32_t sb = max(my_b, pb), se = min(my_e, pe);
-        for (uint32_t j = sb; j < se; ++j) {
-            const float* q = s_rec[j - pb];
+        for (int c = 0; c < 9; ++c) s_rec[j][c] = r[c];
+        s_own[j] = own;
+    }
+    __syncthreads();
+    for (int j = t; j < cnt; j += kGatherThreads) {
+        const uint32_t own = s_own[j];
+        if (j > 0 && s_own[j - 1] == own) continue;   // not the start of a run
+        float d[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        int jj = j;
+        for (; jj < cnt && s_own[jj] == own; ++jj) {
 #pragma unroll
-            for (int c = 0; c < 9; ++c) d[c] += q[c];
+            for (int c = 0; c < 9; ++c) d[c] += s_rec[jj][c];
         }
-    }
-    if (o < vn) {
+        const uint64_t gb = a.offsets[own];
+        const uint64_t ge = min((uint64_t)a.offsets[own + 1], (uint64_t)a.capacity);
+        const bool before = gb < e0, after = ge > e1;
+        float* dst;
+        int64_t stride;
+        if (!before && !after) { dst = a.sums + own; stride = vn; }
+        else if (before) { dst = a.part_first + 9 * (int64_t)blockIdx.x; stride = 1; }
+        else { dst = a.part_last + 9 * (int64_t)blockIdx.x; stride = 1; }
 #pragma unroll
-        for (int c = 0; c < 9; ++c) a.sums[c * vn + o] = d[c];
+        for (int c = 0; c < 9; ++c) dst[c * stride] = d[c];
     }
+}
+
+// Sum of the records of (view, Gaussian) o: complete runs come from sums;
+// a range split over blocks b0 < b1 is part_last[b0] + part_first[b0+1] + ...
+// + part_first[b1], in that order.  Empty ranges give zeros.  The result is
+// also stored to sums for ranges that were split or empty.
+GS_DEV void gather_total(const GatherArgs& a, int64_t o, int64_t vn, float d[9]) {
+    const uint64_t b = min((uint64_t)a.offsets[o], (uint64_t)a.capacity);
+    const uint64_t e = min((uint64_t)a.offsets[o + 1], (uint64_t)a.capacity);
+    if (e <= b) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) { d[c] = 0.f; a.sums[c * vn + o] = 0.f; }
+        return;
+    }
+    const uint64_t b0 = b / kGatherE, b1 = (e - 1) / kGatherE;
+    if (b0 == b1) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) d[c] = a.sums[c * vn + o];
+        return;
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) d[c] = a.part_last[9 * b0 + c];
+    for (uint64_t blk = b0 + 1; blk <= b1; ++blk) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) d[c] += a.part_first[9 * blk + c];
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) a.sums[c * vn + o] = d[c];
 }
 
 struct AdamArgs {
@@ -124,8 +183,7 @@ struct AdamArgs {
     int n_views;
     int tile;
     int32_t gx[GS_MAX_VIEWS], gy[GS_MAX_VIEWS];
-    const uint32_t* offsets;
-    const float* sums;
+    GatherArgs ga;
     float4* m;
     float4* v;
     const float* bias;  // [0] = 1 - beta1^t, [1] = sqrt(1 - beta2^t)
@@ -189,18 +247,15 @@ __global__ __launch_bounds__(256) void k_project_bwd_adam(AdamArgs a) {
     for (int i = 0; i < 48; ++i) gsh[i] = 0.f;
 
     const int64_t vn = (int64_t)a.n_views * n;
-    for (int vi = 0; vi < a.n_views && finite; ++vi) {
+    for (int vi = 0; vi < a.n_views; ++vi) {
         const int64_t o = (int64_t)vi * n + g;
-        const uint32_t b = a.offsets[o];
-        const uint32_t e = a.offsets[o + 1];
-        if (e == b) continue;
+        float d[9];
+        gather_total(a.ga, o, vn, d);
+        if (!finite || a.ga.offsets[o + 1] == a.ga.offsets[o]) continue;
         const gs_view vw = a.views[vi];
         Proj P;
         project_gaussian<true>(p0, p1, p2, sh, vw, a.tile, a.gx[vi], a.gy[vi], P);
         if (!P.valid) continue;
-        float d[9];
-#pragma unroll
-        for (int c = 0; c < 9; ++c) d[c] = a.sums[c * vn + o];
 
         float dmean[3] = {0.f, 0.f, 0.f};
         // colour: c = max(0, raw + 1/2), raw = sum_m sh[m] Y_m(dir)
@@ -389,6 +444,7 @@ int launch_project_bwd_adam(float* params, int64_t n, const gs_view* views, cons
     ga.capacity = b.capacity;
     ga.n_views = L.n_views;
     ga.sums = grads.sums;
+    carve_gather(grads.workspace, b.capacity, ga);
     AdamArgs a;
     memset(&a, 0, sizeof(a));
     a.params = reinterpret_cast<float4*>(params);
@@ -403,8 +459,6 @@ int launch_project_bwd_adam(float* params, int64_t n, const gs_view* views, cons
         ga.tile_base[v] = v < L.n_views ? L.tile_base[v] : 0;
         ga.depth_bits[v] = v < L.n_views ? L.depth_bits[v] : 0;
     }
-    a.offsets = b.offsets;
-    a.sums = grads.sums;
     a.grads_out = reinterpret_cast<float4*>(grads_out);
     if (adam) {
         a.m = reinterpret_cast<float4*>(adam->m);
@@ -420,10 +474,17 @@ int launch_project_bwd_adam(float* params, int64_t n, const gs_view* views, cons
         if (rc != GS_OK) return rc;
     }
     const int64_t vn = (int64_t)L.n_views * n;
-    hipLaunchKernelGGL(k_gather2d, dim3((unsigned)((vn + kGatherG - 1) / kGatherG)), dim3(kGatherG), 0,
-                       s, ga);
-    rc = check_launch("gather2d");
+    hipLaunchKernelGGL(k_gather_index, dim3((unsigned)((vn + 255) / 256)), dim3(256), 0, s, b.offsets, vn,
+                       b.capacity, ga.block_first);
+    rc = check_launch("gather_index");
     if (rc != GS_OK) return rc;
+    if (b.capacity > 0) {
+        hipLaunchKernelGGL(k_gather2d, dim3((unsigned)((b.capacity + kGatherE - 1) / kGatherE)),
+                           dim3(kGatherThreads), 0, s, ga);
+        rc = check_launch("gather2d");
+        if (rc != GS_OK) return rc;
+    }
+    a.ga = ga;
     hipLaunchKernelGGL(k_project_bwd_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
     return check_launch("project_bwd_adam");
 }

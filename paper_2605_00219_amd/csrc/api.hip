@@ -98,6 +98,11 @@ size_t gs_bin_sort_workspace_size(int64_t n, const gs_layout* layout, int64_t ca
     return bin_sort_workspace(n, *layout, capacity);
 }
 
+size_t gs_grads2d_workspace_size(int64_t capacity) {
+    if (capacity < 0) return 0;
+    return gather_workspace(capacity);
+}
+
 int gs_project(const float* params, int64_t n, const gs_view* views, const gs_layout* layout,
                const gs_splats* out, void* stream) {
     REQUIRE(layout_ok(layout), "gs_project: invalid layout");
@@ -167,8 +172,8 @@ int gs_project_bwd_adam(float* params, int64_t n, const gs_view* views, const gs
     REQUIRE(!adam || (adam->m && adam->v && adam->step && adam->scratch),
             "gs_project_bwd_adam: incomplete adam state");
     REQUIRE(splats && (n == 0 || splats->rec), "gs_project_bwd_adam: null splat records");
-    REQUIRE(grads && grads->tile_stop && (grads->sums || n == 0) && (grads->rec || bins->capacity == 0),
-            "gs_project_bwd_adam: null gradient buffers");
+    REQUIRE(grads && grads->tile_stop && (grads->sums || n == 0) && (grads->rec || bins->capacity == 0) &&
+            grads->workspace, "gs_project_bwd_adam: null gradient buffers");
     return launch_project_bwd_adam(params, n, views, *layout, *splats, *bins, *grads, adam, grads_out,
                                    (hipStream_t)stream);
 }

@@ -38,6 +38,7 @@ int launch_project(const float* params, int64_t n, const gs_view* views, const g
 int launch_bin_sort(const gs_splats& sp, int64_t n, const gs_layout& L, const gs_bins& b,
                     void* ws, size_t ws_bytes, hipStream_t s);
 size_t bin_sort_workspace(int64_t n, const gs_layout& L, int64_t capacity);
+size_t gather_workspace(int64_t capacity);
 int launch_raster_fwd(const gs_splats& sp, int64_t n, const gs_layout& L, const gs_bins& b,
                       const gs_view* views, const gs_image& out, int lds_batch,
                       const gs_schedule* sched, hipStream_t s);

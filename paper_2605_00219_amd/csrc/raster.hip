@@ -279,14 +279,22 @@ GS_DEV float dpp(float v) {
         float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xF, false));
 }
 
-GS_DEV float wave_sum_to_last(float v) {
+// Sum over the 16 lanes of each DPP row; every lane of the row gets the sum.
+GS_DEV float row_sum(float v) {
     v += dpp<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
     v += dpp<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
     v += dpp<0x141, 0xF>(v);  // row_half_mirror
-    v += dpp<0x140, 0xF>(v);  // row_mirror: every lane holds its row's sum
-    v += dpp<0x142, 0xA>(v);  // row_bcast:15 into rows 1, 3
-    v += dpp<0x143, 0xC>(v);  // row_bcast:31 into rows 2, 3
+    v += dpp<0x140, 0xF>(v);  // row_mirror
     return v;
+}
+
+// Sum of x over the four rows of the wavefront at the same row position
+// (lane-wise exchange through ds_bpermute); every lane gets its column's sum.
+// addr16 = 4 (lane ^ 16), addr32 = 4 (lane ^ 32).
+GS_DEV float sum_rows(float x, int addr16, int addr32) {
+    x += __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addr16, __builtin_bit_cast(int, x)));
+    x += __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addr32, __builtin_bit_cast(int, x)));
+    return x;
 }
 
 // ---------------------------------------------------------------------------
@@ -314,8 +322,9 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd(RasterArgs a)
         if (gt == -2) continue;
         const TileInfo ti = tile_info(a, gt);
         const uint32_t start = ti.range.x;
-        float px[PPT], py[PPT], Co0[PPT], Co1[PPT], Co2[PPT], g0[PPT], g1[PPT], g2[PPT];
-        float T[PPT], Ca0[PPT], Ca1[PPT], Ca2[PPT];
+        // per pixel: dL/dC (g), transmittance T and R = g . (colour composited
+        // behind the current entry, background included), starting at g . C_out
+        float px[PPT], py[PPT], g0[PPT], g1[PPT], g2[PPT], T[PPT], R[PPT];
         uint32_t lastp[PPT];
         float l1 = 0.0f;
         uint32_t mylen = 0;
@@ -325,19 +334,19 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd(RasterArgs a)
             const int ix = ti.tx * TILE + p % TILE, iy = ti.ty * TILE + p / TILE;
             px[q] = (float)ix + 0.5f;
             py[q] = (float)iy + 0.5f;
-            Co0[q] = Co1[q] = Co2[q] = g0[q] = g1[q] = g2[q] = 0.0f;
-            T[q] = 1.0f; Ca0[q] = Ca1[q] = Ca2[q] = 0.0f;
+            g0[q] = g1[q] = g2[q] = 0.0f;
+            T[q] = 1.0f; R[q] = 0.0f;
             lastp[q] = 0;
             if (ix < ti.W && iy < ti.H) {
                 const int64_t pix = ti.pix_base + (int64_t)iy * ti.W + ix;
-                Co0[q] = a.out_rgb[3 * pix + 0];
-                Co1[q] = a.out_rgb[3 * pix + 1];
-                Co2[q] = a.out_rgb[3 * pix + 2];
+                const float Co0 = a.out_rgb[3 * pix + 0];
+                const float Co1 = a.out_rgb[3 * pix + 1];
+                const float Co2 = a.out_rgb[3 * pix + 2];
                 lastp[q] = a.out_last[pix];
                 if (a.target) {
-                    const float d0 = Co0[q] - a.target[3 * pix + 0];
-                    const float d1 = Co1[q] - a.target[3 * pix + 1];
-                    const float d2 = Co2[q] - a.target[3 * pix + 2];
+                    const float d0 = Co0 - a.target[3 * pix + 0];
+                    const float d1 = Co1 - a.target[3 * pix + 1];
+                    const float d2 = Co2 - a.target[3 * pix + 2];
                     g0[q] = d0 > 0.0f ? a.inv_count : (d0 < 0.0f ? -a.inv_count : 0.0f);
                     g1[q] = d1 > 0.0f ? a.inv_count : (d1 < 0.0f ? -a.inv_count : 0.0f);
                     g2[q] = d2 > 0.0f ? a.inv_count : (d2 < 0.0f ? -a.inv_count : 0.0f);
@@ -347,9 +356,15 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd(RasterArgs a)
                     g1[q] = a.dLdC[3 * pix + 1];
                     g2[q] = a.dLdC[3 * pix + 2];
                 }
+                R[q] = __builtin_fmaf(g2[q], Co2, __builtin_fmaf(g1[q], Co1, g0[q] * Co0));
             }
             mylen = max(mylen, lastp[q]);
         }
+        // lane j < 9 of each DPP row collects reduced component j
+        bool sel[9];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) sel[c] = (lane & 15) == c;
+        const int addr16 = (lane ^ 16) << 2, addr32 = (lane ^ 32) << 2;
         __syncthreads();
         if (threadIdx.x == 0) s_len = 0;
         if (a.loss) {
@@ -407,23 +422,20 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd(RasterArgs a)
                           v7 = 0.f, v8 = 0.f;
 #pragma unroll
                     for (int q = 0; q < PPT; ++q) {
-                        const bool contrib = cq[q];
-                        const float alpha = alq[q], dx = dxq[q], dy = dyq[q];
-                        // pixels that do not composite this Gaussian select zeros
-                        const float wgt = contrib ? alpha * T[q] : 0.0f;
+                        // pixels that do not composite this Gaussian use alpha = 0
+                        const float ae = cq[q] ? alq[q] : 0.0f;
+                        const float wgt = ae * T[q];
                         v6 = __builtin_fmaf(wgt, g0[q], v6);
                         v7 = __builtin_fmaf(wgt, g1[q], v7);
                         v8 = __builtin_fmaf(wgt, g2[q], v8);
-                        Ca0[q] = __builtin_fmaf(wgt, sh.z, Ca0[q]);
-                        Ca1[q] = __builtin_fmaf(wgt, sh.w, Ca1[q]);
-                        Ca2[q] = __builtin_fmaf(wgt, cb, Ca2[q]);
                         const float gc = __builtin_fmaf(g2[q], cb, __builtin_fmaf(g1[q], sh.w, g0[q] * sh.z));
-                        const float gS = __builtin_fmaf(g2[q], Co2[q] - Ca2[q],
-                                                        __builtin_fmaf(g1[q], Co1[q] - Ca1[q],
-                                                                       g0[q] * (Co0[q] - Ca0[q])));
-                        const float one_m = 1.0f - alpha;
-                        const float dalpha = T[q] * gc - gS / one_m;
-                        const float dpow = (contrib && !(agq[q] > kAlphaMax)) ? alpha * dalpha : 0.0f;
+                        R[q] = __builtin_fmaf(-wgt, gc, R[q]);
+                        const float inv1m = __builtin_amdgcn_rcpf(1.0f - alq[q]);
+                        const float dalpha = __builtin_fmaf(T[q], gc, -(R[q] * inv1m));
+                        // no gradient through the clamp at 0.99
+                        const float ag = (agq[q] > kAlphaMax) ? 0.0f : ae;
+                        const float dpow = ag * dalpha;
+                        const float dx = dxq[q], dy = dyq[q];
                         const float ddx = dpow * dx, ddy = dpow * dy;
                         v0 += dpow;
                         v1 += ddx;
@@ -431,22 +443,28 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd(RasterArgs a)
                         v3 = __builtin_fmaf(ddx, dx, v3);
                         v4 = __builtin_fmaf(ddx, dy, v4);
                         v5 = __builtin_fmaf(ddy, dy, v5);
-                        T[q] = contrib ? T[q] * one_m : T[q];
+                        T[q] = T[q] - wgt;
                     }
-                    v0 = wave_sum_to_last(v0);
-                    v1 = wave_sum_to_last(v1);
-                    v2 = wave_sum_to_last(v2);
-                    v3 = wave_sum_to_last(v3);
-                    v4 = wave_sum_to_last(v4);
-                    v5 = wave_sum_to_last(v5);
-                    v6 = wave_sum_to_last(v6);
-                    v7 = wave_sum_to_last(v7);
-                    v8 = wave_sum_to_last(v8);
-                    if (lane == kWave - 1) {
-                        float* r = s_red[w][kk];
-                        r[0] = v0; r[1] = v1; r[2] = v2; r[3] = v3; r[4] = v4;
-                        r[5] = v5; r[6] = v6; r[7] = v7; r[8] = v8;
-                    }
+                    v0 = row_sum(v0);
+                    v1 = row_sum(v1);
+                    v2 = row_sum(v2);
+                    v3 = row_sum(v3);
+                    v4 = row_sum(v4);
+                    v5 = row_sum(v5);
+                    v6 = row_sum(v6);
+                    v7 = row_sum(v7);
+                    v8 = row_sum(v8);
+                    float x = v0;
+                    x = sel[1] ? v1 : x;
+                    x = sel[2] ? v2 : x;
+                    x = sel[3] ? v3 : x;
+                    x = sel[4] ? v4 : x;
+                    x = sel[5] ? v5 : x;
+                    x = sel[6] ? v6 : x;
+                    x = sel[7] ? v7 : x;
+                    x = sel[8] ? v8 : x;
+                    x = sum_rows(x, addr16, addr32);
+                    if (lane < 9) s_red[w][kk][lane] = x;
                     used |= 1ull << kk;
                 }
                 if (lane == 0) s_mask[w] = used;

@@ -99,6 +99,8 @@ class Frame:
         self.grec = torch.zeros(capacity, 12, dtype=torch.float32, device=self.device)
         ws = G.lib.gs_bin_sort_workspace_size(self.n, C.byref(self.layout), capacity)
         self.workspace = torch.zeros(max(int(ws), 1), dtype=torch.uint8, device=self.device)
+        gws = G.lib.gs_grads2d_workspace_size(capacity)
+        self.gather_ws = torch.zeros(max(int(gws), 1), dtype=torch.uint8, device=self.device)
         self.capacity = capacity
         self._structs()
 
@@ -106,7 +108,7 @@ class Frame:
         self.splats = G.GsSplats(_i(self.rec), _i(self.tiles))
         self.bins = G.GsBins(_i(self.offsets), _i(self.keys), _i(self.vals), _i(self.ranges),
                              _i(self.status), self.capacity)
-        self.grads2d = G.GsGrads2d(_i(self.grec), _i(self.tile_stop), _i(self.sums))
+        self.grads2d = G.GsGrads2d(_i(self.grec), _i(self.tile_stop), _i(self.sums), _i(self.gather_ws))
         self.img = G.GsImage(_i(self.image), _i(self.T), _i(self.last),
                              _i(self.tile_stats) if self.tile_stats is not None else None)
 

@@ -534,3 +534,117 @@ def test_float32_oracle_agrees_with_float64_oracle_on_full_step():
     # every mismatch sits in a tile with a fragile pixel, and mismatches are rare
     assert np.all(ok_g[~ex]), np.argwhere(~ok_g & ~ex[:, None])[:10]
     assert (~ok_g).any(axis=1).mean() < 0.01
+
+
+# ---------------------------------------------------------------------------
+# exact tile culling (opacity-threshold ellipse, scan-line spans)
+# ---------------------------------------------------------------------------
+
+def test_log_spec_within_few_ulp_of_log():
+    xs = np.concatenate([np.geomspace(1.0001, 300.0, 3001), np.geomspace(1e-3, 0.999, 500),
+                         [1.0 + 2.0 ** -20, 2.0, 255.0, 0.5, 1.5, 1.41421356]]).astype(np.float32)
+    for x in xs:
+        exact = math.log(float(x))
+        got = oracle.log_spec(float(x))
+        tol = 4.0 * float(np.spacing(np.float32(abs(exact)))) + 1e-12
+        assert abs(got - exact) <= tol, (x, got, exact)
+    assert oracle.log_spec(3.7, double=True) == math.log(3.7)
+
+
+def _box_min_q(A, B, C, xl, xh, yl, yh):
+    """min of A x^2 + 2 B x y + C y^2 over the box [xl, xh] x [yl, yh] (float64);
+    convex, so the minimum is 0 inside or on an edge at the clamped 1D minimiser."""
+    if xl <= 0.0 <= xh and yl <= 0.0 <= yh:
+        return 0.0
+    q = lambda x, y: A * x * x + 2.0 * B * x * y + C * y * y
+    best = math.inf
+    for x in (xl, xh):
+        y = min(max(-B * x / C, yl), yh)
+        best = min(best, q(x, y))
+    for y in (yl, yh):
+        x = min(max(-B * y / A, xl), xh)
+        best = min(best, q(x, y))
+    return best
+
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_ellipse_tiles_match_brute_force_box_minimum(tile):
+    rng = np.random.default_rng(7000 + tile)
+    W, H = 333, 197
+    gx, gy = (W + tile - 1) // tile, (H + tile - 1) // tile
+    checked = fragile = 0
+    for _ in range(300):
+        # 2D covariance with a random orientation and aspect ratio up to 40
+        s1, s2 = np.exp(rng.uniform(np.log(0.8), np.log(60.0), 2))
+        th = rng.uniform(0, np.pi)
+        R = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+        S2 = R @ np.diag([s1 * s1, s2 * s2]) @ R.T
+        Q = np.linalg.inv(S2)
+        A, B, C = (float(np.float32(Q[0, 0])), float(np.float32(Q[0, 1])), float(np.float32(Q[1, 1])))
+        u, v = (float(np.float32(x)) for x in rng.uniform([-60, -60], [W + 60, H + 60]))
+        o = float(np.float32(np.exp(rng.uniform(np.log(0.002), 0.0))))
+        mask = oracle.ellipse_tiles(u, v, A, B, C, o, tile, gx, gy)
+        if 255.0 * o <= 1.0:
+            assert mask.sum() == 0
+            continue
+        tau = 2.0 * math.log(255.0 * o)
+        for ty in range(gy):
+            for tx in range(gx):
+                m = _box_min_q(A, B, C, tx * tile - u, (tx + 1) * tile - u, ty * tile - v,
+                               (ty + 1) * tile - v)
+                if abs(m - tau) <= 1e-4 * tau + 1e-9:
+                    fragile += 1
+                    continue
+                checked += 1
+                assert bool(mask[ty, tx]) == (m <= tau), (u, v, A, B, C, o, tx, ty, m, tau)
+    assert checked > 10000 and fragile < 1e-3 * checked
+
+
+def test_ellipse_emission_follows_the_spans_and_counts():
+    scene, views, _, _ = _two_view_bins()
+    pr = oracle.project(scene, views, 16, cull=oracle.CULL_ELLIPSE)
+    bins = oracle.bin_sort(pr, views, 16)
+    prr = oracle.project(scene, views, 16)
+    n = scene.n
+    assert bins.keys.size < oracle.bin_sort(prr, views, 16).keys.size
+    for vi, vw in enumerate(views):
+        gx = (int(vw["width"]) + 15) // 16
+        gy = (int(vw["height"]) + 15) // 16
+        D = oracle.depth_bits(gx * gy)
+        for g in range(n):
+            o = vi * n + g
+            b, e = int(bins.offsets[o]), int(bins.offsets[o + 1])
+            assert e - b == pr.tiles[vi, g]
+            u, v = pr.xy[vi, g]
+            A, B, C = pr.conic[vi, g]
+            mask = oracle.ellipse_tiles(u, v, A, B, C, pr.opacity[vi, g], 16, gx, gy) \
+                if prr.tiles[vi, g] or e > b else np.zeros((gy, gx), np.uint8)
+            want = np.flatnonzero(mask.reshape(-1))       # row-major = emission order
+            np.testing.assert_array_equal(bins.keys_unsorted[b:e] >> D, want)
+            if e > b:
+                x0, y0, x1, y1 = pr.rect[vi, g]
+                ty, tx = np.divmod(want, gx)
+                assert ty.min() >= y0 and ty.max() < y1 and tx.min() >= x0 and tx.max() < x1
+
+
+def test_ellipse_culling_changes_no_pixel_below_the_three_sigma_opacity():
+    # with o <= 0.35 the opacity ellipse lies inside the 3-sigma box, so exact
+    # culling only drops entries that composite nowhere: same pixels, same order
+    rng = np.random.default_rng(7100)
+    n = 1500
+    scene = _scene_from(rng.uniform(-1, 1, (n, 3)), rng.normal(-3.0, 0.5, (n, 3)),
+                        rng.normal(size=(n, 4)), np.log(np.full(n, 0.3) / 0.7) + rng.uniform(-4, 0, n),
+                        rng.normal(0, 0.3, (n, 48)))
+    views = S.views_array([S.make_view(200, 150, (0.0, 0.0, -4.0), bg=(0.1, 0.2, 0.3)),
+                           S.make_view(123, 77, (3.0, 1.0, -2.0))])
+    for double in (False, True):
+        pr = oracle.project(scene, views, 16, double)
+        pe = oracle.project(scene, views, 16, double, oracle.CULL_ELLIPSE)
+        br, be = oracle.bin_sort(pr, views, 16, double), oracle.bin_sort(pe, views, 16, double)
+        assert be.keys.size < 0.8 * br.keys.size
+        ir = oracle.raster_fwd(pr, br, views, 16, double)
+        ie = oracle.raster_fwd(pe, be, views, 16, double)
+        ok = (ir.fragile == 0) & (ie.fragile == 0)
+        assert ok.mean() > 0.99
+        np.testing.assert_array_equal(ir.rgb[ok], ie.rgb[ok])
+        np.testing.assert_array_equal(ir.T[ok], ie.T[ok])

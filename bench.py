@@ -78,8 +78,10 @@ def parse():
     ap.add_argument("--no-replay", action="store_true", help="skip the work-counting replay")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (for HBM counter scaling)")
-    ap.add_argument("--variants", default="batched,learned",
-                    help="comma list of extra measurements: batched, learned ('' for none)")
+    ap.add_argument("--variants", default="ellipse,batched,learned",
+                    help="comma list of extra measurements: ellipse, batched, learned ('none' for none)")
+    ap.add_argument("--cull", type=int, default=0, choices=(0, 1),
+                    help="tile set of the headline run: 0 = 3-sigma rectangle, 1 = exact ellipse")
     ap.add_argument("--batched-steps", type=int, default=200)
     ap.add_argument("--batched-plain-steps", type=int, default=25)
     ap.add_argument("--learned-steps", type=int, default=10)
@@ -120,99 +122,123 @@ def main():
         targets[i].copy_(P.render(tgt_model.params, tframe, vptr(i)))
     del tgt_model, tframe
 
-    model = P.Model(w.scene.flat(), lr=w.lr)
-    frame = P.Frame(n, [W], [H], 16)
-    kmax = 0
-    for i in range(ncam):
-        kmax = max(kmax, P.fit_capacity(model.params, frame, vptr(i)))
-    frame.resize(int(kmax * 1.3) + 4096)
-    order = [int(x) for x in w.view_order]
+    def run_plain(cull, replay):
+        """Timed plain steps (and the work-counting replay) with the given tile culling."""
+        model = P.Model(w.scene.flat(), lr=w.lr)
+        frame = P.Frame(n, [W], [H], 16, cull=cull)
+        kmax = 0
+        for i in range(ncam):
+            kmax = max(kmax, P.fit_capacity(model.params, frame, vptr(i)))
+        frame.resize(int(kmax * 1.3) + 4096)
+        order = [int(x) for x in w.view_order]
 
-    def step(i, ev=None):
-        vi = order[i % ncam]
-        vd = vptr(vi)
-        if ev is not None:
-            ev[0].record()
-        P.project(model.params, frame, vd)
-        if ev is not None:
-            ev[1].record()
-        P.bin_sort(frame)
-        if ev is not None:
-            ev[2].record()
-        P.rasterize_fwd(frame, vd, args.lds_batch)
-        if ev is not None:
-            ev[3].record()
-        P.rasterize_bwd(frame, vd, target=targets[vi], lds_batch=args.lds_batch)
-        if ev is not None:
-            ev[4].record()
-        P.project_bwd_adam(model, frame, vd)
-        if ev is not None:
-            ev[5].record()
-
-    log(f"warmup {args.warmup} steps (N={n}, {W}x{H}, K<={kmax})")
-    for i in range(args.warmup):
-        step(i)
-    torch.cuda.synchronize()
-    if frame.status_bits():
-        raise RuntimeError("intersection capacity exceeded during warmup")
-    state0 = [t.clone() for t in (model.params, model.m, model.v, model.step)]
-
-    # timed region: plain single-view steps
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(args.warmup + i, evs[i])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    if frame.status_bits():
-        raise RuntimeError("intersection capacity exceeded in the timed region")
-    wall = t1 - t0
-    stages = ["project", "bin_sort", "rasterize_fwd", "rasterize_bwd", "project_bwd_adam"]
-    stage_ms = {s: float(np.mean([evs[i][k].elapsed_time(evs[i][k + 1]) for i in range(args.steps)]))
-                for k, s in enumerate(stages)}
-    ips = args.steps / wall
-    log(f"plain: {ips:.1f} iters/s, {1e3 * wall / args.steps:.3f} ms/step; stages {stage_ms}")
-
-    # replay of the timed steps (deterministic) counting the work each kernel did
-    counts = None
-    if not args.no_replay:
-        for t, s0 in zip((model.params, model.m, model.v, model.step), state0):
-            t.copy_(s0)
-        rframe = P.Frame(n, [W], [H], 16, capacity=frame.capacity, tile_stats=True)
-        gx = (W + 15) // 16
-        tile_of_px = torch.arange(H * W, device=dev)
-        tile_of_px = (tile_of_px // W // 16) * gx + (tile_of_px % W) // 16
-        acc = dict(K=0, trav_bwd=0, eval_bwd=0, contrib=0, eval_fwd=0, trav_fwd=0, visible=0)
-        for i in range(args.steps):
-            vi = order[(args.warmup + i) % ncam]
+        def step(i, ev=None):
+            vi = order[i % ncam]
             vd = vptr(vi)
-            P.project(model.params, rframe, vd)
-            P.bin_sort(rframe)
-            P.rasterize_fwd(rframe, vd, args.lds_batch)
-            last = rframe.last.to(torch.int64)
-            per_tile = torch.zeros(rframe.layout.total_tiles, dtype=torch.int64, device=dev)
-            per_tile.scatter_reduce_(0, tile_of_px, last, reduce="amax")
-            ts = rframe.tile_stats.to(torch.int64)
-            acc["K"] += rframe.intersections()
-            acc["visible"] += int((rframe.tiles != 0).sum().item())
-            acc["trav_bwd"] += int(per_tile.sum().item())
-            acc["eval_bwd"] += int(last.sum().item())
-            acc["contrib"] += int(ts[:, 2].sum().item())
-            acc["eval_fwd"] += int(ts[:, 1].sum().item())
-            acc["trav_fwd"] += int(ts[:, 0].sum().item())
-            P.rasterize_bwd(rframe, vd, target=targets[vi], lds_batch=args.lds_batch)
-            P.project_bwd_adam(model, rframe, vd)
+            if ev is not None:
+                ev[0].record()
+            P.project(model.params, frame, vd)
+            if ev is not None:
+                ev[1].record()
+            P.bin_sort(frame)
+            if ev is not None:
+                ev[2].record()
+            P.rasterize_fwd(frame, vd, args.lds_batch)
+            if ev is not None:
+                ev[3].record()
+            P.rasterize_bwd(frame, vd, target=targets[vi], lds_batch=args.lds_batch)
+            if ev is not None:
+                ev[4].record()
+            P.project_bwd_adam(model, frame, vd)
+            if ev is not None:
+                ev[5].record()
+
+        log(f"warmup {args.warmup} steps (N={n}, {W}x{H}, K<={kmax})")
+        for i in range(args.warmup):
+            step(i)
         torch.cuda.synchronize()
-        counts = {k: v / args.steps for k, v in acc.items()}
-        log(f"per-step work: {counts}")
+        if frame.status_bits():
+            raise RuntimeError("intersection capacity exceeded during warmup")
+        state0 = [t.clone() for t in (model.params, model.m, model.v, model.step)]
+
+        # timed region: plain single-view steps
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            step(args.warmup + i, evs[i])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if frame.status_bits():
+            raise RuntimeError("intersection capacity exceeded in the timed region")
+        wall = t1 - t0
+        stages = ["project", "bin_sort", "rasterize_fwd", "rasterize_bwd", "project_bwd_adam"]
+        stage_ms = {s: float(np.mean([evs[i][k].elapsed_time(evs[i][k + 1]) for i in range(args.steps)]))
+                    for k, s in enumerate(stages)}
+        ips = args.steps / wall
+        log(f"plain (cull {cull}): {ips:.1f} iters/s, {1e3 * wall / args.steps:.3f} ms/step; "
+            f"stages {stage_ms}")
+
+        # replay of the timed steps (deterministic) counting the work each kernel did
+        counts = None
+        if replay:
+            for t, s0 in zip((model.params, model.m, model.v, model.step), state0):
+                t.copy_(s0)
+            rframe = P.Frame(n, [W], [H], 16, capacity=frame.capacity, tile_stats=True, cull=cull,
+                             row_capacity=frame.row_capacity)
+            gx = (W + 15) // 16
+            tile_of_px = torch.arange(H * W, device=dev)
+            tile_of_px = (tile_of_px // W // 16) * gx + (tile_of_px % W) // 16
+            acc = dict(K=0, trav_bwd=0, eval_bwd=0, contrib=0, eval_fwd=0, trav_fwd=0, visible=0)
+            for i in range(args.steps):
+                vi = order[(args.warmup + i) % ncam]
+                vd = vptr(vi)
+                P.project(model.params, rframe, vd)
+                P.bin_sort(rframe)
+                P.rasterize_fwd(rframe, vd, args.lds_batch)
+                last = rframe.last.to(torch.int64)
+                per_tile = torch.zeros(rframe.layout.total_tiles, dtype=torch.int64, device=dev)
+                per_tile.scatter_reduce_(0, tile_of_px, last, reduce="amax")
+                ts = rframe.tile_stats.to(torch.int64)
+                acc["K"] += rframe.intersections()
+                acc["visible"] += int((rframe.tiles != 0).sum().item())
+                acc["trav_bwd"] += int(per_tile.sum().item())
+                acc["eval_bwd"] += int(last.sum().item())
+                acc["contrib"] += int(ts[:, 2].sum().item())
+                acc["eval_fwd"] += int(ts[:, 1].sum().item())
+                acc["trav_fwd"] += int(ts[:, 0].sum().item())
+                P.rasterize_bwd(rframe, vd, target=targets[vi], lds_batch=args.lds_batch)
+                P.project_bwd_adam(model, rframe, vd)
+            torch.cuda.synchronize()
+            counts = {k: v / args.steps for k, v in acc.items()}
+            log(f"per-step work: {counts}")
+        out = dict(stage_ms=stage_ms, ips=ips, wall=wall, counts=counts, kmax=kmax,
+                   ntiles=frame.layout.total_tiles)
+        del model, frame
+        torch.cuda.empty_cache()
+        return out
+
+    order = [int(x) for x in w.view_order]
+    res = run_plain(args.cull, not args.no_replay)
+    stage_ms, ips, wall, counts = res["stage_ms"], res["ips"], res["wall"], res["counts"]
+    variants = [v for v in args.variants.split(",") if v]
+    cull_variant = None
+    if "ellipse" in variants and args.cull == 0:
+        r2 = run_plain(1, True)
+        c2 = r2["counts"]
+        cull_variant = {"culling": "ellipse", "iters_per_s": r2["ips"],
+                        "ms_per_step": 1e3 * r2["wall"] / args.steps, "stage_ms": r2["stage_ms"],
+                        "intersections": c2["K"] if c2 else None,
+                        "traversed": c2["trav_bwd"] if c2 else None,
+                        "pairs_evaluated_bwd": c2["eval_bwd"] if c2 else None,
+                        "speedup_vs_rect": r2["ips"] / ips}
 
     # roofline of the dominant stage (every stage's figure is reported)
     dom = max(stage_ms, key=stage_ms.get)
     roof = None
     extra = {}
     P_px = H * W
-    ntiles = frame.layout.total_tiles
+    ntiles = res["ntiles"]
     if counts is not None:
         def hbm(name, nbytes, kernel):
             t = stage_ms[name] * 1e-3
@@ -277,11 +303,10 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    variants = [v for v in args.variants.split(",") if v]
-    model = frame = targets = state0 = evs = None      # free the plain workload's buffers
-    if counts is not None:
-        rframe = None
+    targets = None                                      # free the plain workload's buffers
     torch.cuda.empty_cache()
+    if cull_variant is not None:
+        extra["cull_ellipse"] = cull_variant
     if "batched" in variants:
         from paper_2605_00219_amd import experiments as X
         log("batched variant: 3M Gaussians, 8 uneven views per step")
@@ -314,7 +339,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"plain-{n // 1000}k-{W}x{H}", "gaussians": n, "width": W,
                    "height": H, "views_per_step": 1, "cameras": ncam, "tile": 16,
-                   "lds_batch": args.lds_batch, "loss": "L1", "lr": w.lr},
+                   "lds_batch": args.lds_batch, "loss": "L1", "lr": w.lr,
+                   "culling": "ellipse" if args.cull else "3-sigma rectangle"},
         "stage_ms": stage_ms,
         "roofline": roof,
         "cpu_baseline": cpu,

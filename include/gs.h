@@ -65,6 +65,13 @@ enum {
 /* bits of the device status word */
 #define GS_STATUS_CAPACITY 1u  /* intersections exceeded gs_bins.capacity */
 #define GS_STATUS_OVERFLOW 2u  /* intersection count exceeded 2^32 - 1 */
+#define GS_STATUS_ROWS 4u      /* tile-row slots exceeded gs_bins.row_capacity */
+
+/* tile-set rules (gs_layout.cull) */
+#define GS_CULL_RECT 0     /* tiles meeting the 3-sigma box [mean +- r] */
+#define GS_CULL_ELLIPSE 1  /* exact culling (Sec. 4.1): tiles meeting the ellipse
+                              A dx^2 + 2 B dx dy + C dy^2 <= 2 ln(255 o), where the
+                              Gaussian can reach alpha 1/255 */
 
 /* One camera view, 128 bytes.  OpenCV camera (x right, y down, z forward);
  * pixel (column j, row i) has its centre at (j + 0.5, i + 0.5). */
@@ -90,6 +97,7 @@ typedef struct gs_layout {
     int32_t pixels_per_lane;               /* rasteriser lanes per tile = T*T / this; 1 for
                                               T = 8, 1, 2 or 4 otherwise (default 4 for
                                               T = 16, 2 for T = 32) */
+    int32_t cull;                          /* GS_CULL_RECT (default) or GS_CULL_ELLIPSE */
     int32_t width[GS_MAX_VIEWS], height[GS_MAX_VIEWS];
     int32_t tiles_x[GS_MAX_VIEWS], tiles_y[GS_MAX_VIEWS];
     int32_t depth_bits[GS_MAX_VIEWS];      /* D = min(23, 32 - B), B = ceil(log2 #tiles), B >= 1 */
@@ -114,8 +122,9 @@ typedef struct gs_splats {
                            (C, o, r, g)   conic C, opacity, colour r, g
                            (b, z, radius, 0)  colour b, depth, radius in pixels
                            (rect0, rect1, dcode, 0) uint32 bits:
-                               rect0 = x0 | y0 << 16, rect1 = x1 | y1 << 16,
-                               tiles [x0, x1) x [y0, y1);
+                               rect0 = x0 | y0 << 16, rect1 = x1 | y1 << 16:
+                               the bounding box [x0, x1) x [y0, y1) of the
+                               tile set (the whole set for GS_CULL_RECT);
                                dcode = the 23 mantissa bits of the float32
                                (2z + 1) / (z + 1) (the depth part of the keys)
                          colour is after the +0.5 shift and the clamp at 0;
@@ -126,9 +135,17 @@ typedef struct gs_splats {
 /* Intersection buffers.  Intersections of view v occupy the contiguous
  * segment [offsets[v*n], offsets[(v+1)*n]); within it Gaussian g owns the
  * "unsorted indices" [offsets[v*n+g], offsets[v*n+g+1]), one per tile of its
- * rectangle in emission order (rows outer, columns inner). */
+ * tile set in emission order: tile rows y0..y1-1 outer, each row's column
+ * span inner.  Every (view, Gaussian) with tiles owns the row slots
+ * [row_offsets[v*n+g], row_offsets[v*n+g+1]), one per tile row y0..y1-1 of
+ * its bounding box (rows whose span is empty included). */
 typedef struct gs_bins {
     uint32_t* offsets;   /* n_views*n + 1: exclusive scan of tiles; [n_views*n] = K */
+    uint32_t* row_offsets; /* n_views*n + 1: exclusive scan of tile rows; [n_views*n] = R */
+    uint32_t* rows;      /* 4 words per row slot: (first unsorted index of the row,
+                            (view, Gaussian) index v*n+g, xa | ty << 16, xb): the
+                            row's tiles are (xa..xb-1, ty) */
+    int64_t row_capacity; /* row slots in `rows` */
     uint32_t* keys;      /* capacity: (tile << D) | depth bits, sorted per view */
     uint32_t* vals;      /* capacity: Gaussian id of each sorted key */
     uint32_t* ranges;    /* 2 * total tiles: [start, end) of each tile in sorted order */
@@ -217,8 +234,9 @@ size_t gs_grads2d_workspace_size(int64_t capacity);
  * culled unless znear < p.z < zfar; 2D covariance J R_v Sigma R_v^T J^T + 0.3 I
  * (J the pinhole Jacobian at p with x/z, y/z clamped to +-lim), culled if its
  * determinant is not positive; conic = its inverse; radius = ceil(3 sqrt of its
- * larger eigenvalue); tile rectangle = tiles overlapping [mean2d - r, mean2d + r]
- * clipped to the image, culled if empty; opacity = sigmoid(logit); colour =
+ * larger eigenvalue); tile set = the tiles overlapping [mean2d - r, mean2d + r]
+ * clipped to the image (GS_CULL_RECT), or the tiles meeting the opacity
+ * ellipse (GS_CULL_ELLIPSE, see the define), culled if empty; opacity = sigmoid(logit); colour =
  * max(0, sum_m sh[m] Y_m(dir) + 0.5) along dir = (mean - campos)/|mean - campos|.
  * Float steps that decide the rectangle are evaluated in float32 without
  * contraction in a fixed order.  Non-finite parameters cull the Gaussian.
@@ -229,14 +247,16 @@ int gs_project(const float* params, int64_t n, const gs_view* views, const gs_la
                const gs_splats* out, void* stream);
 
 /* Binning and sorting (Sec. 4.1 count-then-fill, Sec. 4.4 32-bit keys).
- * offsets = exclusive scan of splats->tiles over (view, g); K = offsets[V*n].
+ * offsets = exclusive scan of splats->tiles over (view, g); K = offsets[V*n];
+ * row_offsets and rows describe each Gaussian's tile rows (R = row_offsets[V*n];
+ * GS_STATUS_ROWS is set if R > row_capacity).
  * For each Gaussian, one key per touched tile at its unsorted index:
  * key = (tile << D) | (mantissa(f) >> (23 - D)) with f = (2z+1)/(z+1) in
  * float32, value = g.  Keys of each view are sorted ascending by a stable LSD
  * radix sort (ties keep emission order), then ranges[t] =
  * [lower_bound(t << D), lower_bound((t+1) << D)) in the view's segment, as
  * global positions.  Unsorted index of Gaussian g's entry for tile (tx, ty):
- * offsets[v*n+g] + (ty - y0) * (x1 - x0) + (tx - x0).  If K > capacity only the first `capacity`
+ * rows[4 r] + (tx - xa) with r = row_offsets[v*n+g] + (ty - y0).  If K > capacity only the first `capacity`
  * intersections are written and GS_STATUS_CAPACITY is set; the caller reads
  * offsets[V*n] to size a retry.
  *   workspace  device scratch of gs_bin_sort_workspace_size bytes */

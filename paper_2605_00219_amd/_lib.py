@@ -20,12 +20,13 @@ MLP_GROUPS = 64
 MLP_SCRATCH = (MLP_GROUPS + 1) * (MLP_PARAMS + 1)
 
 GS_OK, GS_ERR_INVALID_ARG, GS_ERR_HIP, GS_ERR_WORKSPACE, GS_ERR_CAPACITY = 0, -1, -2, -3, -4
-STATUS_CAPACITY, STATUS_OVERFLOW = 1, 2
+STATUS_CAPACITY, STATUS_OVERFLOW, STATUS_ROWS = 1, 2, 4
+CULL_RECT, CULL_ELLIPSE = 0, 1
 
 
 class GsLayout(C.Structure):
     _fields_ = [("n_views", C.c_int32), ("tile", C.c_int32), ("pixels_per_lane", C.c_int32),
-                ("width", C.c_int32 * MAX_VIEWS), ("height", C.c_int32 * MAX_VIEWS),
+                ("cull", C.c_int32), ("width", C.c_int32 * MAX_VIEWS), ("height", C.c_int32 * MAX_VIEWS),
                 ("tiles_x", C.c_int32 * MAX_VIEWS), ("tiles_y", C.c_int32 * MAX_VIEWS),
                 ("depth_bits", C.c_int32 * MAX_VIEWS),
                 ("tile_base", C.c_int32 * (MAX_VIEWS + 1)),
@@ -45,7 +46,8 @@ class GsSplats(C.Structure):
 
 
 class GsBins(C.Structure):
-    _fields_ = [("offsets", C.c_void_p), ("keys", C.c_void_p), ("vals", C.c_void_p),
+    _fields_ = [("offsets", C.c_void_p), ("row_offsets", C.c_void_p), ("rows", C.c_void_p),
+                ("row_capacity", C.c_int64), ("keys", C.c_void_p), ("vals", C.c_void_p),
                 ("ranges", C.c_void_p), ("status", C.c_void_p), ("capacity", C.c_int64)]
 
 
@@ -138,7 +140,8 @@ def stream_ptr(stream=None) -> int:
     return s.cuda_stream
 
 
-def layout_init(widths, heights, tile: int, pixels_per_lane: int | None = None) -> GsLayout:
+def layout_init(widths, heights, tile: int, pixels_per_lane: int | None = None,
+                cull: int = CULL_RECT) -> GsLayout:
     n = len(widths)
     W = (C.c_int32 * n)(*[int(w) for w in widths])
     H = (C.c_int32 * n)(*[int(h) for h in heights])
@@ -146,4 +149,5 @@ def layout_init(widths, heights, tile: int, pixels_per_lane: int | None = None) 
     check(lib.gs_layout_init(W, H, n, int(tile), C.byref(L)), "gs_layout_init")
     if pixels_per_lane is not None:
         L.pixels_per_lane = int(pixels_per_lane)
+    L.cull = int(cull)
     return L

@@ -51,22 +51,25 @@ def save_cache(path: str, data: dict) -> None:
     os.replace(tmp, path)
 
 
-def capacity_for(model: P.Model, n: int, viewset: ViewSet, view_rows, iters, slack=1.15) -> int:
-    """Largest intersection count over the given iterations (synchronises)."""
-    f = P.Frame(n, viewset.widths, viewset.heights, viewset.tile, capacity=1)
-    kmax = 0
+def capacity_for(model: P.Model, n: int, viewset: ViewSet, view_rows, iters, slack=1.15):
+    """Intersection and tile-row capacities covering the given iterations
+    (largest counts times `slack`; synchronises)."""
+    f = P.Frame(n, viewset.widths, viewset.heights, viewset.tile, capacity=1, cull=viewset.cull)
+    kmax = rmax = 0
     for i in iters:
         P.project(model.params, f, view_rows(i).reshape(-1))
         kmax = max(kmax, int(f.tiles.to(torch.int64).sum().item()))
+        rmax = max(rmax, P.tile_rows(f))
     del f
-    return int(kmax * slack) + 4096
+    return int(kmax * slack) + 4096, int(rmax * slack) + 4096
 
 
 def time_candidate(model: P.Model, n: int, resolutions, tile: int, lds: int, view_rows, targets,
-                   iters, capacity: int, ppl: int | None = None) -> float:
+                   iters, capacity, ppl: int | None = None, cull: int = 0) -> float:
     saved = [t.clone() for t in (model.params, model.m, model.v, model.step)]
-    vs = ViewSet(resolutions, tile, ppl)
-    step = BatchedStep(model, n, vs, capacity, lds_batch=lds, persistent=True)
+    vs = ViewSet(resolutions, tile, ppl, cull)
+    step = BatchedStep(model, n, vs, capacity[0], lds_batch=lds, persistent=True,
+                       row_capacity=capacity[1])
     step.load(view_rows(iters[0]), targets(iters[0]))
     step.capture()
     for i in iters[:2]:                        # warm replays
@@ -91,8 +94,8 @@ def time_candidate(model: P.Model, n: int, resolutions, tile: int, lds: int, vie
 
 
 def autotune(model: P.Model, n: int, resolutions, view_rows, targets, iters, cache_path=None,
-             tiles=TILES, batches=BATCHES, lane_pixels=LANE_PIXELS, log=print) -> dict:
-    key = cache_key(resolutions, n)
+             tiles=TILES, batches=BATCHES, lane_pixels=LANE_PIXELS, log=print, cull: int = 0) -> dict:
+    key = cache_key(resolutions, n) + f"|c{int(cull)}"
     cache = load_cache(cache_path) if cache_path else {}
     hit = cache.get(key)
     if (isinstance(hit, dict) and hit.get("tile") in tiles and hit.get("lds_batch") in batches
@@ -100,10 +103,10 @@ def autotune(model: P.Model, n: int, resolutions, view_rows, targets, iters, cac
         return dict(hit, cached=True)
     table = {}
     for T in tiles:
-        cap = capacity_for(model, n, ViewSet(resolutions, T), view_rows, iters)
+        cap = capacity_for(model, n, ViewSet(resolutions, T, cull=cull), view_rows, iters)
         for ppl in ((1,) if T == 8 else lane_pixels):
             for S in batches:
-                dt = time_candidate(model, n, resolutions, T, S, view_rows, targets, iters, cap, ppl)
+                dt = time_candidate(model, n, resolutions, T, S, view_rows, targets, iters, cap, ppl, cull)
                 table[f"T{T}_S{S}_P{ppl}"] = dt * 1e3
                 log(f"autotune T={T} S={S} P={ppl}: {dt * 1e3:.3f} ms/step")
     best = min(table, key=table.get)

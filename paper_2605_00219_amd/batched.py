@@ -22,8 +22,9 @@ from . import pipeline as P
 class ViewSet:
     """Fixed slot resolutions; per iteration a camera goes into each slot."""
 
-    def __init__(self, resolutions, tile: int, pixels_per_lane: int | None = None):
+    def __init__(self, resolutions, tile: int, pixels_per_lane: int | None = None, cull: int = 0):
         self.resolutions = list(resolutions)
+        self.cull = int(cull)
         self.widths = [w for w, _ in self.resolutions]
         self.heights = [h for _, h in self.resolutions]
         self.tile = tile
@@ -39,11 +40,12 @@ class BatchedStep:
 
     def __init__(self, model: P.Model, n: int, viewset: ViewSet, capacity: int, lds_batch: int = 64,
                  persistent: bool = True, order: torch.Tensor | None = None,
-                 n_groups: int | None = None, graph: bool = True):
+                 n_groups: int | None = None, graph: bool = True, row_capacity: int | None = None):
         self.model = model
         self.viewset = viewset
         self.frame = P.Frame(n, viewset.widths, viewset.heights, viewset.tile, capacity=capacity,
-                             pixels_per_lane=viewset.pixels_per_lane)
+                             pixels_per_lane=viewset.pixels_per_lane, cull=viewset.cull,
+                             row_capacity=row_capacity)
         self.views_buf = torch.zeros(128 * len(viewset.resolutions), dtype=torch.uint8, device="cuda")
         self.target_buf = torch.zeros(viewset.pixels, 3, dtype=torch.float32, device="cuda")
         self.lds_batch = lds_batch

@@ -24,16 +24,20 @@ namespace gs {
 struct GatherArgs {
     const float4* rec;
     const uint32_t* offsets;
+    const uint32_t* row_offsets;
+    const uint4* rows;
+    int64_t row_capacity;
     const uint4* stop;
     const float4* grec;
     int64_t n;
     int64_t capacity;
     int32_t gx[GS_MAX_VIEWS];
     int32_t tile_base[GS_MAX_VIEWS];
+    int32_t ntiles[GS_MAX_VIEWS];
     int32_t depth_bits[GS_MAX_VIEWS];
     int n_views;
     float* sums;
-    uint32_t* block_first;  // per block: the (view, Gaussian) owning its first index
+    uint32_t* block_first;  // per block: the row slot holding its first index
     float* part_first;      // per block, 9 floats: sum of its first run if that run
                             // belongs to a Gaussian that started in an earlier block
     float* part_last;       // per block, 9 floats: sum of its last run if that run's
@@ -60,20 +64,30 @@ static void carve_gather(void* ws, int64_t capacity, GatherArgs& g) {
     g.part_last = reinterpret_cast<float*>(p);
 }
 
-// block_first[b] = the (view, Gaussian) whose index range holds index b * E.
-__global__ __launch_bounds__(256) void k_gather_index(const uint32_t* __restrict__ offsets, int64_t vn,
-                                                      int64_t capacity, uint32_t* __restrict__ block_first) {
-    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= vn) return;
-    const uint64_t b = min((uint64_t)offsets[o], (uint64_t)capacity);
-    const uint64_t e = min((uint64_t)offsets[o + 1], (uint64_t)capacity);
+// Number of valid row slots and intersections (both clamped to their capacities).
+GS_DEV uint64_t rows_valid(const GatherArgs& a, int64_t vn) {
+    return min((uint64_t)a.row_offsets[vn], (uint64_t)a.row_capacity);
+}
+GS_DEV uint64_t entries_valid(const GatherArgs& a, int64_t vn) {
+    return min((uint64_t)a.offsets[vn], (uint64_t)a.capacity);
+}
+
+// block_first[b] = the row slot whose index range holds index b * E.
+__global__ __launch_bounds__(256) void k_gather_index(GatherArgs a) {
+    const int64_t vn = (int64_t)a.n_views * a.n;
+    const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t rc = rows_valid(a, vn), kc = entries_valid(a, vn);
+    if (r >= rc) return;
+    const uint64_t b = min((uint64_t)a.rows[r].x, kc);
+    const uint64_t e = r + 1 < rc ? min((uint64_t)a.rows[r + 1].x, kc) : kc;
     for (uint64_t blk = (b + kGatherE - 1) / kGatherE; blk * kGatherE < e; ++blk)
-        block_first[blk] = (uint32_t)o;
+        a.block_first[blk] = (uint32_t)r;
 }
 
 // Gather: workgroup b owns the intersection indices [b E, (b+1) E).  Each
-// index finds its (view, Gaussian) by binary search over the offsets
-// (bounded by the owners of this block's and the next block's first index),
+// index finds its tile row by binary search over the row slots' first
+// indices (bounded by the slots of this block's and the next block's first
+// index), hence its (view, Gaussian) and tile,
 // tests traversal against its tile's stop entry and parks its record (or
 // zeros) in LDS, with coalesced record loads.  Then the first index of every
 // run of equal owner adds up its run in index order: a run that is the whole
@@ -85,13 +99,14 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather2d(GatherArgs a) {
     __shared__ float s_rec[kGatherE][9];
     __shared__ uint32_t s_own[kGatherE];
     const int64_t vn = (int64_t)a.n_views * a.n;
-    const uint64_t kc = min((uint64_t)a.offsets[vn], (uint64_t)a.capacity);
+    const uint64_t kc = entries_valid(a, vn);
     const uint64_t e0 = (uint64_t)blockIdx.x * kGatherE;
     if (e0 >= kc) return;
     const uint64_t e1 = min(e0 + (uint64_t)kGatherE, kc);
     const uint32_t nblk = (uint32_t)((kc + kGatherE - 1) / kGatherE);
-    const uint32_t oa = a.block_first[blockIdx.x];
-    const uint32_t oz = blockIdx.x + 1 < nblk ? a.block_first[blockIdx.x + 1] : (uint32_t)(vn - 1);
+    const uint32_t ra = a.block_first[blockIdx.x];
+    const uint32_t rz = blockIdx.x + 1 < nblk ? a.block_first[blockIdx.x + 1]
+                                              : (uint32_t)(rows_valid(a, vn) - 1);
     const int t = threadIdx.x;
     const int cnt = (int)(e1 - e0);
     for (int j = t; j < kGatherE; j += kGatherThreads) {
@@ -99,19 +114,19 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather2d(GatherArgs a) {
         uint32_t own = 0xFFFFFFFFu;
         if (j < cnt) {
             const uint32_t i = (uint32_t)(e0 + (uint64_t)j);
-            uint32_t lo = oa, hi = oz;
+            uint32_t lo = ra, hi = rz;
             while (lo < hi) {
                 const uint32_t mid = lo + ((hi - lo + 1) >> 1);
-                if (a.offsets[mid] <= i) lo = mid; else hi = mid - 1;
+                if (a.rows[mid].x <= i) lo = mid; else hi = mid - 1;
             }
-            own = lo;
-            const int v = (int)((int64_t)lo / a.n);
-            const float4 q3 = a.rec[4 * (int64_t)lo + 3];
-            const uint32_t r0 = __float_as_uint(q3.x), r1 = __float_as_uint(q3.y);
-            const uint32_t w = (r1 & 0xFFFF) - (r0 & 0xFFFF);
-            const uint32_t k = i - a.offsets[lo];
-            const uint32_t tile = ((r0 >> 16) + k / w) * (uint32_t)a.gx[v] + (r0 & 0xFFFF) + k % w;
-            const uint4 st = a.stop[a.tile_base[v] + (int)tile];
+            const uint4 row = a.rows[lo];
+            own = row.y;
+            const int v = (int)((int64_t)own / a.n);
+            const float4 q3 = a.rec[4 * (int64_t)own + 3];
+            const uint32_t tile = (row.z >> 16) * (uint32_t)a.gx[v] + (row.z & 0xFFFF) + (i - row.x);
+            // (a tile outside the view only arises after a row-capacity overflow)
+            const uint4 st = tile < (uint32_t)a.ntiles[v] ? a.stop[a.tile_base[v] + (int)tile]
+                                                          : make_uint4(0u, 0u, 0u, 0u);
             const int D = a.depth_bits[v];
             const uint32_t key = (tile << D) | (__float_as_uint(q3.z) >> (23 - D));
             if (key < st.y || (key == st.y && i < st.z)) {
@@ -182,6 +197,7 @@ struct AdamArgs {
     const gs_view* views;
     int n_views;
     int tile;
+    int cull;
     int32_t gx[GS_MAX_VIEWS], gy[GS_MAX_VIEWS];
     GatherArgs ga;
     float4* m;
@@ -254,7 +270,7 @@ __global__ __launch_bounds__(256) void k_project_bwd_adam(AdamArgs a) {
         if (!finite || a.ga.offsets[o + 1] == a.ga.offsets[o]) continue;
         const gs_view vw = a.views[vi];
         Proj P;
-        project_gaussian<true>(p0, p1, p2, sh, vw, a.tile, a.gx[vi], a.gy[vi], P);
+        project_gaussian<true, false>(p0, p1, p2, sh, vw, a.tile, a.gx[vi], a.gy[vi], a.cull, P);
         if (!P.valid) continue;
 
         float dmean[3] = {0.f, 0.f, 0.f};
@@ -438,6 +454,9 @@ int launch_project_bwd_adam(float* params, int64_t n, const gs_view* views, cons
     memset(&ga, 0, sizeof(ga));
     ga.rec = reinterpret_cast<const float4*>(splats.rec);
     ga.offsets = b.offsets;
+    ga.row_offsets = b.row_offsets;
+    ga.rows = reinterpret_cast<const uint4*>(b.rows);
+    ga.row_capacity = b.row_capacity;
     ga.stop = reinterpret_cast<const uint4*>(grads.tile_stop);
     ga.grec = reinterpret_cast<const float4*>(grads.rec);
     ga.n = n;
@@ -452,11 +471,13 @@ int launch_project_bwd_adam(float* params, int64_t n, const gs_view* views, cons
     a.views = views;
     a.n_views = L.n_views;
     a.tile = L.tile;
+    a.cull = L.cull;
     for (int v = 0; v < GS_MAX_VIEWS; ++v) {
         a.gx[v] = v < L.n_views ? L.tiles_x[v] : 0;
         a.gy[v] = v < L.n_views ? L.tiles_y[v] : 0;
         ga.gx[v] = a.gx[v];
         ga.tile_base[v] = v < L.n_views ? L.tile_base[v] : 0;
+        ga.ntiles[v] = v < L.n_views ? L.tile_base[v + 1] - L.tile_base[v] : 0;
         ga.depth_bits[v] = v < L.n_views ? L.depth_bits[v] : 0;
     }
     a.grads_out = reinterpret_cast<float4*>(grads_out);
@@ -474,11 +495,13 @@ int launch_project_bwd_adam(float* params, int64_t n, const gs_view* views, cons
         if (rc != GS_OK) return rc;
     }
     const int64_t vn = (int64_t)L.n_views * n;
-    hipLaunchKernelGGL(k_gather_index, dim3((unsigned)((vn + 255) / 256)), dim3(256), 0, s, b.offsets, vn,
-                       b.capacity, ga.block_first);
-    rc = check_launch("gather_index");
-    if (rc != GS_OK) return rc;
-    if (b.capacity > 0) {
+    if (b.row_capacity > 0) {
+        hipLaunchKernelGGL(k_gather_index, dim3((unsigned)((b.row_capacity + 255) / 256)), dim3(256), 0, s,
+                           ga);
+        rc = check_launch("gather_index");
+        if (rc != GS_OK) return rc;
+    }
+    if (b.capacity > 0 && b.row_capacity > 0) {
         hipLaunchKernelGGL(k_gather2d, dim3((unsigned)((b.capacity + kGatherE - 1) / kGatherE)),
                            dim3(kGatherThreads), 0, s, ga);
         rc = check_launch("gather2d");

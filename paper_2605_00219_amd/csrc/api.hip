@@ -32,6 +32,7 @@ static bool layout_ok(const gs_layout* L) {
     if (L->tile == 8 && L->pixels_per_lane != 1) return false;
     if (L->tile != 8 && L->pixels_per_lane != 1 && L->pixels_per_lane != 2 && L->pixels_per_lane != 4)
         return false;
+    if (L->cull != GS_CULL_RECT && L->cull != GS_CULL_ELLIPSE) return false;
     return true;
 }
 
@@ -64,6 +65,7 @@ int gs_layout_init(const int32_t* widths, const int32_t* heights, int n_views, i
     L.n_views = n_views;
     L.tile = tile;
     L.pixels_per_lane = tile == 8 ? 1 : (tile == 16 ? 4 : 2);
+    L.cull = GS_CULL_RECT;
     int64_t tb = 0, pb = 0;
     for (int v = 0; v < n_views; ++v) {
         REQUIRE(widths[v] >= 1 && heights[v] >= 1 && widths[v] <= (1 << 20) && heights[v] <= (1 << 20),
@@ -119,8 +121,10 @@ int gs_bin_sort(const gs_splats* splats, int64_t n, const gs_layout* layout, con
     REQUIRE(n >= 0 && (int64_t)layout->n_views * n < (int64_t(1) << 32), "gs_bin_sort: n out of range");
     REQUIRE(bins->capacity >= 0 && bins->capacity < (int64_t(1) << 32) - 1,
             "gs_bin_sort: capacity out of range");
-    REQUIRE(bins->offsets && bins->ranges && bins->status && (bins->capacity == 0 ||
-            (bins->keys && bins->vals)), "gs_bin_sort: null bins buffer");
+    REQUIRE(bins->offsets && bins->row_offsets && bins->ranges && bins->status &&
+            (bins->capacity == 0 || (bins->keys && bins->vals)), "gs_bin_sort: null bins buffer");
+    REQUIRE(bins->row_capacity >= 0 && bins->row_capacity < (int64_t(1) << 32) - 1 &&
+            (bins->row_capacity == 0 || bins->rows), "gs_bin_sort: bad row buffer");
     REQUIRE(workspace || workspace_bytes == 0, "gs_bin_sort: null workspace");
     return launch_bin_sort(*splats, n, *layout, *bins, workspace, workspace_bytes, (hipStream_t)stream);
 }

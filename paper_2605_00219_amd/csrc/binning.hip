@@ -9,6 +9,7 @@
 // whole histogram array yields every scatter destination directly.  Grids are
 // sized from the capacity (an upper bound known on the host); the actual
 // counts are read on the device, so no step needs a host synchronisation.
+#include "cull_math.h"
 #include "gs_internal.h"
 
 namespace gs {
@@ -26,6 +27,7 @@ constexpr int kDigits = 256;
 // ---------------------------------------------------------------------------
 
 struct Workspace {
+    uint32_t* row_count;   // tile rows per (view, Gaussian)
     uint32_t* keys_tmp;
     uint32_t* vals_tmp;
     uint32_t* hist;        // kDigits * max_chunks
@@ -52,6 +54,7 @@ static size_t carve(int64_t n, const gs_layout& L, int64_t capacity, char* base,
         return p;
     };
     Workspace tmp;
+    tmp.row_count = (uint32_t*)take(sizeof(uint32_t) * (size_t)std::max<int64_t>((int64_t)L.n_views * n, 1));
     tmp.keys_tmp = (uint32_t*)take(sizeof(uint32_t) * (size_t)std::max<int64_t>(capacity, 1));
     tmp.vals_tmp = (uint32_t*)take(sizeof(uint32_t) * (size_t)std::max<int64_t>(capacity, 1));
     tmp.hist = (uint32_t*)take(sizeof(uint32_t) * (size_t)(kDigits * mc + 1));  // +1: scan total
@@ -202,48 +205,105 @@ __global__ void k_view_table(const uint32_t* __restrict__ offsets, int64_t n, in
 }
 
 // ---------------------------------------------------------------------------
-// key emission: one thread per intersection
+// tile rows and key emission
 // ---------------------------------------------------------------------------
 
 struct EmitGeom {
     int32_t tiles_x[GS_MAX_VIEWS];
+    int32_t tiles_y[GS_MAX_VIEWS];
     int32_t depth_bits[GS_MAX_VIEWS];
+    int32_t tile;
+    int32_t cull;
 };
 
-constexpr int kEmitG = 256;  // Gaussians per workgroup
+// Tile rows of each (view, Gaussian) with tiles: the rows of its bounding box.
+__global__ __launch_bounds__(256) void k_row_count(const float4* __restrict__ rec,
+                                                   const uint32_t* __restrict__ tiles, int64_t m,
+                                                   uint32_t* __restrict__ row_count) {
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= m) return;
+    uint32_t h = 0;
+    if (tiles[o] > 0) {
+        const float4 q3 = rec[4 * o + 3];
+        h = (__float_as_uint(q3.y) >> 16) - (__float_as_uint(q3.x) >> 16);
+    }
+    row_count[o] = h;
+}
 
-// A workgroup owns kEmitG consecutive (view, Gaussian) entries.  Their
-// rectangles and depth keys are staged in LDS; the workgroup's intersections
-// [offsets[o0], offsets[o0 + kEmitG]) are then written by consecutive threads
-// (coalesced, balanced however unequal the rectangles are), each finding its
-// Gaussian by binary search over the staged offsets.
+// One thread per (view, Gaussian): the column span of each of its tile rows
+// (the rectangle's columns, or the ellipse's span of that row) and the
+// unsorted index of the row's first tile.  The spans are the ones the
+// projection counted (same function of the same record values).
+__global__ __launch_bounds__(256) void k_rows(const float4* __restrict__ rec,
+                                              const uint32_t* __restrict__ tiles,
+                                              const uint32_t* __restrict__ offsets,
+                                              const uint32_t* __restrict__ row_offsets, int64_t n,
+                                              int64_t m, EmitGeom geo, int64_t row_capacity,
+                                              uint4* __restrict__ rows, uint32_t* __restrict__ status) {
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= m || tiles[o] == 0) return;
+    const int v = (int)(o / n);
+    const float4* r = rec + 4 * o;
+    const float4 q0 = r[0], q1 = r[1], q3 = r[3];
+    const uint32_t r0 = __float_as_uint(q3.x), r1 = __float_as_uint(q3.y);
+    const int x0 = (int)(r0 & 0xFFFF), y0 = (int)(r0 >> 16), x1 = (int)(r1 & 0xFFFF), y1 = (int)(r1 >> 16);
+    Ellipse e;
+    const bool ell = geo.cull == GS_CULL_ELLIPSE;
+    if (ell) ellipse_setup(q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, e);
+    uint32_t first = offsets[o];
+    const uint64_t rs = row_offsets[o];
+    if (rs + (uint64_t)(y1 - y0) > (uint64_t)row_capacity) atomicOr(status, (uint32_t)GS_STATUS_ROWS);
+    for (int ty = y0; ty < y1; ++ty) {
+        int xa = x0, xb = x1;
+        if (ell) ellipse_span(e, geo.tile, geo.tiles_x[v], ty, xa, xb);
+        if (xb < xa) xb = xa;
+        const uint64_t slot = rs + (uint64_t)(ty - y0);
+        if (slot < (uint64_t)row_capacity)
+            rows[slot] = make_uint4(first, (uint32_t)o, (uint32_t)xa | ((uint32_t)ty << 16), (uint32_t)xb);
+        first += (uint32_t)(xb - xa);
+    }
+}
+
+constexpr int kEmitG = 256;  // tile rows per workgroup
+
+// A workgroup owns kEmitG consecutive row slots.  Their first indices, tile
+// bases and depth codes are staged in LDS; the workgroup's intersections
+// [rows[r0].first, rows[r0 + kEmitG].first) are then written by consecutive
+// threads (coalesced, balanced however unequal the rows are), each finding
+// its row by binary search over the staged first indices.
 __global__ __launch_bounds__(kEmitG) void k_emit(const float4* __restrict__ rec,
-                                                 const uint32_t* __restrict__ tiles,
+                                                 const uint4* __restrict__ rows,
+                                                 const uint32_t* __restrict__ row_offsets,
                                                  const uint32_t* __restrict__ offsets, int64_t n,
-                                                 int n_views, EmitGeom geo, int64_t capacity,
-                                                 uint32_t* __restrict__ keys,
+                                                 int64_t m, EmitGeom geo, int64_t capacity,
+                                                 int64_t row_capacity, uint32_t* __restrict__ keys,
                                                  uint32_t* __restrict__ vals) {
     __shared__ uint32_t s_off[kEmitG + 1];
-    __shared__ uint32_t s_xy[kEmitG];
-    __shared__ uint32_t s_w[kEmitG];
-    __shared__ uint32_t s_dk[kEmitG];
-    __shared__ uint32_t s_view[kEmitG];
-    const int64_t m = (int64_t)n_views * n;
-    const int64_t o0 = (int64_t)blockIdx.x * kEmitG;
+    __shared__ uint32_t s_tile[kEmitG];   // tile index (within the view) of the row's first tile
+    __shared__ uint32_t s_dk[kEmitG];     // depth bits
+    __shared__ uint32_t s_gid[kEmitG];
+    __shared__ uint8_t s_D[kEmitG];
+    const uint64_t kc = min((uint64_t)offsets[m], (uint64_t)capacity);
+    const uint64_t rc = min((uint64_t)row_offsets[m], (uint64_t)row_capacity);
+    const uint64_t r0 = (uint64_t)blockIdx.x * kEmitG;
+    if (r0 >= rc) return;
     const int t = threadIdx.x;
-    const int64_t o = o0 + t;
-    s_off[t] = offsets[o < m ? o : m];
-    if (t == 0) s_off[kEmitG] = offsets[o0 + kEmitG < m ? o0 + kEmitG : m];
-    if (o < m && tiles[o] > 0) {
+    const uint64_t r = r0 + (uint64_t)t;
+    if (r < rc) {
+        const uint4 row = rows[r];
+        s_off[t] = (uint32_t)min((uint64_t)row.x, kc);
+        const int64_t o = (int64_t)row.y;
         const int v = (int)(o / n);
-        const float4 q3 = rec[4 * o + 3];
-        const uint32_t r0 = __float_as_uint(q3.x), r1 = __float_as_uint(q3.y);
         const int D = geo.depth_bits[v];
-        s_xy[t] = r0;
-        s_w[t] = (r1 & 0xFFFF) - (r0 & 0xFFFF);
-        s_dk[t] = __float_as_uint(q3.z) >> (23 - D);
-        s_view[t] = (uint32_t)v;
+        s_tile[t] = (row.z >> 16) * (uint32_t)geo.tiles_x[v] + (row.z & 0xFFFF);
+        s_dk[t] = __float_as_uint(rec[4 * o + 3].z) >> (23 - D);
+        s_gid[t] = (uint32_t)(o - (int64_t)v * n);
+        s_D[t] = (uint8_t)D;
+    } else {
+        s_off[t] = (uint32_t)kc;
+        s_tile[t] = 0; s_dk[t] = 0; s_gid[t] = 0; s_D[t] = 0;
     }
+    if (t == 0) s_off[kEmitG] = r0 + kEmitG < rc ? (uint32_t)min((uint64_t)rows[r0 + kEmitG].x, kc) : (uint32_t)kc;
     __syncthreads();
     const uint32_t begin = s_off[0], end = s_off[kEmitG];
     for (uint64_t i = (uint64_t)begin + t; i < end; i += kEmitG) {
@@ -252,14 +312,9 @@ __global__ __launch_bounds__(kEmitG) void k_emit(const float4* __restrict__ rec,
             const int mid = (lo + hi + 1) >> 1;
             if (s_off[mid] <= i) lo = mid; else hi = mid - 1;
         }
-        const uint32_t k = (uint32_t)(i - s_off[lo]);
-        const uint32_t w = s_w[lo], xy = s_xy[lo];
-        const uint32_t tx = (xy & 0xFFFF) + k % w, ty = (xy >> 16) + k / w;
-        const int v = (int)s_view[lo];
-        if (i < (uint64_t)capacity) {
-            keys[i] = ((ty * (uint32_t)geo.tiles_x[v] + tx) << geo.depth_bits[v]) | s_dk[lo];
-            vals[i] = (uint32_t)(o0 + lo - (int64_t)v * n);
-        }
+        const uint32_t tile = s_tile[lo] + (uint32_t)(i - s_off[lo]);
+        keys[i] = (tile << s_D[lo]) | s_dk[lo];
+        vals[i] = s_gid[lo];
     }
 }
 
@@ -543,18 +598,35 @@ int launch_bin_sort(const gs_splats& sp, int64_t n, const gs_layout& L, const gs
     if ((rc = check_launch("view_table")) != GS_OK) return rc;
     EmitGeom eg;
     RangeGeom rg;
+    memset(&eg, 0, sizeof(eg));
     for (int v = 0; v < GS_MAX_VIEWS; ++v) {
         eg.tiles_x[v] = v < V ? L.tiles_x[v] : 0;
+        eg.tiles_y[v] = v < V ? L.tiles_y[v] : 0;
         eg.depth_bits[v] = v < V ? L.depth_bits[v] : 0;
         rg.depth_bits[v] = eg.depth_bits[v];
         rg.tiles_x[v] = eg.tiles_x[v];
     }
+    eg.tile = L.tile;
+    eg.cull = L.cull;
     for (int v = 0; v <= GS_MAX_VIEWS; ++v) rg.tile_base[v] = v <= V ? L.tile_base[v] : L.tile_base[V];
     const float4* rec = reinterpret_cast<const float4*>(sp.rec);
+    uint4* rows = reinterpret_cast<uint4*>(b.rows);
+    const unsigned gm = (unsigned)((m + 255) / 256);
     if (m > 0) {
-        hipLaunchKernelGGL(k_emit, dim3((unsigned)((m + kEmitG - 1) / kEmitG)), dim3(kEmitG), 0, s, rec,
-                           sp.tiles, b.offsets, n, V, eg, b.capacity, b.keys, b.vals);
-        if ((rc = check_launch("emit_keys")) != GS_OK) return rc;
+        hipLaunchKernelGGL(k_row_count, dim3(gm), dim3(256), 0, s, rec, sp.tiles, m, W.row_count);
+        if ((rc = check_launch("row_count")) != GS_OK) return rc;
+    }
+    if ((rc = scan_exclusive(W.row_count, m, b.row_offsets, W.block_sums, nullptr, s)) != GS_OK) return rc;
+    if (m > 0) {
+        hipLaunchKernelGGL(k_rows, dim3(gm), dim3(256), 0, s, rec, sp.tiles, b.offsets, b.row_offsets, n, m,
+                           eg, b.row_capacity, rows, b.status);
+        if ((rc = check_launch("rows")) != GS_OK) return rc;
+        if (b.row_capacity > 0) {
+            hipLaunchKernelGGL(k_emit, dim3((unsigned)((b.row_capacity + kEmitG - 1) / kEmitG)), dim3(kEmitG),
+                               0, s, rec, rows, b.row_offsets, b.offsets, n, m, eg, b.capacity,
+                               b.row_capacity, b.keys, b.vals);
+            if ((rc = check_launch("emit_keys")) != GS_OK) return rc;
+        }
     }
     // 4 stable LSD passes; even count leaves the result in keys / vals
     uint32_t* kin = b.keys;

@@ -13,7 +13,7 @@ struct ViewGrid {
 
 __global__ __launch_bounds__(256) void k_project(const float* __restrict__ params, int64_t n,
                                                  const gs_view* __restrict__ views, int n_views,
-                                                 int tile, ViewGrid grid, gs_splats out) {
+                                                 int tile, int cull, ViewGrid grid, gs_splats out) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n) return;
     const float4 p0 = ld4(params, 0 * n + g);
@@ -30,7 +30,7 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ param
         const gs_view vw = views[v];
         Proj P;
         P.valid = false;
-        if (finite) project_gaussian<true>(p0, p1, p2, sh, vw, tile, grid.gx[v], grid.gy[v], P);
+        if (finite) project_gaussian<true>(p0, p1, p2, sh, vw, tile, grid.gx[v], grid.gy[v], cull, P);
         const int64_t o = (int64_t)v * n + g;
         float4* rec = reinterpret_cast<float4*>(out.rec) + 4 * o;
         if (P.valid) {
@@ -43,7 +43,7 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ param
             rec[3] = make_float4(__uint_as_float((uint32_t)P.x0 | ((uint32_t)P.y0 << 16)),
                                  __uint_as_float((uint32_t)P.x1 | ((uint32_t)P.y1 << 16)),
                                  __uint_as_float(dcode), 0.0f);
-            out.tiles[o] = (uint32_t)((P.x1 - P.x0) * (P.y1 - P.y0));
+            out.tiles[o] = P.count;
         } else {
             const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
             rec[0] = z; rec[1] = z; rec[2] = z; rec[3] = z;
@@ -62,7 +62,7 @@ int launch_project(const float* params, int64_t n, const gs_view* views, const g
     }
     const int64_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, s, params, n, views,
-                       L.n_views, L.tile, grid, out);
+                       L.n_views, L.tile, L.cull, grid, out);
     return check_launch("project");
 }
 

@@ -11,6 +11,7 @@
 // (the HIP default on gfx950).
 #pragma once
 
+#include "cull_math.h"
 #include "gs_internal.h"
 
 #pragma clang fp contract(off)
@@ -80,7 +81,8 @@ struct Proj {
     float o;
     float col[3], raw[3];
     float radius;
-    int x0, y0, x1, y1;
+    int x0, y0, x1, y1;   // bounding tile box of the tile set
+    uint32_t count;       // tiles in the set
     // kept for the backward
     float qn[4], qnorm;
     float Rq[9];
@@ -109,9 +111,12 @@ GS_DEV float sig_at(const float S[6], int i, int j) {
 // Projects Gaussian (p0 = mean xyz + logit, p1 = log-scales, p2 = quaternion
 // wxyz, sh = 48 coefficients) into view vw with tile edge T.  With
 // want_colour = false the SH colour is skipped (binning only needs geometry).
-template <bool kColour>
+// cull selects the tile set (GS_CULL_RECT / GS_CULL_ELLIPSE); with kCount the
+// set is counted into P.count and an empty set culls the Gaussian (callers
+// that already know the Gaussian has tiles pass kCount = false).
+template <bool kColour, bool kCount = true>
 GS_DEV void project_gaussian(float4 p0, float4 p1, float4 p2, const float4* sh, const gs_view& vw,
-                             int tile, int gx, int gy, Proj& P) {
+                             int tile, int gx, int gy, int cull, Proj& P) {
     P.valid = false;
     // quaternion -> rotation
     float w = p2.x, x = p2.y, y = p2.z, z = p2.w;
@@ -215,8 +220,24 @@ GS_DEV void project_gaussian(float4 p0, float4 p1, float4 p2, const float4* sh, 
     const float fy0 = fminf(fmaxf(__builtin_floorf((P.v - r) * invT), 0.0f), fgy);
     const float fy1 = fminf(fmaxf(__builtin_floorf((P.v + r) * invT) + 1.0f, 0.0f), fgy);
     P.x0 = (int)fx0; P.x1 = (int)fx1; P.y0 = (int)fy0; P.y1 = (int)fy1;
-    if (!(P.x1 > P.x0 && P.y1 > P.y0)) return;
     P.o = 1.0f / (1.0f + exp_cw(-p0.w));
+    uint32_t count = (uint32_t)((P.x1 - P.x0) * (P.y1 - P.y0));
+    if (cull == GS_CULL_ELLIPSE) {
+        Ellipse e;
+        if (!ellipse_setup(P.u, P.v, P.A, P.B, P.C, P.o, e)) return;
+        ellipse_rows(e, tile, gy, P.y0, P.y1);
+        ellipse_cols(e, tile, gx, P.x0, P.x1);
+        count = 0;
+        if (kCount) {
+            for (int ty = P.y0; ty < P.y1; ++ty) {
+                int xa, xb;
+                ellipse_span(e, tile, gx, ty, xa, xb);
+                count += xb > xa ? (uint32_t)(xb - xa) : 0u;
+            }
+        }
+    }
+    if (!(P.x1 > P.x0 && P.y1 > P.y0) || (kCount && count == 0)) return;
+    P.count = count;
     // view direction and colour
     float dv[3];
 #pragma unroll

@@ -57,7 +57,9 @@ struct RasterArgs {
     float4* grec;           // 3 float4 per unsorted index
     uint4* tile_stop;       // (stop, key, unsorted index, 0) per tile
     const uint32_t* keys;   // sorted keys
-    const uint32_t* offsets;
+    const uint32_t* row_offsets;
+    const uint4* rows;
+    int64_t row_capacity;
     float* loss;
     int64_t capacity;
 };
@@ -75,13 +77,16 @@ GS_DEV void stage_splat(const RasterArgs& a, int view, uint32_t sorted_pos, floa
     sb = q2.x;
 }
 
-// Unsorted index of (tile (tx, ty), Gaussian gid) in view `view`: the
-// Gaussian's first index plus the tile's row-major position in its rectangle.
+// Unsorted index of (tile (tx, ty), Gaussian gid) in view `view`: the first
+// index of the Gaussian's tile row ty plus the column offset within the
+// row's span; 0xFFFFFFFF if the row slot is missing (row capacity exceeded).
 GS_DEV uint32_t unsorted_index(const RasterArgs& a, int view, uint32_t gid, int tx, int ty) {
     const int64_t o = (int64_t)view * a.n + gid;
-    const uint32_t r0 = __float_as_uint(a.rec[4 * o + 3].x), r1 = __float_as_uint(a.rec[4 * o + 3].y);
-    const uint32_t x0 = r0 & 0xFFFF, y0 = r0 >> 16, w = (r1 & 0xFFFF) - x0;
-    return a.offsets[o] + ((uint32_t)ty - y0) * w + ((uint32_t)tx - x0);
+    const uint32_t y0 = __float_as_uint(a.rec[4 * o + 3].x) >> 16;
+    const uint64_t slot = (uint64_t)a.row_offsets[o] + ((uint32_t)ty - y0);
+    if (slot >= (uint64_t)a.row_capacity) return 0xFFFFFFFFu;
+    const uint4 row = a.rows[slot];
+    return row.x + ((uint32_t)tx - (row.z & 0xFFFFu));
 }
 
 // Quadratic form (log2-scaled power) at the pixel, G = 2^power and o*G.
@@ -617,7 +622,9 @@ int launch_raster_bwd(const gs_splats& sp, int64_t n, const gs_layout& L, const 
     a.grec = reinterpret_cast<float4*>(grads.rec);
     a.tile_stop = reinterpret_cast<uint4*>(grads.tile_stop);
     a.keys = b.keys;
-    a.offsets = b.offsets;
+    a.row_offsets = b.row_offsets;
+    a.rows = reinterpret_cast<const uint4*>(b.rows);
+    a.row_capacity = b.row_capacity;
     int rc = GS_OK;
     if (a.total_tiles == 0) return GS_OK;
     if (a.counter) {

@@ -47,8 +47,9 @@ def run_batched(workload, make_views, steps: int = 200, plain_steps: int = 25, l
     tune = autotune(model, n, res, view_rows, tgt, list(range(tune_iters)), cache_path=cache_path,
                     log=log)
     T, S, ppl = tune["tile"], tune["lds_batch"], tune.get("pixels_per_lane")
-    cap = capacity_for(model, n, ViewSet(res, T), view_rows, list(range(period)))
-    step = BatchedStep(model, n, ViewSet(res, T, ppl), cap, lds_batch=S, persistent=True)
+    cap, rcap = capacity_for(model, n, ViewSet(res, T), view_rows, list(range(period)))
+    step = BatchedStep(model, n, ViewSet(res, T, ppl), cap, lds_batch=S, persistent=True,
+                       row_capacity=rcap)
     step.load(view_rows(0), tgt(0))
     step.capture()
     for i in range(3):                       # warm replays

@@ -64,10 +64,12 @@ class Frame:
     """Per-view-set buffers: projected splats, intersection lists, images."""
 
     def __init__(self, n: int, widths, heights, tile: int = 16, capacity: int = 1 << 16,
-                 device="cuda", tile_stats: bool = False, pixels_per_lane: int | None = None):
+                 device="cuda", tile_stats: bool = False, pixels_per_lane: int | None = None,
+                 cull: int = G.CULL_RECT, row_capacity: int | None = None):
         self.n = int(n)
         self.device = device
-        self.layout = G.layout_init(widths, heights, tile, pixels_per_lane)
+        self.cull = int(cull)
+        self.layout = G.layout_init(widths, heights, tile, pixels_per_lane, cull)
         self.n_views = len(widths)
         self.tile = tile
         V, n = self.n_views, self.n
@@ -76,6 +78,7 @@ class Frame:
         self.rec = torch.zeros(V * n, 16, **f32)    # 64-byte projected records
         self.tiles = torch.zeros(V * n, **u32)
         self.offsets = torch.zeros(V * n + 1, **u32)
+        self.row_offsets = torch.zeros(V * n + 1, **u32)
         self.ranges = torch.zeros(self.layout.total_tiles, 2, **u32)
         self.status = torch.zeros(1, **u32)
         P = self.layout.total_pixels
@@ -88,12 +91,18 @@ class Frame:
         self.sums = torch.zeros(9, V * n, **f32)      # per (view, Gaussian) screen-space gradient
         self.counter = torch.zeros(1, **u32)
         self.capacity = 0
-        self.resize(capacity)
+        self.row_capacity = 0
+        self.resize(capacity, row_capacity)
 
-    # -- buffers sized by the intersection capacity --
-    def resize(self, capacity: int) -> None:
+    # -- buffers sized by the intersection capacity (and the tile-row capacity) --
+    def resize(self, capacity: int, row_capacity: int | None = None) -> None:
         capacity = max(int(capacity), 1)
+        if row_capacity is None:        # rows never outnumber tiles for the 3-sigma rectangle
+            row_capacity = max(capacity, self.row_capacity)
+        row_capacity = max(int(row_capacity), 1)
         u32 = dict(dtype=torch.int32, device=self.device)
+        self.rows = torch.zeros(row_capacity, 4, **u32)
+        self.row_capacity = row_capacity
         self.keys = torch.zeros(capacity, **u32)
         self.vals = torch.zeros(capacity, **u32)
         self.grec = torch.zeros(capacity, 12, dtype=torch.float32, device=self.device)
@@ -106,8 +115,9 @@ class Frame:
 
     def _structs(self) -> None:
         self.splats = G.GsSplats(_i(self.rec), _i(self.tiles))
-        self.bins = G.GsBins(_i(self.offsets), _i(self.keys), _i(self.vals), _i(self.ranges),
-                             _i(self.status), self.capacity)
+        self.bins = G.GsBins(_i(self.offsets), _i(self.row_offsets), _i(self.rows), self.row_capacity,
+                             _i(self.keys), _i(self.vals), _i(self.ranges), _i(self.status),
+                             self.capacity)
         self.grads2d = G.GsGrads2d(_i(self.grec), _i(self.tile_stop), _i(self.sums), _i(self.gather_ws))
         self.img = G.GsImage(_i(self.image), _i(self.T), _i(self.last),
                              _i(self.tile_stats) if self.tile_stats is not None else None)
@@ -189,12 +199,23 @@ def project_bwd_adam(model: Model, frame: Frame, views_dev: torch.Tensor, adam: 
                                       G.stream_ptr(stream)), "gs_project_bwd_adam")
 
 
+def tile_rows(frame: Frame) -> int:
+    """R: tile-row slots the current projection needs (synchronises)."""
+    bits = frame.rec[:, 12:14].view(torch.int32).to(torch.int64)
+    h = ((bits[:, 1] >> 16) & 0xFFFF) - ((bits[:, 0] >> 16) & 0xFFFF)
+    return int(torch.where(frame.tiles != 0, h, torch.zeros_like(h)).sum().item())
+
+
 def fit_capacity(params: torch.Tensor, frame: Frame, views_dev: torch.Tensor, slack: float = 1.25):
-    """Project once and size the intersection buffers for the current K (synchronises)."""
+    """Project once and size the intersection and tile-row buffers for the
+    current K and R (synchronises).  Returns K."""
     project(params, frame, views_dev)
     K = int(frame.tiles.to(torch.int64).sum().item())
-    if K > frame.capacity:
-        frame.resize(int(math.ceil(K * slack)) + 1024)
+    R = tile_rows(frame)
+    if K > frame.capacity or R > frame.row_capacity:
+        cap = max(frame.capacity, int(math.ceil(K * slack)) + 1024)
+        rcap = max(frame.row_capacity, int(math.ceil(R * slack)) + 1024)
+        frame.resize(cap, rcap)
     return K
 
 

@@ -16,13 +16,14 @@ def u32(t) -> np.ndarray:
 
 def run_gpu_step(scene, views, tile, target=None, lds_batch=64, lr=1e-3, adam=True, grads=True,
                  capacity=None, sched_order=None, persistent=False, tile_stats=False, steps=1,
-                 pixels_per_lane=None):
+                 pixels_per_lane=None, cull=0):
     import torch
     from paper_2605_00219_amd import pipeline as P
     n = scene.n
     model = P.Model(scene.flat(), lr=lr)
     frame = P.Frame(n, [int(v["width"]) for v in views], [int(v["height"]) for v in views], tile,
-                    capacity=capacity or 1024, tile_stats=tile_stats, pixels_per_lane=pixels_per_lane)
+                    capacity=capacity or 1024, tile_stats=tile_stats, pixels_per_lane=pixels_per_lane,
+                    cull=cull)
     vd = P.views_to_device(views)
     if capacity is None:
         P.fit_capacity(model.params, frame, vd)
@@ -48,6 +49,8 @@ def run_gpu_step(scene, views, tile, target=None, lds_batch=64, lr=1e-3, adam=Tr
     out["rec"] = rec
     out["rect"] = rec[..., 12:14].copy().view(np.uint32)
     out["offsets"] = u32(frame.offsets)
+    out["row_offsets"] = u32(frame.row_offsets)
+    out["rows"] = u32(frame.rows)[:int(out["row_offsets"][-1])]
     K = int(out["offsets"][-1])
     out["K"] = K
     out["keys"] = u32(frame.keys)[:K]

@@ -254,3 +254,67 @@ def test_invalid_arguments_raise():
         P.rasterize_fwd(frame, vd, lds_batch=48)
     with pytest.raises(G.GsError, match="exactly one"):
         P.rasterize_bwd(frame, vd, target=None, dLdC=None)
+
+
+# ---------------------------------------------------------------------------
+# exact tile culling (opacity-threshold ellipse)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", list(WL))
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_ellipse_culling_tiles_rows_and_keys_bit_exact(name, tile):
+    scene, target_scene, views, _ = WL[name]
+    note(f"exact culling binning parity {name} tile {tile}")
+    pr = oracle.project(scene, views, tile, cull=oracle.CULL_ELLIPSE)
+    bins = oracle.bin_sort(pr, views, tile)
+    g = run_gpu_step(scene, views, tile, cull=1)
+    assert g["status"] == 0
+    np.testing.assert_array_equal(g["tiles"], pr.tiles)
+    vis = pr.tiles > 0
+    np.testing.assert_array_equal(rect_from_packed(g["rect"])[vis], pr.rect[vis])
+    np.testing.assert_array_equal(g["offsets"], bins.offsets)
+    np.testing.assert_array_equal(g["keys"], bins.keys)
+    np.testing.assert_array_equal(g["vals"], bins.gid[bins.vals])
+    np.testing.assert_array_equal(g["ranges"], bins.ranges)
+    # row slots: one per bounding-box row, first index of each row, spans that
+    # reproduce the unsorted keys
+    V, n = pr.tiles.shape
+    h = np.where(vis, pr.rect[..., 3] - pr.rect[..., 1], 0).reshape(-1)
+    np.testing.assert_array_equal(g["row_offsets"], np.concatenate([[0], np.cumsum(h)]).astype(np.uint32))
+    rows = g["rows"]
+    o = rows[:, 1].astype(np.int64)
+    xa, ty, xb = rows[:, 2] & 0xFFFF, rows[:, 2] >> 16, rows[:, 3]
+    assert np.all(xb >= xa)
+    ends = np.append(rows[1:, 0], bins.offsets[-1])
+    np.testing.assert_array_equal(ends - rows[:, 0], xb - xa)
+    np.testing.assert_array_equal(rows[:, 0][np.searchsorted(o, np.flatnonzero(vis.reshape(-1)))],
+                                  bins.offsets[:-1][vis.reshape(-1)])
+    gx = np.array([(int(v["width"]) + tile - 1) // tile for v in views])
+    vw = o // n
+    for r in range(0, len(rows), max(1, len(rows) // 2000)):
+        t = ty[r] * gx[vw[r]] + np.arange(xa[r], xb[r])
+        D = oracle.depth_bits(int(gx[vw[r]]) * ((int(views[vw[r]]["height"]) + tile - 1) // tile))
+        np.testing.assert_array_equal(bins.keys_unsorted[rows[r, 0]:rows[r, 0] + len(t)] >> D, t)
+
+
+@pytest.mark.parametrize("name", list(WL))
+def test_ellipse_culling_training_step(name):
+    scene, target_scene, views, tile = WL[name]
+    note(f"exact culling training-step parity {name}")
+    target = oracle.render(target_scene, views, tile, cull=oracle.CULL_ELLIPSE)
+    ref = oracle.train_step(scene, views, tile, target, cull=oracle.CULL_ELLIPSE)
+    g = run_gpu_step(scene, views, tile, target=target, cull=1)
+    V, n = len(views), scene.n
+    ok = ref.image.fragile == 0
+    assert ok.mean() > 0.995
+    assert np.abs(g["image"] - ref.image.rgb).max(axis=1)[ok].max() <= PIX_TOL
+    np.testing.assert_array_equal(g["last"][ok], ref.image.last[ok])
+    ex = exempt_gaussians(ref.bins.ranges, ref.bins.vals, ref.bins.gid, views, tile, ref.fragile, n)
+    ex_any = ex.any(axis=0)
+    # the gather's per-(view, Gaussian) sums against the oracle's
+    oks = grad_close(g["sums"].reshape(-1, 9), ref.grads2d.reshape(-1, 9), GRAD_RTOL).reshape(V, n, 9)
+    assert not (~oks.all(axis=2) & ~ex).any()
+    okg = grad_close(g["grads"], ref.grads, GRAD_RTOL)
+    assert not (~okg.all(axis=1) & ~ex_any).any()
+    # fewer intersections than the 3-sigma rectangle on the same scene
+    assert g["K"] < oracle.bin_sort(oracle.project(scene, views, tile), views, tile).keys.size

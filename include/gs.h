@@ -143,8 +143,9 @@ typedef struct gs_bins {
     uint32_t* offsets;   /* n_views*n + 1: exclusive scan of tiles; [n_views*n] = K */
     uint32_t* row_offsets; /* n_views*n + 1: exclusive scan of tile rows; [n_views*n] = R */
     uint32_t* rows;      /* 4 words per row slot: (first unsorted index of the row,
-                            (view, Gaussian) index v*n+g, xa | ty << 16, xb): the
-                            row's tiles are (xa..xb-1, ty) */
+                            (view, Gaussian) index v*n+g, xa | ty << 16, depth bits
+                            of the Gaussian's keys): the row's tiles are (xa.., ty),
+                            as many as the next slot's first index minus this one */
     int64_t row_capacity; /* row slots in `rows` */
     uint32_t* keys;      /* capacity: (tile << D) | depth bits, sorted per view */
     uint32_t* vals;      /* capacity: Gaussian id of each sorted key */
@@ -222,7 +223,7 @@ int gs_layout_init(const int32_t* widths, const int32_t* heights, int n_views, i
 size_t gs_bin_sort_workspace_size(int64_t n, const gs_layout* layout, int64_t capacity);
 
 /* Bytes of scratch (gs_grads2d.workspace) that gs_project_bwd_adam needs for
- * the given intersection capacity: per 1024 intersection indices, one owner
+ * the given intersection capacity: per 256 intersection indices, one owner
  * word and two partial sums of 9 floats. */
 size_t gs_grads2d_workspace_size(int64_t capacity);
 
@@ -309,9 +310,10 @@ int gs_project_bwd_adam(float* params, int64_t n, const gs_view* views, const gs
 
 /* ---- learned tile schedule (per-tile cost model) --------------------------- */
 
-/* 8 features per tile of the current bins (float, total tiles x 8): list length,
- * mean and max opacity, mean and min depth, mean radius, tile x and y (the
- * last two normalised by the view's tile grid). */
+/* 8 features per tile of the current bins (float, total tiles x 8): log(1 +
+ * list length); mean and max opacity, mean and min depth and mean radius over
+ * the first min(length, 512) entries of the sorted list; tile x and y (centre,
+ * normalised by the view's tile grid). */
 int gs_tile_features(const gs_splats* splats, int64_t n, const gs_layout* layout,
                      const gs_bins* bins, float* features, void* stream);
 

@@ -45,7 +45,8 @@ struct GatherArgs {
 };
 
 constexpr int kGatherThreads = 256;
-constexpr int kGatherE = 1024;   // intersection indices per workgroup
+constexpr int kGatherE = 256;      // intersection indices per workgroup (one per thread)
+constexpr int kGatherRows = 512;   // row slots staged in LDS per workgroup
 
 size_t gather_workspace(int64_t capacity) {
     const size_t nb = (size_t)((capacity + kGatherE - 1) / kGatherE) + 1;
@@ -84,20 +85,27 @@ __global__ __launch_bounds__(256) void k_gather_index(GatherArgs a) {
         a.block_first[blk] = (uint32_t)r;
 }
 
-// Gather: workgroup b owns the intersection indices [b E, (b+1) E).  Each
-// index finds its tile row by binary search over the row slots' first
-// indices (bounded by the slots of this block's and the next block's first
-// index), hence its (view, Gaussian) and tile,
-// tests traversal against its tile's stop entry and parks its record (or
-// zeros) in LDS, with coalesced record loads.  Then the first index of every
-// run of equal owner adds up its run in index order: a run that is the whole
-// of its Gaussian's range is written to sums directly; the block's first and
-// last runs, if their Gaussian extends past the block, go to per-block
-// partials that the chain-rule kernel adds in block order.  No workgroup
-// handles more than E indices, however long one Gaussian's list is.
+// Gather: workgroup b owns the intersection indices [b E, (b+1) E), one per
+// thread.  The row slots covering them (from the slot holding this block's
+// first index to the one holding the next block's) are staged in LDS.  Each
+// index finds its row by binary search in LDS, hence its (view, Gaussian),
+// tile and key, tests traversal against the tile's stop entry and parks its
+// record (or zeros) in LDS, with coalesced record loads.  (If more slots than
+// fit in LDS cover one block -- only possible with many rows whose span is
+// empty -- the search runs over the slots in global memory instead.)  Then
+// the first index of every run of equal owner adds up its run in index
+// order: a run that is the whole of its Gaussian's range is written to sums
+// directly; the block's first and last runs, if their Gaussian extends past
+// the block, go to per-block partials that the chain-rule kernel adds in
+// block order.  No workgroup handles more than E indices, however long one
+// Gaussian's list is.
 __global__ __launch_bounds__(kGatherThreads) void k_gather2d(GatherArgs a) {
-    __shared__ float s_rec[kGatherE][9];
+    __shared__ float4 s_rec[kGatherE][3];
     __shared__ uint32_t s_own[kGatherE];
+    __shared__ uint32_t s_first[kGatherRows];
+    __shared__ uint32_t s_o[kGatherRows];
+    __shared__ uint32_t s_txy[kGatherRows];
+    __shared__ uint32_t s_dk[kGatherRows];
     const int64_t vn = (int64_t)a.n_views * a.n;
     const uint64_t kc = entries_valid(a, vn);
     const uint64_t e0 = (uint64_t)blockIdx.x * kGatherE;
@@ -107,52 +115,78 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather2d(GatherArgs a) {
     const uint32_t ra = a.block_first[blockIdx.x];
     const uint32_t rz = blockIdx.x + 1 < nblk ? a.block_first[blockIdx.x + 1]
                                               : (uint32_t)(rows_valid(a, vn) - 1);
+    const uint32_t nr = rz - ra + 1;
+    const bool staged = nr <= (uint32_t)kGatherRows;
     const int t = threadIdx.x;
+    if (staged) {
+        for (uint32_t k = t; k < nr; k += kGatherThreads) {
+            const uint4 row = a.rows[ra + k];
+            s_first[k] = row.x;
+            s_o[k] = row.y;
+            s_txy[k] = row.z;
+            s_dk[k] = row.w;
+        }
+    }
+    __syncthreads();
     const int cnt = (int)(e1 - e0);
-    for (int j = t; j < kGatherE; j += kGatherThreads) {
-        float r[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    {
+        const int j = t;
+        float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
         uint32_t own = 0xFFFFFFFFu;
         if (j < cnt) {
             const uint32_t i = (uint32_t)(e0 + (uint64_t)j);
-            uint32_t lo = ra, hi = rz;
-            while (lo < hi) {
-                const uint32_t mid = lo + ((hi - lo + 1) >> 1);
-                if (a.rows[mid].x <= i) lo = mid; else hi = mid - 1;
+            uint32_t first, txy, dk;
+            if (staged) {
+                uint32_t lo = 0, hi = nr - 1;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi + 1) >> 1;
+                    if (s_first[mid] <= i) lo = mid; else hi = mid - 1;
+                }
+                first = s_first[lo]; own = s_o[lo]; txy = s_txy[lo]; dk = s_dk[lo];
+            } else {
+                uint32_t lo = ra, hi = rz;
+                while (lo < hi) {
+                    const uint32_t mid = lo + ((hi - lo + 1) >> 1);
+                    if (a.rows[mid].x <= i) lo = mid; else hi = mid - 1;
+                }
+                const uint4 row = a.rows[lo];
+                first = row.x; own = row.y; txy = row.z; dk = row.w;
             }
-            const uint4 row = a.rows[lo];
-            own = row.y;
-            const int v = (int)((int64_t)own / a.n);
-            const float4 q3 = a.rec[4 * (int64_t)own + 3];
-            const uint32_t tile = (row.z >> 16) * (uint32_t)a.gx[v] + (row.z & 0xFFFF) + (i - row.x);
+            const int v = (int)(own / (uint32_t)a.n);
+            const uint32_t tile = (txy >> 16) * (uint32_t)a.gx[v] + (txy & 0xFFFF) + (i - first);
             // (a tile outside the view only arises after a row-capacity overflow)
             const uint4 st = tile < (uint32_t)a.ntiles[v] ? a.stop[a.tile_base[v] + (int)tile]
                                                           : make_uint4(0u, 0u, 0u, 0u);
-            const int D = a.depth_bits[v];
-            const uint32_t key = (tile << D) | (__float_as_uint(q3.z) >> (23 - D));
+            const uint32_t key = (tile << a.depth_bits[v]) | dk;
             if (key < st.y || (key == st.y && i < st.z)) {
                 const float4* g = a.grec + 3 * (int64_t)i;
-                const float4 q0 = g[0], q1 = g[1], q2 = g[2];
-                r[0] = q0.x; r[1] = q0.y; r[2] = q0.z; r[3] = q0.w;
-                r[4] = q1.x; r[5] = q1.y; r[6] = q1.z; r[7] = q1.w; r[8] = q2.x;
+                r0 = g[0]; r1 = g[1]; r2 = g[2];
+                r2.y = 0.f; r2.z = 0.f; r2.w = 0.f;
             }
         }
-#pragma unroll
-        for (int c = 0; c < 9; ++c) s_rec[j][c] = r[c];
+        s_rec[j][0] = r0; s_rec[j][1] = r1; s_rec[j][2] = r2;
         s_own[j] = own;
     }
     __syncthreads();
-    for (int j = t; j < cnt; j += kGatherThreads) {
+    const int j = t;
+    if (j < cnt && (j == 0 || s_own[j - 1] != s_own[j])) {   // the first index of a run
         const uint32_t own = s_own[j];
-        if (j > 0 && s_own[j - 1] == own) continue;   // not the start of a run
-        float d[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        int jj = j;
-        for (; jj < cnt && s_own[jj] == own; ++jj) {
-#pragma unroll
-            for (int c = 0; c < 9; ++c) d[c] += s_rec[jj][c];
-        }
         const uint64_t gb = a.offsets[own];
         const uint64_t ge = min((uint64_t)a.offsets[own + 1], (uint64_t)a.capacity);
         const bool before = gb < e0, after = ge > e1;
+        // the run is the Gaussian's indices inside this block: a fixed trip count
+        const int jend = (int)(min(ge, e1) - e0);
+        float4 d0 = make_float4(0.f, 0.f, 0.f, 0.f), d1 = d0;
+        float d8 = 0.f;
+#pragma unroll 4
+        for (int jj = j; jj < jend; ++jj) {
+            const float4 q0 = s_rec[jj][0], q1 = s_rec[jj][1];
+            const float q8 = s_rec[jj][2].x;
+            d0.x += q0.x; d0.y += q0.y; d0.z += q0.z; d0.w += q0.w;
+            d1.x += q1.x; d1.y += q1.y; d1.z += q1.z; d1.w += q1.w;
+            d8 += q8;
+        }
+        const float d[9] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w, d8};
         float* dst;
         int64_t stride;
         if (!before && !after) { dst = a.sums + own; stride = vn; }

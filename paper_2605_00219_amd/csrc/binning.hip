@@ -231,8 +231,9 @@ __global__ __launch_bounds__(256) void k_row_count(const float4* __restrict__ re
 }
 
 // One thread per (view, Gaussian): the column span of each of its tile rows
-// (the rectangle's columns, or the ellipse's span of that row) and the
-// unsorted index of the row's first tile.  The spans are the ones the
+// (the rectangle's columns, or the ellipse's span of that row), recorded as
+// the unsorted index of the row's first tile and its first column, with the
+// Gaussian's depth bits.  The spans are the ones the
 // projection counted (same function of the same record values).
 __global__ __launch_bounds__(256) void k_rows(const float4* __restrict__ rec,
                                               const uint32_t* __restrict__ tiles,
@@ -251,6 +252,7 @@ __global__ __launch_bounds__(256) void k_rows(const float4* __restrict__ rec,
     const bool ell = geo.cull == GS_CULL_ELLIPSE;
     if (ell) ellipse_setup(q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, e);
     uint32_t first = offsets[o];
+    const uint32_t dk = __float_as_uint(q3.z) >> (23 - geo.depth_bits[v]);
     const uint64_t rs = row_offsets[o];
     if (rs + (uint64_t)(y1 - y0) > (uint64_t)row_capacity) atomicOr(status, (uint32_t)GS_STATUS_ROWS);
     for (int ty = y0; ty < y1; ++ty) {
@@ -259,7 +261,7 @@ __global__ __launch_bounds__(256) void k_rows(const float4* __restrict__ rec,
         if (xb < xa) xb = xa;
         const uint64_t slot = rs + (uint64_t)(ty - y0);
         if (slot < (uint64_t)row_capacity)
-            rows[slot] = make_uint4(first, (uint32_t)o, (uint32_t)xa | ((uint32_t)ty << 16), (uint32_t)xb);
+            rows[slot] = make_uint4(first, (uint32_t)o, (uint32_t)xa | ((uint32_t)ty << 16), dk);
         first += (uint32_t)(xb - xa);
     }
 }
@@ -296,7 +298,7 @@ __global__ __launch_bounds__(kEmitG) void k_emit(const float4* __restrict__ rec,
         const int v = (int)(o / n);
         const int D = geo.depth_bits[v];
         s_tile[t] = (row.z >> 16) * (uint32_t)geo.tiles_x[v] + (row.z & 0xFFFF);
-        s_dk[t] = __float_as_uint(rec[4 * o + 3].z) >> (23 - D);
+        s_dk[t] = row.w;
         s_gid[t] = (uint32_t)(o - (int64_t)v * n);
         s_D[t] = (uint8_t)D;
     } else {

@@ -16,6 +16,11 @@ static_assert(kOffB3 + 1 == GS_MLP_PARAMS, "weight layout");
 // tile features
 // ---------------------------------------------------------------------------
 
+// Opacity, depth and radius statistics cover the front of the list only (the
+// entries a pixel reaches before it saturates), so the cost of the features
+// does not grow with the length of the list.
+constexpr uint32_t kFeatEntries = 512;
+
 __global__ __launch_bounds__(64) void k_tile_features(const float4* __restrict__ rec,
                                                       const uint32_t* __restrict__ vals,
                                                       const uint2* __restrict__ ranges, int64_t n,
@@ -23,8 +28,9 @@ __global__ __launch_bounds__(64) void k_tile_features(const float4* __restrict__
     const int gt = blockIdx.x;
     const int v = view_of_tile(L, gt);
     const uint2 r = ranges[gt];
+    const uint32_t fe = min(r.y, r.x + kFeatEntries);
     float so = 0.f, mo = 0.f, sz = 0.f, mz = 3.4e38f, sr = 0.f;
-    for (uint32_t j = r.x + threadIdx.x; j < r.y; j += 64) {
+    for (uint32_t j = r.x + threadIdx.x; j < fe; j += 64) {
         const float4* r = rec + 4 * ((int64_t)v * n + vals[j]);
         const float o = r[1].y;
         const float4 q2 = r[2];
@@ -43,7 +49,8 @@ __global__ __launch_bounds__(64) void k_tile_features(const float4* __restrict__
     }
     if (threadIdx.x == 0) {
         const uint32_t len = r.y - r.x;
-        const float inv = len ? 1.0f / (float)len : 0.0f;
+        const uint32_t flen = fe - r.x;
+        const float inv = flen ? 1.0f / (float)flen : 0.0f;
         const int lt = gt - L.tile_base[v];
         const int gx = L.tiles_x[v], gy = L.tiles_y[v];
         float* f = feat + 8 * (int64_t)gt;

@@ -97,8 +97,8 @@ class Frame:
     # -- buffers sized by the intersection capacity (and the tile-row capacity) --
     def resize(self, capacity: int, row_capacity: int | None = None) -> None:
         capacity = max(int(capacity), 1)
-        if row_capacity is None:        # rows never outnumber tiles for the 3-sigma rectangle
-            row_capacity = max(capacity, self.row_capacity)
+        if row_capacity is None:        # keep the row capacity; rows never outnumber tiles
+            row_capacity = self.row_capacity or capacity   # for the 3-sigma rectangle
         row_capacity = max(int(row_capacity), 1)
         u32 = dict(dtype=torch.int32, device=self.device)
         self.rows = torch.zeros(row_capacity, 4, **u32)
@@ -212,9 +212,13 @@ def fit_capacity(params: torch.Tensor, frame: Frame, views_dev: torch.Tensor, sl
     project(params, frame, views_dev)
     K = int(frame.tiles.to(torch.int64).sum().item())
     R = tile_rows(frame)
-    if K > frame.capacity or R > frame.row_capacity:
-        cap = max(frame.capacity, int(math.ceil(K * slack)) + 1024)
-        rcap = max(frame.row_capacity, int(math.ceil(R * slack)) + 1024)
+    need_r = int(math.ceil(R * slack)) + 1024
+    # grow either buffer as needed; also shrink the row slots when far larger
+    # than needed (their launches are sized by the row capacity)
+    if K > frame.capacity or R > frame.row_capacity or frame.row_capacity > 4 * need_r:
+        cap = max(frame.capacity, int(math.ceil(K * slack)) + 1024) if K > frame.capacity \
+            else frame.capacity
+        rcap = max(frame.row_capacity, need_r) if R > frame.row_capacity else need_r
         frame.resize(cap, rcap)
     return K
 

@@ -80,17 +80,21 @@ def test_order_by_cost_is_stable_descending_with_fallback(mods):
     np.testing.assert_array_equal(order, np.arange(p.size))
 
 
-def test_tile_features_match_oracle_bins(mods):
+@pytest.mark.parametrize("dense", [False, True])
+def test_tile_features_match_oracle_bins(mods, dense):
     torch, G, P, SC = mods
-    note("tile features")
+    note(f"tile features (dense={dense})")
     w = S.workload_plain_small()
-    g = run_gpu_step(w.scene, w.views, 16)
+    scene = S.scene_uniform_cube(20_000, 1234, log_scale_mean=-2.0, log_scale_std=0.3) if dense else w.scene
+    g = run_gpu_step(scene, w.views, 16)
     feats = SC.tile_features(g["frame"]).cpu().numpy()
-    pr = oracle.project(w.scene, w.views, 16)
+    pr = oracle.project(scene, w.views, 16)
     bins = oracle.bin_sort(pr, w.views, 16)
+    if dense:   # lists longer than the 512 entries the statistics cover
+        assert (np.diff(bins.ranges, axis=1) > 512).sum() > 20
     for t in range(256):
         s, e = bins.ranges[t]
-        ids = bins.gid[bins.vals[s:e]]
+        ids = bins.gid[bins.vals[s:min(e, s + 512)]]     # statistics over the first 512 entries
         ref = np.zeros(8)
         ref[0] = np.log1p(e - s)
         if e > s:

@@ -95,8 +95,7 @@ typedef struct gs_layout {
     int32_t n_views;
     int32_t tile;                          /* tile edge T in pixels: 8, 16 or 32 */
     int32_t pixels_per_lane;               /* rasteriser lanes per tile = T*T / this; 1 for
-                                              T = 8, 1, 2 or 4 otherwise (default 4 for
-                                              T = 16, 2 for T = 32) */
+                                              T = 8, 1, 2 or 4 otherwise (default 2) */
     int32_t cull;                          /* GS_CULL_RECT (default) or GS_CULL_ELLIPSE */
     int32_t width[GS_MAX_VIEWS], height[GS_MAX_VIEWS];
     int32_t tiles_x[GS_MAX_VIEWS], tiles_y[GS_MAX_VIEWS];
@@ -155,20 +154,19 @@ typedef struct gs_bins {
 } gs_bins;
 
 /* Screen-space gradients written by gs_rasterize_bwd and read by
- * gs_project_bwd_adam: one record per intersection that the backward
- * traversed, at its unsorted index, so that each (view, Gaussian) finds its
- * records in its own contiguous index range.  Which intersections were
- * traversed follows from the tile's stop entry: the sorted order within a
- * tile is ascending (key, unsorted index), and the traversal covers exactly
- * the entries before the first one it did not reach. */
+ * gs_project_bwd_adam: one record per intersection that some pixel of its
+ * tile composited (the only ones with a non-zero gradient), at its unsorted
+ * index, so that each (view, Gaussian) finds its records in its own
+ * contiguous index range; rec_mask flags which records the last call wrote. */
 typedef struct gs_grads2d {
     float* rec;           /* capacity records of 12 floats: (d u, d v, d A, d B, d C,
-                             d opacity, d r, d g, d b, 0, 0, 0); records of entries
-                             not traversed are left as they were */
-    uint32_t* tile_stop;  /* 4 words per tile t: (stop, key, index, 0).  Entries at
-                             sorted positions [ranges[t].start, stop) were traversed;
-                             (key, index) are the key and unsorted index of the entry
-                             at `stop`, or (0xFFFFFFFF, 0xFFFFFFFF) if stop = end */
+                             d opacity, d r, d g, d b, 0, 0, 0); records not flagged in
+                             rec_mask are left as they were */
+    uint32_t* rec_mask;   /* ceil(capacity / 32) words: bit i (word i / 32, bit i % 32)
+                             set iff record i was written by the last gs_rasterize_bwd */
+    uint32_t* tile_stop;  /* total tiles: the backward traversed sorted positions
+                             [ranges[t].start, tile_stop[t]) of tile t (up to the last
+                             entry any of its pixels composited) */
     float* sums;          /* 9 planes of n_views * n floats, plane c at c * n_views * n:
                              per (view, Gaussian) sum of its traversed records
                              (components 0..8), written by gs_project_bwd_adam */
@@ -185,6 +183,9 @@ typedef struct gs_image {
     uint32_t* tile_stats; /* nullable; 4 * total tiles: (entries traversed by the tile
                              = max over its pixels of the entries examined, pixel-Gaussian
                              pairs evaluated, pairs composited, 0) */
+    uint32_t* comp_mask;  /* ceil(capacity / 32) words, written by gs_rasterize_fwd and
+                             read by gs_rasterize_bwd: bit j set iff some pixel of the
+                             tile composited sorted entry j */
 } gs_image;
 
 /* Optional persistent schedule for the rasterisation kernels: a fixed grid of
@@ -284,9 +285,11 @@ int gs_rasterize_fwd(const gs_splats* splats, int64_t n, const gs_layout* layout
  * (pixels * 3) or, if `target` (pixels * 3) is given, from the fused L1 loss
  * mean|C - target| over all channels of all pixels: g = sign(C - target) /
  * (3 * pixels).  Per-pixel contributions are summed over each tile with
- * wavefront reductions (no atomics) into one record per traversed
- * intersection, written at its unsorted index (see gs_grads2d); a tile's
- * traversal ends at the last entry any of its pixels composited.
+ * wavefront reductions (no floating-point atomics) into one record per
+ * intersection that some pixel of its tile composited (fwd->comp_mask), written
+ * at its unsorted index (see gs_grads2d); entries no pixel composited are
+ * skipped without being evaluated, and a tile's traversal ends at the last
+ * entry any of its pixels composited.
  *   loss      nullable device, total tiles floats: per-tile sum |C - target|
  *             (only with `target`) */
 int gs_rasterize_bwd(const gs_splats* splats, int64_t n, const gs_layout* layout,
@@ -295,7 +298,7 @@ int gs_rasterize_bwd(const gs_splats* splats, int64_t n, const gs_layout* layout
                      float* loss, int lds_batch, const gs_schedule* sched, void* stream);
 
 /* Projection backward fused with Adam (Sec. 4.3).  First pass: for each
- * (view, Gaussian), the sum of its traversed intersection records in
+ * (view, Gaussian), the sum of its records flagged in grads->rec_mask, in
  * unsorted-index order, into grads->sums.  Second pass, per Gaussian: applies the
  * chain rule back through colour (SH basis, clamp, view direction), opacity
  * (sigmoid), conic (inverse), 2D covariance (J R Sigma R^T J^T), the pinhole

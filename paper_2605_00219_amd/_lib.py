@@ -52,13 +52,13 @@ class GsBins(C.Structure):
 
 
 class GsGrads2d(C.Structure):
-    _fields_ = [("rec", C.c_void_p), ("tile_stop", C.c_void_p), ("sums", C.c_void_p),
-                ("workspace", C.c_void_p)]
+    _fields_ = [("rec", C.c_void_p), ("rec_mask", C.c_void_p), ("tile_stop", C.c_void_p),
+                ("sums", C.c_void_p), ("workspace", C.c_void_p)]
 
 
 class GsImage(C.Structure):
     _fields_ = [("rgb", C.c_void_p), ("T", C.c_void_p), ("last", C.c_void_p),
-                ("tile_stats", C.c_void_p)]
+                ("tile_stats", C.c_void_p), ("comp_mask", C.c_void_p)]
 
 
 class GsSchedule(C.Structure):

@@ -1,11 +1,9 @@
 // Projection backward fused with Adam, in two passes.
 //
 // Gather: per (view, Gaussian), the sum of the screen-space gradient records
-// of its traversed intersections.  The backward rasteriser wrote them at
-// their unsorted indices, so a Gaussian's records are one contiguous range;
-// whether an entry was traversed follows from its tile's stop entry (sorted
-// order within a tile is ascending (key, unsorted index)).  The sums go to a
-// dense [9][views * n] array.
+// the backward rasteriser flagged.  It wrote them at their unsorted indices,
+// so a Gaussian's records are one contiguous range.  The sums go to a dense
+// [9][views * n] array.
 //
 // Chain rule + Adam: one thread per Gaussian streams its parameter record and
 // both Adam moments once, reads its per-view sums (coalesced), and writes
@@ -27,14 +25,10 @@ struct GatherArgs {
     const uint32_t* row_offsets;
     const uint4* rows;
     int64_t row_capacity;
-    const uint4* stop;
+    const uint32_t* rec_mask;
     const float4* grec;
     int64_t n;
     int64_t capacity;
-    int32_t gx[GS_MAX_VIEWS];
-    int32_t tile_base[GS_MAX_VIEWS];
-    int32_t ntiles[GS_MAX_VIEWS];
-    int32_t depth_bits[GS_MAX_VIEWS];
     int n_views;
     float* sums;
     uint32_t* block_first;  // per block: the row slot holding its first index
@@ -89,23 +83,20 @@ __global__ __launch_bounds__(256) void k_gather_index(GatherArgs a) {
 // thread.  The row slots covering them (from the slot holding this block's
 // first index to the one holding the next block's) are staged in LDS.  Each
 // index finds its row by binary search in LDS, hence its (view, Gaussian),
-// tile and key, tests traversal against the tile's stop entry and parks its
-// record (or zeros) in LDS, with coalesced record loads.  (If more slots than
-// fit in LDS cover one block -- only possible with many rows whose span is
-// empty -- the search runs over the slots in global memory instead.)  Then
-// the first index of every run of equal owner adds up its run in index
-// order: a run that is the whole of its Gaussian's range is written to sums
-// directly; the block's first and last runs, if their Gaussian extends past
-// the block, go to per-block partials that the chain-rule kernel adds in
-// block order.  No workgroup handles more than E indices, however long one
-// Gaussian's list is.
+// and parks its record in LDS if the backward flagged it (else zeros), with
+// coalesced record loads.  (If more slots than fit in LDS cover one block --
+// only possible with many rows whose span is empty -- the search runs over
+// the slots in global memory instead.)  Then the first index of every run of
+// equal owner adds up its run in index order: a run that is the whole of its
+// Gaussian's range is written to sums directly; the block's first and last
+// runs, if their Gaussian extends past the block, go to per-block partials
+// that the chain-rule kernel adds in block order.  No workgroup handles more
+// than E indices, however long one Gaussian's list is.
 __global__ __launch_bounds__(kGatherThreads) void k_gather2d(GatherArgs a) {
     __shared__ float4 s_rec[kGatherE][3];
     __shared__ uint32_t s_own[kGatherE];
     __shared__ uint32_t s_first[kGatherRows];
     __shared__ uint32_t s_o[kGatherRows];
-    __shared__ uint32_t s_txy[kGatherRows];
-    __shared__ uint32_t s_dk[kGatherRows];
     const int64_t vn = (int64_t)a.n_views * a.n;
     const uint64_t kc = entries_valid(a, vn);
     const uint64_t e0 = (uint64_t)blockIdx.x * kGatherE;
@@ -123,8 +114,6 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather2d(GatherArgs a) {
             const uint4 row = a.rows[ra + k];
             s_first[k] = row.x;
             s_o[k] = row.y;
-            s_txy[k] = row.z;
-            s_dk[k] = row.w;
         }
     }
     __syncthreads();
@@ -135,30 +124,23 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather2d(GatherArgs a) {
         uint32_t own = 0xFFFFFFFFu;
         if (j < cnt) {
             const uint32_t i = (uint32_t)(e0 + (uint64_t)j);
-            uint32_t first, txy, dk;
+            const uint32_t flag = (a.rec_mask[i >> 5] >> (i & 31u)) & 1u;
             if (staged) {
                 uint32_t lo = 0, hi = nr - 1;
                 while (lo < hi) {
                     const uint32_t mid = (lo + hi + 1) >> 1;
                     if (s_first[mid] <= i) lo = mid; else hi = mid - 1;
                 }
-                first = s_first[lo]; own = s_o[lo]; txy = s_txy[lo]; dk = s_dk[lo];
+                own = s_o[lo];
             } else {
                 uint32_t lo = ra, hi = rz;
                 while (lo < hi) {
                     const uint32_t mid = lo + ((hi - lo + 1) >> 1);
                     if (a.rows[mid].x <= i) lo = mid; else hi = mid - 1;
                 }
-                const uint4 row = a.rows[lo];
-                first = row.x; own = row.y; txy = row.z; dk = row.w;
+                own = a.rows[lo].y;
             }
-            const int v = (int)(own / (uint32_t)a.n);
-            const uint32_t tile = (txy >> 16) * (uint32_t)a.gx[v] + (txy & 0xFFFF) + (i - first);
-            // (a tile outside the view only arises after a row-capacity overflow)
-            const uint4 st = tile < (uint32_t)a.ntiles[v] ? a.stop[a.tile_base[v] + (int)tile]
-                                                          : make_uint4(0u, 0u, 0u, 0u);
-            const uint32_t key = (tile << a.depth_bits[v]) | dk;
-            if (key < st.y || (key == st.y && i < st.z)) {
+            if (flag) {
                 const float4* g = a.grec + 3 * (int64_t)i;
                 r0 = g[0]; r1 = g[1]; r2 = g[2];
                 r2.y = 0.f; r2.z = 0.f; r2.w = 0.f;
@@ -491,7 +473,7 @@ int launch_project_bwd_adam(float* params, int64_t n, const gs_view* views, cons
     ga.row_offsets = b.row_offsets;
     ga.rows = reinterpret_cast<const uint4*>(b.rows);
     ga.row_capacity = b.row_capacity;
-    ga.stop = reinterpret_cast<const uint4*>(grads.tile_stop);
+    ga.rec_mask = grads.rec_mask;
     ga.grec = reinterpret_cast<const float4*>(grads.rec);
     ga.n = n;
     ga.capacity = b.capacity;
@@ -509,10 +491,6 @@ int launch_project_bwd_adam(float* params, int64_t n, const gs_view* views, cons
     for (int v = 0; v < GS_MAX_VIEWS; ++v) {
         a.gx[v] = v < L.n_views ? L.tiles_x[v] : 0;
         a.gy[v] = v < L.n_views ? L.tiles_y[v] : 0;
-        ga.gx[v] = a.gx[v];
-        ga.tile_base[v] = v < L.n_views ? L.tile_base[v] : 0;
-        ga.ntiles[v] = v < L.n_views ? L.tile_base[v + 1] - L.tile_base[v] : 0;
-        ga.depth_bits[v] = v < L.n_views ? L.depth_bits[v] : 0;
     }
     a.grads_out = reinterpret_cast<float4*>(grads_out);
     if (adam) {

@@ -64,7 +64,7 @@ int gs_layout_init(const int32_t* widths, const int32_t* heights, int n_views, i
     memset(&L, 0, sizeof(L));
     L.n_views = n_views;
     L.tile = tile;
-    L.pixels_per_lane = tile == 8 ? 1 : (tile == 16 ? 4 : 2);
+    L.pixels_per_lane = tile == 8 ? 1 : 2;
     L.cull = GS_CULL_RECT;
     int64_t tb = 0, pb = 0;
     for (int v = 0; v < n_views; ++v) {
@@ -139,8 +139,8 @@ int gs_rasterize_fwd(const gs_splats* splats, int64_t n, const gs_layout* layout
                      const gs_bins* bins, const gs_view* views, const gs_image* out, int lds_batch,
                      const gs_schedule* sched, void* stream) {
     REQUIRE(layout_ok(layout), "gs_rasterize_fwd: invalid layout");
-    REQUIRE(splats && bins && views && out && out->rgb && out->T && out->last,
-            "gs_rasterize_fwd: null pointer");
+    REQUIRE(splats && bins && views && out && out->rgb && out->T && out->last &&
+            (out->comp_mask || bins->capacity == 0), "gs_rasterize_fwd: null pointer");
     REQUIRE(lds_batch == 32 || lds_batch == 64 || lds_batch == 128 || lds_batch == 256,
             "gs_rasterize_fwd: lds_batch %d not in {32, 64, 128, 256}", lds_batch);
     int rc = check_sched(sched);
@@ -154,10 +154,11 @@ int gs_rasterize_bwd(const gs_splats* splats, int64_t n, const gs_layout* layout
                      const float* target, const float* dL_dC, const gs_grads2d* grads,
                      float* loss, int lds_batch, const gs_schedule* sched, void* stream) {
     REQUIRE(layout_ok(layout), "gs_rasterize_bwd: invalid layout");
-    REQUIRE(splats && bins && views && fwd && fwd->rgb && fwd->last, "gs_rasterize_bwd: null pointer");
+    REQUIRE(splats && bins && views && fwd && fwd->rgb && fwd->last &&
+            (fwd->comp_mask || bins->capacity == 0), "gs_rasterize_bwd: null pointer");
     REQUIRE((target != nullptr) != (dL_dC != nullptr),
             "gs_rasterize_bwd: give exactly one of target (fused L1) and dL_dC");
-    REQUIRE(grads && grads->tile_stop && (grads->rec || bins->capacity == 0),
+    REQUIRE(grads && grads->tile_stop && ((grads->rec && grads->rec_mask) || bins->capacity == 0),
             "gs_rasterize_bwd: null gradient buffers");
     REQUIRE(lds_batch == 32 || lds_batch == 64 || lds_batch == 128 || lds_batch == 256,
             "gs_rasterize_bwd: lds_batch %d not in {32, 64, 128, 256}", lds_batch);
@@ -176,7 +177,8 @@ int gs_project_bwd_adam(float* params, int64_t n, const gs_view* views, const gs
     REQUIRE(!adam || (adam->m && adam->v && adam->step && adam->scratch),
             "gs_project_bwd_adam: incomplete adam state");
     REQUIRE(splats && (n == 0 || splats->rec), "gs_project_bwd_adam: null splat records");
-    REQUIRE(grads && grads->tile_stop && (grads->sums || n == 0) && (grads->rec || bins->capacity == 0) &&
+    REQUIRE(grads && (grads->sums || n == 0) &&
+            ((grads->rec && grads->rec_mask) || bins->capacity == 0) &&
             grads->workspace, "gs_project_bwd_adam: null gradient buffers");
     return launch_project_bwd_adam(params, n, views, *layout, *splats, *bins, *grads, adam, grads_out,
                                    (hipStream_t)stream);

@@ -1,7 +1,7 @@
 // Tile rasteriser: forward alpha compositing and its exact backward.
 //
-// One workgroup renders one T x T tile (T = 8, 16, 32: one pixel per lane for
-// T = 8, four pixels per lane otherwise, so 1, 1 or 4 wavefronts per tile).
+// One workgroup renders one T x T tile (T = 8, 16, 32) with T*T/P lanes, each
+// lane rendering P pixels (P = 1 for T = 8; 1, 2 or 4 otherwise, default 2).
 // The tile's sorted Gaussian list is consumed in
 // batches of S records gathered into LDS; every lane then reads the batch
 // with broadcast LDS loads.  The conic is staged pre-scaled by -log2(e)/2 so
@@ -15,11 +15,12 @@
 // are summed over each wavefront with DPP row/broadcast reductions (no
 // atomics), waves whose lanes all skip a Gaussian skip its reduction (ballot),
 // and the per-wave sums are added in a fixed order through LDS: one 48-byte
-// record per traversed (Gaussian, tile) intersection, written at its unsorted
-// index (so each Gaussian's records are contiguous for the gather that
-// follows), deterministic.  A tile stops at the last entry any of its pixels
-// composited; the stop position and the (key, index) of the first entry not
-// traversed are recorded.
+// record per (Gaussian, tile) intersection that some pixel composited,
+// written at its unsorted index (so each Gaussian's records are contiguous
+// for the gather that follows) and flagged in a bit mask, deterministic.  The
+// forward marks, per sorted entry, whether any pixel of the tile composited
+// it; the backward stages only those entries (the others have no gradient),
+// and stops at the last entry any of its pixels composited.
 //
 // Scheduling: either one workgroup per tile, or a persistent grid popping
 // tiles from a device counter in the order of a permutation (static or
@@ -50,13 +51,14 @@ struct RasterArgs {
     float* out_T;
     uint32_t* out_last;
     uint32_t* tile_stats;
+    uint32_t* comp_mask;    // bit per sorted entry: composited by some pixel of its tile
+    uint32_t* rec_mask;     // bit per unsorted index: gradient record written
     // backward
     const float* target;
     const float* dLdC;
     float inv_count;
     float4* grec;           // 3 float4 per unsorted index
-    uint4* tile_stop;       // (stop, key, unsorted index, 0) per tile
-    const uint32_t* keys;   // sorted keys
+    uint32_t* tile_stop;
     const uint32_t* row_offsets;
     const uint4* rows;
     int64_t row_capacity;
@@ -124,11 +126,11 @@ GS_DEV int next_tile(const RasterArgs& a, int* s_tile) {
 }
 
 // Pixels per lane: a T x T tile is covered by T*T/PPT lanes, lane t holding
-// the pixels t, t + NT, t + 2 NT, ... of the tile (row major).  With 16x16
-// tiles and PPT = 4 one wavefront renders a whole tile: each staged Gaussian
-// is read from LDS once per four pixels, the four transmittance chains give
-// independent work to interleave, and the backward's per-Gaussian wavefront
-// reduction is shared by four pixels per lane.
+// the pixels t, t + NT, t + 2 NT, ... of the tile (row major).  More pixels
+// per lane read each staged Gaussian from LDS once for several pixels, give
+// independent transmittance chains to interleave and share the backward's
+// per-Gaussian wavefront reduction; fewer give more wavefronts per tile to
+// hide latency (with 16x16 tiles, PPT = 4 is one wavefront per tile).
 template <int TILE, int PPT_>
 struct Geo {
     static constexpr int PPT = PPT_;
@@ -160,9 +162,28 @@ GS_DEV TileInfo tile_info(const RasterArgs& a, int gt) {
 // forward
 // ---------------------------------------------------------------------------
 
+template <int CTRL, int ROW_MASK>
+GS_DEV uint32_t dpp_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xF, false);
+}
+
+// OR of `bits` over the wavefront (DPP within rows, ds_bpermute across rows),
+// added to *word by one lane if non-zero.  addr16/addr32 = 4 (lane ^ 16 / 32).
+GS_DEV void flush_comp_bits(uint32_t* word, uint32_t bits, int addr16, int addr32) {
+    bits |= dpp_u32<0xB1, 0xF>(bits);
+    bits |= dpp_u32<0x4E, 0xF>(bits);
+    bits |= dpp_u32<0x141, 0xF>(bits);
+    bits |= dpp_u32<0x140, 0xF>(bits);
+    bits |= (uint32_t)__builtin_amdgcn_ds_bpermute(addr16, (int)bits);
+    bits |= (uint32_t)__builtin_amdgcn_ds_bpermute(addr32, (int)bits);
+    if (bits != 0u && (threadIdx.x & (kWave - 1)) == 0) atomicOr(word, bits);
+}
+
 template <int TILE, int S, int PPT_, bool STATS>
 __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_fwd(RasterArgs a) {
     constexpr int PPT = PPT_, NT = Geo<TILE, PPT_>::NT;
+    const int lane_ = threadIdx.x & (kWave - 1);
+    const int addr16 = (lane_ ^ 16) << 2, addr32 = (lane_ ^ 32) << 2;
     __shared__ float4 s_g[S];
     __shared__ float4 s_h[S];
     __shared__ float s_b[S];
@@ -208,11 +229,16 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_fwd(RasterArgs a)
             if (__ballot(any) != 0ull) {
                 const int cnt = (int)min((uint32_t)S, end - b0);
                 const uint32_t base = b0 - start + 1u;
+                // bits of comp_mask for the entries of this batch that this
+                // lane's pixels composited, OR-reduced over the wavefront and
+                // flushed once per 32-bit word of the mask
+                uint32_t lbits = 0;
+                int kend = cnt - 1;
                 for (int k = 0; k < cnt; ++k) {
                     const float4 sg = s_g[k];
                     const float4 sh = s_h[k];
                     const float cb = s_b[k];
-                    bool still = false;
+                    bool still = false, compd = false;
 #pragma unroll
                     for (int q = 0; q < PPT; ++q) {
                         float dx, dy, G, ag;
@@ -232,9 +258,18 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_fwd(RasterArgs a)
                         last[q] = comp ? base + (uint32_t)k : last[q];
                         if (STATS) composited[q] += comp ? 1u : 0u;
                         still = still || active[q];
+                        compd = compd || comp;
                     }
-                    if (__ballot(still) == 0ull) break;
+                    const uint32_t j = b0 + (uint32_t)k;
+                    lbits |= compd ? 1u << (j & 31u) : 0u;
+                    if ((j & 31u) == 31u) {
+                        flush_comp_bits(a.comp_mask + (j >> 5), lbits, addr16, addr32);
+                        lbits = 0;
+                    }
+                    if (__ballot(still) == 0ull) { kend = k; break; }
                 }
+                // the word of the last entry examined, if not flushed yet
+                flush_comp_bits(a.comp_mask + ((b0 + (uint32_t)kend) >> 5), lbits, addr16, addr32);
             }
         }
         const float* bg = a.views[ti.view].bg;
@@ -315,6 +350,8 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd(RasterArgs a)
     __shared__ float s_b[S];
     __shared__ uint32_t s_gid[S];
     __shared__ uint32_t s_idx[S];
+    __shared__ uint32_t s_pos[S];
+    __shared__ uint32_t s_mw[S / 32 + 2];
     __shared__ float s_red[NW][SUB][9];
     __shared__ uint64_t s_mask[NW];
     __shared__ int s_tile;
@@ -389,23 +426,42 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd(RasterArgs a)
         const uint32_t stop = start + s_len;
         for (uint32_t b0 = start; b0 < stop; b0 += S) {
             __syncthreads();
+            // the forward's composite mask for positions [b0, bend): only
+            // entries some pixel of the tile composited are staged, in order
+            const uint32_t bend = min(b0 + (uint32_t)S, stop);
+            const uint32_t w0 = b0 >> 5, nwd = ((bend - 1) >> 5) - w0 + 1;
+            if (threadIdx.x < nwd) {
+                const uint32_t wb = (w0 + threadIdx.x) << 5;
+                uint32_t m = a.comp_mask[w0 + threadIdx.x];
+                if (wb < b0) m &= ~0u << (b0 - wb);
+                if (bend - wb < 32u) m &= (1u << (bend - wb)) - 1u;
+                s_mw[threadIdx.x] = m;
+            }
+            __syncthreads();
+            int cnt = 0;
+            for (uint32_t q = 0; q < nwd; ++q) cnt += __popc(s_mw[q]);
             for (int i = threadIdx.x; i < S; i += NT) {
                 const uint32_t j = b0 + i;
-                if (j < stop) {
-                    uint32_t gid;
-                    stage_splat(a, ti.view, j, s_g[i], s_h[i], s_b[i], gid);
-                    s_gid[i] = gid;
-                    s_idx[i] = unsorted_index(a, ti.view, gid, ti.tx, ti.ty);
+                if (j < bend) {
+                    const uint32_t rel = j - (w0 << 5), wq = rel >> 5, bq = rel & 31u;
+                    if ((s_mw[wq] >> bq) & 1u) {
+                        int slot = __popc(s_mw[wq] & ((1u << bq) - 1u));
+                        for (uint32_t q = 0; q < wq; ++q) slot += __popc(s_mw[q]);
+                        uint32_t gid;
+                        stage_splat(a, ti.view, j, s_g[slot], s_h[slot], s_b[slot], gid);
+                        s_gid[slot] = gid;
+                        s_idx[slot] = unsorted_index(a, ti.view, gid, ti.tx, ti.ty);
+                        s_pos[slot] = j - start;
+                    }
                 }
             }
             __syncthreads();
-            const int cnt = (int)min((uint32_t)S, stop - b0);
             for (int sub = 0; sub < cnt; sub += SUB) {
                 const int scnt = min(SUB, cnt - sub);
                 uint64_t used = 0;
                 for (int kk = 0; kk < scnt; ++kk) {
                     const int k = sub + kk;
-                    const uint32_t pos = b0 - start + (uint32_t)k;
+                    const uint32_t pos = s_pos[k];
                     const float4 sg = s_g[k];
                     const float4 sh = s_h[k];
                     const float cb = s_b[k];
@@ -487,6 +543,7 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd(RasterArgs a)
                     }
                     const uint32_t idx = s_idx[sub + kk];
                     if ((int64_t)idx >= a.capacity) continue;   // only after a capacity overflow
+                    atomicOr(a.rec_mask + (idx >> 5), 1u << (idx & 31u));
                     float4* rec = a.grec + 3 * (int64_t)idx;
                     if (anyw) {
                         // conic and opacity of this Gaussian, unscaled
@@ -507,16 +564,7 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd(RasterArgs a)
                 __syncthreads();
             }
         }
-        // records exist for [start, stop); the first entry not traversed is
-        // identified by its (key, unsorted index) for the per-Gaussian gather
-        if (threadIdx.x == 0) {
-            uint4 st = make_uint4(stop, 0xFFFFFFFFu, 0xFFFFFFFFu, 0u);
-            if (stop < ti.range.y) {
-                st.y = a.keys[stop];
-                st.z = unsorted_index(a, ti.view, a.vals[stop], ti.tx, ti.ty);
-            }
-            a.tile_stop[gt] = st;
-        }
+        if (threadIdx.x == 0) a.tile_stop[gt] = stop;
         if (a.counter == nullptr) break;
     }
 }
@@ -599,9 +647,12 @@ int launch_raster_fwd(const gs_splats& sp, int64_t n, const gs_layout& L, const 
     a.out_T = out.T;
     a.out_last = out.last;
     a.tile_stats = out.tile_stats;
+    a.comp_mask = out.comp_mask;
     if (a.total_tiles == 0) return GS_OK;
+    int rc = launch_fill_u32(a.comp_mask, 0u, (b.capacity + 31) / 32, s);
+    if (rc != GS_OK) return rc;
     if (a.counter) {
-        int rc = launch_fill_u32(a.counter, 0u, 1, s);
+        rc = launch_fill_u32(a.counter, 0u, 1, s);
         if (rc != GS_OK) return rc;
     }
     return dispatch<true>(a, lds_batch, grid_for(a, sched), s);
@@ -620,13 +671,15 @@ int launch_raster_bwd(const gs_splats& sp, int64_t n, const gs_layout& L, const 
     a.loss = target ? loss : nullptr;
     a.inv_count = 1.0f / (3.0f * (float)L.pixel_base[L.n_views]);
     a.grec = reinterpret_cast<float4*>(grads.rec);
-    a.tile_stop = reinterpret_cast<uint4*>(grads.tile_stop);
-    a.keys = b.keys;
+    a.tile_stop = grads.tile_stop;
+    a.comp_mask = fwd.comp_mask;
+    a.rec_mask = grads.rec_mask;
     a.row_offsets = b.row_offsets;
     a.rows = reinterpret_cast<const uint4*>(b.rows);
     a.row_capacity = b.row_capacity;
-    int rc = GS_OK;
     if (a.total_tiles == 0) return GS_OK;
+    int rc = launch_fill_u32(a.rec_mask, 0u, (b.capacity + 31) / 32, s);
+    if (rc != GS_OK) return rc;
     if (a.counter) {
         rc = launch_fill_u32(a.counter, 0u, 1, s);
         if (rc != GS_OK) return rc;

@@ -87,7 +87,7 @@ class Frame:
         self.last = torch.zeros(P, **u32)
         self.tile_stats = torch.zeros(self.layout.total_tiles, 4, **u32) if tile_stats else None
         self.loss_tiles = torch.zeros(self.layout.total_tiles, **f32)
-        self.tile_stop = torch.zeros(self.layout.total_tiles, 4, **u32)   # (stop, key, index, 0)
+        self.tile_stop = torch.zeros(self.layout.total_tiles, **u32)
         self.sums = torch.zeros(9, V * n, **f32)      # per (view, Gaussian) screen-space gradient
         self.counter = torch.zeros(1, **u32)
         self.capacity = 0
@@ -106,6 +106,8 @@ class Frame:
         self.keys = torch.zeros(capacity, **u32)
         self.vals = torch.zeros(capacity, **u32)
         self.grec = torch.zeros(capacity, 12, dtype=torch.float32, device=self.device)
+        self.rec_mask = torch.zeros((capacity + 31) // 32, **u32)
+        self.comp_mask = torch.zeros((capacity + 31) // 32, **u32)
         ws = G.lib.gs_bin_sort_workspace_size(self.n, C.byref(self.layout), capacity)
         self.workspace = torch.zeros(max(int(ws), 1), dtype=torch.uint8, device=self.device)
         gws = G.lib.gs_grads2d_workspace_size(capacity)
@@ -118,9 +120,11 @@ class Frame:
         self.bins = G.GsBins(_i(self.offsets), _i(self.row_offsets), _i(self.rows), self.row_capacity,
                              _i(self.keys), _i(self.vals), _i(self.ranges), _i(self.status),
                              self.capacity)
-        self.grads2d = G.GsGrads2d(_i(self.grec), _i(self.tile_stop), _i(self.sums), _i(self.gather_ws))
+        self.grads2d = G.GsGrads2d(_i(self.grec), _i(self.rec_mask), _i(self.tile_stop), _i(self.sums),
+                                   _i(self.gather_ws))
         self.img = G.GsImage(_i(self.image), _i(self.T), _i(self.last),
-                             _i(self.tile_stats) if self.tile_stats is not None else None)
+                             _i(self.tile_stats) if self.tile_stats is not None else None,
+                             _i(self.comp_mask))
 
     def intersections(self) -> int:
         """K (synchronises)."""

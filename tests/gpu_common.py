@@ -56,8 +56,9 @@ def run_gpu_step(scene, views, tile, target=None, lds_batch=64, lr=1e-3, adam=Tr
     out["keys"] = u32(frame.keys)[:K]
     out["vals"] = u32(frame.vals)[:K]
     out["ranges"] = u32(frame.ranges)
-    out["tile_stop"] = u32(frame.tile_stop)[:, 0].copy()
-    out["stop_entry"] = u32(frame.tile_stop)
+    out["tile_stop"] = u32(frame.tile_stop)
+    out["comp_mask"] = u32(frame.comp_mask)
+    out["rec_mask"] = u32(frame.rec_mask)
     out["image"] = frame.image.cpu().numpy()
     out["T"] = frame.T.cpu().numpy()
     out["last"] = u32(frame.last)

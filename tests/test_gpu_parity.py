@@ -114,24 +114,30 @@ def test_training_step(name, ppl):
     # per-Gaussian 2D gradients (sums of the intersection records)
     tb = np.cumsum([0] + oracle.n_tiles(views, tile))
     g2 = per_gaussian_2d(g["grec"], ref.bins.vals, g["vals"], g["ranges"], g["tile_stop"], tb, n)
-    # traversal stops are within the ranges; the stop entry names the first
-    # entry not traversed by its key and unsorted index
-    stop, st = g["tile_stop"], g["stop_entry"]
+    # traversal stops are within the ranges
+    stop = g["tile_stop"]
     assert np.all(stop >= g["ranges"][:, 0]) and np.all(stop <= g["ranges"][:, 1])
-    inner = stop < g["ranges"][:, 1]
-    assert inner.any() and not inner.all()
-    np.testing.assert_array_equal(st[inner, 1], g["keys"][stop[inner]])
-    np.testing.assert_array_equal(st[inner, 2], ref.bins.vals[stop[inner]])
-    assert np.all(st[~inner, 1:3] == 0xFFFFFFFF)
-    # records of traversed entries match the oracle's partials at the same unsorted index
+    assert (stop < g["ranges"][:, 1]).any()
+    # records: written (flagged) exactly for the traversed entries some pixel
+    # composited; they match the oracle's partials at the same unsorted index,
+    # and the traversed entries without a record have no oracle gradient
+    bit = lambda m, i: (m[i >> 5] >> (i & 31)) & 1
     pos = [np.arange(int(g["ranges"][t, 0]), int(stop[t])) for t in range(len(stop))]
     pview = np.concatenate([np.full(len(p_), np.searchsorted(tb, t, side="right") - 1) for t, p_ in
                             enumerate(pos)]).astype(np.int64)
     pos = np.concatenate(pos).astype(np.int64)
-    trav = ref.bins.vals[pos]
+    trav = ref.bins.vals[pos].astype(np.int64)
+    comp = bit(g["comp_mask"], pos).astype(bool)
+    flag = bit(g["rec_mask"], trav).astype(bool)
+    np.testing.assert_array_equal(comp, flag)
+    assert flag.any() and not flag.all()
+    exr = ex[pview, g["vals"][pos]]
     okr = grad_close(g["grec"][trav, :9], ref.partials[trav], GRAD_RTOL).all(axis=1)
-    badr = ~okr & ~ex[pview, g["vals"][pos]]
+    badr = flag & ~okr & ~exr
     assert not badr.any(), (pos[badr][:5], trav[badr][:5])
+    assert not (~flag & (np.abs(ref.partials[trav]).max(axis=1) > 0) & ~exr).any()
+    untrav = np.setdiff1d(np.arange(g["K"]), trav)
+    assert not bit(g["rec_mask"], untrav).any()
     ok2 = grad_close(g2.reshape(-1, 9), ref.grads2d.reshape(-1, 9), GRAD_RTOL).reshape(V, n, 9)
     bad = ~ok2.all(axis=2) & ~ex
     assert not bad.any(), np.argwhere(bad)[:5]
@@ -164,7 +170,8 @@ def test_deterministic_bitwise():
     target = oracle.render(target_scene, views, tile)
     a = run_gpu_step(scene, views, tile, target=target)
     b = run_gpu_step(scene, views, tile, target=target)
-    for k in ("image", "grec", "stop_entry", "sums", "grads", "params", "keys", "vals"):
+    for k in ("image", "grec", "rec_mask", "comp_mask", "tile_stop", "sums", "grads", "params", "keys",
+              "vals"):
         np.testing.assert_array_equal(a[k], b[k])
 
 
@@ -177,7 +184,8 @@ def test_persistent_and_permuted_schedules_change_no_bit():
     perm = np.random.default_rng(3).permutation(nt).astype(np.int32)
     for kw in (dict(persistent=True), dict(sched_order=perm), dict(sched_order=perm, persistent=True)):
         other = run_gpu_step(scene, views, tile, target=target, **kw)
-        for k in ("image", "T", "last", "grec", "stop_entry", "sums", "grads", "params"):
+        for k in ("image", "T", "last", "grec", "rec_mask", "comp_mask", "tile_stop", "sums", "grads",
+                  "params"):
             np.testing.assert_array_equal(base[k], other[k], err_msg=str(kw))
 
 

@@ -46,21 +46,28 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def source_sha(rel: str) -> str:
+def source_sha() -> str:
+    """Hash of every HIP source and the C header (any change to the kernels
+    invalidates counters taken before it)."""
+    import glob
     import hashlib
-    with open(os.path.join(ROOT, rel), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2605_00219_amd", "csrc", "*")))
+    for p in files + [os.path.join(ROOT, "include", "gs.h")]:
+        with open(p, "rb") as f:
+            h.update(os.path.basename(p).encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
 
 
-def recorded_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` measured by rocprofv3 counters
-    (profiles/hbm_traffic.json), or None if absent or if the kernel's source
-    has changed since the counters were taken."""
+def recorded_traffic(stage: str):
+    """HBM bytes per launch of a stage measured by rocprofv3 counters
+    (profiles/hbm_traffic.json), or None if absent or if the kernel sources
+    have changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     try:
         with open(path) as f:
-            rec = json.load(f).get(kernel)
-        if rec and rec.get("source_sha") == source_sha(rec["source"]):
+            rec = json.load(f).get(stage)
+        if rec and rec.get("source_sha") == source_sha():
             return rec
     except (OSError, ValueError, KeyError):
         pass
@@ -233,8 +240,10 @@ def main():
                         "pairs_evaluated_bwd": c2["eval_bwd"] if c2 else None,
                         "speedup_vs_rect": r2["ips"] / ips}
 
-    # roofline of the dominant stage (every stage's figure is reported)
-    dom = max(stage_ms, key=stage_ms.get)
+    # roofline of the dominant kernel: the single-kernel stage with the largest
+    # time (binning and the projection backward are several kernels each);
+    # every stage's figure is reported under stage_roofline
+    dom = max(("project", "rasterize_fwd", "rasterize_bwd"), key=stage_ms.get)
     roof = None
     extra = {}
     P_px = H * W

@@ -372,19 +372,25 @@ GS_DEV uint64_t lanemask_lt() {
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-// Stable scatter of one radix pass.  The chunk's keys are first ranked and
-// placed in LDS in digit order (chunk-local counting sort, ranks from
-// wavefront match masks built with 8 ballots), then written out from LDS so
-// that consecutive lanes write consecutive addresses of each digit's run.
+// Stable scatter of one radix pass.  Wavefront w of the workgroup owns the
+// contiguous keys [w * 1024, (w + 1) * 1024) of the chunk and ranks them item
+// by item: peers with the same digit are found with 8 ballots, and a running
+// per-(wavefront, digit) count in LDS gives each key its rank among the
+// wavefront's keys of that digit (one wavefront updates only its own counts,
+// so no workgroup barrier is needed while ranking).  One scan over
+// (digit, wavefront) then turns the counts into chunk-local positions, the
+// keys are placed in LDS in digit order, and they are written out so that
+// consecutive lanes write consecutive addresses of each digit's run.  The
+// order of equal digits is (wavefront, item, lane) = input order: stable.
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
     const uint32_t* __restrict__ table, int n_views, int shift,
     const uint32_t* __restrict__ scanned) {
     constexpr int NW = kSortThreads / kWave;
+    constexpr int PER_WAVE = kChunk / NW;
     __shared__ uint32_t gbase[kDigits];   // global destination of the chunk's first key of digit d
     __shared__ uint32_t lstart[kDigits];  // chunk-local start of digit d
-    __shared__ uint32_t lrun[kDigits];    // keys of digit d placed so far
     __shared__ uint32_t wcnt[NW][kDigits];
     __shared__ uint32_t s_k[kChunk];
     __shared__ uint32_t s_v[kChunk];
@@ -393,25 +399,18 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     int v;
     uint32_t c;
     if (!chunk_of(table, n_views, b, &v, &c)) return;
-    const int w = threadIdx.x / kWave;
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const uint32_t nc = table[4 * v + 3], cb = table[4 * v + 2];
-    const int64_t hi = (int64_t)cb * kDigits + (int64_t)threadIdx.x * nc + c;
-    const uint32_t g0 = scanned[hi];
-    const uint32_t cnt = scanned[hi + 1] - g0;   // exclusive scan: next minus this
-    gbase[threadIdx.x] = g0;
-    {
-        uint64_t tot;
-        const uint64_t inc = block_scan_u64(cnt, s_scan, &tot);
-        lstart[threadIdx.x] = (uint32_t)(inc - cnt);
-    }
-    lrun[threadIdx.x] = 0u;
+    gbase[threadIdx.x] = scanned[(int64_t)cb * kDigits + (int64_t)threadIdx.x * nc + c];
+#pragma unroll
+    for (int j = 0; j < NW; ++j) wcnt[j][threadIdx.x] = 0u;
     const uint32_t seg_e = table[4 * v + 1];
     const uint32_t start = table[4 * v] + c * kChunk;
     const uint32_t n_here = min((uint32_t)kChunk, seg_e - start);
-    uint32_t k[kSortItems], val[kSortItems];
+    uint32_t k[kSortItems], val[kSortItems], rank[kSortItems];
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
-        const uint32_t idx = start + i * kSortThreads + threadIdx.x;
+        const uint32_t idx = start + w * PER_WAVE + i * kWave + lane;
         k[i] = idx < seg_e ? keys_in[idx] : 0u;
         val[i] = idx < seg_e ? vals_in[idx] : 0u;
     }
@@ -419,7 +418,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
-        const uint32_t idx = start + i * kSortThreads + threadIdx.x;
+        const uint32_t idx = start + w * PER_WAVE + i * kWave + lane;
         const bool valid = idx < seg_e;
         const uint32_t d = (k[i] >> shift) & 0xFF;
         uint64_t peers = __ballot(valid);
@@ -429,27 +428,42 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
             const uint64_t m = __ballot(set);
             peers &= set ? m : ~m;
         }
-        const uint32_t rank = (uint32_t)__popcll(peers & lt);
-        const bool leader = valid && (peers & lt) == 0ull;
-        for (int j = threadIdx.x; j < NW * kDigits; j += kSortThreads) (&wcnt[0][0])[j] = 0u;
-        __syncthreads();
-        if (leader) wcnt[w][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        if (valid) {
-            uint32_t pos = lstart[d] + lrun[d] + rank;
-            for (int j = 0; j < w; ++j) pos += wcnt[j][d];
+        const uint64_t before = peers & lt;
+        const uint32_t base = valid ? wcnt[w][d] : 0u;
+        rank[i] = base + (uint32_t)__popcll(before);
+        // the first lane of each digit group advances the wavefront's count
+        // (after every lane of the group has read it: same wavefront, in order)
+        if (valid && before == 0ull) wcnt[w][d] = base + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    {
+        // digit-major exclusive scan over (digit, wavefront)
+        const uint32_t d = threadIdx.x;
+        uint32_t t = 0;
+#pragma unroll
+        for (int j = 0; j < NW; ++j) t += wcnt[j][d];
+        uint64_t tot;
+        const uint64_t inc = block_scan_u64(t, s_scan, &tot);
+        uint32_t run = (uint32_t)(inc - t);
+        lstart[d] = run;
+#pragma unroll
+        for (int j = 0; j < NW; ++j) {
+            const uint32_t x = wcnt[j][d];
+            wcnt[j][d] = run;
+            run += x;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        const uint32_t idx = start + w * PER_WAVE + i * kWave + lane;
+        if (idx < seg_e) {
+            const uint32_t pos = wcnt[w][(k[i] >> shift) & 0xFF] + rank[i];
             s_k[pos] = k[i];
             s_v[pos] = val[i];
         }
-        __syncthreads();
-        {
-            uint32_t add = 0;
-#pragma unroll
-            for (int j = 0; j < NW; ++j) add += wcnt[j][threadIdx.x];
-            lrun[threadIdx.x] += add;
-        }
-        __syncthreads();
     }
+    __syncthreads();
     for (uint32_t j = threadIdx.x; j < n_here; j += kSortThreads) {
         const uint32_t key = s_k[j];
         const uint32_t d = (key >> shift) & 0xFF;

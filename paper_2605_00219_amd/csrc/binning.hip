@@ -169,10 +169,53 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* in, 
     if (blockIdx.x == 0 && threadIdx.x == 0) out[len] = (uint32_t)sums[nb];
 }
 
+// Second pass of a two-launch scan (for at most kScanInlineBlocks blocks):
+// each block adds up the block sums before it itself, instead of a separate
+// scan of the block sums; the last block writes the total.
+constexpr int64_t kScanInlineBlocks = 2048;
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_down_inline(const uint32_t* in, int64_t len,
+                                                                   const uint64_t* __restrict__ sums,
+                                                                   int64_t nb, uint32_t* out,
+                                                                   uint32_t* __restrict__ status) {
+    __shared__ uint64_t lds[kScanThreads / kWave];
+    uint64_t carry = 0;
+    for (int64_t i = threadIdx.x; i < (int64_t)blockIdx.x; i += kScanThreads) carry += sums[i];
+    carry = block_reduce_u64(carry, lds);
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock;
+    uint32_t v[kScanItems];
+    uint64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t idx = base + (int64_t)threadIdx.x * kScanItems + i;
+        v[i] = idx < len ? in[idx] : 0u;
+        s += v[i];
+    }
+    uint64_t tot;
+    const uint64_t inc = block_scan_u64(s, lds, &tot);
+    uint64_t run = carry + inc - s;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t idx = base + (int64_t)threadIdx.x * kScanItems + i;
+        if (idx < len) out[idx] = (uint32_t)run;
+        run += v[i];
+    }
+    if (blockIdx.x == nb - 1 && threadIdx.x == 0) {
+        const uint64_t total = carry + tot;
+        out[len] = (uint32_t)total;
+        if (status && total > 0xFFFFFFFFull) atomicOr(status, (uint32_t)GS_STATUS_OVERFLOW);
+    }
+}
+
 static int scan_exclusive(const uint32_t* in, int64_t len, uint32_t* out, uint64_t* sums,
                           uint32_t* status, hipStream_t s) {
     const int64_t nb = std::max<int64_t>((len + kScanBlock - 1) / kScanBlock, 1);
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, len, sums);
+    if (nb <= kScanInlineBlocks) {
+        hipLaunchKernelGGL(k_scan_down_inline, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, len, sums,
+                           nb, out, status);
+        return check_launch("scan");
+    }
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, sums, nb, status);
     hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, len, sums, nb,
                        out);
@@ -335,12 +378,21 @@ GS_DEV bool chunk_of(const uint32_t* table, int n_views, uint32_t b, int* view, 
     return true;
 }
 
+// Workgroups are dealt to the 8 XCDs round robin; this maps the workgroups
+// of one XCD to consecutive chunks, so the histogram words of neighbouring
+// chunks (adjacent in memory) are written through the same L2.
+GS_DEV uint32_t xcd_major_block(uint32_t b, uint32_t grid) {
+    constexpr uint32_t kXcd = 8;
+    const uint32_t x = b % kXcd, per = grid / kXcd, rem = grid % kXcd;
+    return x * per + min(x, rem) + b / kXcd;
+}
+
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __restrict__ keys,
                                                              const uint32_t* __restrict__ table,
                                                              int n_views, int shift,
                                                              uint32_t* __restrict__ hist) {
     __shared__ uint32_t cnt[kSortThreads / kWave][kDigits];
-    const uint32_t b = blockIdx.x;
+    const uint32_t b = xcd_major_block(blockIdx.x, gridDim.x);
     int v;
     uint32_t c;
     if (!chunk_of(table, n_views, b, &v, &c)) {

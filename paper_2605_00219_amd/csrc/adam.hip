@@ -79,103 +79,123 @@ __global__ __launch_bounds__(256) void k_gather_index(GatherArgs a) {
         a.block_first[blk] = (uint32_t)r;
 }
 
-// Gather: workgroup b owns the intersection indices [b E, (b+1) E), one per
-// thread.  The row slots covering them (from the slot holding this block's
-// first index to the one holding the next block's) are staged in LDS.  Each
-// index finds its row by binary search in LDS, hence its (view, Gaussian),
-// and parks its record in LDS if the backward flagged it (else zeros), with
-// coalesced record loads.  (If more slots than fit in LDS cover one block --
-// only possible with many rows whose span is empty -- the search runs over
-// the slots in global memory instead.)  Then the first index of every run of
-// equal owner adds up its run in index order: a run that is the whole of its
-// Gaussian's range is written to sums directly; the block's first and last
-// runs, if their Gaussian extends past the block, go to per-block partials
-// that the chain-rule kernel adds in block order.  No workgroup handles more
-// than E indices, however long one Gaussian's list is.
+// Gather, in units of E = 256 intersection indices.  sums and the per-unit
+// partials are zeroed beforehand, so a unit without any flagged record needs
+// no work: each workgroup reads the record mask of 4 consecutive units (one
+// mask word per thread) and processes only the units with a flag.
+// Processing a unit, one index per thread: the row slots covering it (from
+// the slot holding its first index to the one holding the next unit's) are
+// staged in LDS; each index finds its row by binary search in LDS, hence its
+// (view, Gaussian), and parks its record in LDS if the backward flagged it
+// (else zeros), with coalesced record loads.  (If more slots than fit in LDS
+// cover one unit -- only possible with many rows whose span is empty -- the
+// search runs over the slots in global memory instead.)  Then the first index
+// of every run of equal owner adds up its run in index order: a run that is
+// the whole of its Gaussian's range is written to sums directly; the unit's
+// first and last runs, if their Gaussian extends past the unit, go to
+// per-unit partials that the chain-rule kernel adds in unit order.  No unit
+// has more than E indices, however long one Gaussian's list is.
+constexpr int kGatherUnits = 4;    // units per workgroup
+
 __global__ __launch_bounds__(kGatherThreads) void k_gather2d(GatherArgs a) {
     __shared__ float4 s_rec[kGatherE][3];
     __shared__ uint32_t s_own[kGatherE];
     __shared__ uint32_t s_first[kGatherRows];
     __shared__ uint32_t s_o[kGatherRows];
+    __shared__ uint32_t s_unit[kGatherUnits];
     const int64_t vn = (int64_t)a.n_views * a.n;
     const uint64_t kc = entries_valid(a, vn);
-    const uint64_t e0 = (uint64_t)blockIdx.x * kGatherE;
-    if (e0 >= kc) return;
-    const uint64_t e1 = min(e0 + (uint64_t)kGatherE, kc);
+    const uint64_t g0 = (uint64_t)blockIdx.x * (kGatherUnits * kGatherE);
+    if (g0 >= kc) return;
     const uint32_t nblk = (uint32_t)((kc + kGatherE - 1) / kGatherE);
-    const uint32_t ra = a.block_first[blockIdx.x];
-    const uint32_t rz = blockIdx.x + 1 < nblk ? a.block_first[blockIdx.x + 1]
-                                              : (uint32_t)(rows_valid(a, vn) - 1);
-    const uint32_t nr = rz - ra + 1;
-    const bool staged = nr <= (uint32_t)kGatherRows;
     const int t = threadIdx.x;
-    if (staged) {
-        for (uint32_t k = t; k < nr; k += kGatherThreads) {
-            const uint4 row = a.rows[ra + k];
-            s_first[k] = row.x;
-            s_o[k] = row.y;
-        }
+    // which of the workgroup's units hold a flagged record
+    if (t < kGatherUnits) s_unit[t] = 0u;
+    __syncthreads();
+    if (t < kGatherUnits * kGatherE / 32) {
+        const uint64_t word = g0 / 32 + (uint64_t)t;
+        if (word * 32 < kc && a.rec_mask[word] != 0u) s_unit[t * 32 / kGatherE] = 1u;
     }
     __syncthreads();
-    const int cnt = (int)(e1 - e0);
-    {
+    for (int u = 0; u < kGatherUnits; ++u) {
+        if (s_unit[u] == 0u) continue;       // workgroup-uniform
+        const uint32_t unit = (uint32_t)(g0 / kGatherE) + (uint32_t)u;
+        const uint64_t e0 = (uint64_t)unit * kGatherE;
+        if (e0 >= kc) break;
+        const uint64_t e1 = min(e0 + (uint64_t)kGatherE, kc);
+        const uint32_t ra = a.block_first[unit];
+        const uint32_t rz = unit + 1 < nblk ? a.block_first[unit + 1] : (uint32_t)(rows_valid(a, vn) - 1);
+        const uint32_t nr = rz - ra + 1;
+        const bool staged = nr <= (uint32_t)kGatherRows;
+        __syncthreads();                     // LDS of the previous unit is free
+        if (staged) {
+            for (uint32_t k = t; k < nr; k += kGatherThreads) {
+                const uint4 row = a.rows[ra + k];
+                s_first[k] = row.x;
+                s_o[k] = row.y;
+            }
+        }
+        __syncthreads();
+        const int cnt = (int)(e1 - e0);
+        {
+            const int j = t;
+            float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
+            uint32_t own = 0xFFFFFFFFu;
+            if (j < cnt) {
+                const uint32_t i = (uint32_t)(e0 + (uint64_t)j);
+                const uint32_t flag = (a.rec_mask[i >> 5] >> (i & 31u)) & 1u;
+                if (staged) {
+                    uint32_t lo = 0, hi = nr - 1;
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi + 1) >> 1;
+                        if (s_first[mid] <= i) lo = mid; else hi = mid - 1;
+                    }
+                    own = s_o[lo];
+                } else {
+                    uint32_t lo = ra, hi = rz;
+                    while (lo < hi) {
+                        const uint32_t mid = lo + ((hi - lo + 1) >> 1);
+                        if (a.rows[mid].x <= i) lo = mid; else hi = mid - 1;
+                    }
+                    own = a.rows[lo].y;
+                }
+                if (flag) {
+                    const float4* g = a.grec + 3 * (int64_t)i;
+                    r0 = g[0]; r1 = g[1]; r2 = g[2];
+                    r2.y = 0.f; r2.z = 0.f; r2.w = 0.f;
+                }
+            }
+            s_rec[j][0] = r0; s_rec[j][1] = r1; s_rec[j][2] = r2;
+            s_own[j] = own;
+        }
+        __syncthreads();
         const int j = t;
-        float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
-        uint32_t own = 0xFFFFFFFFu;
-        if (j < cnt) {
-            const uint32_t i = (uint32_t)(e0 + (uint64_t)j);
-            const uint32_t flag = (a.rec_mask[i >> 5] >> (i & 31u)) & 1u;
-            if (staged) {
-                uint32_t lo = 0, hi = nr - 1;
-                while (lo < hi) {
-                    const uint32_t mid = (lo + hi + 1) >> 1;
-                    if (s_first[mid] <= i) lo = mid; else hi = mid - 1;
-                }
-                own = s_o[lo];
-            } else {
-                uint32_t lo = ra, hi = rz;
-                while (lo < hi) {
-                    const uint32_t mid = lo + ((hi - lo + 1) >> 1);
-                    if (a.rows[mid].x <= i) lo = mid; else hi = mid - 1;
-                }
-                own = a.rows[lo].y;
-            }
-            if (flag) {
-                const float4* g = a.grec + 3 * (int64_t)i;
-                r0 = g[0]; r1 = g[1]; r2 = g[2];
-                r2.y = 0.f; r2.z = 0.f; r2.w = 0.f;
-            }
-        }
-        s_rec[j][0] = r0; s_rec[j][1] = r1; s_rec[j][2] = r2;
-        s_own[j] = own;
-    }
-    __syncthreads();
-    const int j = t;
-    if (j < cnt && (j == 0 || s_own[j - 1] != s_own[j])) {   // the first index of a run
-        const uint32_t own = s_own[j];
-        const uint64_t gb = a.offsets[own];
-        const uint64_t ge = min((uint64_t)a.offsets[own + 1], (uint64_t)a.capacity);
-        const bool before = gb < e0, after = ge > e1;
-        // the run is the Gaussian's indices inside this block: a fixed trip count
-        const int jend = (int)(min(ge, e1) - e0);
-        float4 d0 = make_float4(0.f, 0.f, 0.f, 0.f), d1 = d0;
-        float d8 = 0.f;
+        if (j < cnt && (j == 0 || s_own[j - 1] != s_own[j])) {   // the first index of a run
+            const uint32_t own = s_own[j];
+            const uint64_t gb = a.offsets[own];
+            const uint64_t ge = min((uint64_t)a.offsets[own + 1], (uint64_t)a.capacity);
+            const bool before = gb < e0, after = ge > e1;
+            // the run is the Gaussian's indices inside this unit: a fixed trip count
+            const int jend = (int)(min(ge, e1) - e0);
+            float4 d0 = make_float4(0.f, 0.f, 0.f, 0.f), d1 = d0;
+            float d8 = 0.f;
 #pragma unroll 4
-        for (int jj = j; jj < jend; ++jj) {
-            const float4 q0 = s_rec[jj][0], q1 = s_rec[jj][1];
-            const float q8 = s_rec[jj][2].x;
-            d0.x += q0.x; d0.y += q0.y; d0.z += q0.z; d0.w += q0.w;
-            d1.x += q1.x; d1.y += q1.y; d1.z += q1.z; d1.w += q1.w;
-            d8 += q8;
-        }
-        const float d[9] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w, d8};
-        float* dst;
-        int64_t stride;
-        if (!before && !after) { dst = a.sums + own; stride = vn; }
-        else if (before) { dst = a.part_first + 9 * (int64_t)blockIdx.x; stride = 1; }
-        else { dst = a.part_last + 9 * (int64_t)blockIdx.x; stride = 1; }
+            for (int jj = j; jj < jend; ++jj) {
+                const float4 q0 = s_rec[jj][0], q1 = s_rec[jj][1];
+                const float q8 = s_rec[jj][2].x;
+                d0.x += q0.x; d0.y += q0.y; d0.z += q0.z; d0.w += q0.w;
+                d1.x += q1.x; d1.y += q1.y; d1.z += q1.z; d1.w += q1.w;
+                d8 += q8;
+            }
+            const float d[9] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w, d8};
+            float* dst;
+            int64_t stride;
+            if (!before && !after) { dst = a.sums + own; stride = vn; }
+            else if (before) { dst = a.part_first + 9 * (int64_t)unit; stride = 1; }
+            else { dst = a.part_last + 9 * (int64_t)unit; stride = 1; }
 #pragma unroll
-        for (int c = 0; c < 9; ++c) dst[c * stride] = d[c];
+            for (int c = 0; c < 9; ++c) dst[c * stride] = d[c];
+        }
     }
 }
 
@@ -513,8 +533,19 @@ int launch_project_bwd_adam(float* params, int64_t n, const gs_view* views, cons
         rc = check_launch("gather_index");
         if (rc != GS_OK) return rc;
     }
+    // sums of Gaussians without any flagged record, and partials of units
+    // without one, stay zero
+    rc = launch_fill_u32(reinterpret_cast<uint32_t*>(ga.sums), 0u, 9 * vn, s);
+    if (rc != GS_OK) return rc;
+    {
+        const int64_t nb = (b.capacity + kGatherE - 1) / kGatherE + 1;
+        if ((rc = launch_fill_u32(reinterpret_cast<uint32_t*>(ga.part_first), 0u, 9 * nb, s)) != GS_OK ||
+            (rc = launch_fill_u32(reinterpret_cast<uint32_t*>(ga.part_last), 0u, 9 * nb, s)) != GS_OK)
+            return rc;
+    }
     if (b.capacity > 0 && b.row_capacity > 0) {
-        hipLaunchKernelGGL(k_gather2d, dim3((unsigned)((b.capacity + kGatherE - 1) / kGatherE)),
+        const int64_t per = (int64_t)kGatherUnits * kGatherE;
+        hipLaunchKernelGGL(k_gather2d, dim3((unsigned)((b.capacity + per - 1) / per)),
                            dim3(kGatherThreads), 0, s, ga);
         rc = check_launch("gather2d");
         if (rc != GS_OK) return rc;

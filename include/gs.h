@@ -66,6 +66,8 @@ enum {
 #define GS_STATUS_CAPACITY 1u  /* intersections exceeded gs_bins.capacity */
 #define GS_STATUS_OVERFLOW 2u  /* intersection count exceeded 2^32 - 1 */
 #define GS_STATUS_ROWS 4u      /* tile-row slots exceeded gs_bins.row_capacity */
+#define GS_STATUS_SORT 8u      /* a sort pass gave up waiting on an earlier chunk's counts
+                                  (never expected; the sorted order is then invalid) */
 
 /* tile-set rules (gs_layout.cull) */
 #define GS_CULL_RECT 0     /* tiles meeting the 3-sigma box [mean +- r] */

@@ -20,7 +20,7 @@ MLP_GROUPS = 64
 MLP_SCRATCH = (MLP_GROUPS + 1) * (MLP_PARAMS + 1)
 
 GS_OK, GS_ERR_INVALID_ARG, GS_ERR_HIP, GS_ERR_WORKSPACE, GS_ERR_CAPACITY = 0, -1, -2, -3, -4
-STATUS_CAPACITY, STATUS_OVERFLOW, STATUS_ROWS = 1, 2, 4
+STATUS_CAPACITY, STATUS_OVERFLOW, STATUS_ROWS, STATUS_SORT = 1, 2, 4, 8
 CULL_RECT, CULL_ELLIPSE = 0, 1
 
 

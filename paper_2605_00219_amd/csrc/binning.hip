@@ -4,11 +4,13 @@
 // depth part of each key comes precomputed from the projection record.
 //
 // The sort runs over all views at once: each view's segment is cut into
-// chunks of kChunk keys that never straddle two views, and the per-chunk digit
-// histograms are laid out [view][digit][chunk] so one exclusive scan of the
-// whole histogram array yields every scatter destination directly.  Grids are
-// sized from the capacity (an upper bound known on the host); the actual
-// counts are read on the device, so no step needs a host synchronisation.
+// chunks of kChunk keys that never straddle two views.  One histogram pass
+// gives every view's digit totals for all four passes; each pass is then a
+// single kernel in which a chunk's destinations are the digit's start plus
+// the counts of the view's earlier chunks, found by a decoupled look-back.
+// Grids are sized from the capacity (an upper bound known on the host); the
+// actual counts are read on the device, so no step needs a host
+// synchronisation.
 #include "cull_math.h"
 #include "gs_internal.h"
 
@@ -21,23 +23,38 @@ constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;
 constexpr int kChunk = kSortThreads * kSortItems;      // 4096 keys per radix chunk
 constexpr int kDigits = 256;
+constexpr int kPasses = 4;
+constexpr int kHistBlocks = 512;                        // workgroups of the histogram pass
+constexpr int kGroup = 16;                              // chunks per look-back group
+static_assert(kSortThreads == kDigits, "one thread per digit in the scan and look-back");
 
 // ---------------------------------------------------------------------------
 // workspace
 // ---------------------------------------------------------------------------
 
+// Sizes of the sort's device words for n_views segments and max_chunks chunks.
+static inline int64_t max_groups_for(int64_t max_chunks, int n_views) {
+    return max_chunks / kGroup + n_views + 1;
+}
+
+static inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+static size_t sort_words_bytes(int n_views, int64_t mc) {
+    const int64_t mg = max_groups_for(mc, n_views);
+    const size_t nd = (size_t)n_views * kPasses * kDigits;
+    return align_up(4 * nd) * 2 + align_up(8 * (size_t)(kPasses * mc * kDigits)) * 2 +
+           align_up(8 * (size_t)(kPasses * mg * kDigits)) + align_up(4 * (size_t)(kPasses * mg));
+}
+
 struct Workspace {
     uint32_t* row_count;   // tile rows per (view, Gaussian)
     uint32_t* keys_tmp;
     uint32_t* vals_tmp;
-    uint32_t* hist;        // kDigits * max_chunks
     uint64_t* block_sums;  // scan partials
     uint32_t* table;       // 4 * (GS_MAX_VIEWS + 1)
+    uint32_t* sort_words;  // the sort's totals and look-back words (carve_sort)
     int64_t max_chunks;
-    int64_t max_scan_blocks;
 };
-
-static inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 static int64_t max_chunks_for(int64_t capacity, int n_views) {
     return (capacity + kChunk - 1) / kChunk + n_views;
@@ -45,8 +62,7 @@ static int64_t max_chunks_for(int64_t capacity, int n_views) {
 
 static size_t carve(int64_t n, const gs_layout& L, int64_t capacity, char* base, Workspace* w) {
     const int64_t mc = max_chunks_for(capacity, L.n_views);
-    const int64_t scan_elems = std::max<int64_t>((int64_t)L.n_views * n, kDigits * mc);
-    const int64_t sb = (scan_elems + kScanBlock - 1) / kScanBlock;
+    const int64_t sb = ((int64_t)L.n_views * n + kScanBlock - 1) / kScanBlock + 1;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         char* p = base ? base + off : nullptr;
@@ -57,11 +73,10 @@ static size_t carve(int64_t n, const gs_layout& L, int64_t capacity, char* base,
     tmp.row_count = (uint32_t*)take(sizeof(uint32_t) * (size_t)std::max<int64_t>((int64_t)L.n_views * n, 1));
     tmp.keys_tmp = (uint32_t*)take(sizeof(uint32_t) * (size_t)std::max<int64_t>(capacity, 1));
     tmp.vals_tmp = (uint32_t*)take(sizeof(uint32_t) * (size_t)std::max<int64_t>(capacity, 1));
-    tmp.hist = (uint32_t*)take(sizeof(uint32_t) * (size_t)(kDigits * mc + 1));  // +1: scan total
     tmp.block_sums = (uint64_t*)take(sizeof(uint64_t) * (size_t)(sb + 1));
     tmp.table = (uint32_t*)take(sizeof(uint32_t) * 4 * (GS_MAX_VIEWS + 1));
+    tmp.sort_words = (uint32_t*)take(sort_words_bytes(L.n_views, mc));
     tmp.max_chunks = mc;
-    tmp.max_scan_blocks = sb;
     if (w) *w = tmp;
     return off;
 }
@@ -226,9 +241,11 @@ static int scan_exclusive(const uint32_t* in, int64_t len, uint32_t* out, uint64
 // per-view segment table
 // ---------------------------------------------------------------------------
 
+// Also clears the sort's digit totals.
 __global__ void k_view_table(const uint32_t* __restrict__ offsets, int64_t n, int n_views,
                              int64_t capacity, uint32_t* __restrict__ table,
-                             uint32_t* __restrict__ status) {
+                             uint32_t* __restrict__ status, uint32_t* __restrict__ dcount) {
+    for (int i = threadIdx.x; i < n_views * kPasses * kDigits; i += blockDim.x) dcount[i] = 0u;
     if (threadIdx.x != 0) return;
     uint32_t chunks = 0;
     const uint64_t cap = (uint64_t)capacity;
@@ -364,7 +381,9 @@ __global__ __launch_bounds__(kEmitG) void k_emit(const float4* __restrict__ rec,
 }
 
 // ---------------------------------------------------------------------------
-// radix sort passes
+// radix sort: one histogram pass for all four digits, then one single-pass
+// scatter per digit whose global destinations come from a decoupled look-back
+// over the preceding chunks of the same view
 // ---------------------------------------------------------------------------
 
 // Chunk b -> (view, chunk within view).  Returns false for unused chunks.
@@ -378,45 +397,153 @@ GS_DEV bool chunk_of(const uint32_t* table, int n_views, uint32_t b, int* view, 
     return true;
 }
 
-// Workgroups are dealt to the 8 XCDs round robin; this maps the workgroups
-// of one XCD to consecutive chunks, so the histogram words of neighbouring
-// chunks (adjacent in memory) are written through the same L2.
-GS_DEV uint32_t xcd_major_block(uint32_t b, uint32_t grid) {
-    constexpr uint32_t kXcd = 8;
-    const uint32_t x = b % kXcd, per = grid / kXcd, rem = grid % kXcd;
-    return x * per + min(x, rem) + b / kXcd;
+// Look-back words: flag in the high half, a count in the low half.
+constexpr uint64_t kLbAggregate = 1ull << 32;  // count of this chunk (or group) alone
+constexpr uint64_t kLbPrefix = 2ull << 32;     // count of this chunk and all before it in the view
+constexpr uint32_t kLbSpinLimit = 1u << 20;
+
+struct SortWs {
+    uint32_t* dcount;   // [n_views][kPasses][kDigits] digit totals (cleared by the table kernel)
+    uint32_t* dstart;   // [n_views][kPasses][kDigits] first global position of each digit
+    uint64_t* agg;      // [kPasses][max_chunks][kDigits] kLbAggregate | chunk count
+    uint64_t* pre;      // [kPasses][max_chunks][kDigits] kLbPrefix | inclusive prefix
+    uint64_t* gagg;     // [kPasses][max_groups][kDigits] kLbAggregate | group count
+    uint32_t* gdone;    // [kPasses][max_groups] chunks of the group that have published
+    int64_t max_chunks;
+    int64_t max_groups;
+};
+
+static SortWs carve_sort(void* base, int n_views, int64_t mc) {
+    SortWs S;
+    const int64_t mg = max_groups_for(mc, n_views);
+    const size_t nd = (size_t)n_views * kPasses * kDigits;
+    char* p = (char*)base;
+    S.dcount = (uint32_t*)p;
+    p += align_up(4 * nd);
+    S.dstart = (uint32_t*)p;
+    p += align_up(4 * nd);
+    S.agg = (uint64_t*)p;
+    p += align_up(8 * (size_t)(kPasses * mc * kDigits));
+    S.pre = (uint64_t*)p;
+    p += align_up(8 * (size_t)(kPasses * mc * kDigits));
+    S.gagg = (uint64_t*)p;
+    p += align_up(8 * (size_t)(kPasses * mg * kDigits));
+    S.gdone = (uint32_t*)p;
+    S.max_chunks = mc;
+    S.max_groups = mg;
+    return S;
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __restrict__ keys,
+// Look-back groups: kGroup consecutive chunks of a view.  Group (v, i) has
+// slot floor(chunk_base_v / kGroup) + v + i, which is unique and below
+// max_chunks / kGroup + n_views + 1.
+
+GS_DEV uint32_t group_slot(const uint32_t* table, int v, uint32_t c) {
+    return table[4 * v + 2] / kGroup + (uint32_t)v + c / kGroup;
+}
+
+// Digit totals of every pass, per view.  A grid-stride loop over chunks
+// counts keys in per-wavefront LDS histograms and adds the non-zero totals to
+// the view's when the view changes and at the end (few workgroups, so each
+// total takes few global atomics).  Each chunk's look-back words, and its
+// group's if it is the group's first chunk, are cleared for all passes.
+__global__ __launch_bounds__(kSortThreads) void k_digit_hist(const uint32_t* __restrict__ keys,
                                                              const uint32_t* __restrict__ table,
-                                                             int n_views, int shift,
-                                                             uint32_t* __restrict__ hist) {
-    __shared__ uint32_t cnt[kSortThreads / kWave][kDigits];
-    const uint32_t b = xcd_major_block(blockIdx.x, gridDim.x);
-    int v;
-    uint32_t c;
-    if (!chunk_of(table, n_views, b, &v, &c)) {
-        // unused chunk: zero its slot in the tail of the histogram array
-        hist[(int64_t)b * kDigits + threadIdx.x] = 0u;
-        return;
-    }
-    const int w = threadIdx.x / kWave;
-    for (int i = threadIdx.x; i < (kSortThreads / kWave) * kDigits; i += kSortThreads)
-        (&cnt[0][0])[i] = 0u;
-    __syncthreads();
-    const uint32_t seg_b = table[4 * v], seg_e = table[4 * v + 1];
-    const uint32_t start = seg_b + c * kChunk;
+                                                             int n_views, SortWs S) {
+    constexpr int NW = kSortThreads / kWave;
+    __shared__ uint32_t cnt[NW][kPasses][kDigits];
+    const int t = threadIdx.x, w = t / kWave;
+    const uint32_t used = table[4 * n_views];
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i) {
-        const uint32_t idx = start + i * kSortThreads + threadIdx.x;
-        if (idx < seg_e) atomicAdd(&cnt[w][(keys[idx] >> shift) & 0xFF], 1u);
+    for (int j = 0; j < NW * kPasses; ++j) (&cnt[0][0][0])[j * kDigits + t] = 0u;
+    __syncthreads();
+    int cur = -1;
+    for (uint32_t b = blockIdx.x; b < used; b += gridDim.x) {
+        int v;
+        uint32_t c;
+        chunk_of(table, n_views, b, &v, &c);
+        if (cur >= 0 && v != cur) {
+            __syncthreads();
+#pragma unroll
+            for (int p = 0; p < kPasses; ++p) {
+                uint32_t x = 0;
+#pragma unroll
+                for (int j = 0; j < NW; ++j) {
+                    x += cnt[j][p][t];
+                    cnt[j][p][t] = 0u;
+                }
+                if (x) atomicAdd(&S.dcount[(cur * kPasses + p) * kDigits + t], x);
+            }
+            __syncthreads();
+        }
+        cur = v;
+        const uint32_t seg_e = table[4 * v + 1];
+        const uint32_t start = table[4 * v] + c * kChunk;
+        uint32_t k[kSortItems];
+#pragma unroll
+        for (int i = 0; i < kSortItems; ++i) {
+            const uint32_t idx = start + i * kSortThreads + t;
+            k[i] = idx < seg_e ? keys[idx] : 0u;
+        }
+        const uint32_t gs = group_slot(table, v, c);
+#pragma unroll
+        for (int p = 0; p < kPasses; ++p) {
+            S.agg[((int64_t)p * S.max_chunks + b) * kDigits + t] = 0ull;
+            S.pre[((int64_t)p * S.max_chunks + b) * kDigits + t] = 0ull;
+            if (c % kGroup == 0) {
+                S.gagg[((int64_t)p * S.max_groups + gs) * kDigits + t] = 0ull;
+                if (t == 0) S.gdone[p * S.max_groups + gs] = 0u;
+            }
+        }
+        // runs of equal digits in consecutive lanes (a Gaussian's keys share
+        // their depth bits) are counted by their first lane: one LDS atomic per
+        // run instead of one per key
+        const int lane = t % kWave;
+        const uint64_t above = lane == kWave - 1 ? 0ull : (~0ull << (lane + 1));
+#pragma unroll
+        for (int i = 0; i < kSortItems; ++i) {
+            const uint32_t idx = start + i * kSortThreads + t;
+            const bool valid = idx < seg_e;
+            const uint64_t vmask = __ballot(valid);
+            const uint32_t prev = __shfl_up(k[i], 1);
+#pragma unroll
+            for (int p = 0; p < kPasses; ++p) {
+                const uint32_t dg = (k[i] >> (8 * p)) & 0xFF;
+                const bool head = valid && (lane == 0 || ((prev >> (8 * p)) & 0xFF) != dg);
+                const uint64_t heads = __ballot(head) | ~vmask;   // invalid lanes end runs
+                if (head) {
+                    const uint64_t nxt = heads & above;
+                    const int end = nxt ? __builtin_ctzll(nxt) : kWave;
+                    atomicAdd(&cnt[w][p][dg], (uint32_t)(end - lane));
+                }
+            }
+        }
     }
     __syncthreads();
-    uint32_t tot = 0;
+    if (cur >= 0) {
 #pragma unroll
-    for (int i = 0; i < kSortThreads / kWave; ++i) tot += cnt[i][threadIdx.x];
-    const uint32_t nc = table[4 * v + 3], cb = table[4 * v + 2];
-    hist[(int64_t)cb * kDigits + (int64_t)threadIdx.x * nc + c] = tot;
+        for (int p = 0; p < kPasses; ++p) {
+            uint32_t x = 0;
+#pragma unroll
+            for (int j = 0; j < NW; ++j) x += cnt[j][p][t];
+            if (x) atomicAdd(&S.dcount[(cur * kPasses + p) * kDigits + t], x);
+        }
+    }
+}
+
+// Global position of each pass's first key of each digit: the view's segment
+// start plus the exclusive scan of the digit totals.  One workgroup per
+// (view, pass).
+__global__ __launch_bounds__(kDigits) void k_digit_start(const uint32_t* __restrict__ table,
+                                                         const uint32_t* __restrict__ dcount,
+                                                         uint32_t* __restrict__ dstart) {
+    __shared__ uint64_t lds[kDigits / kWave];
+    const int vp = blockIdx.x;
+    const int v = vp / kPasses;
+    const uint32_t x = dcount[vp * kDigits + threadIdx.x];
+    uint64_t tot;
+    const uint64_t inc = block_scan_u64(x, lds, &tot);
+    dstart[vp * kDigits + threadIdx.x] = table[4 * v] + (uint32_t)(inc - x);
 }
 
 GS_DEV uint64_t lanemask_lt() {
@@ -424,21 +551,57 @@ GS_DEV uint64_t lanemask_lt() {
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-// Stable scatter of one radix pass.  Wavefront w of the workgroup owns the
-// contiguous keys [w * 1024, (w + 1) * 1024) of the chunk and ranks them item
-// by item: peers with the same digit are found with 8 ballots, and a running
-// per-(wavefront, digit) count in LDS gives each key its rank among the
-// wavefront's keys of that digit (one wavefront updates only its own counts,
-// so no workgroup barrier is needed while ranking).  One scan over
-// (digit, wavefront) then turns the counts into chunk-local positions, the
-// keys are placed in LDS in digit order, and they are written out so that
-// consecutive lanes write consecutive addresses of each digit's run.  The
-// order of equal digits is (wavefront, item, lane) = input order: stable.
-__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
+
+GS_DEV uint64_t lb_load(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+GS_DEV void lb_store(uint64_t* p, uint64_t x) {
+    __hip_atomic_store(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Polls a look-back word until its flag is set (or the spin limit is hit).
+GS_DEV uint64_t lb_wait(const uint64_t* p, uint32_t* status) {
+    uint64_t x = lb_load(p);
+    for (uint32_t spins = 0; (x >> 32) == 0; ++spins) {
+        if (spins > kLbSpinLimit) {
+            atomicOr(status, (uint32_t)GS_STATUS_SORT);
+            return kLbAggregate;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        x = lb_load(p);
+    }
+    return x;
+}
+
+constexpr int kLbGroupWindow = 8;
+
+// One stable radix pass over a chunk of kChunk keys; chunk b is workgroup b.
+// Workgroups start in index order, and each publishes its per-digit counts
+// before it waits on anything, so every wait of the look-back is on a chunk
+// that has started and will publish; a spin limit bounds the waits all the
+// same (GS_STATUS_SORT).
+//
+// Wavefront w owns the contiguous keys [w * 1024, (w + 1) * 1024) of the chunk
+// and ranks them item by item: peers with the same digit are found with 8
+// ballots, and a running per-(wavefront, digit) count in LDS gives each key its
+// rank among the wavefront's keys of that digit (one wavefront updates only
+// its own counts, so no barrier is needed while ranking).  A scan over
+// (digit, wavefront) turns the counts into chunk-local positions, the keys are
+// placed in LDS in digit order, and they are written out so that consecutive
+// lanes write consecutive addresses of each digit's run.  The order of equal
+// digits is (chunk, wavefront, item, lane) = input order: stable.
+//
+// Destinations: the digit's start in the view plus the counts of the view's
+// earlier chunks.  Each chunk publishes its count, and the chunk of a group of
+// kGroup that publishes last also the group's total; a chunk then adds the
+// counts of the earlier chunks of its group and the totals of the earlier
+// groups, stopping early at a published inclusive prefix.
+__global__ __launch_bounds__(kSortThreads) void k_onesweep(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
-    const uint32_t* __restrict__ table, int n_views, int shift,
-    const uint32_t* __restrict__ scanned) {
+    const uint32_t* __restrict__ table, int n_views, int pass, SortWs S,
+    uint32_t* __restrict__ status) {
     constexpr int NW = kSortThreads / kWave;
     constexpr int PER_WAVE = kChunk / NW;
     __shared__ uint32_t gbase[kDigits];   // global destination of the chunk's first key of digit d
@@ -447,13 +610,13 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     __shared__ uint32_t s_k[kChunk];
     __shared__ uint32_t s_v[kChunk];
     __shared__ uint64_t s_scan[NW];
+    __shared__ uint32_t s_last;
     const uint32_t b = blockIdx.x;
     int v;
     uint32_t c;
     if (!chunk_of(table, n_views, b, &v, &c)) return;
+    const int shift = 8 * pass;
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const uint32_t nc = table[4 * v + 3], cb = table[4 * v + 2];
-    gbase[threadIdx.x] = scanned[(int64_t)cb * kDigits + (int64_t)threadIdx.x * nc + c];
 #pragma unroll
     for (int j = 0; j < NW; ++j) wcnt[j][threadIdx.x] = 0u;
     const uint32_t seg_e = table[4 * v + 1];
@@ -488,15 +651,25 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
         if (valid && before == 0ull) wcnt[w][d] = base + (uint32_t)__popcll(peers);
     }
     __syncthreads();
+    const uint32_t d = threadIdx.x;
+    const int64_t cw = (int64_t)pass * S.max_chunks * kDigits;   // this pass's chunk words
+    const int64_t gw = (int64_t)pass * S.max_groups * kDigits;   // this pass's group words
+    const uint32_t nc = table[4 * v + 3];
+    const uint32_t gi = c / kGroup, g0 = b - c % kGroup;         // group, its first chunk
+    uint32_t total = 0;
+#pragma unroll
+    for (int j = 0; j < NW; ++j) total += wcnt[j][d];
+    lb_store(&S.agg[cw + (int64_t)b * kDigits + d], kLbAggregate | total);
+    if (c == 0) lb_store(&S.pre[cw + (int64_t)b * kDigits + d], kLbPrefix | total);
+    if (d == 0) {
+        const uint32_t gsize = min((uint32_t)kGroup, nc - gi * kGroup);
+        s_last = atomicAdd(&S.gdone[pass * S.max_groups + group_slot(table, v, c)], 1u) + 1 == gsize;
+    }
     {
         // digit-major exclusive scan over (digit, wavefront)
-        const uint32_t d = threadIdx.x;
-        uint32_t t = 0;
-#pragma unroll
-        for (int j = 0; j < NW; ++j) t += wcnt[j][d];
         uint64_t tot;
-        const uint64_t inc = block_scan_u64(t, s_scan, &tot);
-        uint32_t run = (uint32_t)(inc - t);
+        const uint64_t inc = block_scan_u64(total, s_scan, &tot);
+        uint32_t run = (uint32_t)(inc - total);
         lstart[d] = run;
 #pragma unroll
         for (int j = 0; j < NW; ++j) {
@@ -506,6 +679,22 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
         }
     }
     __syncthreads();
+    if (s_last) {
+        // last of its group to publish: every chunk of the group has stored its
+        // count (its flag may still be in flight, so poll it)
+        const uint32_t gsize = min((uint32_t)kGroup, nc - gi * kGroup);
+        uint64_t x[kGroup];
+#pragma unroll
+        for (int j = 0; j < kGroup; ++j)
+            x[j] = (uint32_t)j < gsize ? lb_load(&S.agg[cw + (int64_t)(g0 + j) * kDigits + d]) : kLbAggregate;
+        uint32_t sum = 0;
+#pragma unroll
+        for (int j = 0; j < kGroup; ++j) {
+            if ((x[j] >> 32) == 0) x[j] = lb_wait(&S.agg[cw + (int64_t)(g0 + j) * kDigits + d], status);
+            sum += (uint32_t)x[j];
+        }
+        lb_store(&S.gagg[gw + (int64_t)group_slot(table, v, c) * kDigits + d], kLbAggregate | sum);
+    }
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
         const uint32_t idx = start + w * PER_WAVE + i * kWave + lane;
@@ -515,14 +704,104 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
             s_v[pos] = val[i];
         }
     }
+    // look-back, one digit per thread
+    uint32_t excl = 0;
+    if (c > 0) {
+        bool done = false;
+        // earlier chunks of the own group, nearest first, all loads at once
+        const uint32_t cin = b - g0;
+        uint64_t pj[kGroup - 1], aj[kGroup - 1];
+#pragma unroll
+        for (int q = 0; q < kGroup - 1; ++q) {
+            const bool in = (uint32_t)q < cin;
+            const int64_t j = (int64_t)b - 1 - q;
+            pj[q] = in ? lb_load(&S.pre[cw + j * kDigits + d]) : 0ull;
+            aj[q] = in ? lb_load(&S.agg[cw + j * kDigits + d]) : 0ull;
+        }
+#pragma unroll
+        for (int q = 0; q < kGroup - 1; ++q) {
+            if ((uint32_t)q < cin && !done) {
+                if (pj[q] >> 32) {
+                    excl += (uint32_t)pj[q];
+                    done = true;
+                } else {
+                    if ((aj[q] >> 32) == 0) aj[q] = lb_wait(&S.agg[cw + ((int64_t)b - 1 - q) * kDigits + d], status);
+                    excl += (uint32_t)aj[q];
+                }
+            }
+        }
+        // earlier groups, kLbGroupWindow per round: the inclusive prefix of a
+        // group's last chunk ends the walk, else the group's total is added
+        int64_t g = (int64_t)gi - 1;
+        const uint32_t slot0 = group_slot(table, v, 0);
+        while (!done && g >= 0) {
+            uint64_t pl[kLbGroupWindow], ga[kLbGroupWindow];
+#pragma unroll
+            for (int q = 0; q < kLbGroupWindow; ++q) {
+                const int64_t gq = g - q;
+                const uint32_t last = b - c + (uint32_t)gq * kGroup + (kGroup - 1);
+                pl[q] = gq >= 0 ? lb_load(&S.pre[cw + (int64_t)last * kDigits + d]) : kLbPrefix;
+                ga[q] = gq >= 0 ? lb_load(&S.gagg[gw + (int64_t)(slot0 + gq) * kDigits + d]) : 0ull;
+            }
+            int used = 0;
+            bool stall = false;
+#pragma unroll
+            for (int q = 0; q < kLbGroupWindow; ++q) {
+                if (!done && !stall) {
+                    if (pl[q] >> 32) {
+                        excl += (uint32_t)pl[q];
+                        done = true;
+                    } else if (ga[q] >> 32) {
+                        excl += (uint32_t)ga[q];
+                        ++used;
+                    } else {
+                        stall = true;
+                    }
+                }
+            }
+            g -= used;
+            if (stall && !done) {
+                // the group's total is not out yet: wait for it
+                excl += (uint32_t)lb_wait(&S.gagg[gw + (int64_t)(slot0 + g) * kDigits + d], status);
+                --g;
+            }
+        }
+        lb_store(&S.pre[cw + (int64_t)b * kDigits + d], kLbPrefix | (excl + total));
+    }
+    gbase[d] = S.dstart[(v * kPasses + pass) * kDigits + d] + excl;
     __syncthreads();
     for (uint32_t j = threadIdx.x; j < n_here; j += kSortThreads) {
         const uint32_t key = s_k[j];
-        const uint32_t d = (key >> shift) & 0xFF;
-        const uint32_t dst = gbase[d] + (j - lstart[d]);
+        const uint32_t dg = (key >> shift) & 0xFF;
+        const uint32_t dst = gbase[dg] + (j - lstart[dg]);
         keys_out[dst] = key;
         vals_out[dst] = s_v[j];
     }
+}
+
+// Stable sort of each view's segment of (keys, vals), in place through
+// (ktmp, vtmp).  `table` describes the segments and chunks; dcount and the
+// tickets must be zero.
+static int radix_sort_views(uint32_t* keys, uint32_t* vals, uint32_t* ktmp, uint32_t* vtmp,
+                            const uint32_t* table, int n_views, const SortWs& S, uint32_t* status,
+                            hipStream_t s) {
+    int rc;
+    const unsigned hgrid = (unsigned)std::min<int64_t>(S.max_chunks, kHistBlocks);
+    hipLaunchKernelGGL(k_digit_hist, dim3(hgrid), dim3(kSortThreads), 0, s, keys, table, n_views, S);
+    if ((rc = check_launch("digit_hist")) != GS_OK) return rc;
+    hipLaunchKernelGGL(k_digit_start, dim3((unsigned)(n_views * kPasses)), dim3(kDigits), 0, s, table,
+                       S.dcount, S.dstart);
+    if ((rc = check_launch("digit_start")) != GS_OK) return rc;
+    // an even number of passes leaves the result in keys / vals
+    uint32_t *kin = keys, *vin = vals, *kout = ktmp, *vout = vtmp;
+    for (int pass = 0; pass < kPasses; ++pass) {
+        hipLaunchKernelGGL(k_onesweep, dim3((unsigned)S.max_chunks), dim3(kSortThreads), 0, s, kin, vin, kout,
+                           vout, table, n_views, pass, S, status);
+        if ((rc = check_launch("onesweep")) != GS_OK) return rc;
+        std::swap(kin, kout);
+        std::swap(vin, vout);
+    }
+    return GS_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -597,51 +876,52 @@ int launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s) {
 // stand-alone stable sort of (key, value) pairs, one segment [0, count)
 // ---------------------------------------------------------------------------
 
-__global__ void k_single_table(uint32_t* table, int64_t count) {
+// Table of one segment [0, count); clears the digit totals.
+__global__ void k_single_table(uint32_t* table, int64_t count, uint32_t* dcount, uint32_t* status) {
+    for (int i = threadIdx.x; i < kPasses * kDigits; i += blockDim.x) dcount[i] = 0u;
     if (threadIdx.x != 0) return;
     table[0] = 0u;
     table[1] = (uint32_t)count;
     table[2] = 0u;
     table[3] = (uint32_t)((count + kChunk - 1) / kChunk);
     table[4] = table[3];
+    *status = 0u;
 }
 
-size_t sort_pairs_scratch(int64_t count) {
-    const int64_t mc = (count + kChunk - 1) / kChunk + 1;
-    const int64_t sb = (kDigits * mc + kScanBlock - 1) / kScanBlock;
-    return align_up(8 * (size_t)count) + align_up(4 * (size_t)(kDigits * mc + 1)) +
-           align_up(8 * (size_t)(sb + 1)) + align_up(4 * 8);
+struct PairsScratch {
+    uint32_t *ktmp, *vtmp, *table, *status, *sort_words;
+    int64_t mc;
+};
+
+static size_t carve_pairs(int64_t count, char* base, PairsScratch* out) {
+    PairsScratch P;
+    P.mc = (count + kChunk - 1) / kChunk + 1;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base ? base + off : nullptr;
+        off = align_up(off + bytes);
+        return p;
+    };
+    P.ktmp = (uint32_t*)take(4 * (size_t)count);
+    P.vtmp = (uint32_t*)take(4 * (size_t)count);
+    P.table = (uint32_t*)take(4 * 8);
+    P.status = (uint32_t*)take(4);
+    P.sort_words = (uint32_t*)take(sort_words_bytes(1, P.mc));
+    if (out) *out = P;
+    return off;
 }
+
+size_t sort_pairs_scratch(int64_t count) { return carve_pairs(count, nullptr, nullptr); }
 
 int sort_pairs(uint32_t* keys, uint32_t* vals, int64_t count, void* scratch, hipStream_t s) {
     if (count <= 1) return GS_OK;
-    const int64_t mc = (count + kChunk - 1) / kChunk + 1;
-    const int64_t sb = (kDigits * mc + kScanBlock - 1) / kScanBlock;
-    char* p = (char*)scratch;
-    uint32_t* ktmp = (uint32_t*)p;
-    uint32_t* vtmp = ktmp + count;
-    p += align_up(8 * (size_t)count);
-    uint32_t* hist = (uint32_t*)p;
-    p += align_up(4 * (size_t)(kDigits * mc + 1));
-    uint64_t* sums = (uint64_t*)p;
-    p += align_up(8 * (size_t)(sb + 1));
-    uint32_t* table = (uint32_t*)p;
-    hipLaunchKernelGGL(k_single_table, dim3(1), dim3(64), 0, s, table, count);
+    PairsScratch P;
+    carve_pairs(count, (char*)scratch, &P);
+    const SortWs S = carve_sort(P.sort_words, 1, P.mc);
+    hipLaunchKernelGGL(k_single_table, dim3(1), dim3(256), 0, s, P.table, count, S.dcount, P.status);
     int rc = check_launch("sort_table");
     if (rc != GS_OK) return rc;
-    uint32_t *kin = keys, *vin = vals, *kout = ktmp, *vout = vtmp;
-    for (int pass = 0; pass < 4; ++pass) {
-        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)mc), dim3(kSortThreads), 0, s, kin, table, 1,
-                           8 * pass, hist);
-        if ((rc = check_launch("sort_hist")) != GS_OK) return rc;
-        if ((rc = scan_exclusive(hist, kDigits * mc, hist, sums, nullptr, s)) != GS_OK) return rc;
-        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)mc), dim3(kSortThreads), 0, s, kin, vin, kout,
-                           vout, table, 1, 8 * pass, hist);
-        if ((rc = check_launch("sort_scatter")) != GS_OK) return rc;
-        std::swap(kin, kout);
-        std::swap(vin, vout);
-    }
-    return GS_OK;
+    return radix_sort_views(keys, vals, P.ktmp, P.vtmp, P.table, 1, S, P.status, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -658,11 +938,12 @@ int launch_bin_sort(const gs_splats& sp, int64_t n, const gs_layout& L, const gs
     }
     const int V = L.n_views;
     const int64_t m = (int64_t)V * n;
+    const SortWs S = carve_sort(W.sort_words, V, W.max_chunks);
     int rc;
     if ((rc = launch_fill_u32(b.status, 0u, 1, s)) != GS_OK) return rc;
     if ((rc = scan_exclusive(sp.tiles, m, b.offsets, W.block_sums, b.status, s)) != GS_OK) return rc;
-    hipLaunchKernelGGL(k_view_table, dim3(1), dim3(64), 0, s, b.offsets, n, V, b.capacity, W.table,
-                       b.status);
+    hipLaunchKernelGGL(k_view_table, dim3(1), dim3(256), 0, s, b.offsets, n, V, b.capacity, W.table,
+                       b.status, S.dcount);
     if ((rc = check_launch("view_table")) != GS_OK) return rc;
     EmitGeom eg;
     RangeGeom rg;
@@ -696,26 +977,8 @@ int launch_bin_sort(const gs_splats& sp, int64_t n, const gs_layout& L, const gs
             if ((rc = check_launch("emit_keys")) != GS_OK) return rc;
         }
     }
-    // 4 stable LSD passes; even count leaves the result in keys / vals
-    uint32_t* kin = b.keys;
-    uint32_t* vin = b.vals;
-    uint32_t* kout = W.keys_tmp;
-    uint32_t* vout = W.vals_tmp;
-    const unsigned grid = (unsigned)W.max_chunks;
-    for (int pass = 0; pass < 4; ++pass) {
-        const int shift = 8 * pass;
-        hipLaunchKernelGGL(k_radix_hist, dim3(grid), dim3(kSortThreads), 0, s, kin, W.table, V, shift,
-                           W.hist);
-        if ((rc = check_launch("radix_hist")) != GS_OK) return rc;
-        if ((rc = scan_exclusive(W.hist, kDigits * W.max_chunks, W.hist, W.block_sums, nullptr, s)) !=
-            GS_OK)
-            return rc;
-        hipLaunchKernelGGL(k_radix_scatter, dim3(grid), dim3(kSortThreads), 0, s, kin, vin, kout, vout,
-                           W.table, V, shift, W.hist);
-        if ((rc = check_launch("radix_scatter")) != GS_OK) return rc;
-        std::swap(kin, kout);
-        std::swap(vin, vout);
-    }
+    if ((rc = radix_sort_views(b.keys, b.vals, W.keys_tmp, W.vals_tmp, W.table, V, S, b.status, s)) != GS_OK)
+        return rc;
     const int64_t nt = L.tile_base[V];
     hipLaunchKernelGGL(k_ranges_empty, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, W.table, V,
                        rg, b.ranges);

@@ -596,8 +596,10 @@ constexpr int kLbGroupWindow = 8;
 // earlier chunks.  Each chunk publishes its count, and the chunk of a group of
 // kGroup that publishes last also the group's total; a chunk then adds the
 // counts of the earlier chunks of its group and the totals of the earlier
-// groups, stopping early at a published inclusive prefix.
-__global__ __launch_bounds__(kSortThreads) void k_onesweep(
+// groups, stopping early at the published inclusive prefix of a group's last
+// chunk.
+// At most 128 VGPRs, so that four workgroups (the LDS limit) fit on a CU.
+__global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_onesweep(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
     const uint32_t* __restrict__ table, int n_views, int pass, SortWs S,
@@ -679,6 +681,15 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(
         }
     }
     __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        const uint32_t idx = start + w * PER_WAVE + i * kWave + lane;
+        if (idx < seg_e) {
+            const uint32_t pos = wcnt[w][(k[i] >> shift) & 0xFF] + rank[i];
+            s_k[pos] = k[i];
+            s_v[pos] = val[i];
+        }
+    }
     if (s_last) {
         // last of its group to publish: every chunk of the group has stored its
         // count (its flag may still be in flight, so poll it)
@@ -695,40 +706,20 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(
         }
         lb_store(&S.gagg[gw + (int64_t)group_slot(table, v, c) * kDigits + d], kLbAggregate | sum);
     }
-#pragma unroll
-    for (int i = 0; i < kSortItems; ++i) {
-        const uint32_t idx = start + w * PER_WAVE + i * kWave + lane;
-        if (idx < seg_e) {
-            const uint32_t pos = wcnt[w][(k[i] >> shift) & 0xFF] + rank[i];
-            s_k[pos] = k[i];
-            s_v[pos] = val[i];
-        }
-    }
     // look-back, one digit per thread
     uint32_t excl = 0;
     if (c > 0) {
         bool done = false;
-        // earlier chunks of the own group, nearest first, all loads at once
+        // counts of the earlier chunks of the own group, all loads at once
         const uint32_t cin = b - g0;
-        uint64_t pj[kGroup - 1], aj[kGroup - 1];
+        uint64_t aj[kGroup - 1];
+#pragma unroll
+        for (int q = 0; q < kGroup - 1; ++q)
+            aj[q] = (uint32_t)q < cin ? lb_load(&S.agg[cw + ((int64_t)g0 + q) * kDigits + d]) : kLbAggregate;
 #pragma unroll
         for (int q = 0; q < kGroup - 1; ++q) {
-            const bool in = (uint32_t)q < cin;
-            const int64_t j = (int64_t)b - 1 - q;
-            pj[q] = in ? lb_load(&S.pre[cw + j * kDigits + d]) : 0ull;
-            aj[q] = in ? lb_load(&S.agg[cw + j * kDigits + d]) : 0ull;
-        }
-#pragma unroll
-        for (int q = 0; q < kGroup - 1; ++q) {
-            if ((uint32_t)q < cin && !done) {
-                if (pj[q] >> 32) {
-                    excl += (uint32_t)pj[q];
-                    done = true;
-                } else {
-                    if ((aj[q] >> 32) == 0) aj[q] = lb_wait(&S.agg[cw + ((int64_t)b - 1 - q) * kDigits + d], status);
-                    excl += (uint32_t)aj[q];
-                }
-            }
+            if ((aj[q] >> 32) == 0) aj[q] = lb_wait(&S.agg[cw + ((int64_t)g0 + q) * kDigits + d], status);
+            excl += (uint32_t)aj[q];
         }
         // earlier groups, kLbGroupWindow per round: the inclusive prefix of a
         // group's last chunk ends the walk, else the group's total is added

@@ -162,15 +162,16 @@ typedef struct gs_bins {
  * contiguous index range; rec_mask flags which records the last call wrote. */
 typedef struct gs_grads2d {
     float* rec;           /* capacity records of 12 floats: (d u, d v, d A, d B, d C,
-                             d opacity, d r, d g, d b, 0, 0, 0); records not flagged in
-                             rec_mask are left as they were */
+                             d opacity, d r, d g, d b, owner, 0, 0), owner = the bits of
+                             the uint32 index v*n+g of the record's (view, Gaussian);
+                             records not flagged in rec_mask are left as they were */
     uint32_t* rec_mask;   /* ceil(capacity / 32) words: bit i (word i / 32, bit i % 32)
                              set iff record i was written by the last gs_rasterize_bwd */
     uint32_t* tile_stop;  /* total tiles: the backward traversed sorted positions
                              [ranges[t].start, tile_stop[t]) of tile t (up to the last
                              entry any of its pixels composited) */
     float* sums;          /* 9 planes of n_views * n floats, plane c at c * n_views * n:
-                             per (view, Gaussian) sum of its traversed records
+                             per (view, Gaussian) sum of its records flagged in rec_mask
                              (components 0..8), written by gs_project_bwd_adam */
     void* workspace;      /* device scratch of gs_grads2d_workspace_size(capacity) bytes
                              for gs_project_bwd_adam */
@@ -226,8 +227,8 @@ int gs_layout_init(const int32_t* widths, const int32_t* heights, int n_views, i
 size_t gs_bin_sort_workspace_size(int64_t n, const gs_layout* layout, int64_t capacity);
 
 /* Bytes of scratch (gs_grads2d.workspace) that gs_project_bwd_adam needs for
- * the given intersection capacity: per 256 intersection indices, one owner
- * word and two partial sums of 9 floats. */
+ * the given intersection capacity: per 512 intersection indices, two partial
+ * sums of 9 floats. */
 size_t gs_grads2d_workspace_size(int64_t capacity);
 
 /* ---- the five stages ------------------------------------------------------ */

@@ -20,182 +20,130 @@
 namespace gs {
 
 struct GatherArgs {
-    const float4* rec;
     const uint32_t* offsets;
-    const uint32_t* row_offsets;
-    const uint4* rows;
-    int64_t row_capacity;
     const uint32_t* rec_mask;
     const float4* grec;
     int64_t n;
     int64_t capacity;
     int n_views;
     float* sums;
-    uint32_t* block_first;  // per block: the row slot holding its first index
-    float* part_first;      // per block, 9 floats: sum of its first run if that run
-                            // belongs to a Gaussian that started in an earlier block
-    float* part_last;       // per block, 9 floats: sum of its last run if that run's
-                            // Gaussian started in this block and continues after it
+    float* part_first;      // per unit, 9 floats: sum of its first run if that run
+                            // belongs to a Gaussian that started in an earlier unit
+    float* part_last;       // per unit, 9 floats: sum of its last run if that run's
+                            // Gaussian started in this unit and continues after it
 };
 
 constexpr int kGatherThreads = 256;
-constexpr int kGatherE = 256;      // intersection indices per workgroup (one per thread)
-constexpr int kGatherRows = 512;   // row slots staged in LDS per workgroup
+constexpr int kGatherE = 512;                           // intersection indices per unit
+constexpr int kGatherPer = kGatherE / kGatherThreads;   // indices per thread
+static_assert(kGatherPer >= 1 && kGatherPer <= 32 && 32 % kGatherPer == 0, "mask bits per thread");
 
 size_t gather_workspace(int64_t capacity) {
     const size_t nb = (size_t)((capacity + kGatherE - 1) / kGatherE) + 1;
     auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
-    return up(4 * (nb + 1)) + 2 * up(4 * 9 * nb);
+    return 2 * up(4 * 9 * nb);
 }
 
 static void carve_gather(void* ws, int64_t capacity, GatherArgs& g) {
     const size_t nb = (size_t)((capacity + kGatherE - 1) / kGatherE) + 1;
     auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
     char* p = static_cast<char*>(ws);
-    g.block_first = reinterpret_cast<uint32_t*>(p);
-    p += up(4 * (nb + 1));
     g.part_first = reinterpret_cast<float*>(p);
     p += up(4 * 9 * nb);
     g.part_last = reinterpret_cast<float*>(p);
 }
 
-// Number of valid row slots and intersections (both clamped to their capacities).
-GS_DEV uint64_t rows_valid(const GatherArgs& a, int64_t vn) {
-    return min((uint64_t)a.row_offsets[vn], (uint64_t)a.row_capacity);
-}
+// Number of valid intersections (clamped to the capacity).
 GS_DEV uint64_t entries_valid(const GatherArgs& a, int64_t vn) {
     return min((uint64_t)a.offsets[vn], (uint64_t)a.capacity);
 }
 
-// block_first[b] = the row slot whose index range holds index b * E.
-__global__ __launch_bounds__(256) void k_gather_index(GatherArgs a) {
-    const int64_t vn = (int64_t)a.n_views * a.n;
-    const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t rc = rows_valid(a, vn), kc = entries_valid(a, vn);
-    if (r >= rc) return;
-    const uint64_t b = min((uint64_t)a.rows[r].x, kc);
-    const uint64_t e = r + 1 < rc ? min((uint64_t)a.rows[r + 1].x, kc) : kc;
-    for (uint64_t blk = (b + kGatherE - 1) / kGatherE; blk * kGatherE < e; ++blk)
-        a.block_first[blk] = (uint32_t)r;
-}
-
-// Gather, in units of E = 256 intersection indices.  sums and the per-unit
-// partials are zeroed beforehand, so a unit without any flagged record needs
-// no work: each workgroup reads the record mask of 4 consecutive units (one
-// mask word per thread) and processes only the units with a flag.
-// Processing a unit, one index per thread: the row slots covering it (from
-// the slot holding its first index to the one holding the next unit's) are
-// staged in LDS; each index finds its row by binary search in LDS, hence its
-// (view, Gaussian), and parks its record in LDS if the backward flagged it
-// (else zeros), with coalesced record loads.  (If more slots than fit in LDS
-// cover one unit -- only possible with many rows whose span is empty -- the
-// search runs over the slots in global memory instead.)  Then the first index
-// of every run of equal owner adds up its run in index order: a run that is
-// the whole of its Gaussian's range is written to sums directly; the unit's
-// first and last runs, if their Gaussian extends past the unit, go to
-// per-unit partials that the chain-rule kernel adds in unit order.  No unit
-// has more than E indices, however long one Gaussian's list is.
-constexpr int kGatherUnits = 4;    // units per workgroup
-
+// Gather, one workgroup per unit of E = 512 intersection indices.  Each
+// thread reads the record-mask bits of its two indices; a workgroup scan of
+// the flag counts gives every flagged record a slot, and the flagged records
+// (9 gradient components and the owner (view, Gaussian) the backward stored
+// in the record) are compacted into LDS in index order.  A Gaussian's
+// indices are one contiguous range, so its flagged records in the unit are
+// one run of equal owner; the first record of each run adds up the run in
+// index order.  A run whose Gaussian lies inside the unit is written to
+// sums; the unit's first and last runs, if their Gaussian extends past the
+// unit, go to the unit's partials, which the chain-rule kernel adds in unit
+// order.  Every unit writes both of its partials (zeros when unused); sums of
+// Gaussians without a flagged record keep the zeros filled beforehand.
 __global__ __launch_bounds__(kGatherThreads) void k_gather2d(GatherArgs a) {
-    __shared__ float4 s_rec[kGatherE][3];
+    constexpr int NW = kGatherThreads / kWave;
+    __shared__ float s_val[9][kGatherE];
     __shared__ uint32_t s_own[kGatherE];
-    __shared__ uint32_t s_first[kGatherRows];
-    __shared__ uint32_t s_o[kGatherRows];
-    __shared__ uint32_t s_unit[kGatherUnits];
+    __shared__ uint32_t s_wsum[NW];
     const int64_t vn = (int64_t)a.n_views * a.n;
     const uint64_t kc = entries_valid(a, vn);
-    const uint64_t g0 = (uint64_t)blockIdx.x * (kGatherUnits * kGatherE);
-    if (g0 >= kc) return;
-    const uint32_t nblk = (uint32_t)((kc + kGatherE - 1) / kGatherE);
-    const int t = threadIdx.x;
-    // which of the workgroup's units hold a flagged record
-    if (t < kGatherUnits) s_unit[t] = 0u;
-    __syncthreads();
-    if (t < kGatherUnits * kGatherE / 32) {
-        const uint64_t word = g0 / 32 + (uint64_t)t;
-        if (word * 32 < kc && a.rec_mask[word] != 0u) s_unit[t * 32 / kGatherE] = 1u;
+    const uint32_t unit = blockIdx.x;
+    const uint64_t e0 = (uint64_t)unit * kGatherE;
+    if (e0 >= kc) return;
+    const uint64_t e1 = min(e0 + (uint64_t)kGatherE, kc);
+    const int t = threadIdx.x, lane = t % kWave, w = t / kWave;
+    const uint64_t i0 = e0 + (uint64_t)kGatherPer * t;
+    uint32_t bits = 0;
+    if (i0 < e1) {
+        bits = (a.rec_mask[i0 >> 5] >> (uint32_t)(i0 & 31)) & ((1u << kGatherPer) - 1u);
+        const uint64_t left = e1 - i0;
+        if (left < (uint64_t)kGatherPer) bits &= (1u << left) - 1u;
+    }
+    const uint32_t cnt = (uint32_t)__popc(bits);
+    uint32_t incl = cnt;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off);
+        if (lane >= off) incl += y;
+    }
+    if (lane == kWave - 1) s_wsum[w] = incl;
+    if (t < 9) {
+        a.part_first[9 * (int64_t)unit + t] = 0.f;
+        a.part_last[9 * (int64_t)unit + t] = 0.f;
     }
     __syncthreads();
-    for (int u = 0; u < kGatherUnits; ++u) {
-        if (s_unit[u] == 0u) continue;       // workgroup-uniform
-        const uint32_t unit = (uint32_t)(g0 / kGatherE) + (uint32_t)u;
-        const uint64_t e0 = (uint64_t)unit * kGatherE;
-        if (e0 >= kc) break;
-        const uint64_t e1 = min(e0 + (uint64_t)kGatherE, kc);
-        const uint32_t ra = a.block_first[unit];
-        const uint32_t rz = unit + 1 < nblk ? a.block_first[unit + 1] : (uint32_t)(rows_valid(a, vn) - 1);
-        const uint32_t nr = rz - ra + 1;
-        const bool staged = nr <= (uint32_t)kGatherRows;
-        __syncthreads();                     // LDS of the previous unit is free
-        if (staged) {
-            for (uint32_t k = t; k < nr; k += kGatherThreads) {
-                const uint4 row = a.rows[ra + k];
-                s_first[k] = row.x;
-                s_o[k] = row.y;
-            }
-        }
-        __syncthreads();
-        const int cnt = (int)(e1 - e0);
-        {
-            const int j = t;
-            float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
-            uint32_t own = 0xFFFFFFFFu;
-            if (j < cnt) {
-                const uint32_t i = (uint32_t)(e0 + (uint64_t)j);
-                const uint32_t flag = (a.rec_mask[i >> 5] >> (i & 31u)) & 1u;
-                if (staged) {
-                    uint32_t lo = 0, hi = nr - 1;
-                    while (lo < hi) {
-                        const uint32_t mid = (lo + hi + 1) >> 1;
-                        if (s_first[mid] <= i) lo = mid; else hi = mid - 1;
-                    }
-                    own = s_o[lo];
-                } else {
-                    uint32_t lo = ra, hi = rz;
-                    while (lo < hi) {
-                        const uint32_t mid = lo + ((hi - lo + 1) >> 1);
-                        if (a.rows[mid].x <= i) lo = mid; else hi = mid - 1;
-                    }
-                    own = a.rows[lo].y;
-                }
-                if (flag) {
-                    const float4* g = a.grec + 3 * (int64_t)i;
-                    r0 = g[0]; r1 = g[1]; r2 = g[2];
-                    r2.y = 0.f; r2.z = 0.f; r2.w = 0.f;
-                }
-            }
-            s_rec[j][0] = r0; s_rec[j][1] = r1; s_rec[j][2] = r2;
-            s_own[j] = own;
-        }
-        __syncthreads();
-        const int j = t;
-        if (j < cnt && (j == 0 || s_own[j - 1] != s_own[j])) {   // the first index of a run
-            const uint32_t own = s_own[j];
-            const uint64_t gb = a.offsets[own];
-            const uint64_t ge = min((uint64_t)a.offsets[own + 1], (uint64_t)a.capacity);
-            const bool before = gb < e0, after = ge > e1;
-            // the run is the Gaussian's indices inside this unit: a fixed trip count
-            const int jend = (int)(min(ge, e1) - e0);
-            float4 d0 = make_float4(0.f, 0.f, 0.f, 0.f), d1 = d0;
-            float d8 = 0.f;
-#pragma unroll 4
-            for (int jj = j; jj < jend; ++jj) {
-                const float4 q0 = s_rec[jj][0], q1 = s_rec[jj][1];
-                const float q8 = s_rec[jj][2].x;
-                d0.x += q0.x; d0.y += q0.y; d0.z += q0.z; d0.w += q0.w;
-                d1.x += q1.x; d1.y += q1.y; d1.z += q1.z; d1.w += q1.w;
-                d8 += q8;
-            }
-            const float d[9] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w, d8};
-            float* dst;
-            int64_t stride;
-            if (!before && !after) { dst = a.sums + own; stride = vn; }
-            else if (before) { dst = a.part_first + 9 * (int64_t)unit; stride = 1; }
-            else { dst = a.part_last + 9 * (int64_t)unit; stride = 1; }
+    uint32_t pos = incl - cnt, nf = 0;
 #pragma unroll
-            for (int c = 0; c < 9; ++c) dst[c * stride] = d[c];
+    for (int j = 0; j < NW; ++j) {
+        if (j < w) pos += s_wsum[j];
+        nf += s_wsum[j];
+    }
+    if (nf == 0) return;
+#pragma unroll
+    for (int q = 0; q < kGatherPer; ++q) {
+        if ((bits >> q) & 1u) {
+            const float4* g = a.grec + 3 * (int64_t)(i0 + (uint64_t)q);
+            const float4 r0 = g[0], r1 = g[1], r2 = g[2];
+            s_val[0][pos] = r0.x; s_val[1][pos] = r0.y; s_val[2][pos] = r0.z; s_val[3][pos] = r0.w;
+            s_val[4][pos] = r1.x; s_val[5][pos] = r1.y; s_val[6][pos] = r1.z; s_val[7][pos] = r1.w;
+            s_val[8][pos] = r2.x;
+            s_own[pos] = __float_as_uint(r2.y);
+            ++pos;
         }
+    }
+    __syncthreads();
+    for (uint32_t p = t; p < nf; p += kGatherThreads) {
+        const uint32_t own = s_own[p];
+        if ((p > 0 && s_own[p - 1] == own) || (int64_t)own >= vn) continue;   // not a run's first record
+        uint32_t q = p + 1;
+        while (q < nf && s_own[q] == own) ++q;
+        float d[9];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) d[c] = 0.f;
+        for (uint32_t jj = p; jj < q; ++jj) {
+#pragma unroll
+            for (int c = 0; c < 9; ++c) d[c] += s_val[c][jj];
+        }
+        const uint64_t gb = a.offsets[own];
+        const uint64_t ge = min((uint64_t)a.offsets[own + 1], (uint64_t)a.capacity);
+        const bool before = gb < e0, after = ge > e1;
+        float* dst;
+        int64_t stride;
+        if (!before && !after) { dst = a.sums + own; stride = vn; }
+        else if (before) { dst = a.part_first + 9 * (int64_t)unit; stride = 1; }
+        else { dst = a.part_last + 9 * (int64_t)unit; stride = 1; }
+#pragma unroll
+        for (int c = 0; c < 9; ++c) dst[c * stride] = d[c];
     }
 }
 
@@ -488,11 +436,7 @@ int launch_project_bwd_adam(float* params, int64_t n, const gs_view* views, cons
     int rc = GS_OK;
     GatherArgs ga;
     memset(&ga, 0, sizeof(ga));
-    ga.rec = reinterpret_cast<const float4*>(splats.rec);
     ga.offsets = b.offsets;
-    ga.row_offsets = b.row_offsets;
-    ga.rows = reinterpret_cast<const uint4*>(b.rows);
-    ga.row_capacity = b.row_capacity;
     ga.rec_mask = grads.rec_mask;
     ga.grec = reinterpret_cast<const float4*>(grads.rec);
     ga.n = n;
@@ -527,25 +471,11 @@ int launch_project_bwd_adam(float* params, int64_t n, const gs_view* views, cons
         if (rc != GS_OK) return rc;
     }
     const int64_t vn = (int64_t)L.n_views * n;
-    if (b.row_capacity > 0) {
-        hipLaunchKernelGGL(k_gather_index, dim3((unsigned)((b.row_capacity + 255) / 256)), dim3(256), 0, s,
-                           ga);
-        rc = check_launch("gather_index");
-        if (rc != GS_OK) return rc;
-    }
-    // sums of Gaussians without any flagged record, and partials of units
-    // without one, stay zero
+    // sums of Gaussians without any flagged record stay zero
     rc = launch_fill_u32(reinterpret_cast<uint32_t*>(ga.sums), 0u, 9 * vn, s);
     if (rc != GS_OK) return rc;
-    {
-        const int64_t nb = (b.capacity + kGatherE - 1) / kGatherE + 1;
-        if ((rc = launch_fill_u32(reinterpret_cast<uint32_t*>(ga.part_first), 0u, 9 * nb, s)) != GS_OK ||
-            (rc = launch_fill_u32(reinterpret_cast<uint32_t*>(ga.part_last), 0u, 9 * nb, s)) != GS_OK)
-            return rc;
-    }
-    if (b.capacity > 0 && b.row_capacity > 0) {
-        const int64_t per = (int64_t)kGatherUnits * kGatherE;
-        hipLaunchKernelGGL(k_gather2d, dim3((unsigned)((b.capacity + per - 1) / per)),
+    if (b.capacity > 0) {
+        hipLaunchKernelGGL(k_gather2d, dim3((unsigned)((b.capacity + kGatherE - 1) / kGatherE)),
                            dim3(kGatherThreads), 0, s, ga);
         rc = check_launch("gather2d");
         if (rc != GS_OK) return rc;

@@ -545,9 +545,10 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd(RasterArgs a)
                     if ((int64_t)idx >= a.capacity) continue;   // only after a capacity overflow
                     atomicOr(a.rec_mask + (idx >> 5), 1u << (idx & 31u));
                     float4* rec = a.grec + 3 * (int64_t)idx;
+                    const uint32_t owner = (uint32_t)((int64_t)ti.view * a.n + s_gid[sub + kk]);
                     if (anyw) {
                         // conic and opacity of this Gaussian, unscaled
-                        const float4* rr = a.rec + 4 * ((int64_t)ti.view * a.n + s_gid[sub + kk]);
+                        const float4* rr = a.rec + 4 * (int64_t)owner;
                         const float4 q0 = rr[0];
                         const float4 q1 = rr[1];
                         const float A = q0.z, B = q0.w, C = q1.x, op = q1.y;
@@ -555,10 +556,10 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd(RasterArgs a)
                         const float dv = B * r1 + C * r2;
                         rec[0] = make_float4(du, dv, -0.5f * r3, -r4);
                         rec[1] = make_float4(-0.5f * r5, r0 / op, r6, r7);
-                        rec[2] = make_float4(r8, 0.0f, 0.0f, 0.0f);
+                        rec[2] = make_float4(r8, __uint_as_float(owner), 0.0f, 0.0f);
                     } else {
                         const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-                        rec[0] = z; rec[1] = z; rec[2] = z;
+                        rec[0] = z; rec[1] = z; rec[2] = make_float4(0.f, __uint_as_float(owner), 0.f, 0.f);
                     }
                 }
                 __syncthreads();

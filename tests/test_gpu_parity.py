@@ -135,6 +135,9 @@ def test_training_step(name, ppl):
     okr = grad_close(g["grec"][trav, :9], ref.partials[trav], GRAD_RTOL).all(axis=1)
     badr = flag & ~okr & ~exr
     assert not badr.any(), (pos[badr][:5], trav[badr][:5])
+    # each written record names its (view, Gaussian)
+    owner = np.ascontiguousarray(g["grec"][trav[flag], 9]).view(np.uint32)
+    np.testing.assert_array_equal(owner, (pview * n + g["vals"][pos])[flag])
     assert not (~flag & (np.abs(ref.partials[trav]).max(axis=1) > 0) & ~exr).any()
     untrav = np.setdiff1d(np.arange(g["K"]), trav)
     assert not bit(g["rec_mask"], untrav).any()

@@ -227,8 +227,8 @@ int gs_layout_init(const int32_t* widths, const int32_t* heights, int n_views, i
 size_t gs_bin_sort_workspace_size(int64_t n, const gs_layout* layout, int64_t capacity);
 
 /* Bytes of scratch (gs_grads2d.workspace) that gs_project_bwd_adam needs for
- * the given intersection capacity: per 512 intersection indices, two partial
- * sums of 9 floats. */
+ * the given intersection capacity: per 256 intersection indices, two partial
+ * sums of 9 floats, each with its owner. */
 size_t gs_grads2d_workspace_size(int64_t capacity);
 
 /* ---- the five stages ------------------------------------------------------ */

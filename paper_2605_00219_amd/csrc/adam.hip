@@ -27,21 +27,23 @@ struct GatherArgs {
     int64_t capacity;
     int n_views;
     float* sums;
-    float* part_first;      // per unit, 9 floats: sum of its first run if that run
-                            // belongs to a Gaussian that started in an earlier unit
-    float* part_last;       // per unit, 9 floats: sum of its last run if that run's
-                            // Gaussian started in this unit and continues after it
+    float* part_first;      // per unit, kPart floats: owner bits, then the sum of the
+                            // unit's first run (owner 0xFFFFFFFF: no run)
+    float* part_last;       // per unit, kPart floats: the same for its last run, if it
+                            // is not also the first
 };
+
+constexpr int kPart = 10;   // floats per partial slot
 
 constexpr int kGatherThreads = 256;
 constexpr int kGatherE = 512;                           // intersection indices per unit
 constexpr int kGatherPer = kGatherE / kGatherThreads;   // indices per thread
-static_assert(kGatherPer >= 1 && kGatherPer <= 32 && 32 % kGatherPer == 0, "mask bits per thread");
+static_assert(kGatherPer == 2, "two compacted records per thread in the segmented scan");
 
 size_t gather_workspace(int64_t capacity) {
     const size_t nb = (size_t)((capacity + kGatherE - 1) / kGatherE) + 1;
     auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
-    return 2 * up(4 * 9 * nb);
+    return 2 * up(4 * kPart * nb);
 }
 
 static void carve_gather(void* ws, int64_t capacity, GatherArgs& g) {
@@ -49,7 +51,7 @@ static void carve_gather(void* ws, int64_t capacity, GatherArgs& g) {
     auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
     char* p = static_cast<char*>(ws);
     g.part_first = reinterpret_cast<float*>(p);
-    p += up(4 * 9 * nb);
+    p += up(4 * kPart * nb);
     g.part_last = reinterpret_cast<float*>(p);
 }
 
@@ -58,22 +60,24 @@ GS_DEV uint64_t entries_valid(const GatherArgs& a, int64_t vn) {
     return min((uint64_t)a.offsets[vn], (uint64_t)a.capacity);
 }
 
-// Gather, one workgroup per unit of E = 512 intersection indices.  Each
-// thread reads the record-mask bits of its two indices; a workgroup scan of
-// the flag counts gives every flagged record a slot, and the flagged records
-// (9 gradient components and the owner (view, Gaussian) the backward stored
-// in the record) are compacted into LDS in index order.  A Gaussian's
-// indices are one contiguous range, so its flagged records in the unit are
-// one run of equal owner; the first record of each run adds up the run in
-// index order.  A run whose Gaussian lies inside the unit is written to
-// sums; the unit's first and last runs, if their Gaussian extends past the
-// unit, go to the unit's partials, which the chain-rule kernel adds in unit
-// order.  Every unit writes both of its partials (zeros when unused); sums of
-// Gaussians without a flagged record keep the zeros filled beforehand.
+// Gather, one workgroup per unit of E intersection indices.  Each thread
+// reads the record-mask bits of its indices; a workgroup scan of the flag
+// counts gives every flagged record a slot, and the flagged records (9
+// gradient components and the owner (view, Gaussian) the backward stored in
+// the record) are compacted into LDS in index order.  A Gaussian's indices
+// are one contiguous range, so its flagged records in the unit are one run of
+// equal owner, summed by a segmented scan over the compacted records.
+// A run with runs on both sides lies wholly inside the unit, so its sum is the
+// Gaussian's and goes to sums; the unit's first run goes to its first partial
+// slot and its last run (if there are two or more) to its last partial slot,
+// each tagged with the owner, for the chain-rule kernel to add up.  Every unit
+// writes the tags of both slots; sums of Gaussians without a middle run keep
+// the zeros filled beforehand.
 __global__ __launch_bounds__(kGatherThreads) void k_gather2d(GatherArgs a) {
     constexpr int NW = kGatherThreads / kWave;
     __shared__ float s_val[9][kGatherE];
     __shared__ uint32_t s_own[kGatherE];
+    __shared__ uint32_t s_flag[kGatherThreads];
     __shared__ uint32_t s_wsum[NW];
     const int64_t vn = (int64_t)a.n_views * a.n;
     const uint64_t kc = entries_valid(a, vn);
@@ -97,9 +101,9 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather2d(GatherArgs a) {
         if (lane >= off) incl += y;
     }
     if (lane == kWave - 1) s_wsum[w] = incl;
-    if (t < 9) {
-        a.part_first[9 * (int64_t)unit + t] = 0.f;
-        a.part_last[9 * (int64_t)unit + t] = 0.f;
+    if (t == 0) {
+        a.part_first[kPart * (int64_t)unit] = __uint_as_float(0xFFFFFFFFu);
+        a.part_last[kPart * (int64_t)unit] = __uint_as_float(0xFFFFFFFFu);
     }
     __syncthreads();
     uint32_t pos = incl - cnt, nf = 0;
@@ -122,57 +126,105 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather2d(GatherArgs a) {
         }
     }
     __syncthreads();
-    for (uint32_t p = t; p < nf; p += kGatherThreads) {
-        const uint32_t own = s_own[p];
-        if ((p > 0 && s_own[p - 1] == own) || (int64_t)own >= vn) continue;   // not a run's first record
-        uint32_t q = p + 1;
-        while (q < nf && s_own[q] == own) ++q;
-        float d[9];
+    // segmented inclusive scan over the compacted records, two per thread
+    // (records 2t and 2t + 1): the last record of each run ends up with the
+    // run's sum.  Per thread: the pair's aggregate; across threads: a
+    // Hillis-Steele scan of (aggregate, run-start flag); then each record adds
+    // the running sum before it unless a run starts at it.
+    const uint32_t p0 = 2 * (uint32_t)t, p1 = p0 + 1;
+    const bool act0 = p0 < nf, act1 = p1 < nf;
+    const uint32_t own0 = act0 ? s_own[p0] : 0xFFFFFFFFu;
+    const uint32_t own1 = act1 ? s_own[p1] : 0xFFFFFFFFu;
+    const bool head0 = act0 && (p0 == 0 || s_own[p0 - 1] != own0);
+    const bool head1 = act1 && own1 != own0;
+    const bool tail0 = act0 && (!act1 || own1 != own0);
+    const bool tail1 = act1 && (p1 == nf - 1 || s_own[p1 + 1] != own1);
+    float v0[9], v1[9], agg[9];
 #pragma unroll
-        for (int c = 0; c < 9; ++c) d[c] = 0.f;
-        for (uint32_t jj = p; jj < q; ++jj) {
+    for (int c = 0; c < 9; ++c) {
+        v0[c] = act0 ? s_val[c][p0] : 0.f;
+        v1[c] = act1 ? s_val[c][p1] : 0.f;
+        agg[c] = head1 ? v1[c] : v0[c] + v1[c];
+    }
+    uint32_t f = (head0 || head1) ? 1u : 0u;
+    const uint32_t nt = (nf + 1) / 2;   // threads holding records
+    for (uint32_t off = 1; off < nt; off <<= 1) {
+        __syncthreads();
+        s_flag[t] = f;
 #pragma unroll
-            for (int c = 0; c < 9; ++c) d[c] += s_val[c][jj];
+        for (int c = 0; c < 9; ++c) s_val[c][t] = agg[c];
+        __syncthreads();
+        if ((uint32_t)t >= off && !f) {
+#pragma unroll
+            for (int c = 0; c < 9; ++c) agg[c] = s_val[c][t - off] + agg[c];
+            f = s_flag[t - off];
         }
-        const uint64_t gb = a.offsets[own];
-        const uint64_t ge = min((uint64_t)a.offsets[own + 1], (uint64_t)a.capacity);
-        const bool before = gb < e0, after = ge > e1;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 9; ++c) s_val[c][t] = agg[c];   // inclusive, per thread
+    __syncthreads();
+    if (!head0 && t > 0) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) v0[c] = s_val[c][t - 1] + v0[c];
+    }
+    if (!head1) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) v1[c] = v0[c] + v1[c];
+    }
+    // the unit's first run goes to the first slot, its last run (if not also
+    // the first) to the last slot, every other run to sums
+    const uint32_t first_own = s_own[0];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const bool tl = h == 0 ? tail0 : tail1;
+        const uint32_t own = h == 0 ? own0 : own1;
+        const uint32_t p = h == 0 ? p0 : p1;
+        if (!tl || (int64_t)own >= vn) continue;
         float* dst;
         int64_t stride;
-        if (!before && !after) { dst = a.sums + own; stride = vn; }
-        else if (before) { dst = a.part_first + 9 * (int64_t)unit; stride = 1; }
-        else { dst = a.part_last + 9 * (int64_t)unit; stride = 1; }
+        if (own == first_own) { dst = a.part_first + kPart * (int64_t)unit; stride = 1; }
+        else if (p == nf - 1) { dst = a.part_last + kPart * (int64_t)unit; stride = 1; }
+        else { dst = a.sums + own; stride = vn; }
+        if (stride == 1) {
+            dst[0] = __uint_as_float(own);
+            ++dst;
+        }
 #pragma unroll
-        for (int c = 0; c < 9; ++c) dst[c * stride] = d[c];
+        for (int c = 0; c < 9; ++c) dst[c * stride] = h == 0 ? v0[c] : v1[c];
     }
 }
 
-// Sum of the records of (view, Gaussian) o: complete runs come from sums;
-// a range split over blocks b0 < b1 is part_last[b0] + part_first[b0+1] + ...
-// + part_first[b1], in that order.  Empty ranges give zeros.  The result is
-// also stored to sums for ranges that were split or empty.
+// Sum of the flagged records of (view, Gaussian) o: its middle run if it had
+// one (sums, zero otherwise), then, unit by unit over the units its index
+// range covers, the first and last partial slots tagged with o.  The result
+// is also stored to sums when a partial slot contributed.
 GS_DEV void gather_total(const GatherArgs& a, int64_t o, int64_t vn, float d[9]) {
     const uint64_t b = min((uint64_t)a.offsets[o], (uint64_t)a.capacity);
     const uint64_t e = min((uint64_t)a.offsets[o + 1], (uint64_t)a.capacity);
-    if (e <= b) {
 #pragma unroll
-        for (int c = 0; c < 9; ++c) { d[c] = 0.f; a.sums[c * vn + o] = 0.f; }
-        return;
+    for (int c = 0; c < 9; ++c) d[c] = a.sums[c * vn + o];
+    if (e <= b) return;
+    const uint32_t tag = (uint32_t)o;
+    bool added = false;
+    for (uint64_t u = b / kGatherE; u <= (e - 1) / kGatherE; ++u) {
+        const float* pf = a.part_first + kPart * u;
+        if (__float_as_uint(pf[0]) == tag) {
+#pragma unroll
+            for (int c = 0; c < 9; ++c) d[c] += pf[1 + c];
+            added = true;
+        }
+        const float* pl = a.part_last + kPart * u;
+        if (__float_as_uint(pl[0]) == tag) {
+#pragma unroll
+            for (int c = 0; c < 9; ++c) d[c] += pl[1 + c];
+            added = true;
+        }
     }
-    const uint64_t b0 = b / kGatherE, b1 = (e - 1) / kGatherE;
-    if (b0 == b1) {
+    if (added) {
 #pragma unroll
-        for (int c = 0; c < 9; ++c) d[c] = a.sums[c * vn + o];
-        return;
+        for (int c = 0; c < 9; ++c) a.sums[c * vn + o] = d[c];
     }
-#pragma unroll
-    for (int c = 0; c < 9; ++c) d[c] = a.part_last[9 * b0 + c];
-    for (uint64_t blk = b0 + 1; blk <= b1; ++blk) {
-#pragma unroll
-        for (int c = 0; c < 9; ++c) d[c] += a.part_first[9 * blk + c];
-    }
-#pragma unroll
-    for (int c = 0; c < 9; ++c) a.sums[c * vn + o] = d[c];
 }
 
 struct AdamArgs {

@@ -125,18 +125,53 @@ GS_DEV int next_tile(const RasterArgs& a, int* s_tile) {
     return *s_tile;
 }
 
-// Pixels per lane: a T x T tile is covered by T*T/PPT lanes, lane t holding
-// the pixels t, t + NT, t + 2 NT, ... of the tile (row major).  More pixels
-// per lane read each staged Gaussian from LDS once for several pixels, give
-// independent transmittance chains to interleave and share the backward's
-// per-Gaussian wavefront reduction; fewer give more wavefronts per tile to
-// hide latency (with 16x16 tiles, PPT = 4 is one wavefront per tile).
+// Pixels per lane: a T x T tile is covered by T*T/PPT lanes.  Wavefront w
+// holds the 64 PPT consecutive pixels [64 PPT w, 64 PPT (w + 1)) of the tile
+// (row major), i.e. whole tile rows, lane l the pixels 64 PPT w + 64 q + l.
+// More pixels per lane read each staged Gaussian from LDS once for several
+// pixels, give independent transmittance chains to interleave and share the
+// backward's per-Gaussian wavefront reduction; fewer give more wavefronts per
+// tile to hide latency (with 16x16 tiles, PPT = 4 is one wavefront per tile).
 template <int TILE, int PPT_>
 struct Geo {
     static constexpr int PPT = PPT_;
     static constexpr int NT = TILE * TILE / PPT;
     static constexpr int NW = NT / kWave;
+    static constexpr int ROWS = kWave * PPT / TILE;   // tile rows per wavefront
+    static_assert(NT % kWave == 0 && (kWave * PPT) % TILE == 0, "whole rows per wavefront");
+    // tile-local pixel index of lane t's q-th pixel
+    static GS_DEV int pixel(int t, int q) { return (t / kWave) * (kWave * PPT) + q * kWave + (t % kWave); }
 };
+
+// Whether any pixel centre of the rectangle [x0, x1] x [y0, y1] can give the
+// staged Gaussian alpha >= 1/255, decided conservatively: the largest
+// log2-scaled power over the rectangle (the concave quadratic's maximum, at
+// the mean if it lies inside, else on an edge at the clamped 1D maximiser)
+// plus a margin for float rounding, against log2(1 / (255 o)).  False only
+// when every pixel of the rectangle would skip the pair, so leaving such
+// pairs out changes no result.
+GS_DEV bool rect_may_composite(const float4& sg, const float4& sh, float x0, float x1, float y0,
+                               float y1) {
+    const float a = sg.z, b = sg.w, c = sh.x;   // p2 = a dx^2 + b dx dy + c dy^2, a, c < 0
+    const float X0 = x0 - sg.x, X1 = x1 - sg.x, Y0 = y0 - sg.y, Y1 = y1 - sg.y;
+    float fmax = 0.0f;
+    if (!(X0 <= 0.0f && X1 >= 0.0f && Y0 <= 0.0f && Y1 >= 0.0f)) {
+        const float ky = -b / (2.0f * c), kx = -b / (2.0f * a);
+        float dy = fminf(fmaxf(ky * X0, Y0), Y1);
+        const float e0 = a * X0 * X0 + (b * X0) * dy + c * dy * dy;
+        dy = fminf(fmaxf(ky * X1, Y0), Y1);
+        const float e1 = a * X1 * X1 + (b * X1) * dy + c * dy * dy;
+        float dx = fminf(fmaxf(kx * Y0, X0), X1);
+        const float e2 = c * Y0 * Y0 + (b * Y0) * dx + a * dx * dx;
+        dx = fminf(fmaxf(kx * Y1, X0), X1);
+        const float e3 = c * Y1 * Y1 + (b * Y1) * dx + a * dx * dx;
+        fmax = fmaxf(fmaxf(e0, e1), fmaxf(e2, e3));
+    }
+    const float DX = fmaxf(fabsf(X0), fabsf(X1)), DY = fmaxf(fabsf(Y0), fabsf(Y1));
+    const float mag = fabsf(a) * DX * DX + fabsf(c) * DY * DY + fabsf(b) * DX * DY;
+    const float L = -__log2f(255.0f * sh.y);
+    return !(fmax + 1e-5f * (mag + fabsf(L) + 1.0f) < L);
+}
 
 struct TileInfo {
     int view, tx, ty, W, H;
@@ -182,7 +217,7 @@ GS_DEV void flush_comp_bits(uint32_t* word, uint32_t bits, int addr16, int addr3
 template <int TILE, int S, int PPT_, bool STATS>
 __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_fwd(RasterArgs a) {
     constexpr int PPT = PPT_, NT = Geo<TILE, PPT_>::NT;
-    const int lane_ = threadIdx.x & (kWave - 1);
+    const int lane_ = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     const int addr16 = (lane_ ^ 16) << 2, addr32 = (lane_ ^ 32) << 2;
     __shared__ float4 s_g[S];
     __shared__ float4 s_h[S];
@@ -200,7 +235,7 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_fwd(RasterArgs a)
         bool active[PPT], inside[PPT];
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
-            const int p = (int)threadIdx.x + q * NT;
+            const int p = Geo<TILE, PPT_>::pixel((int)threadIdx.x, q);
             const int ix = ti.tx * TILE + p % TILE, iy = ti.ty * TILE + p / TILE;
             px[q] = (float)ix + 0.5f;
             py[q] = (float)iy + 0.5f;
@@ -229,54 +264,82 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_fwd(RasterArgs a)
             if (__ballot(any) != 0ull) {
                 const int cnt = (int)min((uint32_t)S, end - b0);
                 const uint32_t base = b0 - start + 1u;
+                // the staged Gaussians some pixel of this wavefront's rows can
+                // composite; the others would change nothing and are passed over
+                constexpr int NR = (S + kWave - 1) / kWave;
+                const float rx0 = (float)(ti.tx * TILE) + 0.5f, rx1 = rx0 + (float)(TILE - 1);
+                const float ry0 = (float)(ti.ty * TILE + wv * Geo<TILE, PPT_>::ROWS) + 0.5f;
+                const float ry1 = ry0 + (float)(Geo<TILE, PPT_>::ROWS - 1);
+                uint64_t rel[NR];
+#pragma unroll
+                for (int i = 0; i < NR; ++i) {
+                    const int k = i * kWave + lane_;
+                    rel[i] = __ballot(k < cnt && rect_may_composite(s_g[k], s_h[k], rx0, rx1, ry0, ry1));
+                }
                 // bits of comp_mask for the entries of this batch that this
                 // lane's pixels composited, OR-reduced over the wavefront and
                 // flushed once per 32-bit word of the mask
-                uint32_t lbits = 0;
-                int kend = cnt - 1;
-                for (int k = 0; k < cnt; ++k) {
-                    const float4 sg = s_g[k];
-                    const float4 sh = s_h[k];
-                    const float cb = s_b[k];
-                    bool still = false, compd = false;
+                uint32_t lbits = 0, word = b0 >> 5;
+                int prev = -1;
+                bool done = false;
 #pragma unroll
-                    for (int q = 0; q < PPT; ++q) {
-                        float dx, dy, G, ag;
-                        const bool in = eval_pair(px[q], py[q], sg, sh, dx, dy, G, ag);
-                        const float alpha = fminf(kAlphaMax, ag);
-                        const bool ok = active[q] && in && alpha >= kAlphaMin;
-                        const float test_T = T[q] * (1.0f - alpha);
-                        const bool stop = ok && test_T < kTMin;
-                        const bool comp = ok && !stop;
-                        if (STATS) examined[q] += active[q] ? 1u : 0u;
-                        active[q] = active[q] && !stop;
-                        const float w = comp ? alpha * T[q] : 0.0f;
-                        C0[q] = __builtin_fmaf(w, sh.z, C0[q]);
-                        C1[q] = __builtin_fmaf(w, sh.w, C1[q]);
-                        C2[q] = __builtin_fmaf(w, cb, C2[q]);
-                        T[q] = comp ? test_T : T[q];
-                        last[q] = comp ? base + (uint32_t)k : last[q];
-                        if (STATS) composited[q] += comp ? 1u : 0u;
-                        still = still || active[q];
-                        compd = compd || comp;
+                for (int i = 0; i < NR; ++i) {
+                    if (done) break;
+                    for (uint64_t m = rel[i]; m != 0ull; m &= m - 1ull) {
+                        const int k = i * kWave + (int)__builtin_ctzll(m);
+                        const uint32_t j = b0 + (uint32_t)k;
+                        if ((j >> 5) != word) {
+                            if (__ballot(lbits != 0u) != 0ull)
+                                flush_comp_bits(a.comp_mask + word, lbits, addr16, addr32);
+                            lbits = 0;
+                            word = j >> 5;
+                        }
+                        const float4 sg = s_g[k];
+                        const float4 sh = s_h[k];
+                        const float cb = s_b[k];
+                        bool still = false, compd = false;
+#pragma unroll
+                        for (int q = 0; q < PPT; ++q) {
+                            float dx, dy, G, ag;
+                            const bool in = eval_pair(px[q], py[q], sg, sh, dx, dy, G, ag);
+                            const float alpha = fminf(kAlphaMax, ag);
+                            const bool ok = active[q] && in && alpha >= kAlphaMin;
+                            const float test_T = T[q] * (1.0f - alpha);
+                            const bool stop = ok && test_T < kTMin;
+                            const bool comp = ok && !stop;
+                            // entries passed over since the previous one count as examined
+                            if (STATS) examined[q] += active[q] ? (uint32_t)(k - prev) : 0u;
+                            active[q] = active[q] && !stop;
+                            const float w = comp ? alpha * T[q] : 0.0f;
+                            C0[q] = __builtin_fmaf(w, sh.z, C0[q]);
+                            C1[q] = __builtin_fmaf(w, sh.w, C1[q]);
+                            C2[q] = __builtin_fmaf(w, cb, C2[q]);
+                            T[q] = comp ? test_T : T[q];
+                            last[q] = comp ? base + (uint32_t)k : last[q];
+                            if (STATS) composited[q] += comp ? 1u : 0u;
+                            still = still || active[q];
+                            compd = compd || comp;
+                        }
+                        prev = k;
+                        lbits |= compd ? 1u << (j & 31u) : 0u;
+                        if (__ballot(still) == 0ull) {
+                            done = true;
+                            break;
+                        }
                     }
-                    const uint32_t j = b0 + (uint32_t)k;
-                    lbits |= compd ? 1u << (j & 31u) : 0u;
-                    if ((j & 31u) == 31u) {
-                        flush_comp_bits(a.comp_mask + (j >> 5), lbits, addr16, addr32);
-                        lbits = 0;
-                    }
-                    if (__ballot(still) == 0ull) { kend = k; break; }
                 }
-                // the word of the last entry examined, if not flushed yet
-                flush_comp_bits(a.comp_mask + ((b0 + (uint32_t)kend) >> 5), lbits, addr16, addr32);
+                if (STATS && !done) {
+#pragma unroll
+                    for (int q = 0; q < PPT; ++q) examined[q] += active[q] ? (uint32_t)(cnt - 1 - prev) : 0u;
+                }
+                if (__ballot(lbits != 0u) != 0ull) flush_comp_bits(a.comp_mask + word, lbits, addr16, addr32);
             }
         }
         const float* bg = a.views[ti.view].bg;
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
             if (!inside[q]) continue;
-            const int p = (int)threadIdx.x + q * NT;
+            const int p = Geo<TILE, PPT_>::pixel((int)threadIdx.x, q);
             const int64_t pix = ti.pix_base + (int64_t)(ti.ty * TILE + p / TILE) * ti.W +
                                 ti.tx * TILE + p % TILE;
             a.out_rgb[3 * pix + 0] = __builtin_fmaf(T[q], bg[0], C0[q]);
@@ -345,6 +408,7 @@ template <int TILE, int S, int PPT_>
 __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd(RasterArgs a) {
     constexpr int PPT = PPT_, NT = Geo<TILE, PPT_>::NT, NW = Geo<TILE, PPT_>::NW;
     constexpr int SUB = 64;  // Gaussians per reduction sub-batch
+    static_assert(SUB == kWave, "one relevance ballot per sub-batch");
     __shared__ float4 s_g[S];
     __shared__ float4 s_h[S];
     __shared__ float s_b[S];
@@ -372,7 +436,7 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd(RasterArgs a)
         uint32_t mylen = 0;
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
-            const int p = (int)threadIdx.x + q * NT;
+            const int p = Geo<TILE, PPT_>::pixel((int)threadIdx.x, q);
             const int ix = ti.tx * TILE + p % TILE, iy = ti.ty * TILE + p / TILE;
             px[q] = (float)ix + 0.5f;
             py[q] = (float)iy + 0.5f;
@@ -456,10 +520,19 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd(RasterArgs a)
                 }
             }
             __syncthreads();
+            // this wavefront's rectangle of pixel centres
+            const float rx0 = (float)(ti.tx * TILE) + 0.5f, rx1 = rx0 + (float)(TILE - 1);
+            const float ry0 = (float)(ti.ty * TILE + w * Geo<TILE, PPT_>::ROWS) + 0.5f;
+            const float ry1 = ry0 + (float)(Geo<TILE, PPT_>::ROWS - 1);
             for (int sub = 0; sub < cnt; sub += SUB) {
                 const int scnt = min(SUB, cnt - sub);
                 uint64_t used = 0;
-                for (int kk = 0; kk < scnt; ++kk) {
+                // staged Gaussians no pixel of this wavefront can composite are
+                // passed over (their gradient terms here would all be zero)
+                const uint64_t rel = __ballot(lane < scnt && rect_may_composite(s_g[sub + lane], s_h[sub + lane],
+                                                                                  rx0, rx1, ry0, ry1));
+                for (uint64_t mrel = rel; mrel != 0ull; mrel &= mrel - 1ull) {
+                    const int kk = (int)__builtin_ctzll(mrel);
                     const int k = sub + kk;
                     const uint32_t pos = s_pos[k];
                     const float4 sg = s_g[k];

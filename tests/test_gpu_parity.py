@@ -81,6 +81,43 @@ def test_projection_and_binning_bit_exact(name):
     np.testing.assert_array_equal(g["ranges"], ref.bins.ranges)
 
 
+def _tile_of_pixel(views, tile):
+    """Global tile index of every pixel (views concatenated)."""
+    out, tb = [], 0
+    for v in views:
+        W, H = int(v["width"]), int(v["height"])
+        gx, gy = (W + tile - 1) // tile, (H + tile - 1) // tile
+        iy, ix = np.divmod(np.arange(W * H), W)
+        out.append(tb + (iy // tile) * gx + ix // tile)
+        tb += gx * gy
+    return np.concatenate(out)
+
+
+@pytest.mark.parametrize("name,tile,ppl", [("plain-2k-256", 16, 1), ("plain-2k-256", 16, 2),
+                                           ("plain-2k-256", 16, 4), ("plain-2k-256", 8, 1),
+                                           ("plain-2k-256", 32, 2), ("ragged-2view", 16, 2),
+                                           ("ragged-2view", 32, 4)])
+def test_tile_statistics(name, tile, ppl):
+    """Per tile: the most list entries any pixel examined and the pixel-Gaussian
+    pairs examined, equal to the oracle's on tiles without a fragile pixel."""
+    scene, _, views, _ = WL[name]
+    note(f"tile statistics {name} tile={tile} pixels/lane={ppl}")
+    pr = oracle.project(scene, views, tile)
+    bins = oracle.bin_sort(pr, views, tile)
+    ref = oracle.raster_fwd(pr, bins, views, tile)
+    g = run_gpu_step(scene, views, tile, pixels_per_lane=ppl, tile_stats=True)
+    st = g["tile_stats"].reshape(-1, 4).astype(np.int64)
+    nt = st.shape[0]
+    frag = np.zeros(nt, bool)
+    frag[_tile_of_pixel(views, tile)[ref.fragile != 0]] = True
+    ok = ~frag
+    assert ok.mean() > 0.8      # large tiles: few tiles, more of them hold a fragile pixel
+    np.testing.assert_array_equal(st[ok, 0], ref.tile_traversed[ok].astype(np.int64))
+    np.testing.assert_array_equal(st[ok, 1], ref.tile_evaluated[ok].astype(np.int64))
+    assert np.all(st[:, 2] <= st[:, 1])
+    assert st[:, 2].sum() > 0
+
+
 @pytest.mark.parametrize("name", list(WL))
 @pytest.mark.parametrize("lds_batch,ppl", [(32, 4), (64, 1), (64, 2), (256, 4)])
 def test_forward_pixels(name, lds_batch, ppl):

@@ -30,16 +30,17 @@ FP32_PEAK_TFLOPS = 157.3
 # design notes): bytes that must cross HBM, or flops that must be executed.
 PROJ_BYTES_G = 308           # parameters 240 read; splat record 64 + tile count 4 written
 SORT_BYTES_G = 28            # counts, offsets, rectangle/depth word per (view, Gaussian)
-SORT_BYTES_K = 92            # emit 8 w; 4 passes x (8 r + 8 w + 4 histogram r); ranges 4 r
+SORT_BYTES_K = 80            # emit 8 w; digit histogram 4 r; 4 passes x (8 r + 8 w); ranges 4 r
 FWD_FLOP_EVAL = 14           # power, G, alpha, thresholds per evaluated pixel-Gaussian pair
 FWD_FLOP_COMP = 9            # colour and transmittance update per composited pair
-BWD_BYTES_TRAVERSED = 88     # Gaussian id 4 + splat 36 + index 12 read, gradient record 36 written
+BWD_BYTES_TRAVERSED = 40     # Gaussian id 4 + splat 36 read per traversed entry
+BWD_BYTES_FLAGGED = 64       # row slot 16 read, gradient record 48 written per composited entry
 BWD_BYTES_PIXEL = 28         # C 12 + target 12 + last 4
-BWD_BYTES_TILE = 32          # range 8 + loss 4 + stop entry 16 + key 4
+BWD_BYTES_TILE = 16          # range 8 + loss 4 + stop 4
 BWD_FLOP_EVAL = 14           # recompute of power, G, alpha, thresholds per evaluated pair
 BWD_FLOP_CONTRIB = 44        # gradient terms and their sums per composited pair
 ADAM_BYTES_G = 1516          # params, m, v 720 r + 720 w; offsets 4; per-view sums 36 w + 36 r
-ADAM_BYTES_TRAVERSED = 48    # one gradient record per traversed intersection
+ADAM_BYTES_FLAGGED = 48      # one gradient record read per composited entry (+ K/8 of mask)
 
 
 def log(msg):
@@ -196,7 +197,7 @@ def main():
             gx = (W + 15) // 16
             tile_of_px = torch.arange(H * W, device=dev)
             tile_of_px = (tile_of_px // W // 16) * gx + (tile_of_px % W) // 16
-            acc = dict(K=0, trav_bwd=0, eval_bwd=0, contrib=0, eval_fwd=0, trav_fwd=0, visible=0)
+            acc = dict(K=0, trav_bwd=0, eval_bwd=0, contrib=0, eval_fwd=0, trav_fwd=0, visible=0, flagged=0)
             for i in range(args.steps):
                 vi = order[(args.warmup + i) % ncam]
                 vd = vptr(vi)
@@ -215,6 +216,8 @@ def main():
                 acc["eval_fwd"] += int(ts[:, 1].sum().item())
                 acc["trav_fwd"] += int(ts[:, 0].sum().item())
                 P.rasterize_bwd(rframe, vd, target=targets[vi], lds_batch=args.lds_batch)
+                nw = (rframe.intersections() + 31) // 32
+                acc["flagged"] += int(np.unpackbits(rframe.rec_mask[:nw].cpu().numpy().view(np.uint8)).sum())
                 P.project_bwd_adam(model, rframe, vd)
             torch.cuda.synchronize()
             counts = {k: v / args.steps for k, v in acc.items()}
@@ -276,11 +279,12 @@ def main():
                                  68 * counts["trav_fwd"] + 20 * P_px + 8 * ntiles, "rasterize_fwd"),
             "rasterize_bwd": alu("rasterize_bwd",
                                  BWD_FLOP_EVAL * counts["eval_bwd"] + BWD_FLOP_CONTRIB * counts["contrib"],
-                                 BWD_BYTES_TRAVERSED * counts["trav_bwd"] + BWD_BYTES_PIXEL * P_px
+                                 BWD_BYTES_TRAVERSED * counts["trav_bwd"]
+                                 + BWD_BYTES_FLAGGED * counts["flagged"] + BWD_BYTES_PIXEL * P_px
                                  + BWD_BYTES_TILE * ntiles, "rasterize_bwd"),
             "project_bwd_adam": hbm("project_bwd_adam",
-                                    ADAM_BYTES_G * n + ADAM_BYTES_TRAVERSED * counts["trav_bwd"],
-                                    "project_bwd_adam"),
+                                    ADAM_BYTES_G * n + ADAM_BYTES_FLAGGED * counts["flagged"]
+                                    + counts["K"] / 8, "project_bwd_adam"),
         }
         rb = per_stage["rasterize_bwd"]
         extra["rasterize_bwd"] = {
@@ -288,6 +292,7 @@ def main():
             "hbm_frac": rb["hbm_frac"], "algorithmic_flop": rb["algorithmic_flop"],
             "tflops": rb["achieved"], "alu_frac": rb["frac"],
             "intersections": counts["K"], "traversed": counts["trav_bwd"],
+            "composited_entries": counts["flagged"],
             "pairs_evaluated": counts["eval_bwd"], "pairs_composited": counts["contrib"],
             "visible_gaussians": vis}
         tr = recorded_traffic("rasterize_bwd")

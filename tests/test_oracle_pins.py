@@ -327,6 +327,48 @@ def test_single_gaussian_closed_form(double):
     np.testing.assert_allclose(c, colour, atol=1e-6)
 
 
+@pytest.mark.parametrize("double", [False, True])
+def test_traversal_counts_without_early_stop(double):
+    # opacities <= 0.02 and at most a few hundred entries per tile keep T above
+    # the 1e-4 stop, so every pixel examines its tile's whole list
+    scene = S.workload_plain_small().scene.copy()
+    scene.opacity_logits[:] = np.minimum(scene.opacity_logits, np.float32(math.log(0.02 / 0.98)))
+    views = _view(200, 150)
+    pr = oracle.project(scene, views, 16, double)
+    bins = oracle.bin_sort(pr, views, 16, double)
+    img = oracle.raster_fwd(pr, bins, views, 16, double)
+    length = (bins.ranges[:, 1] - bins.ranges[:, 0]).astype(np.int64)
+    assert length.max() < 400 and length.max() > 20
+    assert img.T.min() > 1e-3
+    gx, gy = (200 + 15) // 16, (150 + 15) // 16
+    tx, ty = np.arange(gx * gy) % gx, np.arange(gx * gy) // gx
+    npix = (np.minimum(16, 200 - 16 * tx) * np.minimum(16, 150 - 16 * ty)).astype(np.int64)
+    np.testing.assert_array_equal(img.tile_traversed.astype(np.int64), length)
+    np.testing.assert_array_equal(img.tile_evaluated.astype(np.int64), length * npix)
+
+
+@pytest.mark.parametrize("double", [False, True])
+def test_traversal_stops_at_the_fourth_of_stacked_gaussians(double):
+    # ten identical Gaussians centred on the only pixel, alpha = o = 0.95 each:
+    # T = 0.05, 0.0025, 1.25e-4 after three; the fourth would leave 6.25e-6 <
+    # 1e-4, so it stops the pixel: 4 entries examined, 3 composited
+    n = 10
+    sh = np.zeros((n, 16, 3))
+    sh[:, 0] = _dc_for_colour([0.7, 0.7, 0.7])
+    scene = _scene_from([[0, 0, 0]] * n, [[math.log(0.05)] * 3] * n, [[1, 0, 0, 0]] * n,
+                        [math.log(0.95 / 0.05)] * n, sh)
+    views = _view(1, 1)
+    pr = oracle.project(scene, views, 16, double)
+    bins = oracle.bin_sort(pr, views, 16, double)
+    img = oracle.raster_fwd(pr, bins, views, 16, double)
+    np.testing.assert_allclose(pr.xy[0, :, 0], 0.5, atol=1e-6)
+    np.testing.assert_allclose(pr.opacity[0], 0.95, rtol=1e-6)
+    assert int(bins.ranges[0, 1] - bins.ranges[0, 0]) == n
+    assert int(img.tile_traversed[0]) == 4 and int(img.tile_evaluated[0]) == 4
+    assert int(img.last[0]) == 3
+    np.testing.assert_allclose(img.T[0], 0.05 ** 3, rtol=1e-5)
+
+
 def test_two_gaussians_closed_form_depth_order():
     sh = np.zeros((2, 16, 3))
     sh[0, 0] = _dc_for_colour([1.0, 0.0, 0.0])

@@ -22,6 +22,8 @@ constexpr int kScanBlock = kScanThreads * kScanItems;  // 2048 elements per bloc
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;
 constexpr int kChunk = kSortThreads * kSortItems;      // 4096 keys per radix chunk
+constexpr int kDepthItems = 4;                          // the depth sort of (view, Gaussian)s:
+constexpr int kDepthChunk = kSortThreads * kDepthItems; // 1024-key chunks
 constexpr int kDigits = 256;
 constexpr int kPasses = 4;
 constexpr int kHistBlocks = 512;                        // workgroups of the histogram pass
@@ -42,7 +44,7 @@ static inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 static size_t sort_words_bytes(int n_views, int64_t mc) {
     const int64_t mg = max_groups_for(mc, n_views);
     const size_t nd = (size_t)n_views * kPasses * kDigits;
-    return align_up(4 * nd) * 2 + align_up(8 * (size_t)(kPasses * mc * kDigits)) * 2 +
+    return align_up(4 * nd) + align_up(8 * (size_t)(kPasses * mc * kDigits)) * 2 +
            align_up(8 * (size_t)(kPasses * mg * kDigits)) + align_up(4 * (size_t)(kPasses * mg));
 }
 
@@ -54,6 +56,12 @@ struct Workspace {
     uint32_t* table;       // 4 * (GS_MAX_VIEWS + 1)
     uint32_t* sort_words;  // the sort's totals and look-back words (carve_sort)
     int64_t max_chunks;
+    // depth order of the (view, Gaussian)s
+    uint32_t *dkey, *dval, *dkey_tmp, *dval_tmp;
+    uint32_t* dshift;      // per (view, Gaussian): depth-order position - unsorted index
+    uint32_t* dtable;      // segments of the depth sort
+    uint32_t* dsort_words;
+    int64_t max_dchunks;
 };
 
 static int64_t max_chunks_for(int64_t capacity, int n_views) {
@@ -77,6 +85,16 @@ static size_t carve(int64_t n, const gs_layout& L, int64_t capacity, char* base,
     tmp.table = (uint32_t*)take(sizeof(uint32_t) * 4 * (GS_MAX_VIEWS + 1));
     tmp.sort_words = (uint32_t*)take(sort_words_bytes(L.n_views, mc));
     tmp.max_chunks = mc;
+    const int64_t m = std::max<int64_t>((int64_t)L.n_views * n, 1);
+    const int64_t mcd = (m + kDepthChunk - 1) / kDepthChunk + L.n_views;
+    tmp.dkey = (uint32_t*)take(sizeof(uint32_t) * (size_t)m);
+    tmp.dval = (uint32_t*)take(sizeof(uint32_t) * (size_t)m);
+    tmp.dkey_tmp = (uint32_t*)take(sizeof(uint32_t) * (size_t)m);
+    tmp.dval_tmp = (uint32_t*)take(sizeof(uint32_t) * (size_t)m);
+    tmp.dshift = (uint32_t*)take(sizeof(uint32_t) * (size_t)m);
+    tmp.dtable = (uint32_t*)take(sizeof(uint32_t) * 4 * (GS_MAX_VIEWS + 1));
+    tmp.dsort_words = (uint32_t*)take(sort_words_bytes(L.n_views, mcd));
+    tmp.max_dchunks = mcd;
     if (w) *w = tmp;
     return off;
 }
@@ -123,8 +141,35 @@ GS_DEV uint64_t block_scan_u64(uint64_t v, uint64_t* lds, uint64_t* total) {
     return x + pre;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __restrict__ in,
-                                                              int64_t len,
+// With `perm`, element i of the sequence is in[perm[i]], and the exclusive
+// scan value of element i is stored as out[perm[i]] = scan_i - sub[perm[i]]
+// (no total is stored); without, element i is in[i] and out[i] = scan_i, with
+// the total in out[len].
+// `clear`, if set, is zeroed by the first launch (the status word of the call).
+struct ScanIO {
+    const uint32_t* in;
+    const uint32_t* perm;
+    const uint32_t* sub;
+    uint32_t* out;
+    uint32_t* clear;
+};
+
+// Tile rows of the bounding box in a projection record (rect0, rect1 words).
+GS_DEV uint32_t rect_rows(const float4& q3) {
+    return (__float_as_uint(q3.y) >> 16) - (__float_as_uint(q3.x) >> 16);
+}
+
+GS_DEV uint32_t scan_load(const ScanIO& io, int64_t i) { return io.perm ? io.in[io.perm[i]] : io.in[i]; }
+GS_DEV void scan_store(const ScanIO& io, int64_t i, uint32_t x) {
+    if (io.perm) {
+        const uint32_t j = io.perm[i];
+        io.out[j] = x - io.sub[j];
+    } else {
+        io.out[i] = x;
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(ScanIO io, int64_t len,
                                                               uint64_t* __restrict__ sums) {
     __shared__ uint64_t lds[kScanThreads / kWave];
     const int64_t base = (int64_t)blockIdx.x * kScanBlock;
@@ -132,8 +177,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
         const int64_t idx = base + (int64_t)i * kScanThreads + threadIdx.x;
-        if (idx < len) s += in[idx];
+        if (idx < len) s += scan_load(io, idx);
     }
+    if (io.clear && blockIdx.x == 0 && threadIdx.x == 0) *io.clear = 0u;
     s = block_reduce_u64(s, lds);
     if (threadIdx.x == 0) sums[blockIdx.x] = s;
 }
@@ -157,10 +203,10 @@ __global__ __launch_bounds__(1024) void k_scan_top(uint64_t* __restrict__ sums, 
     }
 }
 
-// `in` and `out` may be the same array (the radix histograms are scanned in place).
-__global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* in, int64_t len,
+// `in` and `out` may be the same array.
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(ScanIO io, int64_t len,
                                                             const uint64_t* __restrict__ sums,
-                                                            int64_t nb, uint32_t* out) {
+                                                            int64_t nb) {
     __shared__ uint64_t lds[kScanThreads / kWave];
     const int64_t base = (int64_t)blockIdx.x * kScanBlock;
     // each thread owns kScanItems consecutive elements
@@ -169,7 +215,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* in, 
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
         const int64_t idx = base + (int64_t)threadIdx.x * kScanItems + i;
-        v[i] = idx < len ? in[idx] : 0u;
+        v[i] = idx < len ? scan_load(io, idx) : 0u;
         s += v[i];
     }
     uint64_t tot;
@@ -178,10 +224,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* in, 
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
         const int64_t idx = base + (int64_t)threadIdx.x * kScanItems + i;
-        if (idx < len) out[idx] = (uint32_t)run;
+        if (idx < len) scan_store(io, idx, (uint32_t)run);
         run += v[i];
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) out[len] = (uint32_t)sums[nb];
+    if (!io.perm && blockIdx.x == 0 && threadIdx.x == 0) io.out[len] = (uint32_t)sums[nb];
 }
 
 // Second pass of a two-launch scan (for at most kScanInlineBlocks blocks):
@@ -189,9 +235,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* in, 
 // scan of the block sums; the last block writes the total.
 constexpr int64_t kScanInlineBlocks = 2048;
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_down_inline(const uint32_t* in, int64_t len,
+__global__ __launch_bounds__(kScanThreads) void k_scan_down_inline(ScanIO io, int64_t len,
                                                                    const uint64_t* __restrict__ sums,
-                                                                   int64_t nb, uint32_t* out,
+                                                                   int64_t nb,
                                                                    uint32_t* __restrict__ status) {
     __shared__ uint64_t lds[kScanThreads / kWave];
     uint64_t carry = 0;
@@ -203,7 +249,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down_inline(const uint32_
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
         const int64_t idx = base + (int64_t)threadIdx.x * kScanItems + i;
-        v[i] = idx < len ? in[idx] : 0u;
+        v[i] = idx < len ? scan_load(io, idx) : 0u;
         s += v[i];
     }
     uint64_t tot;
@@ -212,28 +258,29 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down_inline(const uint32_
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
         const int64_t idx = base + (int64_t)threadIdx.x * kScanItems + i;
-        if (idx < len) out[idx] = (uint32_t)run;
+        if (idx < len) scan_store(io, idx, (uint32_t)run);
         run += v[i];
     }
     if (blockIdx.x == nb - 1 && threadIdx.x == 0) {
         const uint64_t total = carry + tot;
-        out[len] = (uint32_t)total;
+        if (!io.perm) io.out[len] = (uint32_t)total;
         if (status && total > 0xFFFFFFFFull) atomicOr(status, (uint32_t)GS_STATUS_OVERFLOW);
     }
 }
 
 static int scan_exclusive(const uint32_t* in, int64_t len, uint32_t* out, uint64_t* sums,
-                          uint32_t* status, hipStream_t s) {
+                          uint32_t* status, hipStream_t s, const uint32_t* perm = nullptr,
+                          const uint32_t* sub = nullptr, uint32_t* clear = nullptr) {
+    const ScanIO io{in, perm, sub, out, clear};
     const int64_t nb = std::max<int64_t>((len + kScanBlock - 1) / kScanBlock, 1);
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, len, sums);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, io, len, sums);
     if (nb <= kScanInlineBlocks) {
-        hipLaunchKernelGGL(k_scan_down_inline, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, len, sums,
-                           nb, out, status);
+        hipLaunchKernelGGL(k_scan_down_inline, dim3((unsigned)nb), dim3(kScanThreads), 0, s, io, len, sums, nb,
+                           status);
         return check_launch("scan");
     }
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, sums, nb, status);
-    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, len, sums, nb,
-                       out);
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0, s, io, len, sums, nb);
     return check_launch("scan");
 }
 
@@ -241,12 +288,26 @@ static int scan_exclusive(const uint32_t* in, int64_t len, uint32_t* out, uint64
 // per-view segment table
 // ---------------------------------------------------------------------------
 
-// Also clears the sort's digit totals.
+// Also the table of the depth sort (one segment of n per view); clears both
+// sorts' digit totals.
 __global__ void k_view_table(const uint32_t* __restrict__ offsets, int64_t n, int n_views,
                              int64_t capacity, uint32_t* __restrict__ table,
-                             uint32_t* __restrict__ status, uint32_t* __restrict__ dcount) {
-    for (int i = threadIdx.x; i < n_views * kPasses * kDigits; i += blockDim.x) dcount[i] = 0u;
+                             uint32_t* __restrict__ status, uint32_t* __restrict__ dcount,
+                             uint32_t* __restrict__ dtable, uint32_t* __restrict__ ddcount) {
+    for (int i = threadIdx.x; i < n_views * kPasses * kDigits; i += blockDim.x) {
+        dcount[i] = 0u;
+        ddcount[i] = 0u;
+    }
     if (threadIdx.x != 0) return;
+    // the depth sort: one segment of n per view
+    const uint32_t dnc = (uint32_t)((n + kDepthChunk - 1) / kDepthChunk);
+    for (int v = 0; v < n_views; ++v) {
+        dtable[4 * v + 0] = (uint32_t)(v * n);
+        dtable[4 * v + 1] = (uint32_t)((v + 1) * n);
+        dtable[4 * v + 2] = (uint32_t)v * dnc;
+        dtable[4 * v + 3] = dnc;
+    }
+    dtable[4 * n_views] = (uint32_t)n_views * dnc;
     uint32_t chunks = 0;
     const uint64_t cap = (uint64_t)capacity;
     for (int v = 0; v < n_views; ++v) {
@@ -282,30 +343,33 @@ __global__ __launch_bounds__(256) void k_row_count(const float4* __restrict__ re
                                                    uint32_t* __restrict__ row_count) {
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= m) return;
-    uint32_t h = 0;
-    if (tiles[o] > 0) {
-        const float4 q3 = rec[4 * o + 3];
-        h = (__float_as_uint(q3.y) >> 16) - (__float_as_uint(q3.x) >> 16);
-    }
-    row_count[o] = h;
+    row_count[o] = tiles[o] > 0 ? rect_rows(rec[4 * o + 3]) : 0u;
 }
 
 // One thread per (view, Gaussian): the column span of each of its tile rows
 // (the rectangle's columns, or the ellipse's span of that row), recorded as
 // the unsorted index of the row's first tile and its first column, with the
-// Gaussian's depth bits.  The spans are the ones the
-// projection counted (same function of the same record values).
+// Gaussian's depth bits.  The spans are the ones the projection counted (same
+// function of the same record values).  Also writes the (view, Gaussian)'s
+// key for the depth sort.
 __global__ __launch_bounds__(256) void k_rows(const float4* __restrict__ rec,
                                               const uint32_t* __restrict__ tiles,
                                               const uint32_t* __restrict__ offsets,
                                               const uint32_t* __restrict__ row_offsets, int64_t n,
                                               int64_t m, EmitGeom geo, int64_t row_capacity,
-                                              uint4* __restrict__ rows, uint32_t* __restrict__ status) {
+                                              uint4* __restrict__ rows, uint32_t* __restrict__ status,
+                                              uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval) {
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= m || tiles[o] == 0) return;
+    if (o >= m) return;
     const int v = (int)(o / n);
     const float4* r = rec + 4 * o;
-    const float4 q0 = r[0], q1 = r[1], q3 = r[3];
+    const bool vis = tiles[o] != 0;
+    // depth key of the (view, Gaussian) for the depth sort
+    const float4 q3 = r[3];
+    dkey[o] = vis ? __float_as_uint(q3.z) >> (23 - geo.depth_bits[v]) : 0u;
+    dval[o] = (uint32_t)o;
+    if (!vis) return;
+    const float4 q0 = r[0], q1 = r[1];
     const uint32_t r0 = __float_as_uint(q3.x), r1 = __float_as_uint(q3.y);
     const int x0 = (int)(r0 & 0xFFFF), y0 = (int)(r0 >> 16), x1 = (int)(r1 & 0xFFFF), y1 = (int)(r1 >> 16);
     Ellipse e;
@@ -330,13 +394,16 @@ constexpr int kEmitG = 256;  // tile rows per workgroup
 
 // A workgroup owns kEmitG consecutive row slots.  Their first indices, tile
 // bases and depth codes are staged in LDS; the workgroup's intersections
-// [rows[r0].first, rows[r0 + kEmitG].first) are then written by consecutive
-// threads (coalesced, balanced however unequal the rows are), each finding
-// its row by binary search over the staged first indices.
+// [rows[r0].first, rows[r0 + kEmitG].first) are then produced by consecutive
+// threads (balanced however unequal the rows are), each finding its row by
+// binary search over the staged first indices.  Each key goes to its
+// Gaussian's depth-order position: the unsorted index plus the Gaussian's
+// shift, so that the keys of a view are laid out by (depth bits, Gaussian id).
 __global__ __launch_bounds__(kEmitG) void k_emit(const float4* __restrict__ rec,
                                                  const uint4* __restrict__ rows,
                                                  const uint32_t* __restrict__ row_offsets,
-                                                 const uint32_t* __restrict__ offsets, int64_t n,
+                                                 const uint32_t* __restrict__ offsets,
+                                                 const uint32_t* __restrict__ dshift, int64_t n,
                                                  int64_t m, EmitGeom geo, int64_t capacity,
                                                  int64_t row_capacity, uint32_t* __restrict__ keys,
                                                  uint32_t* __restrict__ vals) {
@@ -344,6 +411,7 @@ __global__ __launch_bounds__(kEmitG) void k_emit(const float4* __restrict__ rec,
     __shared__ uint32_t s_tile[kEmitG];   // tile index (within the view) of the row's first tile
     __shared__ uint32_t s_dk[kEmitG];     // depth bits
     __shared__ uint32_t s_gid[kEmitG];
+    __shared__ uint32_t s_sh[kEmitG];     // depth-order position minus unsorted index
     __shared__ uint8_t s_D[kEmitG];
     const uint64_t kc = min((uint64_t)offsets[m], (uint64_t)capacity);
     const uint64_t rc = min((uint64_t)row_offsets[m], (uint64_t)row_capacity);
@@ -360,10 +428,11 @@ __global__ __launch_bounds__(kEmitG) void k_emit(const float4* __restrict__ rec,
         s_tile[t] = (row.z >> 16) * (uint32_t)geo.tiles_x[v] + (row.z & 0xFFFF);
         s_dk[t] = row.w;
         s_gid[t] = (uint32_t)(o - (int64_t)v * n);
+        s_sh[t] = dshift[o];
         s_D[t] = (uint8_t)D;
     } else {
         s_off[t] = (uint32_t)kc;
-        s_tile[t] = 0; s_dk[t] = 0; s_gid[t] = 0; s_D[t] = 0;
+        s_tile[t] = 0; s_dk[t] = 0; s_gid[t] = 0; s_sh[t] = 0; s_D[t] = 0;
     }
     if (t == 0) s_off[kEmitG] = r0 + kEmitG < rc ? (uint32_t)min((uint64_t)rows[r0 + kEmitG].x, kc) : (uint32_t)kc;
     __syncthreads();
@@ -375,8 +444,11 @@ __global__ __launch_bounds__(kEmitG) void k_emit(const float4* __restrict__ rec,
             if (s_off[mid] <= i) lo = mid; else hi = mid - 1;
         }
         const uint32_t tile = s_tile[lo] + (uint32_t)(i - s_off[lo]);
-        keys[i] = (tile << s_D[lo]) | s_dk[lo];
-        vals[i] = s_gid[lo];
+        const uint32_t pos = (uint32_t)i + s_sh[lo];
+        if ((uint64_t)pos < kc) {
+            keys[pos] = (tile << s_D[lo]) | s_dk[lo];
+            vals[pos] = s_gid[lo];
+        }
     }
 }
 
@@ -404,14 +476,19 @@ constexpr uint32_t kLbSpinLimit = 1u << 20;
 
 struct SortWs {
     uint32_t* dcount;   // [n_views][kPasses][kDigits] digit totals (cleared by the table kernel)
-    uint32_t* dstart;   // [n_views][kPasses][kDigits] first global position of each digit
     uint64_t* agg;      // [kPasses][max_chunks][kDigits] kLbAggregate | chunk count
     uint64_t* pre;      // [kPasses][max_chunks][kDigits] kLbPrefix | inclusive prefix
     uint64_t* gagg;     // [kPasses][max_groups][kDigits] kLbAggregate | group count
     uint32_t* gdone;    // [kPasses][max_groups] chunks of the group that have published
     int64_t max_chunks;
     int64_t max_groups;
+    int32_t passes;                  // digits sorted (1..kPasses), least significant first
+    int32_t shift0[GS_MAX_VIEWS];    // bit position of each view's first digit
 };
+
+// Digit of `key` for a pass whose digit starts at bit `shift` (bits past 31
+// read as zero).
+GS_DEV uint32_t digit_at(uint32_t key, int shift) { return shift < 32 ? (key >> shift) & 0xFFu : 0u; }
 
 static SortWs carve_sort(void* base, int n_views, int64_t mc) {
     SortWs S;
@@ -419,8 +496,6 @@ static SortWs carve_sort(void* base, int n_views, int64_t mc) {
     const size_t nd = (size_t)n_views * kPasses * kDigits;
     char* p = (char*)base;
     S.dcount = (uint32_t*)p;
-    p += align_up(4 * nd);
-    S.dstart = (uint32_t*)p;
     p += align_up(4 * nd);
     S.agg = (uint64_t*)p;
     p += align_up(8 * (size_t)(kPasses * mc * kDigits));
@@ -431,6 +506,8 @@ static SortWs carve_sort(void* base, int n_views, int64_t mc) {
     S.gdone = (uint32_t*)p;
     S.max_chunks = mc;
     S.max_groups = mg;
+    S.passes = kPasses;
+    for (int v = 0; v < GS_MAX_VIEWS; ++v) S.shift0[v] = 0;
     return S;
 }
 
@@ -447,6 +524,7 @@ GS_DEV uint32_t group_slot(const uint32_t* table, int v, uint32_t c) {
 // the view's when the view changes and at the end (few workgroups, so each
 // total takes few global atomics).  Each chunk's look-back words, and its
 // group's if it is the group's first chunk, are cleared for all passes.
+template <int ITEMS>
 __global__ __launch_bounds__(kSortThreads) void k_digit_hist(const uint32_t* __restrict__ keys,
                                                              const uint32_t* __restrict__ table,
                                                              int n_views, SortWs S) {
@@ -472,22 +550,22 @@ __global__ __launch_bounds__(kSortThreads) void k_digit_hist(const uint32_t* __r
                     x += cnt[j][p][t];
                     cnt[j][p][t] = 0u;
                 }
-                if (x) atomicAdd(&S.dcount[(cur * kPasses + p) * kDigits + t], x);
+                if (x && p < S.passes) atomicAdd(&S.dcount[(cur * kPasses + p) * kDigits + t], x);
             }
             __syncthreads();
         }
         cur = v;
         const uint32_t seg_e = table[4 * v + 1];
-        const uint32_t start = table[4 * v] + c * kChunk;
-        uint32_t k[kSortItems];
+        const uint32_t start = table[4 * v] + c * (ITEMS * kSortThreads);
+        uint32_t k[ITEMS];
 #pragma unroll
-        for (int i = 0; i < kSortItems; ++i) {
+        for (int i = 0; i < ITEMS; ++i) {
             const uint32_t idx = start + i * kSortThreads + t;
             k[i] = idx < seg_e ? keys[idx] : 0u;
         }
         const uint32_t gs = group_slot(table, v, c);
-#pragma unroll
-        for (int p = 0; p < kPasses; ++p) {
+        const int sh0 = S.shift0[v];
+        for (int p = 0; p < S.passes; ++p) {
             S.agg[((int64_t)p * S.max_chunks + b) * kDigits + t] = 0ull;
             S.pre[((int64_t)p * S.max_chunks + b) * kDigits + t] = 0ull;
             if (c % kGroup == 0) {
@@ -501,15 +579,16 @@ __global__ __launch_bounds__(kSortThreads) void k_digit_hist(const uint32_t* __r
         const int lane = t % kWave;
         const uint64_t above = lane == kWave - 1 ? 0ull : (~0ull << (lane + 1));
 #pragma unroll
-        for (int i = 0; i < kSortItems; ++i) {
+        for (int i = 0; i < ITEMS; ++i) {
             const uint32_t idx = start + i * kSortThreads + t;
             const bool valid = idx < seg_e;
             const uint64_t vmask = __ballot(valid);
             const uint32_t prev = __shfl_up(k[i], 1);
 #pragma unroll
             for (int p = 0; p < kPasses; ++p) {
-                const uint32_t dg = (k[i] >> (8 * p)) & 0xFF;
-                const bool head = valid && (lane == 0 || ((prev >> (8 * p)) & 0xFF) != dg);
+                if (p >= S.passes) break;
+                const uint32_t dg = digit_at(k[i], sh0 + 8 * p);
+                const bool head = valid && (lane == 0 || digit_at(prev, sh0 + 8 * p) != dg);
                 const uint64_t heads = __ballot(head) | ~vmask;   // invalid lanes end runs
                 if (head) {
                     const uint64_t nxt = heads & above;
@@ -526,24 +605,9 @@ __global__ __launch_bounds__(kSortThreads) void k_digit_hist(const uint32_t* __r
             uint32_t x = 0;
 #pragma unroll
             for (int j = 0; j < NW; ++j) x += cnt[j][p][t];
-            if (x) atomicAdd(&S.dcount[(cur * kPasses + p) * kDigits + t], x);
+            if (x && p < S.passes) atomicAdd(&S.dcount[(cur * kPasses + p) * kDigits + t], x);
         }
     }
-}
-
-// Global position of each pass's first key of each digit: the view's segment
-// start plus the exclusive scan of the digit totals.  One workgroup per
-// (view, pass).
-__global__ __launch_bounds__(kDigits) void k_digit_start(const uint32_t* __restrict__ table,
-                                                         const uint32_t* __restrict__ dcount,
-                                                         uint32_t* __restrict__ dstart) {
-    __shared__ uint64_t lds[kDigits / kWave];
-    const int vp = blockIdx.x;
-    const int v = vp / kPasses;
-    const uint32_t x = dcount[vp * kDigits + threadIdx.x];
-    uint64_t tot;
-    const uint64_t inc = block_scan_u64(x, lds, &tot);
-    dstart[vp * kDigits + threadIdx.x] = table[4 * v] + (uint32_t)(inc - x);
 }
 
 GS_DEV uint64_t lanemask_lt() {
@@ -576,7 +640,7 @@ GS_DEV uint64_t lb_wait(const uint64_t* p, uint32_t* status) {
 
 constexpr int kLbGroupWindow = 8;
 
-// One stable radix pass over a chunk of kChunk keys; chunk b is workgroup b.
+// One stable radix pass over a chunk of 256 ITEMS keys; chunk b is workgroup b.
 // Workgroups start in index order, and each publishes its per-digit counts
 // before it waits on anything, so every wait of the look-back is on a chunk
 // that has started and will publish; a spin limit bounds the waits all the
@@ -599,45 +663,49 @@ constexpr int kLbGroupWindow = 8;
 // groups, stopping early at the published inclusive prefix of a group's last
 // chunk.
 // At most 128 VGPRs, so that four workgroups (the LDS limit) fit on a CU.
+template <int ITEMS>
 __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_onesweep(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
     const uint32_t* __restrict__ table, int n_views, int pass, SortWs S,
     uint32_t* __restrict__ status) {
     constexpr int NW = kSortThreads / kWave;
-    constexpr int PER_WAVE = kChunk / NW;
+    constexpr int CHUNK = ITEMS * kSortThreads;
+    constexpr int PER_WAVE = CHUNK / NW;
     __shared__ uint32_t gbase[kDigits];   // global destination of the chunk's first key of digit d
     __shared__ uint32_t lstart[kDigits];  // chunk-local start of digit d
     __shared__ uint32_t wcnt[NW][kDigits];
-    __shared__ uint32_t s_k[kChunk];
-    __shared__ uint32_t s_v[kChunk];
+    __shared__ uint32_t s_k[CHUNK];
+    __shared__ uint32_t s_v[CHUNK];
     __shared__ uint64_t s_scan[NW];
     __shared__ uint32_t s_last;
     const uint32_t b = blockIdx.x;
     int v;
     uint32_t c;
     if (!chunk_of(table, n_views, b, &v, &c)) return;
-    const int shift = 8 * pass;
+    const int shift = S.shift0[v] + 8 * pass;
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
 #pragma unroll
     for (int j = 0; j < NW; ++j) wcnt[j][threadIdx.x] = 0u;
     const uint32_t seg_e = table[4 * v + 1];
-    const uint32_t start = table[4 * v] + c * kChunk;
-    const uint32_t n_here = min((uint32_t)kChunk, seg_e - start);
-    uint32_t k[kSortItems], val[kSortItems], rank[kSortItems];
+    const uint32_t start = table[4 * v] + c * CHUNK;
+    const uint32_t n_here = min((uint32_t)CHUNK, seg_e - start);
+    uint32_t k[ITEMS], val[ITEMS], rank[ITEMS];
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i) {
+    for (int i = 0; i < ITEMS; ++i) {
         const uint32_t idx = start + w * PER_WAVE + i * kWave + lane;
         k[i] = idx < seg_e ? keys_in[idx] : 0u;
         val[i] = idx < seg_e ? vals_in[idx] : 0u;
     }
     const uint64_t lt = lanemask_lt();
+    // the view's total of this thread's digit (its start is their exclusive scan)
+    const uint32_t dtot = S.dcount[(v * kPasses + pass) * kDigits + threadIdx.x];
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i) {
+    for (int i = 0; i < ITEMS; ++i) {
         const uint32_t idx = start + w * PER_WAVE + i * kWave + lane;
         const bool valid = idx < seg_e;
-        const uint32_t d = (k[i] >> shift) & 0xFF;
+        const uint32_t d = digit_at(k[i], shift);
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int bit = 0; bit < 8; ++bit) {
@@ -667,11 +735,16 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4)
         const uint32_t gsize = min((uint32_t)kGroup, nc - gi * kGroup);
         s_last = atomicAdd(&S.gdone[pass * S.max_groups + group_slot(table, v, c)], 1u) + 1 == gsize;
     }
+    uint32_t dbase;
     {
-        // digit-major exclusive scan over (digit, wavefront)
+        // digit-major exclusive scan over (digit, wavefront), and in the high
+        // half the exclusive scan of the view's digit totals (no carry: the
+        // chunk's counts sum to at most CHUNK)
         uint64_t tot;
-        const uint64_t inc = block_scan_u64(total, s_scan, &tot);
-        uint32_t run = (uint32_t)(inc - total);
+        const uint64_t both = ((uint64_t)dtot << 32) | total;
+        const uint64_t inc = block_scan_u64(both, s_scan, &tot);
+        dbase = table[4 * v] + (uint32_t)((inc - both) >> 32);
+        uint32_t run = (uint32_t)(inc - both);
         lstart[d] = run;
 #pragma unroll
         for (int j = 0; j < NW; ++j) {
@@ -682,10 +755,10 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4)
     }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i) {
+    for (int i = 0; i < ITEMS; ++i) {
         const uint32_t idx = start + w * PER_WAVE + i * kWave + lane;
         if (idx < seg_e) {
-            const uint32_t pos = wcnt[w][(k[i] >> shift) & 0xFF] + rank[i];
+            const uint32_t pos = wcnt[w][digit_at(k[i], shift)] + rank[i];
             s_k[pos] = k[i];
             s_v[pos] = val[i];
         }
@@ -759,34 +832,33 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4)
         }
         lb_store(&S.pre[cw + (int64_t)b * kDigits + d], kLbPrefix | (excl + total));
     }
-    gbase[d] = S.dstart[(v * kPasses + pass) * kDigits + d] + excl;
+    gbase[d] = dbase + excl;
     __syncthreads();
     for (uint32_t j = threadIdx.x; j < n_here; j += kSortThreads) {
         const uint32_t key = s_k[j];
-        const uint32_t dg = (key >> shift) & 0xFF;
+        const uint32_t dg = digit_at(key, shift);
         const uint32_t dst = gbase[dg] + (j - lstart[dg]);
         keys_out[dst] = key;
         vals_out[dst] = s_v[j];
     }
 }
 
-// Stable sort of each view's segment of (keys, vals), in place through
-// (ktmp, vtmp).  `table` describes the segments and chunks; dcount and the
-// tickets must be zero.
+// Stable sort of each view's segment of (keys, vals) by S.passes 8-bit digits
+// starting at bit S.shift0[view], through (ktmp, vtmp).  `table` describes the
+// segments and chunks; dcount must be zero.
+template <int ITEMS>
 static int radix_sort_views(uint32_t* keys, uint32_t* vals, uint32_t* ktmp, uint32_t* vtmp,
                             const uint32_t* table, int n_views, const SortWs& S, uint32_t* status,
                             hipStream_t s) {
     int rc;
     const unsigned hgrid = (unsigned)std::min<int64_t>(S.max_chunks, kHistBlocks);
-    hipLaunchKernelGGL(k_digit_hist, dim3(hgrid), dim3(kSortThreads), 0, s, keys, table, n_views, S);
+    hipLaunchKernelGGL(k_digit_hist<ITEMS>, dim3(hgrid), dim3(kSortThreads), 0, s, keys, table, n_views, S);
     if ((rc = check_launch("digit_hist")) != GS_OK) return rc;
-    hipLaunchKernelGGL(k_digit_start, dim3((unsigned)(n_views * kPasses)), dim3(kDigits), 0, s, table,
-                       S.dcount, S.dstart);
-    if ((rc = check_launch("digit_start")) != GS_OK) return rc;
-    // an even number of passes leaves the result in keys / vals
+    // an even number of passes leaves the result in keys / vals, an odd
+    // number in ktmp / vtmp
     uint32_t *kin = keys, *vin = vals, *kout = ktmp, *vout = vtmp;
-    for (int pass = 0; pass < kPasses; ++pass) {
-        hipLaunchKernelGGL(k_onesweep, dim3((unsigned)S.max_chunks), dim3(kSortThreads), 0, s, kin, vin, kout,
+    for (int pass = 0; pass < S.passes; ++pass) {
+        hipLaunchKernelGGL(k_onesweep<ITEMS>, dim3((unsigned)S.max_chunks), dim3(kSortThreads), 0, s, kin, vin, kout,
                            vout, table, n_views, pass, S, status);
         if ((rc = check_launch("onesweep")) != GS_OK) return rc;
         std::swap(kin, kout);
@@ -805,23 +877,25 @@ struct RangeGeom {
     int32_t tile_base[GS_MAX_VIEWS + 1];
 };
 
-__global__ __launch_bounds__(256) void k_ranges_empty(const uint32_t* __restrict__ table, int n_views,
-                                                      RangeGeom geo, uint32_t* __restrict__ ranges) {
-    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gt >= geo.tile_base[n_views]) return;
-    int v = 0;
-    for (int i = 1; i < n_views; ++i)
-        if (gt >= geo.tile_base[i]) v = i;
-    const uint32_t b = table[4 * v], e = table[4 * v + 1];
-    if (b == e) reinterpret_cast<uint2*>(ranges)[gt] = make_uint2(b, b);
-}
-
 // One thread per sorted position j: tile boundaries -> ranges (lower-bound
-// semantics, empty tiles get start = end = insertion point).
+// semantics, empty tiles get start = end = insertion point).  Workgroups past
+// the first ceil(capacity / 256) handle the tiles of views without any
+// intersection, one thread per tile.
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ keys,
                                                 const uint32_t* __restrict__ table, int n_views,
                                                 RangeGeom geo, int64_t capacity,
                                                 uint32_t* __restrict__ ranges) {
+    const int64_t cap_blocks = (capacity + 255) / 256;
+    if ((int64_t)blockIdx.x >= cap_blocks) {
+        const int64_t gt = ((int64_t)blockIdx.x - cap_blocks) * blockDim.x + threadIdx.x;
+        if (gt >= geo.tile_base[n_views]) return;
+        int v = 0;
+        for (int i = 1; i < n_views; ++i)
+            if (gt >= geo.tile_base[i]) v = i;
+        const uint32_t b = table[4 * v], e = table[4 * v + 1];
+        if (b == e) reinterpret_cast<uint2*>(ranges)[gt] = make_uint2(b, b);
+        return;
+    }
     const int64_t j64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j64 >= capacity) return;
     const uint32_t j = (uint32_t)j64;
@@ -912,7 +986,7 @@ int sort_pairs(uint32_t* keys, uint32_t* vals, int64_t count, void* scratch, hip
     hipLaunchKernelGGL(k_single_table, dim3(1), dim3(256), 0, s, P.table, count, S.dcount, P.status);
     int rc = check_launch("sort_table");
     if (rc != GS_OK) return rc;
-    return radix_sort_views(keys, vals, P.ktmp, P.vtmp, P.table, 1, S, P.status, s);
+    return radix_sort_views<kSortItems>(keys, vals, P.ktmp, P.vtmp, P.table, 1, S, P.status, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -929,12 +1003,25 @@ int launch_bin_sort(const gs_splats& sp, int64_t n, const gs_layout& L, const gs
     }
     const int V = L.n_views;
     const int64_t m = (int64_t)V * n;
-    const SortWs S = carve_sort(W.sort_words, V, W.max_chunks);
+    // tile sort: the keys' tile bits, from bit D of each view up
+    SortWs S = carve_sort(W.sort_words, V, W.max_chunks);
+    int tile_bits = 1, max_d = 1;
+    for (int v = 0; v < V; ++v) {
+        S.shift0[v] = L.depth_bits[v];
+        tile_bits = std::max(tile_bits, 32 - L.depth_bits[v]);
+        max_d = std::max(max_d, L.depth_bits[v]);
+    }
+    S.passes = std::min(kPasses, (tile_bits + 7) / 8);
+    // depth sort: the depth bits of each (view, Gaussian)
+    SortWs SD = carve_sort(W.dsort_words, V, W.max_dchunks);
+    SD.passes = std::min(kPasses, (max_d + 7) / 8);
     int rc;
-    if ((rc = launch_fill_u32(b.status, 0u, 1, s)) != GS_OK) return rc;
-    if ((rc = scan_exclusive(sp.tiles, m, b.offsets, W.block_sums, b.status, s)) != GS_OK) return rc;
+    // offsets (clearing the status word first) and row offsets
+    if ((rc = scan_exclusive(sp.tiles, m, b.offsets, W.block_sums, b.status, s, nullptr, nullptr, b.status)) !=
+        GS_OK)
+        return rc;
     hipLaunchKernelGGL(k_view_table, dim3(1), dim3(256), 0, s, b.offsets, n, V, b.capacity, W.table,
-                       b.status, S.dcount);
+                       b.status, S.dcount, W.dtable, SD.dcount);
     if ((rc = check_launch("view_table")) != GS_OK) return rc;
     EmitGeom eg;
     RangeGeom rg;
@@ -959,27 +1046,37 @@ int launch_bin_sort(const gs_splats& sp, int64_t n, const gs_layout& L, const gs
     if ((rc = scan_exclusive(W.row_count, m, b.row_offsets, W.block_sums, nullptr, s)) != GS_OK) return rc;
     if (m > 0) {
         hipLaunchKernelGGL(k_rows, dim3(gm), dim3(256), 0, s, rec, sp.tiles, b.offsets, b.row_offsets, n, m,
-                           eg, b.row_capacity, rows, b.status);
+                           eg, b.row_capacity, rows, b.status, W.dkey, W.dval);
         if ((rc = check_launch("rows")) != GS_OK) return rc;
-        if (b.row_capacity > 0) {
-            hipLaunchKernelGGL(k_emit, dim3((unsigned)((b.row_capacity + kEmitG - 1) / kEmitG)), dim3(kEmitG),
-                               0, s, rec, rows, b.row_offsets, b.offsets, n, m, eg, b.capacity,
-                               b.row_capacity, b.keys, b.vals);
-            if ((rc = check_launch("emit_keys")) != GS_OK) return rc;
-        }
+        // depth order: a stable sort of the (view, Gaussian)s by depth bits,
+        // then each one's first position in that order
+        if ((rc = radix_sort_views<kDepthItems>(W.dkey, W.dval, W.dkey_tmp, W.dval_tmp, W.dtable, V, SD, b.status, s)) !=
+            GS_OK)
+            return rc;
+        // scan of the tile counts in depth order, stored per (view, Gaussian)
+        // as its depth-order position minus its unsorted index
+        const uint32_t* perm = SD.passes % 2 == 0 ? W.dval : W.dval_tmp;
+        if ((rc = scan_exclusive(sp.tiles, m, W.dshift, W.block_sums, nullptr, s, perm, b.offsets)) != GS_OK)
+            return rc;
     }
-    if ((rc = radix_sort_views(b.keys, b.vals, W.keys_tmp, W.vals_tmp, W.table, V, S, b.status, s)) != GS_OK)
-        return rc;
+    // keys in depth order, then a stable sort by tile; the emit goes to the
+    // buffer that leaves the sorted keys in bins.keys
+    uint32_t* ek = S.passes % 2 == 0 ? b.keys : W.keys_tmp;
+    uint32_t* ev = S.passes % 2 == 0 ? b.vals : W.vals_tmp;
+    uint32_t* ok = S.passes % 2 == 0 ? W.keys_tmp : b.keys;
+    uint32_t* ov = S.passes % 2 == 0 ? W.vals_tmp : b.vals;
+    if (m > 0 && b.row_capacity > 0) {
+        hipLaunchKernelGGL(k_emit, dim3((unsigned)((b.row_capacity + kEmitG - 1) / kEmitG)), dim3(kEmitG), 0, s,
+                           rec, rows, b.row_offsets, b.offsets, W.dshift, n, m, eg, b.capacity, b.row_capacity,
+                           ek, ev);
+        if ((rc = check_launch("emit_keys")) != GS_OK) return rc;
+    }
+    if ((rc = radix_sort_views<kSortItems>(ek, ev, ok, ov, W.table, V, S, b.status, s)) != GS_OK) return rc;
     const int64_t nt = L.tile_base[V];
-    hipLaunchKernelGGL(k_ranges_empty, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, W.table, V,
-                       rg, b.ranges);
-    if ((rc = check_launch("ranges_empty")) != GS_OK) return rc;
-    if (b.capacity > 0) {
-        hipLaunchKernelGGL(k_ranges, dim3((unsigned)((b.capacity + 255) / 256)), dim3(256), 0, s,
-                           b.keys, W.table, V, rg, b.capacity, b.ranges);
-        if ((rc = check_launch("ranges")) != GS_OK) return rc;
-    }
-    return GS_OK;
+    const int64_t rgrid = (b.capacity + 255) / 256 + (nt + 255) / 256;
+    hipLaunchKernelGGL(k_ranges, dim3((unsigned)rgrid), dim3(256), 0, s, b.keys, W.table, V, rg, b.capacity,
+                       b.ranges);
+    return check_launch("ranges");
 }
 
 }  // namespace gs

@@ -29,8 +29,12 @@ FP32_PEAK_TFLOPS = 157.3
 # Algorithmic work per unit of each stage (the same figures are derived in the
 # design notes): bytes that must cross HBM, or flops that must be executed.
 PROJ_BYTES_G = 308           # parameters 240 read; splat record 64 + tile count 4 written
-SORT_BYTES_G = 28            # counts, offsets, rectangle/depth word per (view, Gaussian)
-SORT_BYTES_K = 80            # emit 8 w; digit histogram 4 r; 4 passes x (8 r + 8 w); ranges 4 r
+SORT_BYTES_G = 96            # per (view, Gaussian): count/offset/row-count scans 16; depth key and
+                             # index 8 w; depth histogram 4 r; 3 depth passes x 16; depth-order
+                             # scan 16 (index, count, offset r; shift w); emit reads the shift 4
+SORT_BYTES_ROW = 32          # per tile-row slot: written 16, read by the emit 16
+SORT_BYTES_K = 48            # per intersection: emit 8 w; tile histogram 4 r; 2 passes x (8 r + 8 w);
+                             # ranges 4 r
 FWD_FLOP_EVAL = 14           # power, G, alpha, thresholds per evaluated pixel-Gaussian pair
 FWD_FLOP_COMP = 9            # colour and transmittance update per composited pair
 BWD_BYTES_TRAVERSED = 40     # Gaussian id 4 + splat 36 read per traversed entry
@@ -197,7 +201,8 @@ def main():
             gx = (W + 15) // 16
             tile_of_px = torch.arange(H * W, device=dev)
             tile_of_px = (tile_of_px // W // 16) * gx + (tile_of_px % W) // 16
-            acc = dict(K=0, trav_bwd=0, eval_bwd=0, contrib=0, eval_fwd=0, trav_fwd=0, visible=0, flagged=0)
+            acc = dict(K=0, trav_bwd=0, eval_bwd=0, contrib=0, eval_fwd=0, trav_fwd=0, visible=0, flagged=0,
+                       rows=0)
             for i in range(args.steps):
                 vi = order[(args.warmup + i) % ncam]
                 vd = vptr(vi)
@@ -209,6 +214,7 @@ def main():
                 per_tile.scatter_reduce_(0, tile_of_px, last, reduce="amax")
                 ts = rframe.tile_stats.to(torch.int64)
                 acc["K"] += rframe.intersections()
+                acc["rows"] += int(rframe.row_offsets[-1].item())
                 acc["visible"] += int((rframe.tiles != 0).sum().item())
                 acc["trav_bwd"] += int(per_tile.sum().item())
                 acc["eval_bwd"] += int(last.sum().item())
@@ -273,7 +279,8 @@ def main():
         vis = counts["visible"]
         per_stage = {
             "project": hbm("project", PROJ_BYTES_G * n, "project"),
-            "bin_sort": hbm("bin_sort", SORT_BYTES_G * n + SORT_BYTES_K * counts["K"], "bin_sort"),
+            "bin_sort": hbm("bin_sort", SORT_BYTES_G * n + SORT_BYTES_ROW * counts["rows"]
+                            + SORT_BYTES_K * counts["K"], "bin_sort"),
             "rasterize_fwd": alu("rasterize_fwd",
                                  FWD_FLOP_EVAL * counts["eval_fwd"] + FWD_FLOP_COMP * counts["contrib"],
                                  68 * counts["trav_fwd"] + 20 * P_px + 8 * ntiles, "rasterize_fwd"),

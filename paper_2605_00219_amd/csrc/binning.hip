@@ -24,6 +24,7 @@ constexpr int kSortItems = 16;
 constexpr int kChunk = kSortThreads * kSortItems;      // 4096 keys per radix chunk
 constexpr int kDepthItems = 4;                          // the depth sort of (view, Gaussian)s:
 constexpr int kDepthChunk = kSortThreads * kDepthItems; // 1024-key chunks
+constexpr int64_t kDepthFirstRatio = 12;                // capacity / (views x n) to sort by depth first
 constexpr int kDigits = 256;
 constexpr int kPasses = 4;
 constexpr int kHistBlocks = 512;                        // workgroups of the histogram pass
@@ -428,7 +429,7 @@ __global__ __launch_bounds__(kEmitG) void k_emit(const float4* __restrict__ rec,
         s_tile[t] = (row.z >> 16) * (uint32_t)geo.tiles_x[v] + (row.z & 0xFFFF);
         s_dk[t] = row.w;
         s_gid[t] = (uint32_t)(o - (int64_t)v * n);
-        s_sh[t] = dshift[o];
+        s_sh[t] = dshift ? dshift[o] : 0u;
         s_D[t] = (uint8_t)D;
     } else {
         s_off[t] = (uint32_t)kc;
@@ -444,7 +445,7 @@ __global__ __launch_bounds__(kEmitG) void k_emit(const float4* __restrict__ rec,
             if (s_off[mid] <= i) lo = mid; else hi = mid - 1;
         }
         const uint32_t tile = s_tile[lo] + (uint32_t)(i - s_off[lo]);
-        const uint32_t pos = (uint32_t)i + s_sh[lo];
+        const uint32_t pos = (uint32_t)i + s_sh[lo];   // shift 0 without the depth order
         if ((uint64_t)pos < kc) {
             keys[pos] = (tile << s_D[lo]) | s_dk[lo];
             vals[pos] = s_gid[lo];
@@ -1003,15 +1004,20 @@ int launch_bin_sort(const gs_splats& sp, int64_t n, const gs_layout& L, const gs
     }
     const int V = L.n_views;
     const int64_t m = (int64_t)V * n;
-    // tile sort: the keys' tile bits, from bit D of each view up
+    // With many intersections per (view, Gaussian) the keys are emitted in
+    // depth order (a sort of the (view, Gaussian)s by their depth bits) and
+    // then sorted by their tile bits only; with few, the depth sort costs more
+    // than the two passes it saves, and all 32 bits are sorted directly.  Both
+    // give the same order: (tile, depth bits, Gaussian id).
+    const bool depth_first = m > 0 && b.capacity >= kDepthFirstRatio * m;
     SortWs S = carve_sort(W.sort_words, V, W.max_chunks);
     int tile_bits = 1, max_d = 1;
     for (int v = 0; v < V; ++v) {
-        S.shift0[v] = L.depth_bits[v];
+        S.shift0[v] = depth_first ? L.depth_bits[v] : 0;
         tile_bits = std::max(tile_bits, 32 - L.depth_bits[v]);
         max_d = std::max(max_d, L.depth_bits[v]);
     }
-    S.passes = std::min(kPasses, (tile_bits + 7) / 8);
+    S.passes = depth_first ? std::min(kPasses, (tile_bits + 7) / 8) : kPasses;
     // depth sort: the depth bits of each (view, Gaussian)
     SortWs SD = carve_sort(W.dsort_words, V, W.max_dchunks);
     SD.passes = std::min(kPasses, (max_d + 7) / 8);
@@ -1048,6 +1054,8 @@ int launch_bin_sort(const gs_splats& sp, int64_t n, const gs_layout& L, const gs
         hipLaunchKernelGGL(k_rows, dim3(gm), dim3(256), 0, s, rec, sp.tiles, b.offsets, b.row_offsets, n, m,
                            eg, b.row_capacity, rows, b.status, W.dkey, W.dval);
         if ((rc = check_launch("rows")) != GS_OK) return rc;
+    }
+    if (depth_first) {
         // depth order: a stable sort of the (view, Gaussian)s by depth bits,
         // then each one's first position in that order
         if ((rc = radix_sort_views<kDepthItems>(W.dkey, W.dval, W.dkey_tmp, W.dval_tmp, W.dtable, V, SD, b.status, s)) !=
@@ -1059,16 +1067,16 @@ int launch_bin_sort(const gs_splats& sp, int64_t n, const gs_layout& L, const gs
         if ((rc = scan_exclusive(sp.tiles, m, W.dshift, W.block_sums, nullptr, s, perm, b.offsets)) != GS_OK)
             return rc;
     }
-    // keys in depth order, then a stable sort by tile; the emit goes to the
-    // buffer that leaves the sorted keys in bins.keys
+    // keys (in depth order if depth_first), then the sort; the emit goes to
+    // the buffer that leaves the sorted keys in bins.keys
     uint32_t* ek = S.passes % 2 == 0 ? b.keys : W.keys_tmp;
     uint32_t* ev = S.passes % 2 == 0 ? b.vals : W.vals_tmp;
     uint32_t* ok = S.passes % 2 == 0 ? W.keys_tmp : b.keys;
     uint32_t* ov = S.passes % 2 == 0 ? W.vals_tmp : b.vals;
     if (m > 0 && b.row_capacity > 0) {
         hipLaunchKernelGGL(k_emit, dim3((unsigned)((b.row_capacity + kEmitG - 1) / kEmitG)), dim3(kEmitG), 0, s,
-                           rec, rows, b.row_offsets, b.offsets, W.dshift, n, m, eg, b.capacity, b.row_capacity,
-                           ek, ev);
+                           rec, rows, b.row_offsets, b.offsets, depth_first ? W.dshift : nullptr, n, m, eg,
+                           b.capacity, b.row_capacity, ek, ev);
         if ((rc = check_launch("emit_keys")) != GS_OK) return rc;
     }
     if ((rc = radix_sort_views<kSortItems>(ek, ev, ok, ov, W.table, V, S, b.status, s)) != GS_OK) return rc;

@@ -51,11 +51,18 @@ def _oracle_step(scene, target_scene, views, tile, lr=1e-3):
 
 
 @pytest.mark.parametrize("name", list(WL))
-def test_projection_and_binning_bit_exact(name):
+@pytest.mark.parametrize("order", ["direct", "depth_first"])
+def test_projection_and_binning_bit_exact(name, order):
+    """Both sort orders: all 32 key bits directly (few intersections per
+    Gaussian, the fitted capacity) and depth bits of the Gaussians first, then
+    tile bits (chosen when the capacity is at least 12 x views x n)."""
     scene, target_scene, views, tile = WL[name]
-    note(f"projection/binning parity {name}")
+    note(f"projection/binning parity {name} ({order})")
     ref = oracle.train_step(scene, views, tile, oracle.render(target_scene, views, tile), adam_step=False)
-    g = run_gpu_step(scene, views, tile)
+    cap = None if order == "direct" else 16 * len(views) * scene.n
+    if order == "direct":
+        assert int(ref.bins.offsets[-1]) * 1.25 + 1024 < 12 * len(views) * scene.n
+    g = run_gpu_step(scene, views, tile, capacity=cap)
     assert g["status"] == 0
     np.testing.assert_array_equal(g["tiles"], ref.proj.tiles)
     vis = ref.proj.tiles > 0

@@ -35,6 +35,10 @@ SORT_BYTES_G = 96            # per (view, Gaussian): count/offset/row-count scan
 SORT_BYTES_ROW = 32          # per tile-row slot: written 16, read by the emit 16
 SORT_BYTES_K = 48            # per intersection: emit 8 w; tile histogram 4 r; 2 passes x (8 r + 8 w);
                              # ranges 4 r
+# with few intersections per (view, Gaussian) all 32 key bits are sorted directly
+SORT_DIRECT_BYTES_G = 16     # count/offset/row-count scans
+SORT_DIRECT_BYTES_K = 80     # emit 8 w; histogram 4 r; 4 passes x (8 r + 8 w); ranges 4 r
+SORT_DEPTH_FIRST_RATIO = 12  # capacity / (views x n) from which the depth order is used
 FWD_FLOP_EVAL = 14           # power, G, alpha, thresholds per evaluated pixel-Gaussian pair
 FWD_FLOP_COMP = 9            # colour and transmittance update per composited pair
 BWD_BYTES_TRAVERSED = 40     # Gaussian id 4 + splat 36 read per traversed entry
@@ -229,7 +233,8 @@ def main():
             counts = {k: v / args.steps for k, v in acc.items()}
             log(f"per-step work: {counts}")
         out = dict(stage_ms=stage_ms, ips=ips, wall=wall, counts=counts, kmax=kmax,
-                   ntiles=frame.layout.total_tiles)
+                   ntiles=frame.layout.total_tiles,
+                   depth_first=frame.capacity >= SORT_DEPTH_FIRST_RATIO * n)
         del model, frame
         torch.cuda.empty_cache()
         return out
@@ -280,7 +285,9 @@ def main():
         per_stage = {
             "project": hbm("project", PROJ_BYTES_G * n, "project"),
             "bin_sort": hbm("bin_sort", SORT_BYTES_G * n + SORT_BYTES_ROW * counts["rows"]
-                            + SORT_BYTES_K * counts["K"], "bin_sort"),
+                            + SORT_BYTES_K * counts["K"] if res["depth_first"] else
+                            SORT_DIRECT_BYTES_G * n + SORT_BYTES_ROW * counts["rows"]
+                            + SORT_DIRECT_BYTES_K * counts["K"], "bin_sort"),
             "rasterize_fwd": alu("rasterize_fwd",
                                  FWD_FLOP_EVAL * counts["eval_fwd"] + FWD_FLOP_COMP * counts["contrib"],
                                  68 * counts["trav_fwd"] + 20 * P_px + 8 * ntiles, "rasterize_fwd"),

@@ -270,12 +270,16 @@ GS_DEV void sh_dir_grad(float x, float y, float z, const float w[16], float out[
     out[0] = gx; out[1] = gy; out[2] = gz;
 }
 
-GS_DEV float adam_one(float p, float g, float& m, float& v, float lr, float beta1, float beta2,
-                      float eps, float bc1, float bc2s) {
+// One Adam update (Kingma & Ba; the bias-corrected form of torch.optim.Adam):
+// step = lr / (1 - beta1^t), inv_bc2s = 1 / sqrt(1 - beta2^t), both computed
+// once per thread; the per-component square root and reciprocal are the
+// hardware's (about 1 ulp), which moves the update by a relative 1e-7.
+GS_DEV float adam_one(float p, float g, float& m, float& v, float step, float beta1, float beta2,
+                      float eps, float inv_bc2s) {
     m = beta1 * m + (1.0f - beta1) * g;
     v = beta2 * v + (1.0f - beta2) * (g * g);
-    const float denom = __builtin_sqrtf(v) / bc2s + eps;
-    return p - (lr / bc1) * (m / denom);
+    const float denom = __builtin_amdgcn_sqrtf(v) * inv_bc2s + eps;
+    return p - step * (m * __builtin_amdgcn_rcpf(denom));
 }
 
 __global__ __launch_bounds__(256) void k_project_bwd_adam(AdamArgs a) {
@@ -446,28 +450,47 @@ __global__ __launch_bounds__(256) void k_project_bwd_adam(AdamArgs a) {
     if (a.m) {
         const float bc1 = a.bias[0], bc2s = a.bias[1];
         const float b1 = a.beta1, b2 = a.beta2, eps = a.eps;
+        const float inv_bc2s = 1.0f / bc2s;
+        float step[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) step[k] = a.lr[k] / bc1;
         float4 P4[15];
         P4[0] = p0; P4[1] = p1; P4[2] = p2;
 #pragma unroll
         for (int q = 0; q < 12; ++q) P4[3 + q] = sh[q];
+        // the moments of kAdamBatch planes are loaded together, so a thread
+        // waits on memory three times rather than fifteen
+        constexpr int kAdamBatch = 5;
 #pragma unroll
-        for (int q = 0; q < 15; ++q) {
-            float4 mm = a.m[q * n + g], vv = a.v[q * n + g], pp = P4[q];
-            const float4 gg = G[q];
-            // parameter group of each component
-            int gr[4];
-            if (q == 0) { gr[0] = gr[1] = gr[2] = 0; gr[3] = 3; }
-            else if (q == 1) { gr[0] = gr[1] = gr[2] = 1; gr[3] = -1; }
-            else if (q == 2) { gr[0] = gr[1] = gr[2] = gr[3] = 2; }
-            else if (q == 3) { gr[0] = gr[1] = gr[2] = 4; gr[3] = 5; }
-            else { gr[0] = gr[1] = gr[2] = gr[3] = 5; }
-            if (gr[0] >= 0) pp.x = adam_one(pp.x, gg.x, mm.x, vv.x, a.lr[gr[0]], b1, b2, eps, bc1, bc2s);
-            if (gr[1] >= 0) pp.y = adam_one(pp.y, gg.y, mm.y, vv.y, a.lr[gr[1]], b1, b2, eps, bc1, bc2s);
-            if (gr[2] >= 0) pp.z = adam_one(pp.z, gg.z, mm.z, vv.z, a.lr[gr[2]], b1, b2, eps, bc1, bc2s);
-            if (gr[3] >= 0) pp.w = adam_one(pp.w, gg.w, mm.w, vv.w, a.lr[gr[3]], b1, b2, eps, bc1, bc2s);
-            a.params[q * n + g] = pp;
-            a.m[q * n + g] = mm;
-            a.v[q * n + g] = vv;
+        for (int q0 = 0; q0 < 15; q0 += kAdamBatch) {
+            float4 mm[kAdamBatch], vv[kAdamBatch];
+#pragma unroll
+            for (int j = 0; j < kAdamBatch; ++j) {
+                if (q0 + j >= 15) break;
+                mm[j] = a.m[(q0 + j) * n + g];
+                vv[j] = a.v[(q0 + j) * n + g];
+            }
+#pragma unroll
+            for (int j = 0; j < kAdamBatch; ++j) {
+                const int q = q0 + j;
+                if (q >= 15) break;
+                float4 pp = P4[q];
+                const float4 gg = G[q];
+                // parameter group of each component
+                int gr[4];
+                if (q == 0) { gr[0] = gr[1] = gr[2] = 0; gr[3] = 3; }
+                else if (q == 1) { gr[0] = gr[1] = gr[2] = 1; gr[3] = -1; }
+                else if (q == 2) { gr[0] = gr[1] = gr[2] = gr[3] = 2; }
+                else if (q == 3) { gr[0] = gr[1] = gr[2] = 4; gr[3] = 5; }
+                else { gr[0] = gr[1] = gr[2] = gr[3] = 5; }
+                if (gr[0] >= 0) pp.x = adam_one(pp.x, gg.x, mm[j].x, vv[j].x, step[gr[0]], b1, b2, eps, inv_bc2s);
+                if (gr[1] >= 0) pp.y = adam_one(pp.y, gg.y, mm[j].y, vv[j].y, step[gr[1]], b1, b2, eps, inv_bc2s);
+                if (gr[2] >= 0) pp.z = adam_one(pp.z, gg.z, mm[j].z, vv[j].z, step[gr[2]], b1, b2, eps, inv_bc2s);
+                if (gr[3] >= 0) pp.w = adam_one(pp.w, gg.w, mm[j].w, vv[j].w, step[gr[3]], b1, b2, eps, inv_bc2s);
+                a.params[q * n + g] = pp;
+                a.m[q * n + g] = mm[j];
+                a.v[q * n + g] = vv[j];
+            }
         }
     }
 }

@@ -1,0 +1,74 @@
+"""The plain workload at its full size, in the configuration bench.py times:
+300k Gaussians (means N(0,1), log-scales N(-4, 0.7)), one 1280x720 view,
+16x16 tiles, 2 pixels per lane, S = 64, the fitted capacity (so the binning
+takes its depth-first order and every sort pass runs in two rounds of
+workgroups).  Projection, keys, values and ranges are compared bit for bit in
+full; pixels and gradient records on a seeded sample of tiles, with the
+oracle restricted to those tiles."""
+import numpy as np
+import pytest
+
+import oracle
+import synthetic as S
+from gpu_common import note, run_gpu_step
+from helpers import exempt_gaussians, grad_close
+
+pytestmark = pytest.mark.gpu
+
+
+def test_plain_300k_1280x720_full_size():
+    w = S.workload_plain_300k()
+    views = w.views[:1]
+    scene = w.scene
+    W, H = 1280, 720
+    note("full size: 300k Gaussians, 1280x720, tile 16")
+    target = S.random_image(H, W, 4242).reshape(-1, 3)
+    g = run_gpu_step(scene, views, 16, target=target)
+    assert g["status"] == 0
+    pr = oracle.project(scene, views, 16)
+    bins = oracle.bin_sort(pr, views, 16)
+    K = int(bins.offsets[-1])
+    assert K > 4_000_000
+    assert g["frame"].capacity >= 12 * scene.n          # depth-first order
+    np.testing.assert_array_equal(g["tiles"], pr.tiles)
+    np.testing.assert_array_equal(g["offsets"], bins.offsets)
+    np.testing.assert_array_equal(g["keys"], bins.keys)
+    np.testing.assert_array_equal(g["vals"], bins.gid[bins.vals])
+    np.testing.assert_array_equal(g["ranges"], bins.ranges)
+    # a sample of tiles: pixels, last, T, then the backward's records
+    gx, gy = (W + 15) // 16, (H + 15) // 16
+    rng = np.random.default_rng(7)
+    sample = rng.choice(gx * gy, size=48, replace=False)
+    tmask = np.zeros(gx * gy, np.uint8)
+    tmask[sample] = 1
+    fwd = oracle.raster_fwd(pr, bins, views, 16, tile_mask=tmask)
+    pix_tile = (np.arange(W * H) // W // 16) * gx + (np.arange(W * H) % W) // 16
+    inside = tmask[pix_tile].astype(bool)
+    _, dLdC = oracle.l1(fwd.rgb, target, fragile=fwd.fragile)
+    ok = inside & (fwd.fragile == 0)
+    assert ok.sum() > 0.9 * inside.sum()
+    err = np.abs(g["image"] - fwd.rgb).max(axis=1)
+    assert err[ok].max() <= 1e-4, err[ok].max()
+    np.testing.assert_array_equal(g["last"][ok], fwd.last[ok])
+    assert np.abs(g["T"] - fwd.T)[ok].max() <= 1e-4
+    partials, _ = oracle.raster_bwd(pr, bins, views, 16, dLdC, tile_mask=tmask)
+    ex = exempt_gaussians(bins.ranges, bins.vals, bins.gid, views, 16, fwd.fragile & inside, scene.n)[0]
+    bit = lambda m, i: (m[i >> 5] >> (i & 31)) & 1
+    kept, quiet = [], []
+    for t in sample:
+        s, stop = int(g["ranges"][t, 0]), int(g["tile_stop"][t])
+        pos = np.arange(s, stop)
+        idx = bins.vals[pos].astype(np.int64)
+        flag = bit(g["rec_mask"], idx).astype(bool)
+        np.testing.assert_array_equal(flag, bit(g["comp_mask"], pos).astype(bool))
+        free = ~ex[bins.gid[idx]]
+        kept.append(idx[flag & free])
+        quiet.append(idx[~flag & free])
+    kept, quiet = np.concatenate(kept), np.concatenate(quiet)
+    checked = kept.size
+    okr = grad_close(g["grec"][kept, :9], partials[kept], 1e-3).all(axis=1)
+    assert okr.all(), kept[~okr][:5]
+    # entries traversed without a record carry no oracle gradient
+    assert not (np.abs(partials[quiet]).max(axis=1) > 0).any()
+    note(f"  K = {K}, {checked} records checked on {len(sample)} tiles")
+    assert checked > 1000

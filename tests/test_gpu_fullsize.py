@@ -72,3 +72,38 @@ def test_plain_300k_1280x720_full_size():
     assert not (np.abs(partials[quiet]).max(axis=1) > 0).any()
     note(f"  K = {K}, {checked} records checked on {len(sample)} tiles")
     assert checked > 1000
+
+
+def test_batched_3m_8_views_binning_full_size():
+    """The batched workload's first step at full size: 3M Gaussians, 8 views
+    of uneven resolution in one frame, 32x32 tiles (the autotuner's choice),
+    fitted capacity (few intersections per (view, Gaussian): the direct
+    32-bit sort over 8 view segments).  Projection, keys, values and ranges
+    bit for bit."""
+    import torch
+    from paper_2605_00219_amd import pipeline as P
+    w = S.workload_batched()
+    cams, res = w.extra["cameras"], w.extra["resolutions"]
+    views = S.batched_views(cams, res, 0)
+    tile = 32
+    note("full size: 3M Gaussians, 8 views, tile 32, binning")
+    frame = P.Frame(w.scene.n, [wd for wd, _ in res], [ht for _, ht in res], tile)
+    vd = P.views_to_device(views)
+    params = P.pack_flat(w.scene.flat())
+    P.fit_capacity(params, frame, vd)
+    P.project(params, frame, vd)
+    P.bin_sort(frame)
+    torch.cuda.synchronize()
+    assert frame.status_bits() == 0
+    m = len(views) * w.scene.n
+    assert frame.capacity < 12 * m                      # direct order
+    u32 = lambda t: t.cpu().numpy().view(np.uint32)
+    pr = oracle.project(w.scene, views, tile)
+    bins = oracle.bin_sort(pr, views, tile)
+    K = int(bins.offsets[-1])
+    np.testing.assert_array_equal(u32(frame.tiles).reshape(len(views), -1), pr.tiles)
+    np.testing.assert_array_equal(u32(frame.offsets), bins.offsets)
+    np.testing.assert_array_equal(u32(frame.keys)[:K], bins.keys)
+    np.testing.assert_array_equal(u32(frame.vals)[:K], bins.gid[bins.vals])
+    np.testing.assert_array_equal(u32(frame.ranges), bins.ranges)
+    note(f"  K = {K} over {len(views)} views")

@@ -264,6 +264,11 @@ int gs_project(const float* params, int64_t n, const gs_view* views, const gs_la
  * rows[4 r] + (tx - xa) with r = row_offsets[v*n+g] + (ty - y0).  If K > capacity only the first `capacity`
  * intersections are written and GS_STATUS_CAPACITY is set; the caller reads
  * offsets[V*n] to size a retry.
+ * With many intersections per (view, Gaussian) part of the work runs on an
+ * auxiliary stream of the library (one per host thread and device, default
+ * priority, created on the first such call and kept), forked from and joined
+ * back to `stream` with events, so the call remains ordered on `stream` and
+ * capturable in a graph once that stream exists.
  *   workspace  device scratch of gs_bin_sort_workspace_size bytes */
 int gs_bin_sort(const gs_splats* splats, int64_t n, const gs_layout* layout, const gs_bins* bins,
                 void* workspace, size_t workspace_bytes, void* stream);

@@ -25,6 +25,7 @@ constexpr int kChunk = kSortThreads * kSortItems;      // 4096 keys per radix ch
 constexpr int kDepthItems = 4;                          // the depth sort of (view, Gaussian)s:
 constexpr int kDepthChunk = kSortThreads * kDepthItems; // 1024-key chunks
 constexpr int64_t kDepthFirstRatio = 12;                // capacity / (views x n) to sort by depth first
+constexpr int kDepthSplit = 16;                          // key bits sorted per Gaussian in the depth order
 constexpr int kDigits = 256;
 constexpr int kPasses = 4;
 constexpr int kHistBlocks = 512;                        // workgroups of the histogram pass
@@ -59,7 +60,8 @@ struct Workspace {
     int64_t max_chunks;
     // depth order of the (view, Gaussian)s
     uint32_t *dkey, *dval, *dkey_tmp, *dval_tmp;
-    uint32_t* dshift;      // per (view, Gaussian): depth-order position - unsorted index
+    uint32_t* dpos;        // per (view, Gaussian): its first position in depth order
+    uint64_t* dblock_sums; // scan partials of the depth-order scan (runs beside the others)
     uint32_t* dtable;      // segments of the depth sort
     uint32_t* dsort_words;
     int64_t max_dchunks;
@@ -92,7 +94,8 @@ static size_t carve(int64_t n, const gs_layout& L, int64_t capacity, char* base,
     tmp.dval = (uint32_t*)take(sizeof(uint32_t) * (size_t)m);
     tmp.dkey_tmp = (uint32_t*)take(sizeof(uint32_t) * (size_t)m);
     tmp.dval_tmp = (uint32_t*)take(sizeof(uint32_t) * (size_t)m);
-    tmp.dshift = (uint32_t*)take(sizeof(uint32_t) * (size_t)m);
+    tmp.dpos = (uint32_t*)take(sizeof(uint32_t) * (size_t)m);
+    tmp.dblock_sums = (uint64_t*)take(sizeof(uint64_t) * (size_t)(sb + 1));
     tmp.dtable = (uint32_t*)take(sizeof(uint32_t) * 4 * (GS_MAX_VIEWS + 1));
     tmp.dsort_words = (uint32_t*)take(sort_words_bytes(L.n_views, mcd));
     tmp.max_dchunks = mcd;
@@ -143,9 +146,9 @@ GS_DEV uint64_t block_scan_u64(uint64_t v, uint64_t* lds, uint64_t* total) {
 }
 
 // With `perm`, element i of the sequence is in[perm[i]], and the exclusive
-// scan value of element i is stored as out[perm[i]] = scan_i - sub[perm[i]]
-// (no total is stored); without, element i is in[i] and out[i] = scan_i, with
-// the total in out[len].
+// scan value of element i is stored as out[perm[i]] = scan_i (minus
+// sub[perm[i]] if sub is set; no total is stored); without, element i is
+// in[i] and out[i] = scan_i, with the total in out[len].
 // `clear`, if set, is zeroed by the first launch (the status word of the call).
 struct ScanIO {
     const uint32_t* in;
@@ -164,7 +167,7 @@ GS_DEV uint32_t scan_load(const ScanIO& io, int64_t i) { return io.perm ? io.in[
 GS_DEV void scan_store(const ScanIO& io, int64_t i, uint32_t x) {
     if (io.perm) {
         const uint32_t j = io.perm[i];
-        io.out[j] = x - io.sub[j];
+        io.out[j] = io.sub ? x - io.sub[j] : x;
     } else {
         io.out[i] = x;
     }
@@ -289,26 +292,12 @@ static int scan_exclusive(const uint32_t* in, int64_t len, uint32_t* out, uint64
 // per-view segment table
 // ---------------------------------------------------------------------------
 
-// Also the table of the depth sort (one segment of n per view); clears both
-// sorts' digit totals.
+// Also clears the tile sort's digit totals.
 __global__ void k_view_table(const uint32_t* __restrict__ offsets, int64_t n, int n_views,
                              int64_t capacity, uint32_t* __restrict__ table,
-                             uint32_t* __restrict__ status, uint32_t* __restrict__ dcount,
-                             uint32_t* __restrict__ dtable, uint32_t* __restrict__ ddcount) {
-    for (int i = threadIdx.x; i < n_views * kPasses * kDigits; i += blockDim.x) {
-        dcount[i] = 0u;
-        ddcount[i] = 0u;
-    }
+                             uint32_t* __restrict__ status, uint32_t* __restrict__ dcount) {
+    for (int i = threadIdx.x; i < n_views * kPasses * kDigits; i += blockDim.x) dcount[i] = 0u;
     if (threadIdx.x != 0) return;
-    // the depth sort: one segment of n per view
-    const uint32_t dnc = (uint32_t)((n + kDepthChunk - 1) / kDepthChunk);
-    for (int v = 0; v < n_views; ++v) {
-        dtable[4 * v + 0] = (uint32_t)(v * n);
-        dtable[4 * v + 1] = (uint32_t)((v + 1) * n);
-        dtable[4 * v + 2] = (uint32_t)v * dnc;
-        dtable[4 * v + 3] = dnc;
-    }
-    dtable[4 * n_views] = (uint32_t)n_views * dnc;
     uint32_t chunks = 0;
     const uint64_t cap = (uint64_t)capacity;
     for (int v = 0; v < n_views; ++v) {
@@ -338,39 +327,61 @@ struct EmitGeom {
     int32_t cull;
 };
 
-// Tile rows of each (view, Gaussian) with tiles: the rows of its bounding box.
+// The first kernel of a call: clears the status word; per (view, Gaussian)
+// its tile rows (the rows of its bounding box) and, for the depth order, the
+// low min(kDepthSplit, D) bits of its keys (all depth bits) with its index;
+// workgroup 0 also writes the depth sort's table (one segment of n per view)
+// and clears its digit totals.
 __global__ __launch_bounds__(256) void k_row_count(const float4* __restrict__ rec,
-                                                   const uint32_t* __restrict__ tiles, int64_t m,
-                                                   uint32_t* __restrict__ row_count) {
+                                                   const uint32_t* __restrict__ tiles, int64_t n,
+                                                   int64_t m, EmitGeom geo, uint32_t* __restrict__ row_count,
+                                                   uint32_t* __restrict__ status, uint32_t* __restrict__ dkey,
+                                                   uint32_t* __restrict__ dval, uint32_t* __restrict__ dtable,
+                                                   uint32_t* __restrict__ ddcount, int n_views) {
+    if (blockIdx.x == 0) {
+        for (int i = threadIdx.x; i < n_views * kPasses * kDigits; i += blockDim.x) ddcount[i] = 0u;
+        if (threadIdx.x == 0) {
+            *status = 0u;
+            const uint32_t dnc = (uint32_t)((n + kDepthChunk - 1) / kDepthChunk);
+            for (int v = 0; v < n_views; ++v) {
+                dtable[4 * v + 0] = (uint32_t)(v * n);
+                dtable[4 * v + 1] = (uint32_t)((v + 1) * n);
+                dtable[4 * v + 2] = (uint32_t)v * dnc;
+                dtable[4 * v + 3] = dnc;
+            }
+            dtable[4 * n_views] = (uint32_t)n_views * dnc;
+        }
+    }
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= m) return;
-    row_count[o] = tiles[o] > 0 ? rect_rows(rec[4 * o + 3]) : 0u;
+    const bool vis = tiles[o] > 0;
+    const float4 q3 = rec[4 * o + 3];
+    row_count[o] = vis ? rect_rows(q3) : 0u;
+    const int v = (int)(o / n);
+    // the key's bits below min(kDepthSplit, D): depth bits only
+    const int D = geo.depth_bits[v];
+    const int split = D < kDepthSplit ? D : kDepthSplit;
+    const uint32_t dk = __float_as_uint(q3.z) >> (23 - D);
+    dkey[o] = vis ? dk & ((1u << split) - 1u) : 0u;
+    dval[o] = (uint32_t)o;
 }
 
 // One thread per (view, Gaussian): the column span of each of its tile rows
 // (the rectangle's columns, or the ellipse's span of that row), recorded as
 // the unsorted index of the row's first tile and its first column, with the
 // Gaussian's depth bits.  The spans are the ones the projection counted (same
-// function of the same record values).  Also writes the (view, Gaussian)'s
-// key for the depth sort.
+// function of the same record values).
 __global__ __launch_bounds__(256) void k_rows(const float4* __restrict__ rec,
                                               const uint32_t* __restrict__ tiles,
                                               const uint32_t* __restrict__ offsets,
                                               const uint32_t* __restrict__ row_offsets, int64_t n,
                                               int64_t m, EmitGeom geo, int64_t row_capacity,
-                                              uint4* __restrict__ rows, uint32_t* __restrict__ status,
-                                              uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval) {
+                                              uint4* __restrict__ rows, uint32_t* __restrict__ status) {
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= m) return;
+    if (o >= m || tiles[o] == 0) return;
     const int v = (int)(o / n);
     const float4* r = rec + 4 * o;
-    const bool vis = tiles[o] != 0;
-    // depth key of the (view, Gaussian) for the depth sort
-    const float4 q3 = r[3];
-    dkey[o] = vis ? __float_as_uint(q3.z) >> (23 - geo.depth_bits[v]) : 0u;
-    dval[o] = (uint32_t)o;
-    if (!vis) return;
-    const float4 q0 = r[0], q1 = r[1];
+    const float4 q0 = r[0], q1 = r[1], q3 = r[3];
     const uint32_t r0 = __float_as_uint(q3.x), r1 = __float_as_uint(q3.y);
     const int x0 = (int)(r0 & 0xFFFF), y0 = (int)(r0 >> 16), x1 = (int)(r1 & 0xFFFF), y1 = (int)(r1 >> 16);
     Ellipse e;
@@ -397,14 +408,16 @@ constexpr int kEmitG = 256;  // tile rows per workgroup
 // bases and depth codes are staged in LDS; the workgroup's intersections
 // [rows[r0].first, rows[r0 + kEmitG].first) are then produced by consecutive
 // threads (balanced however unequal the rows are), each finding its row by
-// binary search over the staged first indices.  Each key goes to its
-// Gaussian's depth-order position: the unsorted index plus the Gaussian's
-// shift, so that the keys of a view are laid out by (depth bits, Gaussian id).
+// binary search over the staged first indices.  With `dpos` (each
+// (view, Gaussian)'s first position in depth order) each key goes to its
+// unsorted index minus its Gaussian's first unsorted index plus that
+// position, so that the keys of a view are laid out by (depth bits,
+// Gaussian id).
 __global__ __launch_bounds__(kEmitG) void k_emit(const float4* __restrict__ rec,
                                                  const uint4* __restrict__ rows,
                                                  const uint32_t* __restrict__ row_offsets,
                                                  const uint32_t* __restrict__ offsets,
-                                                 const uint32_t* __restrict__ dshift, int64_t n,
+                                                 const uint32_t* __restrict__ dpos, int64_t n,
                                                  int64_t m, EmitGeom geo, int64_t capacity,
                                                  int64_t row_capacity, uint32_t* __restrict__ keys,
                                                  uint32_t* __restrict__ vals) {
@@ -429,7 +442,7 @@ __global__ __launch_bounds__(kEmitG) void k_emit(const float4* __restrict__ rec,
         s_tile[t] = (row.z >> 16) * (uint32_t)geo.tiles_x[v] + (row.z & 0xFFFF);
         s_dk[t] = row.w;
         s_gid[t] = (uint32_t)(o - (int64_t)v * n);
-        s_sh[t] = dshift ? dshift[o] : 0u;
+        s_sh[t] = dpos ? dpos[o] - offsets[o] : 0u;
         s_D[t] = (uint8_t)D;
     } else {
         s_off[t] = (uint32_t)kc;
@@ -991,6 +1004,38 @@ int sort_pairs(uint32_t* keys, uint32_t* vals, int64_t count, void* scratch, hip
 }
 
 // ---------------------------------------------------------------------------
+// auxiliary stream: the depth sort runs beside the scans and row slots
+// ---------------------------------------------------------------------------
+
+struct AuxStream {
+    hipStream_t stream = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+
+// One auxiliary stream (default priority) and two events per host thread and
+// device, created on first use and kept for the life of the process.
+static int aux_stream(AuxStream** out) {
+    constexpr int kMaxDevices = 64;
+    static thread_local AuxStream aux[kMaxDevices];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        set_error("bin_sort: no current device");
+        return GS_ERR_HIP;
+    }
+    AuxStream& a = aux[dev];
+    if (!a.stream) {
+        if (hipStreamCreateWithFlags(&a.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&a.fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&a.join, hipEventDisableTiming) != hipSuccess) {
+            set_error("bin_sort: cannot create the auxiliary stream");
+            return GS_ERR_HIP;
+        }
+    }
+    *out = &a;
+    return GS_OK;
+}
+
+// ---------------------------------------------------------------------------
 // driver
 // ---------------------------------------------------------------------------
 
@@ -1010,25 +1055,23 @@ int launch_bin_sort(const gs_splats& sp, int64_t n, const gs_layout& L, const gs
     // than the two passes it saves, and all 32 bits are sorted directly.  Both
     // give the same order: (tile, depth bits, Gaussian id).
     const bool depth_first = m > 0 && b.capacity >= kDepthFirstRatio * m;
+    // (An LSD sort may split the key anywhere: the keys' bits below
+    // split = min(kDepthSplit, D) are depth bits, the same for all of a
+    // Gaussian's keys, so they are sorted per (view, Gaussian); the keys'
+    // bits from split up are then sorted stably.)
     SortWs S = carve_sort(W.sort_words, V, W.max_chunks);
-    int tile_bits = 1, max_d = 1;
+    int high_bits = 1, low_bits = 1;
     for (int v = 0; v < V; ++v) {
-        S.shift0[v] = depth_first ? L.depth_bits[v] : 0;
-        tile_bits = std::max(tile_bits, 32 - L.depth_bits[v]);
-        max_d = std::max(max_d, L.depth_bits[v]);
+        const int split = std::min(kDepthSplit, L.depth_bits[v]);
+        S.shift0[v] = depth_first ? split : 0;
+        high_bits = std::max(high_bits, 32 - split);
+        low_bits = std::max(low_bits, split);
     }
-    S.passes = depth_first ? std::min(kPasses, (tile_bits + 7) / 8) : kPasses;
-    // depth sort: the depth bits of each (view, Gaussian)
+    S.passes = depth_first ? std::min(kPasses, (high_bits + 7) / 8) : kPasses;
+    // depth sort: the low bits of each (view, Gaussian)'s keys
     SortWs SD = carve_sort(W.dsort_words, V, W.max_dchunks);
-    SD.passes = std::min(kPasses, (max_d + 7) / 8);
+    SD.passes = std::min(kPasses, (low_bits + 7) / 8);
     int rc;
-    // offsets (clearing the status word first) and row offsets
-    if ((rc = scan_exclusive(sp.tiles, m, b.offsets, W.block_sums, b.status, s, nullptr, nullptr, b.status)) !=
-        GS_OK)
-        return rc;
-    hipLaunchKernelGGL(k_view_table, dim3(1), dim3(256), 0, s, b.offsets, n, V, b.capacity, W.table,
-                       b.status, S.dcount, W.dtable, SD.dcount);
-    if ((rc = check_launch("view_table")) != GS_OK) return rc;
     EmitGeom eg;
     RangeGeom rg;
     memset(&eg, 0, sizeof(eg));
@@ -1044,28 +1087,46 @@ int launch_bin_sort(const gs_splats& sp, int64_t n, const gs_layout& L, const gs
     for (int v = 0; v <= GS_MAX_VIEWS; ++v) rg.tile_base[v] = v <= V ? L.tile_base[v] : L.tile_base[V];
     const float4* rec = reinterpret_cast<const float4*>(sp.rec);
     uint4* rows = reinterpret_cast<uint4*>(b.rows);
-    const unsigned gm = (unsigned)((m + 255) / 256);
-    if (m > 0) {
-        hipLaunchKernelGGL(k_row_count, dim3(gm), dim3(256), 0, s, rec, sp.tiles, m, W.row_count);
-        if ((rc = check_launch("row_count")) != GS_OK) return rc;
+    const unsigned gm = (unsigned)std::max<int64_t>((m + 255) / 256, 1);
+    // status cleared, tile rows and depth keys per (view, Gaussian)
+    hipLaunchKernelGGL(k_row_count, dim3(gm), dim3(256), 0, s, rec, sp.tiles, n, m, eg, W.row_count, b.status,
+                       W.dkey, W.dval, W.dtable, SD.dcount, V);
+    if ((rc = check_launch("row_count")) != GS_OK) return rc;
+    AuxStream* aux = nullptr;
+    if (depth_first) {
+        // depth order on the auxiliary stream: a stable sort of the
+        // (view, Gaussian)s by depth bits, then the scan of their tile counts
+        // in that order (each one's first position)
+        if ((rc = aux_stream(&aux)) != GS_OK) return rc;
+        if (hipEventRecord(aux->fork, s) != hipSuccess || hipStreamWaitEvent(aux->stream, aux->fork, 0) != hipSuccess) {
+            set_error("bin_sort: cannot fork to the auxiliary stream");
+            return GS_ERR_HIP;
+        }
+        if ((rc = radix_sort_views<kDepthItems>(W.dkey, W.dval, W.dkey_tmp, W.dval_tmp, W.dtable, V, SD, b.status,
+                                                aux->stream)) != GS_OK)
+            return rc;
+        const uint32_t* perm = SD.passes % 2 == 0 ? W.dval : W.dval_tmp;
+        if ((rc = scan_exclusive(sp.tiles, m, W.dpos, W.dblock_sums, nullptr, aux->stream, perm)) != GS_OK)
+            return rc;
+        if (hipEventRecord(aux->join, aux->stream) != hipSuccess) {
+            set_error("bin_sort: cannot join the auxiliary stream");
+            return GS_ERR_HIP;
+        }
     }
+    // offsets and row offsets, the view table, the row slots
+    if ((rc = scan_exclusive(sp.tiles, m, b.offsets, W.block_sums, b.status, s)) != GS_OK) return rc;
+    hipLaunchKernelGGL(k_view_table, dim3(1), dim3(256), 0, s, b.offsets, n, V, b.capacity, W.table,
+                       b.status, S.dcount);
+    if ((rc = check_launch("view_table")) != GS_OK) return rc;
     if ((rc = scan_exclusive(W.row_count, m, b.row_offsets, W.block_sums, nullptr, s)) != GS_OK) return rc;
     if (m > 0) {
         hipLaunchKernelGGL(k_rows, dim3(gm), dim3(256), 0, s, rec, sp.tiles, b.offsets, b.row_offsets, n, m,
-                           eg, b.row_capacity, rows, b.status, W.dkey, W.dval);
+                           eg, b.row_capacity, rows, b.status);
         if ((rc = check_launch("rows")) != GS_OK) return rc;
     }
-    if (depth_first) {
-        // depth order: a stable sort of the (view, Gaussian)s by depth bits,
-        // then each one's first position in that order
-        if ((rc = radix_sort_views<kDepthItems>(W.dkey, W.dval, W.dkey_tmp, W.dval_tmp, W.dtable, V, SD, b.status, s)) !=
-            GS_OK)
-            return rc;
-        // scan of the tile counts in depth order, stored per (view, Gaussian)
-        // as its depth-order position minus its unsorted index
-        const uint32_t* perm = SD.passes % 2 == 0 ? W.dval : W.dval_tmp;
-        if ((rc = scan_exclusive(sp.tiles, m, W.dshift, W.block_sums, nullptr, s, perm, b.offsets)) != GS_OK)
-            return rc;
+    if (depth_first && hipStreamWaitEvent(s, aux->join, 0) != hipSuccess) {
+        set_error("bin_sort: cannot wait for the auxiliary stream");
+        return GS_ERR_HIP;
     }
     // keys (in depth order if depth_first), then the sort; the emit goes to
     // the buffer that leaves the sorted keys in bins.keys
@@ -1075,7 +1136,7 @@ int launch_bin_sort(const gs_splats& sp, int64_t n, const gs_layout& L, const gs
     uint32_t* ov = S.passes % 2 == 0 ? W.vals_tmp : b.vals;
     if (m > 0 && b.row_capacity > 0) {
         hipLaunchKernelGGL(k_emit, dim3((unsigned)((b.row_capacity + kEmitG - 1) / kEmitG)), dim3(kEmitG), 0, s,
-                           rec, rows, b.row_offsets, b.offsets, depth_first ? W.dshift : nullptr, n, m, eg,
+                           rec, rows, b.row_offsets, b.offsets, depth_first ? W.dpos : nullptr, n, m, eg,
                            b.capacity, b.row_capacity, ek, ev);
         if ((rc = check_launch("emit_keys")) != GS_OK) return rc;
     }

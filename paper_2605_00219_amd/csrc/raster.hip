@@ -520,17 +520,22 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd(RasterArgs a)
                 }
             }
             __syncthreads();
-            // this wavefront's rectangle of pixel centres
+            // this wavefront's rectangle of pixel centres, and the list length
+            // its pixels need (the largest of their `last`)
+            uint32_t wlen = mylen;
+            for (int off = 32; off > 0; off >>= 1) wlen = max(wlen, (uint32_t)__shfl_xor((int)wlen, off));
             const float rx0 = (float)(ti.tx * TILE) + 0.5f, rx1 = rx0 + (float)(TILE - 1);
             const float ry0 = (float)(ti.ty * TILE + w * Geo<TILE, PPT_>::ROWS) + 0.5f;
             const float ry1 = ry0 + (float)(Geo<TILE, PPT_>::ROWS - 1);
             for (int sub = 0; sub < cnt; sub += SUB) {
                 const int scnt = min(SUB, cnt - sub);
                 uint64_t used = 0;
-                // staged Gaussians no pixel of this wavefront can composite are
-                // passed over (their gradient terms here would all be zero)
-                const uint64_t rel = __ballot(lane < scnt && rect_may_composite(s_g[sub + lane], s_h[sub + lane],
-                                                                                  rx0, rx1, ry0, ry1));
+                // staged Gaussians no pixel of this wavefront can composite (past
+                // its pixels' last entries, or outside their reach) are passed
+                // over: their gradient terms here would all be zero
+                const uint64_t rel = __ballot(lane < scnt && s_pos[sub + lane] < wlen &&
+                                              rect_may_composite(s_g[sub + lane], s_h[sub + lane], rx0, rx1, ry0,
+                                                                 ry1));
                 for (uint64_t mrel = rel; mrel != 0ull; mrel &= mrel - 1ull) {
                     const int kk = (int)__builtin_ctzll(mrel);
                     const int k = sub + kk;

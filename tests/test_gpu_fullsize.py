@@ -1,6 +1,6 @@
 """The plain workload at its full size, in the configuration bench.py times:
 300k Gaussians (means N(0,1), log-scales N(-4, 0.7)), one 1280x720 view,
-16x16 tiles, 2 pixels per lane, S = 64, the fitted capacity (so the binning
+16x16 tiles, 2 pixels per lane, S = 128, the fitted capacity (so the binning
 takes its depth-first order and every sort pass runs in two rounds of
 workgroups).  Projection, keys, values and ranges are compared bit for bit in
 full; pixels and gradient records on a seeded sample of tiles, with the
@@ -23,7 +23,7 @@ def test_plain_300k_1280x720_full_size():
     W, H = 1280, 720
     note("full size: 300k Gaussians, 1280x720, tile 16")
     target = S.random_image(H, W, 4242).reshape(-1, 3)
-    g = run_gpu_step(scene, views, 16, target=target)
+    g = run_gpu_step(scene, views, 16, target=target, lds_batch=128)
     assert g["status"] == 0
     pr = oracle.project(scene, views, 16)
     bins = oracle.bin_sort(pr, views, 16)

@@ -305,6 +305,31 @@ int gs_rasterize_bwd(const gs_splats* splats, int64_t n, const gs_layout* layout
                      const float* target, const float* dL_dC, const gs_grads2d* grads,
                      float* loss, int lds_batch, const gs_schedule* sched, void* stream);
 
+/* Fused L1 + D-SSIM loss gradient against an RGBA8 reference (Sec. 4.5: the
+ * weighted sum of the L1 and SSIM losses in one fused evaluation, the reference
+ * kept as 4 x uint8, alpha masking fused):
+ *   L = (1 - lambda)/(3P) sum_p m_p sum_k |x_pk - y_pk|
+ *     + lambda/(3P) sum_p m_p sum_k (1 - S_pk)
+ * over the P pixels of all views, x the render, y = rgb / 255, m = alpha / 255
+ * if use_mask else 1, S the SSIM map of each colour channel of each view (an
+ * 11 x 11 Gaussian window with sigma 1.5, zero outside the view's image,
+ * C1 = 0.01^2, C2 = 0.03^2).  The gradient dL/dx goes to dL_dC, the input of
+ * gs_rasterize_bwd.
+ *   rgb          device, pixels x 3 float: the render (gs_image.rgb)
+ *   target       device, pixels x 4 uint8 (R, G, B, A), 4-byte aligned
+ *   dL_dC        device, pixels x 3 float, written
+ *   loss_blocks  device, 2 x gs_loss_blocks(layout) floats, nullable: per 16 x 16
+ *                block of each view (views in order, blocks row-major), the sums
+ *                of m |x - y| and of m (1 - S) over its pixels and channels;
+ *                L = ((1 - lambda) sum of the first + lambda sum of the second) / (3P)
+ *   workspace    device scratch of gs_loss_workspace_size(layout) bytes
+ * Deterministic; no atomics. */
+int64_t gs_loss_blocks(const gs_layout* layout);
+size_t gs_loss_workspace_size(const gs_layout* layout);
+int gs_loss_l1_ssim(const float* rgb, const uint8_t* target, const gs_layout* layout, float lambda,
+                    int use_mask, float* dL_dC, float* loss_blocks, void* workspace,
+                    size_t workspace_bytes, void* stream);
+
 /* Projection backward fused with Adam (Sec. 4.3).  First pass: for each
  * (view, Gaussian), the sum of its records flagged in grads->rec_mask, in
  * unsorted-index order, into grads->sums.  Second pass, per Gaussian: applies the

@@ -95,6 +95,10 @@ _SIGS = {
     "gs_mlp_train_step": (C.c_int, [_P, _P, _P, _P, C.c_int64, _P, _P, _P, _P, C.c_float, _P, _P]),
     "gs_order_by_cost_scratch_size": (C.c_size_t, [C.c_int32]),
     "gs_order_by_cost": (C.c_int, [_P, C.c_int32, _P, _P, _P]),
+    "gs_loss_blocks": (C.c_int64, [C.POINTER(GsLayout)]),
+    "gs_loss_workspace_size": (C.c_size_t, [C.POINTER(GsLayout)]),
+    "gs_loss_l1_ssim": (C.c_int, [_P, _P, C.POINTER(GsLayout), C.c_float, C.c_int, _P, _P, _P, C.c_size_t,
+                                  _P]),
 }
 EXPORTS = tuple(_SIGS)
 

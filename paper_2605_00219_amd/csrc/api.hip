@@ -184,6 +184,29 @@ int gs_project_bwd_adam(float* params, int64_t n, const gs_view* views, const gs
                                    (hipStream_t)stream);
 }
 
+int64_t gs_loss_blocks(const gs_layout* layout) {
+    if (!layout_ok(layout)) return 0;
+    return loss_blocks(*layout);
+}
+
+size_t gs_loss_workspace_size(const gs_layout* layout) {
+    if (!layout_ok(layout)) return 0;
+    return (size_t)9 * sizeof(float) * (size_t)std::max<int64_t>(layout->pixel_base[layout->n_views], 1);
+}
+
+int gs_loss_l1_ssim(const float* rgb, const uint8_t* target, const gs_layout* layout, float lambda,
+                    int use_mask, float* dL_dC, float* loss_blocks_out, void* workspace,
+                    size_t workspace_bytes, void* stream) {
+    REQUIRE(layout_ok(layout), "gs_loss_l1_ssim: invalid layout");
+    REQUIRE(rgb && target && dL_dC && workspace, "gs_loss_l1_ssim: null pointer");
+    REQUIRE(((uintptr_t)target & 3u) == 0, "gs_loss_l1_ssim: target not 4-byte aligned");
+    REQUIRE(lambda >= 0.0f && lambda <= 1.0f, "gs_loss_l1_ssim: lambda %g not in [0, 1]", (double)lambda);
+    REQUIRE(workspace_bytes >= gs_loss_workspace_size(layout), "gs_loss_l1_ssim: workspace of %zu bytes, %zu needed",
+            workspace_bytes, gs_loss_workspace_size(layout));
+    return launch_loss_l1_ssim(rgb, target, *layout, lambda, use_mask, dL_dC, loss_blocks_out, workspace,
+                               (hipStream_t)stream);
+}
+
 int gs_tile_features(const gs_splats* splats, int64_t n, const gs_layout* layout,
                      const gs_bins* bins, float* features, void* stream) {
     REQUIRE(layout_ok(layout), "gs_tile_features: invalid layout");

@@ -59,6 +59,9 @@ int launch_mlp_train_step(float* w, const float* norm, const float* x, const flo
                           float* loss_out, hipStream_t s);
 int launch_order_by_cost(const float* pred, int32_t total, uint32_t* order, void* scratch,
                          hipStream_t s);
+int64_t loss_blocks(const gs_layout& L);
+int launch_loss_l1_ssim(const float* rgb, const uint8_t* target, const gs_layout& L, float lam, int use_mask,
+                        float* dLdC, float* loss_blocks_out, void* ws, hipStream_t s);
 // stable ascending sort of (key, value) pairs in place; scratch of sort_pairs_scratch(count) bytes
 size_t sort_pairs_scratch(int64_t count);
 int sort_pairs(uint32_t* keys, uint32_t* vals, int64_t count, void* scratch, hipStream_t s);

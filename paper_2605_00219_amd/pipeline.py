@@ -193,6 +193,37 @@ def rasterize_bwd(frame: Frame, views_dev: torch.Tensor, target: torch.Tensor | 
                                    G.stream_ptr(stream)), "gs_rasterize_bwd")
 
 
+class LossL1SSIM:
+    """Fused L1 + D-SSIM loss gradient of a frame's render against an RGBA8
+    reference (gs_loss_l1_ssim); owns its workspace and per-block sums."""
+
+    def __init__(self, frame: Frame, lam: float = 0.2, use_mask: bool = True):
+        dev = frame.image.device
+        self.frame = frame
+        self.lam = float(lam)
+        self.use_mask = bool(use_mask)
+        nb = int(G.lib.gs_loss_blocks(C.byref(frame.layout)))
+        ws = int(G.lib.gs_loss_workspace_size(C.byref(frame.layout)))
+        self.blocks = torch.zeros(2 * max(nb, 1), dtype=torch.float32, device=dev)
+        self.workspace = torch.empty(ws, dtype=torch.uint8, device=dev)
+        self.dLdC = torch.zeros_like(frame.image)
+
+    def __call__(self, target_rgba: torch.Tensor, stream=None) -> torch.Tensor:
+        """target_rgba: uint8 [pixels, 4] on the device; returns dL/dC [pixels, 3]."""
+        assert target_rgba.dtype == torch.uint8 and target_rgba.is_contiguous()
+        G.check(G.lib.gs_loss_l1_ssim(_i(self.frame.image), _i(target_rgba), C.byref(self.frame.layout),
+                                      self.lam, int(self.use_mask), _i(self.dLdC), _i(self.blocks),
+                                      _i(self.workspace), self.workspace.numel(), G.stream_ptr(stream)),
+                "gs_loss_l1_ssim")
+        return self.dLdC
+
+    def loss(self) -> float:
+        """The loss of the last call (synchronises)."""
+        b = self.blocks.double().view(-1, 2).sum(0)
+        P = self.frame.layout.total_pixels
+        return float(((1 - self.lam) * b[0] + self.lam * b[1]).item()) / (3.0 * P)
+
+
 def project_bwd_adam(model: Model, frame: Frame, views_dev: torch.Tensor, adam: bool = True,
                      grads_out: torch.Tensor | None = None, stream=None) -> None:
     G.check(G.lib.gs_project_bwd_adam(_i(model.params), frame.n, _i(views_dev), C.byref(frame.layout),

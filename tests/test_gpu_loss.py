@@ -1,0 +1,112 @@
+"""Fused L1 + D-SSIM loss gradient (gs_loss_l1_ssim) against the oracle
+(oracle/ssim.py): two ragged views whole, and the 1280x720 bench resolution
+on padded crops.  Bar: gradients within 1e-3 relative (floored at 1e-2 of the
+maximum), pixels whose L1 sign is a near-tie (fragile) excluded; loss sums
+within 1e-5 relative."""
+import numpy as np
+import pytest
+
+import synthetic as S
+from gpu_common import note
+from helpers import grad_close
+from oracle import ssim as O
+
+pytestmark = pytest.mark.gpu
+
+
+def _frame(sizes):
+    from paper_2605_00219_amd import pipeline as P
+    return P.Frame(16, [w for w, _ in sizes], [h for _, h in sizes], 16, capacity=1024)
+
+
+def _inputs(sizes, seed):
+    rng = np.random.default_rng(seed)
+    P = sum(w * h for w, h in sizes)
+    x = rng.uniform(0.0, 1.0, size=(P, 3)).astype(np.float32)
+    t = rng.integers(0, 256, size=(P, 4)).astype(np.uint8)
+    # smooth structure as well as noise, and some fully masked pixels
+    base = 0
+    for w, h in sizes:
+        yy, xx = np.mgrid[0:h, 0:w]
+        wave = (0.5 + 0.4 * np.sin(xx / 7.0) * np.cos(yy / 5.0)).reshape(-1)
+        x[base:base + w * h, 1] = wave.astype(np.float32)
+        t[base:base + w * h, 1] = np.clip(wave * 255 + rng.normal(0, 10, w * h), 0, 255).astype(np.uint8)
+        base += w * h
+    t[rng.random(P) < 0.05, 3] = 0
+    return x, t
+
+
+def _run(frame, x, t, lam, mask):
+    import torch
+    from paper_2605_00219_amd import pipeline as P
+    frame.image.copy_(torch.as_tensor(x, device="cuda"))
+    loss = P.LossL1SSIM(frame, lam=lam, use_mask=mask)
+    g = loss(torch.as_tensor(t, device="cuda").contiguous())
+    torch.cuda.synchronize()
+    return g.cpu().numpy(), loss.blocks.cpu().numpy().reshape(-1, 2), loss.loss()
+
+
+@pytest.mark.parametrize("lam,mask", [(0.2, True), (0.2, False), (0.0, True), (1.0, True)])
+def test_loss_gradient_two_ragged_views(lam, mask):
+    sizes = [(200, 150), (333, 97)]
+    note(f"L1 + D-SSIM loss gradient, lam={lam}, mask={mask}")
+    x, t = _inputs(sizes, 11)
+    g, blocks, loss = _run(_frame(sizes), x, t, lam, mask)
+    ref_loss, ref, parts, fragile = O.loss_and_grad(x, t, sizes, lam=lam, mask=mask)
+    ok = fragile == 0
+    assert ok.mean() > 0.99
+    close = grad_close(g[ok], ref[ok], 1e-3)
+    assert close.all(), np.argwhere(~close)[:5]
+    assert loss == pytest.approx(ref_loss, rel=1e-5)
+    # per-view block sums
+    nb = [((w + 15) // 16) * ((h + 15) // 16) for w, h in sizes]
+    b0 = blocks[:nb[0]].astype(np.float64).sum(0)
+    b1 = blocks[nb[0]:nb[0] + nb[1]].astype(np.float64).sum(0)
+    np.testing.assert_allclose(b0, parts[0], rtol=1e-5)
+    np.testing.assert_allclose(b1, parts[1], rtol=1e-5)
+
+
+def test_loss_gradient_1280x720_on_padded_crops():
+    W, H = 1280, 720
+    note("L1 + D-SSIM loss gradient at 1280x720, 12 crops")
+    x = np.clip(np.random.default_rng(21).normal(0.5, 0.25, size=(W * H, 3)), 0, 1).astype(np.float32)
+    t = (S.random_image(H, W, 22).reshape(-1, 3) * 255).astype(np.uint8)
+    t = np.concatenate([t, np.full((W * H, 1), 255, np.uint8)], axis=1)
+    t[np.random.default_rng(23).random(W * H) < 0.1, 3] = 128
+    g, blocks, _ = _run(_frame([(W, H)]), x, t, 0.2, True)
+    rng = np.random.default_rng(24)
+    xi, ti, gi = x.reshape(H, W, 3), t.reshape(H, W, 4), g.reshape(H, W, 3)
+    bw = (W + 15) // 16
+    for c in range(12):
+        # a 64 x 64 region on the 16-pixel grid (corners included), margin 10
+        if c < 4:
+            bx, by = [(0, 0), (W // 16 - 4, 0), (0, H // 16 - 4), (W // 16 - 4, H // 16 - 4)][c]
+        else:
+            bx, by = int(rng.integers(0, W // 16 - 3)), int(rng.integers(0, H // 16 - 3))
+        x0, y0 = 16 * bx, 16 * by
+        cx0, cy0 = max(0, x0 - 10), max(0, y0 - 10)
+        cx1, cy1 = min(W, x0 + 64 + 10), min(H, y0 + 64 + 10)
+        cw, ch = cx1 - cx0, cy1 - cy0
+        xc = xi[cy0:cy1, cx0:cx1].reshape(-1, 3)
+        tc = ti[cy0:cy1, cx0:cx1].reshape(-1, 4)
+        _, rc, _, fr = O.loss_and_grad(xc, tc, [(cw, ch)], lam=0.2, mask=True)
+        rc = rc.reshape(ch, cw, 3) * (cw * ch) / (W * H)     # the crop's own 1/(3P)
+        fr = fr.reshape(ch, cw)
+        sl = (slice(y0 - cy0, y0 - cy0 + 64), slice(x0 - cx0, x0 - cx0 + 64))
+        got, want, ok = gi[y0:y0 + 64, x0:x0 + 64], rc[sl], fr[sl] == 0
+        close = grad_close(got[ok], want[ok], 1e-3)
+        assert close.all(), (c, np.argwhere(~close)[:5])
+        # block sums of the region's 16 blocks
+        s, _, _, _ = O.ssim_terms(xc.reshape(ch, cw, 3)[..., 0].astype(np.float64),
+                                   tc.reshape(ch, cw, 4)[..., 0].astype(np.float64) / 255.0)
+        for k in range(1, 3):
+            s = s + O.ssim_terms(xc.reshape(ch, cw, 3)[..., k].astype(np.float64),
+                                 tc.reshape(ch, cw, 4)[..., k].astype(np.float64) / 255.0)[0]
+        m = tc.reshape(ch, cw, 4)[..., 3].astype(np.float64) / 255.0
+        one_minus = (3.0 - s) * m
+        for j in range(4):
+            for i in range(4):
+                blk = (by + j) * bw + bx + i
+                yy, xx = y0 - cy0 + 16 * j, x0 - cx0 + 16 * i
+                want_s = one_minus[yy:yy + 16, xx:xx + 16].sum()
+                assert blocks[blk, 1] == pytest.approx(want_s, rel=1e-5, abs=1e-4)

@@ -49,6 +49,13 @@ BWD_FLOP_EVAL = 14           # recompute of power, G, alpha, thresholds per eval
 BWD_FLOP_CONTRIB = 44        # gradient terms and their sums per composited pair
 ADAM_BYTES_G = 1516          # params, m, v 720 r + 720 w; offsets 4; per-view sums 36 w + 36 r
 ADAM_BYTES_FLAGGED = 48      # one gradient record read per composited entry (+ K/8 of mask)
+LOSS_FLOP_PX = 1215          # L1 + D-SSIM gradient, per pixel (3 channels x 405): window sums of
+                             # x, y, x^2, y^2, xy (5 x 2 passes x 11 FMA) 220, products 3, SSIM and
+                             # its three derivatives 40, window sums of the derivative maps
+                             # (3 x 2 x 11 FMA) 132, L1 sign and the gradient 10
+LOSS_BYTES_PX = 28           # render 12 + RGBA8 reference 4 read, dL/dC 12 written
+LOSS_KERNEL_BYTES_PX = 116   # two-kernel form: derivative maps 36 written and read back, render
+                             # and reference read by both kernels
 
 
 def log(msg):
@@ -94,8 +101,8 @@ def parse():
     ap.add_argument("--no-replay", action="store_true", help="skip the work-counting replay")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (for HBM counter scaling)")
-    ap.add_argument("--variants", default="ellipse,batched,learned",
-                    help="comma list of extra measurements: ellipse, batched, learned ('none' for none)")
+    ap.add_argument("--variants", default="ellipse,ssim,batched,learned",
+                    help="comma list of extra measurements: ellipse, ssim, batched, learned ('none' for none)")
     ap.add_argument("--cull", type=int, default=0, choices=(0, 1),
                     help="tile set of the headline run: 0 = 3-sigma rectangle, 1 = exact ellipse")
     ap.add_argument("--batched-steps", type=int, default=200)
@@ -133,15 +140,25 @@ def main():
     tgt_model = P.Model(w.target_scene.flat())
     tframe = P.Frame(n, [W], [H], 16)
     targets = torch.empty(ncam, H * W, 3, device=dev)
+    variants = [v for v in args.variants.split(",") if v]
+    # RGBA8 references for the L1 + D-SSIM variant: the target render quantised
+    # to 8 bits, its coverage 1 - T as the alpha mask
+    targets8 = torch.empty(ncam, H * W, 4, dtype=torch.uint8, device=dev) if "ssim" in variants else None
     for i in range(ncam):
         P.fit_capacity(tgt_model.params, tframe, vptr(i))
         targets[i].copy_(P.render(tgt_model.params, tframe, vptr(i)))
+        if targets8 is not None:
+            rgba = torch.cat([targets[i], 1.0 - tframe.T[:, None]], 1)
+            targets8[i].copy_(torch.round(rgba.clamp(0, 1) * 255).to(torch.uint8))
     del tgt_model, tframe
 
-    def run_plain(cull, replay):
-        """Timed plain steps (and the work-counting replay) with the given tile culling."""
+    def run_plain(cull, replay, loss="l1"):
+        """Timed plain steps (and the work-counting replay) with the given tile
+        culling; loss "l1" (fused into the backward) or "ssim" (L1 + D-SSIM
+        against the RGBA8 references, lambda 0.2, alpha mask)."""
         model = P.Model(w.scene.flat(), lr=w.lr)
         frame = P.Frame(n, [W], [H], 16, cull=cull)
+        lossfn = P.LossL1SSIM(frame, 0.2, True) if loss == "ssim" else None
         kmax = 0
         for i in range(ncam):
             kmax = max(kmax, P.fit_capacity(model.params, frame, vptr(i)))
@@ -162,12 +179,20 @@ def main():
             P.rasterize_fwd(frame, vd, args.lds_batch)
             if ev is not None:
                 ev[3].record()
-            P.rasterize_bwd(frame, vd, target=targets[vi], lds_batch=args.lds_batch)
+            k = 4
+            if lossfn is not None:
+                lossfn(targets8[vi])
+                if ev is not None:
+                    ev[4].record()
+                k = 5
+                P.rasterize_bwd(frame, vd, dLdC=lossfn.dLdC, lds_batch=args.lds_batch)
+            else:
+                P.rasterize_bwd(frame, vd, target=targets[vi], lds_batch=args.lds_batch)
             if ev is not None:
-                ev[4].record()
+                ev[k].record()
             P.project_bwd_adam(model, frame, vd)
             if ev is not None:
-                ev[5].record()
+                ev[k + 1].record()
 
         log(f"warmup {args.warmup} steps (N={n}, {W}x{H}, K<={kmax})")
         for i in range(args.warmup):
@@ -178,7 +203,11 @@ def main():
         state0 = [t.clone() for t in (model.params, model.m, model.v, model.step)]
 
         # timed region: plain single-view steps
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
+        stages = ["project", "bin_sort", "rasterize_fwd", "rasterize_bwd", "project_bwd_adam"]
+        if lossfn is not None:
+            stages.insert(3, "loss_l1_ssim")
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)]
+               for _ in range(args.steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i in range(args.steps):
@@ -188,11 +217,10 @@ def main():
         if frame.status_bits():
             raise RuntimeError("intersection capacity exceeded in the timed region")
         wall = t1 - t0
-        stages = ["project", "bin_sort", "rasterize_fwd", "rasterize_bwd", "project_bwd_adam"]
         stage_ms = {s: float(np.mean([evs[i][k].elapsed_time(evs[i][k + 1]) for i in range(args.steps)]))
                     for k, s in enumerate(stages)}
         ips = args.steps / wall
-        log(f"plain (cull {cull}): {ips:.1f} iters/s, {1e3 * wall / args.steps:.3f} ms/step; "
+        log(f"plain (cull {cull}, loss {loss}): {ips:.1f} iters/s, {1e3 * wall / args.steps:.3f} ms/step; "
             f"stages {stage_ms}")
 
         # replay of the timed steps (deterministic) counting the work each kernel did
@@ -232,17 +260,19 @@ def main():
             torch.cuda.synchronize()
             counts = {k: v / args.steps for k, v in acc.items()}
             log(f"per-step work: {counts}")
+        if lossfn is not None:
+            out_loss = lossfn.loss()
         out = dict(stage_ms=stage_ms, ips=ips, wall=wall, counts=counts, kmax=kmax,
+                   loss=out_loss if lossfn is not None else None,
                    ntiles=frame.layout.total_tiles,
                    depth_first=frame.capacity >= SORT_DEPTH_FIRST_RATIO * n)
-        del model, frame
+        del model, frame, lossfn
         torch.cuda.empty_cache()
         return out
 
     order = [int(x) for x in w.view_order]
     res = run_plain(args.cull, not args.no_replay)
     stage_ms, ips, wall, counts = res["stage_ms"], res["ips"], res["wall"], res["counts"]
-    variants = [v for v in args.variants.split(",") if v]
     cull_variant = None
     if "ellipse" in variants and args.cull == 0:
         r2 = run_plain(1, True)
@@ -253,6 +283,25 @@ def main():
                         "traversed": c2["trav_bwd"] if c2 else None,
                         "pairs_evaluated_bwd": c2["eval_bwd"] if c2 else None,
                         "speedup_vs_rect": r2["ips"] / ips}
+    ssim_variant = None
+    if "ssim" in variants:
+        r3 = run_plain(args.cull, False, loss="ssim")
+        t_loss = r3["stage_ms"]["loss_l1_ssim"] * 1e-3
+        px = H * W
+        ssim_variant = {
+            "loss": "0.8 L1 + 0.2 D-SSIM, RGBA8 reference, alpha mask", "iters_per_s": r3["ips"],
+            "ms_per_step": 1e3 * r3["wall"] / args.steps, "stage_ms": r3["stage_ms"],
+            "final_loss": r3["loss"], "slowdown_vs_l1": ips / r3["ips"],
+            "loss_roofline": {
+                "bound": "alu", "kernel": "loss_l1_ssim", "ms": 1e3 * t_loss,
+                "achieved": LOSS_FLOP_PX * px / t_loss / 1e12, "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": LOSS_FLOP_PX * px / t_loss / 1e12 / FP32_PEAK_TFLOPS,
+                "algorithmic_flop": LOSS_FLOP_PX * px,
+                "algorithmic_bytes": LOSS_BYTES_PX * px,
+                "hbm_gbs": LOSS_BYTES_PX * px / t_loss / 1e9,
+                "kernel_bytes": LOSS_KERNEL_BYTES_PX * px,
+                "kernel_bytes_gbs": LOSS_KERNEL_BYTES_PX * px / t_loss / 1e9}}
+        del targets8
 
     # roofline of the dominant kernel: the single-kernel stage with the largest
     # time (binning and the projection backward are several kernels each);
@@ -335,6 +384,8 @@ def main():
     torch.cuda.empty_cache()
     if cull_variant is not None:
         extra["cull_ellipse"] = cull_variant
+    if ssim_variant is not None:
+        extra["ssim"] = ssim_variant
     if "batched" in variants:
         from paper_2605_00219_amd import experiments as X
         log("batched variant: 3M Gaussians, 8 uneven views per step")

@@ -318,11 +318,17 @@ int gs_rasterize_bwd(const gs_splats* splats, int64_t n, const gs_layout* layout
  *   rgb          device, pixels x 3 float: the render (gs_image.rgb)
  *   target       device, pixels x 4 uint8 (R, G, B, A), 4-byte aligned
  *   dL_dC        device, pixels x 3 float, written
- *   loss_blocks  device, 2 x gs_loss_blocks(layout) floats, nullable: per 16 x 16
- *                block of each view (views in order, blocks row-major), the sums
- *                of m |x - y| and of m (1 - S) over its pixels and channels;
+ *   loss_blocks  device, 2 x gs_loss_blocks(layout) floats, nullable: per unit
+ *                (64 x 16 pixel block of a view, colour channel) -- unit
+ *                3 b + k for block b (views in order, blocks row-major) and
+ *                channel k -- the sums of m |x - y| and of m (1 - S) over the
+ *                block's pixels in that channel;
  *                L = ((1 - lambda) sum of the first + lambda sum of the second) / (3P)
- *   workspace    device scratch of gs_loss_workspace_size(layout) bytes
+ *   workspace    device scratch of gs_loss_workspace_size(layout) bytes, 16-byte
+ *                aligned (9 floats per pixel of each view padded to whole
+ *                64 x 16 blocks); gs_loss_workspace_size returns 0, and the call
+ *                fails, when 9 x the padded pixels or 3 x the pixels exceed
+ *                2^31 - 1
  * Deterministic; no atomics. */
 int64_t gs_loss_blocks(const gs_layout* layout);
 size_t gs_loss_workspace_size(const gs_layout* layout);

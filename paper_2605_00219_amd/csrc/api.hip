@@ -191,7 +191,7 @@ int64_t gs_loss_blocks(const gs_layout* layout) {
 
 size_t gs_loss_workspace_size(const gs_layout* layout) {
     if (!layout_ok(layout)) return 0;
-    return (size_t)9 * sizeof(float) * (size_t)std::max<int64_t>(layout->pixel_base[layout->n_views], 1);
+    return loss_workspace(*layout);
 }
 
 int gs_loss_l1_ssim(const float* rgb, const uint8_t* target, const gs_layout* layout, float lambda,
@@ -200,6 +200,8 @@ int gs_loss_l1_ssim(const float* rgb, const uint8_t* target, const gs_layout* la
     REQUIRE(layout_ok(layout), "gs_loss_l1_ssim: invalid layout");
     REQUIRE(rgb && target && dL_dC && workspace, "gs_loss_l1_ssim: null pointer");
     REQUIRE(((uintptr_t)target & 3u) == 0, "gs_loss_l1_ssim: target not 4-byte aligned");
+    REQUIRE(((uintptr_t)workspace & 15u) == 0, "gs_loss_l1_ssim: workspace not 16-byte aligned");
+    REQUIRE(gs_loss_workspace_size(layout) > 0, "gs_loss_l1_ssim: views too large for 32-bit pixel indices");
     REQUIRE(lambda >= 0.0f && lambda <= 1.0f, "gs_loss_l1_ssim: lambda %g not in [0, 1]", (double)lambda);
     REQUIRE(workspace_bytes >= gs_loss_workspace_size(layout), "gs_loss_l1_ssim: workspace of %zu bytes, %zu needed",
             workspace_bytes, gs_loss_workspace_size(layout));

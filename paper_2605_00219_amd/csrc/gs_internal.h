@@ -60,6 +60,7 @@ int launch_mlp_train_step(float* w, const float* norm, const float* x, const flo
 int launch_order_by_cost(const float* pred, int32_t total, uint32_t* order, void* scratch,
                          hipStream_t s);
 int64_t loss_blocks(const gs_layout& L);
+size_t loss_workspace(const gs_layout& L);
 int launch_loss_l1_ssim(const float* rgb, const uint8_t* target, const gs_layout& L, float lam, int use_mask,
                         float* dLdC, float* loss_blocks_out, void* ws, hipStream_t s);
 // stable ascending sort of (key, value) pairs in place; scratch of sort_pairs_scratch(count) bytes

@@ -58,12 +58,27 @@ def test_loss_gradient_two_ragged_views(lam, mask):
     close = grad_close(g[ok], ref[ok], 1e-3)
     assert close.all(), np.argwhere(~close)[:5]
     assert loss == pytest.approx(ref_loss, rel=1e-5)
-    # per-view block sums
-    nb = [((w + 15) // 16) * ((h + 15) // 16) for w, h in sizes]
-    b0 = blocks[:nb[0]].astype(np.float64).sum(0)
-    b1 = blocks[nb[0]:nb[0] + nb[1]].astype(np.float64).sum(0)
+    # per-view sums of the (64 x 16 block, channel) units
+    nu = [3 * ((w + 63) // 64) * ((h + 15) // 16) for w, h in sizes]
+    assert blocks.shape[0] == nu[0] + nu[1]
+    b0 = blocks[:nu[0]].astype(np.float64).sum(0)
+    b1 = blocks[nu[0]:nu[0] + nu[1]].astype(np.float64).sum(0)
     np.testing.assert_allclose(b0, parts[0], rtol=1e-5)
     np.testing.assert_allclose(b1, parts[1], rtol=1e-5)
+
+
+def test_loss_gradient_small_views():
+    """Views smaller than one 64 x 16 block, and one block wider than a view."""
+    sizes = [(40, 9), (7, 30), (130, 17)]
+    note("L1 + D-SSIM loss gradient on views smaller than a block")
+    x, t = _inputs(sizes, 12)
+    g, blocks, loss = _run(_frame(sizes), x, t, 0.2, True)
+    ref_loss, ref, parts, fragile = O.loss_and_grad(x, t, sizes, lam=0.2, mask=True)
+    ok = fragile == 0
+    close = grad_close(g[ok], ref[ok], 1e-3)
+    assert close.all(), np.argwhere(~close)[:5]
+    assert loss == pytest.approx(ref_loss, rel=1e-5)
+    assert blocks.shape[0] == 3 * (1 + 2 + 3 * 2)
 
 
 def test_loss_gradient_1280x720_on_padded_crops():
@@ -76,14 +91,14 @@ def test_loss_gradient_1280x720_on_padded_crops():
     g, blocks, _ = _run(_frame([(W, H)]), x, t, 0.2, True)
     rng = np.random.default_rng(24)
     xi, ti, gi = x.reshape(H, W, 3), t.reshape(H, W, 4), g.reshape(H, W, 3)
-    bw = (W + 15) // 16
+    bw = (W + 63) // 64
     for c in range(12):
-        # a 64 x 64 region on the 16-pixel grid (corners included), margin 10
+        # a 64 x 64 region on the 64 x 16 block grid (corners included), margin 10
         if c < 4:
-            bx, by = [(0, 0), (W // 16 - 4, 0), (0, H // 16 - 4), (W // 16 - 4, H // 16 - 4)][c]
+            bx, by = [(0, 0), (W // 64 - 1, 0), (0, H // 16 - 4), (W // 64 - 1, H // 16 - 4)][c]
         else:
-            bx, by = int(rng.integers(0, W // 16 - 3)), int(rng.integers(0, H // 16 - 3))
-        x0, y0 = 16 * bx, 16 * by
+            bx, by = int(rng.integers(0, W // 64)), int(rng.integers(0, H // 16 - 3))
+        x0, y0 = 64 * bx, 16 * by
         cx0, cy0 = max(0, x0 - 10), max(0, y0 - 10)
         cx1, cy1 = min(W, x0 + 64 + 10), min(H, y0 + 64 + 10)
         cw, ch = cx1 - cx0, cy1 - cy0
@@ -96,7 +111,7 @@ def test_loss_gradient_1280x720_on_padded_crops():
         got, want, ok = gi[y0:y0 + 64, x0:x0 + 64], rc[sl], fr[sl] == 0
         close = grad_close(got[ok], want[ok], 1e-3)
         assert close.all(), (c, np.argwhere(~close)[:5])
-        # block sums of the region's 16 blocks
+        # sums of the region's 4 blocks (3 channel units each)
         s, _, _, _ = O.ssim_terms(xc.reshape(ch, cw, 3)[..., 0].astype(np.float64),
                                    tc.reshape(ch, cw, 4)[..., 0].astype(np.float64) / 255.0)
         for k in range(1, 3):
@@ -105,8 +120,8 @@ def test_loss_gradient_1280x720_on_padded_crops():
         m = tc.reshape(ch, cw, 4)[..., 3].astype(np.float64) / 255.0
         one_minus = (3.0 - s) * m
         for j in range(4):
-            for i in range(4):
-                blk = (by + j) * bw + bx + i
-                yy, xx = y0 - cy0 + 16 * j, x0 - cx0 + 16 * i
-                want_s = one_minus[yy:yy + 16, xx:xx + 16].sum()
-                assert blocks[blk, 1] == pytest.approx(want_s, rel=1e-5, abs=1e-4)
+            blk = (by + j) * bw + bx
+            yy, xx = y0 - cy0 + 16 * j, x0 - cx0
+            want_s = one_minus[yy:yy + 16, xx:xx + 64].sum()
+            got_s = blocks[3 * blk:3 * blk + 3, 1].astype(np.float64).sum()
+            assert got_s == pytest.approx(want_s, rel=1e-5, abs=1e-4)

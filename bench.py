@@ -101,8 +101,9 @@ def parse():
     ap.add_argument("--no-replay", action="store_true", help="skip the work-counting replay")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (for HBM counter scaling)")
-    ap.add_argument("--variants", default="ellipse,ssim,batched,learned",
-                    help="comma list of extra measurements: ellipse, ssim, batched, learned ('none' for none)")
+    ap.add_argument("--variants", default="ellipse,ssim,thompson,batched,learned",
+                    help="comma list of extra measurements: ellipse, ssim, thompson, batched, learned "
+                         "('none' for none)")
     ap.add_argument("--cull", type=int, default=0, choices=(0, 1),
                     help="tile set of the headline run: 0 = 3-sigma rectangle, 1 = exact ellipse")
     ap.add_argument("--batched-steps", type=int, default=200)
@@ -152,13 +153,15 @@ def main():
             targets8[i].copy_(torch.round(rgba.clamp(0, 1) * 255).to(torch.uint8))
     del tgt_model, tframe
 
-    def run_plain(cull, replay, loss="l1"):
+    def run_plain(cull, replay, loss="l1", ts_arms=None):
         """Timed plain steps (and the work-counting replay) with the given tile
         culling; loss "l1" (fused into the backward) or "ssim" (L1 + D-SSIM
         against the RGBA8 references, lambda 0.2, alpha mask)."""
         model = P.Model(w.scene.flat(), lr=w.lr)
         frame = P.Frame(n, [W], [H], 16, cull=cull)
         lossfn = P.LossL1SSIM(frame, 0.2, True) if loss == "ssim" else None
+        # backward LDS batch chosen per step by Thompson sampling over ts_arms
+        sbwd = P.ScheduledBackward(ts_arms, seed=0, prior_ms=0.3) if ts_arms else None
         kmax = 0
         for i in range(ncam):
             kmax = max(kmax, P.fit_capacity(model.params, frame, vptr(i)))
@@ -186,6 +189,8 @@ def main():
                     ev[4].record()
                 k = 5
                 P.rasterize_bwd(frame, vd, dLdC=lossfn.dLdC, lds_batch=args.lds_batch)
+            elif sbwd is not None:
+                sbwd(frame, vd, target=targets[vi])
             else:
                 P.rasterize_bwd(frame, vd, target=targets[vi], lds_batch=args.lds_batch)
             if ev is not None:
@@ -262,11 +267,19 @@ def main():
             log(f"per-step work: {counts}")
         if lossfn is not None:
             out_loss = lossfn.loss()
+        ts_out = None
+        if sbwd is not None:
+            sbwd.harvest(block=True)
+            timed = sbwd.history[-args.steps:]
+            ts_out = {"arms": list(sbwd.arms),
+                      "picks_timed": [timed.count(a) for a in range(len(sbwd.arms))],
+                      "picks_all": sbwd.ts.counts(),
+                      "posterior_mean_ms": [sbwd.ts.posterior(a)[0] for a in range(len(sbwd.arms))]}
         out = dict(stage_ms=stage_ms, ips=ips, wall=wall, counts=counts, kmax=kmax,
-                   loss=out_loss if lossfn is not None else None,
+                   loss=out_loss if lossfn is not None else None, ts=ts_out,
                    ntiles=frame.layout.total_tiles,
                    depth_first=frame.capacity >= SORT_DEPTH_FIRST_RATIO * n)
-        del model, frame, lossfn
+        del model, frame, lossfn, sbwd
         torch.cuda.empty_cache()
         return out
 
@@ -283,6 +296,12 @@ def main():
                         "traversed": c2["trav_bwd"] if c2 else None,
                         "pairs_evaluated_bwd": c2["eval_bwd"] if c2 else None,
                         "speedup_vs_rect": r2["ips"] / ips}
+    ts_variant = None
+    if "thompson" in variants:
+        r4 = run_plain(args.cull, False, ts_arms=(64, 128, 256, -128))
+        ts_variant = {"arms": "backward LDS batch 64, 128, 256, per tile (cap 128)",
+                      "iters_per_s": r4["ips"], "ms_per_step": 1e3 * r4["wall"] / args.steps,
+                      "stage_ms": r4["stage_ms"], "vs_fixed": r4["ips"] / ips, **r4["ts"]}
     ssim_variant = None
     if "ssim" in variants:
         r3 = run_plain(args.cull, False, loss="ssim")
@@ -386,6 +405,8 @@ def main():
         extra["cull_ellipse"] = cull_variant
     if ssim_variant is not None:
         extra["ssim"] = ssim_variant
+    if ts_variant is not None:
+        extra["thompson"] = ts_variant
     if "batched" in variants:
         from paper_2605_00219_amd import experiments as X
         log("batched variant: 3M Gaussians, 8 uneven views per step")

@@ -299,7 +299,12 @@ int gs_rasterize_fwd(const gs_splats* splats, int64_t n, const gs_layout* layout
  * skipped without being evaluated, and a tile's traversal ends at the last
  * entry any of its pixels composited.
  *   loss      nullable device, total tiles floats: per-tile sum |C - target|
- *             (only with `target`) */
+ *             (only with `target`)
+ *   lds_batch  Gaussians staged in LDS per batch: 32, 64, 128 or 256; or
+ *             -64, -128, -256 for a per-tile batch (Sec. 4.2): for a tile of P
+ *             pixels with N listed Gaussians, sqrt(N P) rounded up to a
+ *             multiple of 64 and capped at -lds_batch.  The batch size changes
+ *             no result, only the schedule. */
 int gs_rasterize_bwd(const gs_splats* splats, int64_t n, const gs_layout* layout,
                      const gs_bins* bins, const gs_view* views, const gs_image* fwd,
                      const float* target, const float* dL_dC, const gs_grads2d* grads,
@@ -381,6 +386,41 @@ int gs_mlp_train_step(float* weights, const float* norm, const float* features,
 size_t gs_order_by_cost_scratch_size(int32_t total_tiles);
 int gs_order_by_cost(const float* predicted, int32_t total_tiles, uint32_t* order, void* scratch,
                      void* stream);
+
+/* Thompson-sampling choice among rasterisation-backward variants (Sec. 4.2:
+ * a latency belief per implementation, a random choice favouring the faster
+ * ones, a belief update from each measured latency).  Host code, no GPU.
+ * Each arm's latencies are Normal(mu, 1/tau) under the conjugate Normal-Gamma
+ * prior (mu0, kappa0, alpha0, beta0); after n observations with mean xbar and
+ * squared deviations m2:
+ *   kappa_n = kappa0 + n, mu_n = (kappa0 mu0 + n xbar) / kappa_n,
+ *   alpha_n = alpha0 + n/2, beta_n = beta0 + m2/2 + kappa0 n (xbar - mu0)^2 / (2 kappa_n).
+ * gs_ts_select draws tau ~ Gamma(alpha_n, rate beta_n) and mu ~ Normal(mu_n,
+ * 1/(kappa_n tau)) per arm and returns the arm with the smallest mu (or a
+ * negative GS_ERR_*).  Random numbers come from the splitmix64 sequence seeded
+ * by `seed`, so a state replays exactly.  The caller owns the state; calls on
+ * one state must not overlap.
+ *   gs_ts_init       prior: finite mu0, kappa0 > 0, alpha0 >= 1, beta0 > 0;
+ *                    1 <= n_arms <= GS_TS_MAX_ARMS
+ *   gs_ts_update     folds one measured latency of `arm` into its belief
+ *   gs_ts_posterior  out[4] = (mu_n, kappa_n, alpha_n, beta_n) of `arm`
+ *   gs_ts_sample     one draw of `arm`'s mean latency (NaN for an invalid arm) */
+#define GS_TS_MAX_ARMS 8
+typedef struct gs_ts_state {
+    int32_t n_arms;
+    int32_t reserved;
+    uint64_t rng;                              /* splitmix64 state */
+    double mu0, kappa0, alpha0, beta0;         /* prior */
+    double n[GS_TS_MAX_ARMS];                  /* observations per arm */
+    double mean[GS_TS_MAX_ARMS];               /* their running mean */
+    double m2[GS_TS_MAX_ARMS];                 /* their sum of squared deviations */
+} gs_ts_state;
+int gs_ts_init(gs_ts_state* st, int n_arms, uint64_t seed, double mu0, double kappa0, double alpha0,
+               double beta0);
+int gs_ts_select(gs_ts_state* st);
+int gs_ts_update(gs_ts_state* st, int arm, double latency);
+int gs_ts_posterior(const gs_ts_state* st, int arm, double* out);
+double gs_ts_sample(gs_ts_state* st, int arm);
 
 #ifdef __cplusplus
 }

@@ -70,6 +70,16 @@ class GsAdam(C.Structure):
                 ("lr", C.c_float * 6), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float)]
 
 
+TS_MAX_ARMS = 8
+
+
+class GsTsState(C.Structure):
+    _fields_ = [("n_arms", C.c_int32), ("reserved", C.c_int32), ("rng", C.c_uint64),
+                ("mu0", C.c_double), ("kappa0", C.c_double), ("alpha0", C.c_double), ("beta0", C.c_double),
+                ("n", C.c_double * TS_MAX_ARMS), ("mean", C.c_double * TS_MAX_ARMS),
+                ("m2", C.c_double * TS_MAX_ARMS)]
+
+
 _P = C.c_void_p
 _SIGS = {
     "gs_version": (C.c_int, []),
@@ -99,6 +109,12 @@ _SIGS = {
     "gs_loss_workspace_size": (C.c_size_t, [C.POINTER(GsLayout)]),
     "gs_loss_l1_ssim": (C.c_int, [_P, _P, C.POINTER(GsLayout), C.c_float, C.c_int, _P, _P, _P, C.c_size_t,
                                   _P]),
+    "gs_ts_init": (C.c_int, [C.POINTER(GsTsState), C.c_int, C.c_uint64, C.c_double, C.c_double, C.c_double,
+                             C.c_double]),
+    "gs_ts_select": (C.c_int, [C.POINTER(GsTsState)]),
+    "gs_ts_update": (C.c_int, [C.POINTER(GsTsState), C.c_int, C.c_double]),
+    "gs_ts_posterior": (C.c_int, [C.POINTER(GsTsState), C.c_int, C.POINTER(C.c_double)]),
+    "gs_ts_sample": (C.c_double, [C.POINTER(GsTsState), C.c_int]),
 }
 EXPORTS = tuple(_SIGS)
 

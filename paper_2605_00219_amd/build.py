@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgs.so")
-SOURCES = ["api.hip", "project.hip", "binning.hip", "raster.hip", "adam.hip", "mlp.hip", "loss.hip"]
+SOURCES = ["api.hip", "project.hip", "binning.hip", "raster.hip", "adam.hip", "mlp.hip", "loss.hip", "thompson.hip"]
 ARCH = os.environ.get("GS_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

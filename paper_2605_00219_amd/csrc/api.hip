@@ -160,8 +160,9 @@ int gs_rasterize_bwd(const gs_splats* splats, int64_t n, const gs_layout* layout
             "gs_rasterize_bwd: give exactly one of target (fused L1) and dL_dC");
     REQUIRE(grads && grads->tile_stop && ((grads->rec && grads->rec_mask) || bins->capacity == 0),
             "gs_rasterize_bwd: null gradient buffers");
-    REQUIRE(lds_batch == 32 || lds_batch == 64 || lds_batch == 128 || lds_batch == 256,
-            "gs_rasterize_bwd: lds_batch %d not in {32, 64, 128, 256}", lds_batch);
+    REQUIRE(lds_batch == 32 || lds_batch == 64 || lds_batch == 128 || lds_batch == 256 || lds_batch == -64 ||
+                lds_batch == -128 || lds_batch == -256,
+            "gs_rasterize_bwd: lds_batch %d not in {32, 64, 128, 256, -64, -128, -256}", lds_batch);
     int rc = check_sched(sched);
     if (rc != GS_OK) return rc;
     return launch_raster_bwd(*splats, n, *layout, *bins, views, *fwd, target, dL_dC, *grads, loss,

@@ -64,6 +64,7 @@ struct RasterArgs {
     int64_t row_capacity;
     float* loss;
     int64_t capacity;
+    int adaptive_batch;     // backward: per-tile batch ceil(sqrt(N P)) to a multiple of 64, capped at S
 };
 
 // Staged splat: (u, v, -A log2e / 2, -B log2e), (-C log2e / 2, o, r, g), b
@@ -488,11 +489,20 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd(RasterArgs a)
         }
         __syncthreads();
         const uint32_t stop = start + s_len;
-        for (uint32_t b0 = start; b0 < stop; b0 += S) {
+        // batch size: S, or per tile the S_t minimising (batches) x (entries
+        // per batch) for N listed Gaussians and P pixels (Sec. 4.2):
+        // sqrt(N P) rounded up to a wavefront multiple, at most S
+        uint32_t St = (uint32_t)S;
+        if (a.adaptive_batch) {
+            const uint64_t np = (uint64_t)(ti.range.y - ti.range.x) * (uint64_t)(TILE * TILE);
+            St = kWave;
+            while (St < (uint32_t)S && (uint64_t)St * St < np) St += kWave;
+        }
+        for (uint32_t b0 = start; b0 < stop; b0 += St) {
             __syncthreads();
             // the forward's composite mask for positions [b0, bend): only
             // entries some pixel of the tile composited are staged, in order
-            const uint32_t bend = min(b0 + (uint32_t)S, stop);
+            const uint32_t bend = min(b0 + St, stop);
             const uint32_t w0 = b0 >> 5, nwd = ((bend - 1) >> 5) - w0 + 1;
             if (threadIdx.x < nwd) {
                 const uint32_t wb = (w0 + threadIdx.x) << 5;
@@ -504,7 +514,7 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd(RasterArgs a)
             __syncthreads();
             int cnt = 0;
             for (uint32_t q = 0; q < nwd; ++q) cnt += __popc(s_mw[q]);
-            for (int i = threadIdx.x; i < S; i += NT) {
+            for (int i = threadIdx.x; i < (int)St; i += NT) {
                 const uint32_t j = b0 + i;
                 if (j < bend) {
                     const uint32_t rel = j - (w0 << 5), wq = rel >> 5, bq = rel & 31u;
@@ -756,6 +766,15 @@ int launch_raster_bwd(const gs_splats& sp, int64_t n, const gs_layout& L, const 
     a.row_offsets = b.row_offsets;
     a.rows = reinterpret_cast<const uint4*>(b.rows);
     a.row_capacity = b.row_capacity;
+    // a negative batch selects the per-tile batch with cap -lds_batch
+    a.adaptive_batch = lds_batch < 0;
+    if (lds_batch < 0) {
+        lds_batch = -lds_batch;
+        if (lds_batch < kWave) {
+            set_error("an adaptive lds_batch needs a cap of at least 64 (got %d)", lds_batch);
+            return GS_ERR_INVALID_ARG;
+        }
+    }
     if (a.total_tiles == 0) return GS_OK;
     int rc = launch_fill_u32(a.rec_mask, 0u, (b.capacity + 31) / 32, s);
     if (rc != GS_OK) return rc;

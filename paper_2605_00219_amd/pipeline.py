@@ -224,6 +224,74 @@ class LossL1SSIM:
         return float(((1 - self.lam) * b[0] + self.lam * b[1]).item()) / (3.0 * P)
 
 
+class ThompsonScheduler:
+    """Latency beliefs over a set of arms (gs_ts_*); host state, no GPU."""
+
+    def __init__(self, n_arms: int, seed: int = 0, mu0: float = 0.0, kappa0: float = 1e-3,
+                 alpha0: float = 1.0, beta0: float = 1e-4):
+        self.state = G.GsTsState()
+        G.check(G.lib.gs_ts_init(C.byref(self.state), int(n_arms), int(seed), float(mu0), float(kappa0),
+                                 float(alpha0), float(beta0)), "gs_ts_init")
+
+    def select(self) -> int:
+        a = G.lib.gs_ts_select(C.byref(self.state))
+        G.check(0 if a >= 0 else a, "gs_ts_select")
+        return a
+
+    def update(self, arm: int, latency: float) -> None:
+        G.check(G.lib.gs_ts_update(C.byref(self.state), int(arm), float(latency)), "gs_ts_update")
+
+    def posterior(self, arm: int):
+        out = (C.c_double * 4)()
+        G.check(G.lib.gs_ts_posterior(C.byref(self.state), int(arm), out), "gs_ts_posterior")
+        return tuple(out)
+
+    def sample(self, arm: int) -> float:
+        return float(G.lib.gs_ts_sample(C.byref(self.state), int(arm)))
+
+    def counts(self):
+        return [int(self.state.n[a]) for a in range(self.state.n_arms)]
+
+
+class ScheduledBackward:
+    """rasterize_bwd whose LDS batch (fixed, or per tile when negative) is chosen
+    per call by Thompson sampling on measured latency (Sec. 4.2).  Each call is
+    bracketed by two events on the launch stream; finished calls are folded into
+    the belief at later calls without synchronising."""
+
+    def __init__(self, arms=(64, 128, 256, -128), seed: int = 0, prior_ms: float = 0.3):
+        import collections
+        self.arms = tuple(int(a) for a in arms)
+        # weak prior centred on prior_ms, standard deviation about 10 % of it
+        self.ts = ThompsonScheduler(len(self.arms), seed, mu0=prior_ms, kappa0=1e-3, alpha0=1.0,
+                                    beta0=(0.1 * prior_ms) ** 2)
+        self.pending = collections.deque()
+        self.history = []
+
+    def harvest(self, block: bool = False) -> None:
+        while self.pending:
+            arm, e0, e1 = self.pending[0]
+            if not block and not e1.query():
+                break
+            e1.synchronize()
+            self.pending.popleft()
+            self.ts.update(arm, e0.elapsed_time(e1))
+
+    def __call__(self, frame: Frame, views_dev: torch.Tensor, target=None, dLdC=None, sched=None,
+                 stream=None) -> int:
+        self.harvest()
+        arm = self.ts.select()
+        s = stream if stream is not None else torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        rasterize_bwd(frame, views_dev, target=target, dLdC=dLdC, lds_batch=self.arms[arm], sched=sched,
+                      stream=s)
+        e1.record(s)
+        self.pending.append((arm, e0, e1))
+        self.history.append(arm)
+        return arm
+
+
 def project_bwd_adam(model: Model, frame: Frame, views_dev: torch.Tensor, adam: bool = True,
                      grads_out: torch.Tensor | None = None, stream=None) -> None:
     G.check(G.lib.gs_project_bwd_adam(_i(model.params), frame.n, _i(views_dev), C.byref(frame.layout),
@@ -272,8 +340,10 @@ def render(params: torch.Tensor, frame: Frame, views_dev: torch.Tensor, lds_batc
 
 def train_step(model: Model, frame: Frame, views_dev: torch.Tensor, target: torch.Tensor,
                lds_batch: int = 64, sched=None, check: bool = True,
-               grads_out: torch.Tensor | None = None, adam: bool = True) -> None:
-    """One L1 training step over the frame's views: 5 stages, gradients summed over views."""
+               grads_out: torch.Tensor | None = None, adam: bool = True,
+               bwd_batch: int | None = None) -> None:
+    """One L1 training step over the frame's views: 5 stages, gradients summed over views.
+    bwd_batch: the backward's LDS batch if not lds_batch (negative: per-tile batch)."""
     project(model.params, frame, views_dev)
     bin_sort(frame)
     if check and frame.status_bits():
@@ -282,7 +352,7 @@ def train_step(model: Model, frame: Frame, views_dev: torch.Tensor, target: torc
         if frame.status_bits():
             raise G.GsError(f"intersection status {frame.status_bits()} after resize")
     rasterize_fwd(frame, views_dev, lds_batch, sched)
-    rasterize_bwd(frame, views_dev, target=target, lds_batch=lds_batch, sched=sched)
+    rasterize_bwd(frame, views_dev, target=target, lds_batch=bwd_batch or lds_batch, sched=sched)
     project_bwd_adam(model, frame, views_dev, adam=adam, grads_out=grads_out)
 
 

@@ -16,7 +16,7 @@ def u32(t) -> np.ndarray:
 
 def run_gpu_step(scene, views, tile, target=None, lds_batch=64, lr=1e-3, adam=True, grads=True,
                  capacity=None, sched_order=None, persistent=False, tile_stats=False, steps=1,
-                 pixels_per_lane=None, cull=0):
+                 pixels_per_lane=None, cull=0, bwd_batch=None):
     import torch
     from paper_2605_00219_amd import pipeline as P
     n = scene.n
@@ -40,7 +40,8 @@ def run_gpu_step(scene, views, tile, target=None, lds_batch=64, lr=1e-3, adam=Tr
         if tgt is None:
             P.render(model.params, frame, vd, lds_batch, sched)
         else:
-            P.train_step(model, frame, vd, tgt, lds_batch, sched, grads_out=gout, adam=adam)
+            P.train_step(model, frame, vd, tgt, lds_batch, sched, grads_out=gout, adam=adam,
+                         bwd_batch=bwd_batch)
     torch.cuda.synchronize()
     out = dict(frame=frame, model=model)
     out["status"] = frame.status_bits()

@@ -236,6 +236,54 @@ def test_persistent_and_permuted_schedules_change_no_bit():
             np.testing.assert_array_equal(base[k], other[k], err_msg=str(kw))
 
 
+@pytest.mark.parametrize("name", ["plain-2k-256", "ragged-2view"])
+def test_backward_batch_changes_no_bit(name):
+    """The backward's LDS batch -- fixed 64 / 256, or per tile sqrt(N P) to a
+    multiple of 64 capped at 64, 128, 256 -- changes the schedule, not a bit."""
+    scene, target_scene, views, tile = WL[name]
+    note(f"backward batch invariance {name}")
+    target = oracle.render(target_scene, views, tile)
+    base = run_gpu_step(scene, views, tile, target=target, lds_batch=128)
+    for bb in (64, 256, -64, -128, -256):
+        other = run_gpu_step(scene, views, tile, target=target, lds_batch=128, bwd_batch=bb)
+        for k in ("grec", "rec_mask", "tile_stop", "sums", "grads", "params"):
+            np.testing.assert_array_equal(base[k], other[k], err_msg=f"bwd_batch={bb} {k}")
+
+
+def test_thompson_scheduled_backward_trains_the_same_bits():
+    """Six training steps whose backward batch is chosen by Thompson sampling
+    end with the parameters of six fixed-batch steps, bit for bit."""
+    import torch
+    from paper_2605_00219_amd import pipeline as P
+    scene, target_scene, views, tile = WL["ragged-2view"]
+    note("Thompson-scheduled backward, 6 steps")
+    target = torch.as_tensor(np.ascontiguousarray(oracle.render(target_scene, views, tile), np.float32),
+                             device="cuda").reshape(-1, 3)
+    vd = P.views_to_device(views)
+    outs = []
+    for scheduled in (False, True):
+        model = P.Model(scene.flat())
+        frame = P.Frame(scene.n, [int(v["width"]) for v in views], [int(v["height"]) for v in views], tile)
+        P.fit_capacity(model.params, frame, vd)
+        sbwd = P.ScheduledBackward((64, 128, 256, -128), seed=2, prior_ms=0.05) if scheduled else None
+        for _ in range(6):
+            P.project(model.params, frame, vd)
+            P.bin_sort(frame)
+            P.rasterize_fwd(frame, vd, 128)
+            if sbwd is None:
+                P.rasterize_bwd(frame, vd, target=target, lds_batch=128)
+            else:
+                sbwd(frame, vd, target=target)
+            P.project_bwd_adam(model, frame, vd)
+        torch.cuda.synchronize()
+        assert frame.status_bits() == 0
+        outs.append(model.params.cpu().numpy())
+        if sbwd is not None:
+            sbwd.harvest(block=True)
+            assert sum(sbwd.ts.counts()) == 6 and len(set(sbwd.history)) > 1
+    np.testing.assert_array_equal(outs[0], outs[1])
+
+
 @pytest.mark.parametrize("tile,ppl", [(8, 1), (32, 1), (32, 2), (32, 4)])
 def test_other_tile_sizes(tile, ppl):
     scene, target_scene, views, _ = WL["ragged-2view"]
@@ -307,6 +355,10 @@ def test_invalid_arguments_raise():
     vd = P.views_to_device(views)
     with pytest.raises(G.GsError, match="lds_batch"):
         P.rasterize_fwd(frame, vd, lds_batch=48)
+    with pytest.raises(G.GsError, match="lds_batch"):
+        P.rasterize_fwd(frame, vd, lds_batch=-128)     # the per-tile batch is the backward's
+    with pytest.raises(G.GsError, match="lds_batch"):
+        P.rasterize_bwd(frame, vd, dLdC=frame.image, lds_batch=-32)
     with pytest.raises(G.GsError, match="exactly one"):
         P.rasterize_bwd(frame, vd, target=None, dLdC=None)
 

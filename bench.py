@@ -101,9 +101,9 @@ def parse():
     ap.add_argument("--no-replay", action="store_true", help="skip the work-counting replay")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (for HBM counter scaling)")
-    ap.add_argument("--variants", default="ellipse,ssim,thompson,batched,learned",
-                    help="comma list of extra measurements: ellipse, ssim, thompson, batched, learned "
-                         "('none' for none)")
+    ap.add_argument("--variants", default="ellipse,ssim,twophase,thompson,batched,learned",
+                    help="comma list of extra measurements: ellipse, ssim, twophase, thompson, batched, "
+                         "learned ('none' for none)")
     ap.add_argument("--cull", type=int, default=0, choices=(0, 1),
                     help="tile set of the headline run: 0 = 3-sigma rectangle, 1 = exact ellipse")
     ap.add_argument("--batched-steps", type=int, default=200)
@@ -153,7 +153,7 @@ def main():
             targets8[i].copy_(torch.round(rgba.clamp(0, 1) * 255).to(torch.uint8))
     del tgt_model, tframe
 
-    def run_plain(cull, replay, loss="l1", ts_arms=None):
+    def run_plain(cull, replay, loss="l1", ts_arms=None, bwd_variant=None):
         """Timed plain steps (and the work-counting replay) with the given tile
         culling; loss "l1" (fused into the backward) or "ssim" (L1 + D-SSIM
         against the RGBA8 references, lambda 0.2, alpha mask)."""
@@ -191,6 +191,8 @@ def main():
                 P.rasterize_bwd(frame, vd, dLdC=lossfn.dLdC, lds_batch=args.lds_batch)
             elif sbwd is not None:
                 sbwd(frame, vd, target=targets[vi])
+            elif bwd_variant is not None:
+                P.backward(frame, vd, bwd_variant, target=targets[vi])
             else:
                 P.rasterize_bwd(frame, vd, target=targets[vi], lds_batch=args.lds_batch)
             if ev is not None:
@@ -271,7 +273,7 @@ def main():
         if sbwd is not None:
             sbwd.harvest(block=True)
             timed = sbwd.history[-args.steps:]
-            ts_out = {"arms": list(sbwd.arms),
+            ts_out = {"arms": [str(a) for a in sbwd.arms],
                       "picks_timed": [timed.count(a) for a in range(len(sbwd.arms))],
                       "picks_all": sbwd.ts.counts(),
                       "posterior_mean_ms": [sbwd.ts.posterior(a)[0] for a in range(len(sbwd.arms))]}
@@ -296,10 +298,19 @@ def main():
                         "traversed": c2["trav_bwd"] if c2 else None,
                         "pairs_evaluated_bwd": c2["eval_bwd"] if c2 else None,
                         "speedup_vs_rect": r2["ips"] / ips}
+    tp_variant = None
+    if "twophase" in variants:
+        tp_variant = {}
+        for S in (16, 32):
+            r5 = run_plain(args.cull, False, bwd_variant=("twophase", S))
+            tp_variant[f"S{S}"] = {"iters_per_s": r5["ips"], "ms_per_step": 1e3 * r5["wall"] / args.steps,
+                                   "rasterize_bwd_ms": r5["stage_ms"]["rasterize_bwd"],
+                                   "vs_first_backward": stage_ms["rasterize_bwd"] / r5["stage_ms"]["rasterize_bwd"]}
     ts_variant = None
     if "thompson" in variants:
-        r4 = run_plain(args.cull, False, ts_arms=(64, 128, 256, -128))
-        ts_variant = {"arms": "backward LDS batch 64, 128, 256, per tile (cap 128)",
+        r4 = run_plain(args.cull, False, ts_arms=(128, 256, -128, ("twophase", 16), ("twophase", 32)))
+        ts_variant = {"arms": "first backward with LDS batch 128, 256, per tile (cap 128); two-phase "
+                              "backward with batch 16, 32",
                       "iters_per_s": r4["ips"], "ms_per_step": 1e3 * r4["wall"] / args.steps,
                       "stage_ms": r4["stage_ms"], "vs_fixed": r4["ips"] / ips, **r4["ts"]}
     ssim_variant = None
@@ -407,6 +418,8 @@ def main():
         extra["ssim"] = ssim_variant
     if ts_variant is not None:
         extra["thompson"] = ts_variant
+    if tp_variant is not None:
+        extra["twophase"] = tp_variant
     if "batched" in variants:
         from paper_2605_00219_amd import experiments as X
         log("batched variant: 3M Gaussians, 8 uneven views per step")

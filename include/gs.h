@@ -310,6 +310,19 @@ int gs_rasterize_bwd(const gs_splats* splats, int64_t n, const gs_layout* layout
                      const float* target, const float* dL_dC, const gs_grads2d* grads,
                      float* loss, int lds_batch, const gs_schedule* sched, void* stream);
 
+/* Rasterisation backward, two-phase form (Sec. 4.2, the second
+ * implementation): per batch of lds_batch (16 or 32) entries some pixel
+ * composited, a pixel-parallel pass recomputes transmittance front to back and
+ * stores, per (entry, pixel), dL/dpower and alpha T in LDS; a Gaussian-
+ * parallel pass then sums them over the tile's pixels into the entry's record
+ * (no cross-lane reductions).  Same arguments, outputs and record format as
+ * gs_rasterize_bwd (the records agree with it up to float summation order);
+ * 8x8 and 16x16 tiles only. */
+int gs_rasterize_bwd_twophase(const gs_splats* splats, int64_t n, const gs_layout* layout,
+                              const gs_bins* bins, const gs_view* views, const gs_image* fwd,
+                              const float* target, const float* dL_dC, const gs_grads2d* grads,
+                              float* loss, int lds_batch, const gs_schedule* sched, void* stream);
+
 /* Fused L1 + D-SSIM loss gradient against an RGBA8 reference (Sec. 4.5: the
  * weighted sum of the L1 and SSIM losses in one fused evaluation, the reference
  * kept as 4 x uint8, alpha masking fused):

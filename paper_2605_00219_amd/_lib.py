@@ -96,6 +96,9 @@ _SIGS = {
     "gs_rasterize_bwd": (C.c_int, [C.POINTER(GsSplats), C.c_int64, C.POINTER(GsLayout),
                                    C.POINTER(GsBins), _P, C.POINTER(GsImage), _P, _P,
                                    C.POINTER(GsGrads2d), _P, C.c_int, C.POINTER(GsSchedule), _P]),
+    "gs_rasterize_bwd_twophase": (C.c_int, [C.POINTER(GsSplats), C.c_int64, C.POINTER(GsLayout),
+                                            C.POINTER(GsBins), _P, C.POINTER(GsImage), _P, _P,
+                                            C.POINTER(GsGrads2d), _P, C.c_int, C.POINTER(GsSchedule), _P]),
     "gs_project_bwd_adam": (C.c_int, [_P, C.c_int64, _P, C.POINTER(GsLayout), C.POINTER(GsSplats),
                                       C.POINTER(GsBins), C.POINTER(GsGrads2d), C.POINTER(GsAdam),
                                       _P, _P]),

@@ -169,6 +169,27 @@ int gs_rasterize_bwd(const gs_splats* splats, int64_t n, const gs_layout* layout
                              lds_batch, sched, (hipStream_t)stream);
 }
 
+int gs_rasterize_bwd_twophase(const gs_splats* splats, int64_t n, const gs_layout* layout,
+                              const gs_bins* bins, const gs_view* views, const gs_image* fwd,
+                              const float* target, const float* dL_dC, const gs_grads2d* grads,
+                              float* loss, int lds_batch, const gs_schedule* sched, void* stream) {
+    REQUIRE(layout_ok(layout), "gs_rasterize_bwd_twophase: invalid layout");
+    REQUIRE(splats && bins && views && fwd && fwd->rgb && fwd->last &&
+            (fwd->comp_mask || bins->capacity == 0), "gs_rasterize_bwd_twophase: null pointer");
+    REQUIRE((target != nullptr) != (dL_dC != nullptr),
+            "gs_rasterize_bwd_twophase: give exactly one of target (fused L1) and dL_dC");
+    REQUIRE(grads && grads->tile_stop && ((grads->rec && grads->rec_mask) || bins->capacity == 0),
+            "gs_rasterize_bwd_twophase: null gradient buffers");
+    REQUIRE(lds_batch == 16 || lds_batch == 32, "gs_rasterize_bwd_twophase: lds_batch %d not in {16, 32}",
+            lds_batch);
+    REQUIRE(layout->tile == 8 || layout->tile == 16, "gs_rasterize_bwd_twophase: tile %d not in {8, 16}",
+            layout->tile);
+    int rc = check_sched(sched);
+    if (rc != GS_OK) return rc;
+    return launch_raster_bwd2(*splats, n, *layout, *bins, views, *fwd, target, dL_dC, *grads, loss,
+                              lds_batch, sched, (hipStream_t)stream);
+}
+
 int gs_project_bwd_adam(float* params, int64_t n, const gs_view* views, const gs_layout* layout,
                         const gs_splats* splats, const gs_bins* bins, const gs_grads2d* grads,
                         const gs_adam* adam, float* grads_out, void* stream) {

@@ -46,6 +46,10 @@ int launch_raster_bwd(const gs_splats& sp, int64_t n, const gs_layout& L, const 
                       const gs_view* views, const gs_image& fwd, const float* target,
                       const float* dLdC, const gs_grads2d& grads, float* loss, int lds_batch,
                       const gs_schedule* sched, hipStream_t s);
+int launch_raster_bwd2(const gs_splats& sp, int64_t n, const gs_layout& L, const gs_bins& b,
+                       const gs_view* views, const gs_image& fwd, const float* target,
+                       const float* dLdC, const gs_grads2d& grads, float* loss, int lds_batch,
+                       const gs_schedule* sched, hipStream_t s);
 int launch_project_bwd_adam(float* params, int64_t n, const gs_view* views, const gs_layout& L,
                             const gs_splats& splats, const gs_bins& b, const gs_grads2d& grads,
                             const gs_adam* adam, float* grads_out, hipStream_t s);

@@ -659,6 +659,219 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd(RasterArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// backward, two-phase form (Sec. 4.2, second implementation)
+// ---------------------------------------------------------------------------
+// Per batch of S staged entries: a pixel-parallel pass runs through the batch
+// front to back, recomputing transmittance, and stores per (entry, pixel)
+// u = dL/dpower and w = alpha T in LDS; then a Gaussian-parallel pass sums,
+// for each entry, u (1, dx, dy, dx^2, dx dy, dy^2) and w g over the tile's
+// pixels (the 9 sums of the record).  No cross-lane reductions: thread t sums
+// entry t % S over the pixels i J + t / S (J = NT / S slices), and the slices'
+// partial sums are added in slice order.  The pair evaluation is the
+// forward's (offsets from the mean), so composite decisions agree with it.
+
+template <int TILE, int S, int PPT_>
+__global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd2(RasterArgs a) {
+    constexpr int PPT = PPT_, NT = Geo<TILE, PPT_>::NT;
+    constexpr int NP = TILE * TILE;
+    constexpr int UP = NP + 1;           // row pitch of the per-pair arrays (entries on distinct banks)
+    constexpr int J = NT / S;            // pixel slices per entry in the Gaussian-parallel pass
+    static_assert(NT % S == 0 && NP % J == 0, "whole slices");
+    __shared__ float4 s_g[S];
+    __shared__ float4 s_h[S];
+    __shared__ float s_b[S];
+    __shared__ uint32_t s_gid[S];
+    __shared__ uint32_t s_idx[S];
+    __shared__ uint32_t s_mw[S / 32 + 2];
+    __shared__ float s_u[S * UP];        // dL/dpower per (entry, pixel)
+    __shared__ float s_w[S * UP];        // alpha T per (entry, pixel)
+    __shared__ float s_gp[3][NP];        // dL/dC per pixel
+    __shared__ float s_part[J][S][9];    // per-slice sums
+    __shared__ int s_tile;
+    __shared__ uint32_t s_len;
+    __shared__ float s_loss[NT / kWave];
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    for (;;) {
+        const int gt = next_tile(a, &s_tile);
+        if (gt == -1 || (gt == -2 && a.counter == nullptr)) break;
+        if (gt == -2) continue;
+        const TileInfo ti = tile_info(a, gt);
+        const uint32_t start = ti.range.x;
+        float px[PPT], py[PPT], g0[PPT], g1[PPT], g2[PPT], T[PPT], R[PPT];
+        uint32_t lastp[PPT];
+        float l1 = 0.0f;
+        uint32_t mylen = 0;
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            const int p = Geo<TILE, PPT_>::pixel((int)threadIdx.x, q);
+            const int ix = ti.tx * TILE + p % TILE, iy = ti.ty * TILE + p / TILE;
+            px[q] = (float)ix + 0.5f;
+            py[q] = (float)iy + 0.5f;
+            g0[q] = g1[q] = g2[q] = 0.0f;
+            T[q] = 1.0f; R[q] = 0.0f;
+            lastp[q] = 0;
+            if (ix < ti.W && iy < ti.H) {
+                const int64_t pix = ti.pix_base + (int64_t)iy * ti.W + ix;
+                const float Co0 = a.out_rgb[3 * pix + 0];
+                const float Co1 = a.out_rgb[3 * pix + 1];
+                const float Co2 = a.out_rgb[3 * pix + 2];
+                lastp[q] = a.out_last[pix];
+                if (a.target) {
+                    const float d0 = Co0 - a.target[3 * pix + 0];
+                    const float d1 = Co1 - a.target[3 * pix + 1];
+                    const float d2 = Co2 - a.target[3 * pix + 2];
+                    g0[q] = d0 > 0.0f ? a.inv_count : (d0 < 0.0f ? -a.inv_count : 0.0f);
+                    g1[q] = d1 > 0.0f ? a.inv_count : (d1 < 0.0f ? -a.inv_count : 0.0f);
+                    g2[q] = d2 > 0.0f ? a.inv_count : (d2 < 0.0f ? -a.inv_count : 0.0f);
+                    l1 += (fabsf(d0) + fabsf(d1)) + fabsf(d2);
+                } else {
+                    g0[q] = a.dLdC[3 * pix + 0];
+                    g1[q] = a.dLdC[3 * pix + 1];
+                    g2[q] = a.dLdC[3 * pix + 2];
+                }
+                R[q] = __builtin_fmaf(g2[q], Co2, __builtin_fmaf(g1[q], Co1, g0[q] * Co0));
+            }
+            mylen = max(mylen, lastp[q]);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) s_len = 0;
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            const int p = Geo<TILE, PPT_>::pixel((int)threadIdx.x, q);
+            s_gp[0][p] = g0[q];
+            s_gp[1][p] = g1[q];
+            s_gp[2][p] = g2[q];
+        }
+        if (a.loss) {
+            float sl = l1;
+            for (int off = 32; off > 0; off >>= 1) sl += __shfl_xor(sl, off);
+            if (lane == 0) s_loss[w] = sl;
+        }
+        __syncthreads();
+        atomicMax(&s_len, mylen);
+        if (a.loss && threadIdx.x == 0) {
+            float sl = 0.0f;
+            for (int i = 0; i < NT / kWave; ++i) sl += s_loss[i];
+            a.loss[gt] = sl;
+        }
+        __syncthreads();
+        const uint32_t stop = start + s_len;
+        for (uint32_t b0 = start; b0 < stop; b0 += S) {
+            __syncthreads();
+            // stage the entries of [b0, bend) some pixel composited, in order
+            const uint32_t bend = min(b0 + (uint32_t)S, stop);
+            const uint32_t w0 = b0 >> 5, nwd = ((bend - 1) >> 5) - w0 + 1;
+            if (threadIdx.x < nwd) {
+                const uint32_t wb = (w0 + threadIdx.x) << 5;
+                uint32_t m = a.comp_mask[w0 + threadIdx.x];
+                if (wb < b0) m &= ~0u << (b0 - wb);
+                if (bend - wb < 32u) m &= (1u << (bend - wb)) - 1u;
+                s_mw[threadIdx.x] = m;
+            }
+            __syncthreads();
+            int cnt = 0;
+            for (uint32_t q = 0; q < nwd; ++q) cnt += __popc(s_mw[q]);
+            for (int i = threadIdx.x; i < S; i += NT) {
+                const uint32_t j = b0 + i;
+                if (j < bend) {
+                    const uint32_t rel = j - (w0 << 5), wq = rel >> 5, bq = rel & 31u;
+                    if ((s_mw[wq] >> bq) & 1u) {
+                        int slot = __popc(s_mw[wq] & ((1u << bq) - 1u));
+                        for (uint32_t q = 0; q < wq; ++q) slot += __popc(s_mw[q]);
+                        uint32_t gid;
+                        stage_splat(a, ti.view, j, s_g[slot], s_h[slot], s_b[slot], gid);
+                        s_gid[slot] = gid;
+                        s_idx[slot] = unsorted_index(a, ti.view, gid, ti.tx, ti.ty);
+                    }
+                }
+            }
+            __syncthreads();
+            // pixel-parallel pass: per staged entry in order, this thread's pixels
+            {
+                int k = 0;
+                for (uint32_t q = 0; q < nwd && k < cnt; ++q) {
+                    for (uint32_t m = s_mw[q]; m != 0u; m &= m - 1u, ++k) {
+                        const uint32_t pos = ((w0 + q) << 5) + (uint32_t)__builtin_ctz(m) - start;
+                        const float4 sg = s_g[k];
+                        const float4 sh = s_h[k];
+                        const float cb = s_b[k];
+#pragma unroll
+                        for (int qq = 0; qq < PPT; ++qq) {
+                            float dx, dy, G, ag;
+                            const bool in = eval_pair(px[qq], py[qq], sg, sh, dx, dy, G, ag);
+                            const float al = fminf(kAlphaMax, ag);
+                            const bool c = pos < lastp[qq] && in && al >= kAlphaMin;
+                            const float ae = c ? al : 0.0f;
+                            const float wgt = ae * T[qq];
+                            const float gc = __builtin_fmaf(g2[qq], cb, __builtin_fmaf(g1[qq], sh.w, g0[qq] * sh.z));
+                            R[qq] = __builtin_fmaf(-wgt, gc, R[qq]);
+                            const float inv1m = __builtin_amdgcn_rcpf(1.0f - al);
+                            const float dalpha = __builtin_fmaf(T[qq], gc, -(R[qq] * inv1m));
+                            const float agc = (ag > kAlphaMax) ? 0.0f : ae;
+                            const int p = Geo<TILE, PPT_>::pixel((int)threadIdx.x, qq);
+                            s_u[k * UP + p] = agc * dalpha;
+                            s_w[k * UP + p] = wgt;
+                            T[qq] = T[qq] - wgt;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            // Gaussian-parallel pass: entry t % S over pixels i J + t / S
+            {
+                const int k = threadIdx.x % S, j = threadIdx.x / S;
+                float r0 = 0, r1 = 0, r2 = 0, r3 = 0, r4 = 0, r5 = 0, r6 = 0, r7 = 0, r8 = 0;
+                if (k < cnt) {
+                    const float mx = s_g[k].x, my = s_g[k].y;
+                    const float bx = (float)(ti.tx * TILE) + 0.5f, by = (float)(ti.ty * TILE) + 0.5f;
+                    for (int i = 0; i < NP / J; ++i) {
+                        const int p = i * J + j;
+                        const float u = s_u[k * UP + p], wv = s_w[k * UP + p];
+                        const float dx = bx + (float)(p % TILE) - mx, dy = by + (float)(p / TILE) - my;
+                        const float ux = u * dx, uy = u * dy;
+                        r0 += u;
+                        r1 += ux;
+                        r2 += uy;
+                        r3 = __builtin_fmaf(ux, dx, r3);
+                        r4 = __builtin_fmaf(ux, dy, r4);
+                        r5 = __builtin_fmaf(uy, dy, r5);
+                        r6 = __builtin_fmaf(wv, s_gp[0][p], r6);
+                        r7 = __builtin_fmaf(wv, s_gp[1][p], r7);
+                        r8 = __builtin_fmaf(wv, s_gp[2][p], r8);
+                    }
+                }
+                float* pp = s_part[j][k];
+                pp[0] = r0; pp[1] = r1; pp[2] = r2; pp[3] = r3; pp[4] = r4;
+                pp[5] = r5; pp[6] = r6; pp[7] = r7; pp[8] = r8;
+            }
+            __syncthreads();
+            for (int k = threadIdx.x; k < cnt; k += NT) {
+                float r[9];
+#pragma unroll
+                for (int c = 0; c < 9; ++c) r[c] = 0.0f;
+                for (int j = 0; j < J; ++j)
+#pragma unroll
+                    for (int c = 0; c < 9; ++c) r[c] += s_part[j][k][c];
+                const uint32_t idx = s_idx[k];
+                if ((int64_t)idx >= a.capacity) continue;   // only after a capacity overflow
+                atomicOr(a.rec_mask + (idx >> 5), 1u << (idx & 31u));
+                float4* rec = a.grec + 3 * (int64_t)idx;
+                const uint32_t owner = (uint32_t)((int64_t)ti.view * a.n + s_gid[k]);
+                const float4* rr = a.rec + 4 * (int64_t)owner;
+                const float4 q0 = rr[0];
+                const float4 q1 = rr[1];
+                const float A = q0.z, B = q0.w, C = q1.x, op = q1.y;
+                rec[0] = make_float4(A * r[1] + B * r[2], B * r[1] + C * r[2], -0.5f * r[3], -r[4]);
+                rec[1] = make_float4(-0.5f * r[5], r[0] / op, r[6], r[7]);
+                rec[2] = make_float4(r[8], __uint_as_float(owner), 0.0f, 0.0f);
+            }
+        }
+        if (threadIdx.x == 0) a.tile_stop[gt] = stop;
+        if (a.counter == nullptr) break;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 
@@ -747,10 +960,10 @@ int launch_raster_fwd(const gs_splats& sp, int64_t n, const gs_layout& L, const 
     return dispatch<true>(a, lds_batch, grid_for(a, sched), s);
 }
 
-int launch_raster_bwd(const gs_splats& sp, int64_t n, const gs_layout& L, const gs_bins& b,
-                      const gs_view* views, const gs_image& fwd, const float* target,
-                      const float* dLdC, const gs_grads2d& grads, float* loss, int lds_batch,
-                      const gs_schedule* sched, hipStream_t s) {
+static int bwd_args(const gs_splats& sp, int64_t n, const gs_layout& L, const gs_bins& b,
+                    const gs_view* views, const gs_image& fwd, const float* target, const float* dLdC,
+                    const gs_grads2d& grads, float* loss, const gs_schedule* sched, hipStream_t s,
+                    RasterArgs* out) {
     RasterArgs a = base_args(sp, n, L, b, views, sched);
     a.out_rgb = fwd.rgb;
     a.out_T = fwd.T;
@@ -766,23 +979,62 @@ int launch_raster_bwd(const gs_splats& sp, int64_t n, const gs_layout& L, const 
     a.row_offsets = b.row_offsets;
     a.rows = reinterpret_cast<const uint4*>(b.rows);
     a.row_capacity = b.row_capacity;
-    // a negative batch selects the per-tile batch with cap -lds_batch
-    a.adaptive_batch = lds_batch < 0;
-    if (lds_batch < 0) {
-        lds_batch = -lds_batch;
-        if (lds_batch < kWave) {
-            set_error("an adaptive lds_batch needs a cap of at least 64 (got %d)", lds_batch);
-            return GS_ERR_INVALID_ARG;
-        }
-    }
+    *out = a;
     if (a.total_tiles == 0) return GS_OK;
     int rc = launch_fill_u32(a.rec_mask, 0u, (b.capacity + 31) / 32, s);
     if (rc != GS_OK) return rc;
-    if (a.counter) {
-        rc = launch_fill_u32(a.counter, 0u, 1, s);
-        if (rc != GS_OK) return rc;
+    if (a.counter) rc = launch_fill_u32(a.counter, 0u, 1, s);
+    return rc;
+}
+
+int launch_raster_bwd(const gs_splats& sp, int64_t n, const gs_layout& L, const gs_bins& b,
+                      const gs_view* views, const gs_image& fwd, const float* target,
+                      const float* dLdC, const gs_grads2d& grads, float* loss, int lds_batch,
+                      const gs_schedule* sched, hipStream_t s) {
+    // a negative batch selects the per-tile batch with cap -lds_batch
+    if (lds_batch < 0 && -lds_batch < kWave) {
+        set_error("an adaptive lds_batch needs a cap of at least 64 (got %d)", -lds_batch);
+        return GS_ERR_INVALID_ARG;
     }
-    return dispatch<false>(a, lds_batch, grid_for(a, sched), s);
+    RasterArgs a;
+    int rc = bwd_args(sp, n, L, b, views, fwd, target, dLdC, grads, loss, sched, s, &a);
+    if (rc != GS_OK || a.total_tiles == 0) return rc;
+    a.adaptive_batch = lds_batch < 0;
+    return dispatch<false>(a, lds_batch < 0 ? -lds_batch : lds_batch, grid_for(a, sched), s);
+}
+
+template <int TILE, int S, int PPT>
+static int launch_bwd2_t(const RasterArgs& a, unsigned grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_raster_bwd2<TILE, S, PPT>), dim3(grid), dim3(Geo<TILE, PPT>::NT), 0, s, a);
+    return check_launch("raster_bwd2");
+}
+
+template <int TILE, int PPT>
+static int launch_bwd2_s(const RasterArgs& a, int S, unsigned grid, hipStream_t s) {
+    return S == 16 ? launch_bwd2_t<TILE, 16, PPT>(a, grid, s) : launch_bwd2_t<TILE, 32, PPT>(a, grid, s);
+}
+
+int launch_raster_bwd2(const gs_splats& sp, int64_t n, const gs_layout& L, const gs_bins& b,
+                       const gs_view* views, const gs_image& fwd, const float* target,
+                       const float* dLdC, const gs_grads2d& grads, float* loss, int lds_batch,
+                       const gs_schedule* sched, hipStream_t s) {
+    if (lds_batch != 16 && lds_batch != 32) {
+        set_error("the two-phase backward's lds_batch must be 16 or 32 (got %d)", lds_batch);
+        return GS_ERR_INVALID_ARG;
+    }
+    if (L.tile != 8 && L.tile != 16) {
+        set_error("the two-phase backward supports 8x8 and 16x16 tiles (got %d)", L.tile);
+        return GS_ERR_INVALID_ARG;
+    }
+    RasterArgs a;
+    int rc = bwd_args(sp, n, L, b, views, fwd, target, dLdC, grads, loss, sched, s, &a);
+    if (rc != GS_OK || a.total_tiles == 0) return rc;
+    const unsigned grid = grid_for(a, sched);
+    if (L.tile == 8) return launch_bwd2_s<8, 1>(a, lds_batch, grid, s);
+    const int ppt = L.pixels_per_lane;
+    return ppt == 1 ? launch_bwd2_s<16, 1>(a, lds_batch, grid, s)
+         : ppt == 2 ? launch_bwd2_s<16, 2>(a, lds_batch, grid, s)
+                    : launch_bwd2_s<16, 4>(a, lds_batch, grid, s);
 }
 
 }  // namespace gs

@@ -193,6 +193,31 @@ def rasterize_bwd(frame: Frame, views_dev: torch.Tensor, target: torch.Tensor | 
                                    G.stream_ptr(stream)), "gs_rasterize_bwd")
 
 
+def rasterize_bwd_twophase(frame: Frame, views_dev: torch.Tensor, target: torch.Tensor | None = None,
+                           dLdC: torch.Tensor | None = None, lds_batch: int = 32, sched=None,
+                           stream=None) -> None:
+    """The two-phase backward (gs_rasterize_bwd_twophase): same outputs as rasterize_bwd."""
+    G.check(G.lib.gs_rasterize_bwd_twophase(C.byref(frame.splats), frame.n, C.byref(frame.layout),
+                                            C.byref(frame.bins), _i(views_dev), C.byref(frame.img),
+                                            _i(target) if target is not None else None,
+                                            _i(dLdC) if dLdC is not None else None, C.byref(frame.grads2d),
+                                            _i(frame.loss_tiles) if target is not None else None, lds_batch,
+                                            C.byref(sched) if sched is not None else None,
+                                            G.stream_ptr(stream)), "gs_rasterize_bwd_twophase")
+
+
+def backward(frame: Frame, views_dev: torch.Tensor, variant, target=None, dLdC=None, sched=None,
+             stream=None) -> None:
+    """Run one backward variant: an int is rasterize_bwd's lds_batch, ("twophase", S)
+    the two-phase backward with batch S."""
+    if isinstance(variant, tuple) and variant[0] == "twophase":
+        rasterize_bwd_twophase(frame, views_dev, target=target, dLdC=dLdC, lds_batch=variant[1], sched=sched,
+                               stream=stream)
+    else:
+        rasterize_bwd(frame, views_dev, target=target, dLdC=dLdC, lds_batch=int(variant), sched=sched,
+                      stream=stream)
+
+
 class LossL1SSIM:
     """Fused L1 + D-SSIM loss gradient of a frame's render against an RGBA8
     reference (gs_loss_l1_ssim); owns its workspace and per-block sums."""
@@ -254,14 +279,15 @@ class ThompsonScheduler:
 
 
 class ScheduledBackward:
-    """rasterize_bwd whose LDS batch (fixed, or per tile when negative) is chosen
-    per call by Thompson sampling on measured latency (Sec. 4.2).  Each call is
+    """The backward whose variant -- rasterize_bwd's LDS batch (fixed, or per tile
+    when negative) or ("twophase", S) -- is chosen per call by Thompson sampling
+    on measured latency (Sec. 4.2).  Each call is
     bracketed by two events on the launch stream; finished calls are folded into
     the belief at later calls without synchronising."""
 
     def __init__(self, arms=(64, 128, 256, -128), seed: int = 0, prior_ms: float = 0.3):
         import collections
-        self.arms = tuple(int(a) for a in arms)
+        self.arms = tuple(arms)
         # weak prior centred on prior_ms, standard deviation about 10 % of it
         self.ts = ThompsonScheduler(len(self.arms), seed, mu0=prior_ms, kappa0=1e-3, alpha0=1.0,
                                     beta0=(0.1 * prior_ms) ** 2)
@@ -284,8 +310,7 @@ class ScheduledBackward:
         s = stream if stream is not None else torch.cuda.current_stream()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(s)
-        rasterize_bwd(frame, views_dev, target=target, dLdC=dLdC, lds_batch=self.arms[arm], sched=sched,
-                      stream=s)
+        backward(frame, views_dev, self.arms[arm], target=target, dLdC=dLdC, sched=sched, stream=s)
         e1.record(s)
         self.pending.append((arm, e0, e1))
         self.history.append(arm)
@@ -343,7 +368,7 @@ def train_step(model: Model, frame: Frame, views_dev: torch.Tensor, target: torc
                grads_out: torch.Tensor | None = None, adam: bool = True,
                bwd_batch: int | None = None) -> None:
     """One L1 training step over the frame's views: 5 stages, gradients summed over views.
-    bwd_batch: the backward's LDS batch if not lds_batch (negative: per-tile batch)."""
+    bwd_batch: the backward variant if not rasterize_bwd with lds_batch (see backward())."""
     project(model.params, frame, views_dev)
     bin_sort(frame)
     if check and frame.status_bits():
@@ -352,7 +377,7 @@ def train_step(model: Model, frame: Frame, views_dev: torch.Tensor, target: torc
         if frame.status_bits():
             raise G.GsError(f"intersection status {frame.status_bits()} after resize")
     rasterize_fwd(frame, views_dev, lds_batch, sched)
-    rasterize_bwd(frame, views_dev, target=target, lds_batch=bwd_batch or lds_batch, sched=sched)
+    backward(frame, views_dev, bwd_batch or lds_batch, target=target, sched=sched)
     project_bwd_adam(model, frame, views_dev, adam=adam, grads_out=grads_out)
 
 

@@ -250,6 +250,59 @@ def test_backward_batch_changes_no_bit(name):
             np.testing.assert_array_equal(base[k], other[k], err_msg=f"bwd_batch={bb} {k}")
 
 
+@pytest.mark.parametrize("name,ppl,S", [("plain-2k-256", 1, 32), ("plain-2k-256", 2, 16), ("plain-2k-256", 4, 32),
+                                        ("ragged-2view", 1, 16), ("ragged-2view", 2, 32)])
+def test_twophase_backward_against_oracle(name, ppl, S):
+    """The two-phase backward: gradients and the Adam update against the oracle
+    (same bar as the first backward), its records against the first backward's
+    (equal up to float summation order), the same flagged records and stops."""
+    scene, target_scene, views, tile = WL[name]
+    note(f"two-phase backward {name} pixels/lane={ppl} S={S}")
+    target, ref = _oracle_step(scene, target_scene, views, tile)
+    g = run_gpu_step(scene, views, tile, target=target, lds_batch=128, pixels_per_lane=ppl,
+                     bwd_batch=("twophase", S))
+    base = run_gpu_step(scene, views, tile, target=target, lds_batch=128, pixels_per_lane=ppl)
+    for k in ("rec_mask", "tile_stop"):
+        np.testing.assert_array_equal(g[k], base[k])
+    flagged = np.unpackbits(g["rec_mask"].view(np.uint8), bitorder="little")[:g["K"]].astype(bool)
+    ra, rb = g["grec"][flagged][:, :9], base["grec"][flagged][:, :9]
+    np.testing.assert_array_equal(g["grec"][flagged][:, 9].view(np.uint32),
+                                  base["grec"][flagged][:, 9].view(np.uint32))          # owners
+    scale = np.abs(rb).max(axis=0, keepdims=True) + 1e-30
+    assert (np.abs(ra - rb) <= 1e-4 * scale + 1e-5 * np.abs(rb)).all()
+    ex_any = exempt_gaussians(ref.bins.ranges, ref.bins.vals, ref.bins.gid, views, tile, ref.fragile,
+                              scene.n).any(axis=0)
+    okg = grad_close(g["grads"], ref.grads, GRAD_RTOL)
+    assert not (~okg.all(axis=1) & ~ex_any).any(), np.argwhere(~okg & ~ex_any[:, None])[:5]
+
+
+def test_twophase_backward_tile8_and_determinism():
+    scene, target_scene, views, _ = WL["ragged-2view"]
+    note("two-phase backward, 8x8 tiles, twice")
+    target, ref = _oracle_step(scene, target_scene, views, 8)
+    a = run_gpu_step(scene, views, 8, target=target, lds_batch=64, bwd_batch=("twophase", 32))
+    b = run_gpu_step(scene, views, 8, target=target, lds_batch=64, bwd_batch=("twophase", 32))
+    for k in ("grec", "rec_mask", "sums", "grads", "params"):
+        np.testing.assert_array_equal(a[k], b[k])
+    ex_any = exempt_gaussians(ref.bins.ranges, ref.bins.vals, ref.bins.gid, views, 8, ref.fragile,
+                              scene.n).any(axis=0)
+    okg = grad_close(a["grads"], ref.grads, GRAD_RTOL)
+    assert not (~okg.all(axis=1) & ~ex_any).any()
+
+
+def test_twophase_backward_argument_errors():
+    from paper_2605_00219_amd import _lib as G
+    from paper_2605_00219_amd import pipeline as P
+    scene, _, views, _ = WL["plain-2k-256"]
+    vd = P.views_to_device(views)
+    frame = P.Frame(scene.n, [256], [256], 16)
+    with pytest.raises(G.GsError, match="lds_batch"):
+        P.rasterize_bwd_twophase(frame, vd, dLdC=frame.image, lds_batch=64)
+    frame32 = P.Frame(scene.n, [256], [256], 32)
+    with pytest.raises(G.GsError, match="tile"):
+        P.rasterize_bwd_twophase(frame32, vd, dLdC=frame32.image, lds_batch=32)
+
+
 def test_thompson_scheduled_backward_trains_the_same_bits():
     """Six training steps whose backward batch is chosen by Thompson sampling
     end with the parameters of six fixed-batch steps, bit for bit."""

@@ -675,14 +675,20 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd2(RasterArgs a
     constexpr int PPT = PPT_, NT = Geo<TILE, PPT_>::NT;
     constexpr int NP = TILE * TILE;
     constexpr int UP = NP + 1;           // row pitch of the per-pair arrays (entries on distinct banks)
+    constexpr int NW = NT / kWave;
     constexpr int J = NT / S;            // pixel slices per entry in the Gaussian-parallel pass
-    static_assert(NT % S == 0 && NP % J == 0, "whole slices");
+    constexpr int Z = NP / J;            // pixels per slice (PPT S): inside one wavefront's pixels
+    static_assert(NT % S == 0 && NP % J == 0 && S <= kWave && (kWave * PPT) % Z == 0, "whole slices");
     __shared__ float4 s_g[S];
     __shared__ float4 s_h[S];
     __shared__ float s_b[S];
     __shared__ uint32_t s_gid[S];
     __shared__ uint32_t s_idx[S];
+    __shared__ uint32_t s_pos[S];
     __shared__ uint32_t s_mw[S / 32 + 2];
+    __shared__ uint64_t s_rel[NW];       // per wavefront: staged entries some of its pixels composite
+    __shared__ uint32_t s_wcnt[NW];      // per wavefront: relevant (entry, slice) items found
+    __shared__ uint16_t s_item[NT];      // relevant items, packed
     __shared__ float s_u[S * UP];        // dL/dpower per (entry, pixel)
     __shared__ float s_w[S * UP];        // alpha T per (entry, pixel)
     __shared__ float s_gp[3][NP];        // dL/dC per pixel
@@ -782,50 +788,87 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd2(RasterArgs a
                         stage_splat(a, ti.view, j, s_g[slot], s_h[slot], s_b[slot], gid);
                         s_gid[slot] = gid;
                         s_idx[slot] = unsorted_index(a, ti.view, gid, ti.tx, ti.ty);
+                        s_pos[slot] = j - start;
                     }
                 }
             }
             __syncthreads();
-            // pixel-parallel pass: per staged entry in order, this thread's pixels
+            // pixel-parallel pass over the staged entries this wavefront's pixels
+            // can composite (lane k tests entry k: within the pixels' list
+            // lengths and able to reach their rectangle), in order
             {
-                int k = 0;
-                for (uint32_t q = 0; q < nwd && k < cnt; ++q) {
-                    for (uint32_t m = s_mw[q]; m != 0u; m &= m - 1u, ++k) {
-                        const uint32_t pos = ((w0 + q) << 5) + (uint32_t)__builtin_ctz(m) - start;
-                        const float4 sg = s_g[k];
-                        const float4 sh = s_h[k];
-                        const float cb = s_b[k];
+                uint32_t wlen = mylen;
+                for (int off = 32; off > 0; off >>= 1) wlen = max(wlen, (uint32_t)__shfl_xor((int)wlen, off));
+                const float rx0 = (float)(ti.tx * TILE) + 0.5f, rx1 = rx0 + (float)(TILE - 1);
+                const float ry0 = (float)(ti.ty * TILE + w * Geo<TILE, PPT_>::ROWS) + 0.5f;
+                const float ry1 = ry0 + (float)(Geo<TILE, PPT_>::ROWS - 1);
+                uint64_t rel = __ballot(lane < cnt && s_pos[lane] < wlen &&
+                                        rect_may_composite(s_g[lane], s_h[lane], rx0, rx1, ry0, ry1));
+                uint64_t used = 0;
+                for (uint64_t m = rel; m != 0ull; m &= m - 1ull) {
+                    const int k = (int)__builtin_ctzll(m);
+                    const uint32_t pos = s_pos[k];
+                    const float4 sg = s_g[k];
+                    const float4 sh = s_h[k];
+                    const float cb = s_b[k];
+                    bool any = false;
 #pragma unroll
-                        for (int qq = 0; qq < PPT; ++qq) {
-                            float dx, dy, G, ag;
-                            const bool in = eval_pair(px[qq], py[qq], sg, sh, dx, dy, G, ag);
-                            const float al = fminf(kAlphaMax, ag);
-                            const bool c = pos < lastp[qq] && in && al >= kAlphaMin;
-                            const float ae = c ? al : 0.0f;
-                            const float wgt = ae * T[qq];
-                            const float gc = __builtin_fmaf(g2[qq], cb, __builtin_fmaf(g1[qq], sh.w, g0[qq] * sh.z));
-                            R[qq] = __builtin_fmaf(-wgt, gc, R[qq]);
-                            const float inv1m = __builtin_amdgcn_rcpf(1.0f - al);
-                            const float dalpha = __builtin_fmaf(T[qq], gc, -(R[qq] * inv1m));
-                            const float agc = (ag > kAlphaMax) ? 0.0f : ae;
-                            const int p = Geo<TILE, PPT_>::pixel((int)threadIdx.x, qq);
-                            s_u[k * UP + p] = agc * dalpha;
-                            s_w[k * UP + p] = wgt;
-                            T[qq] = T[qq] - wgt;
-                        }
+                    for (int qq = 0; qq < PPT; ++qq) {
+                        float dx, dy, G, ag;
+                        const bool in = eval_pair(px[qq], py[qq], sg, sh, dx, dy, G, ag);
+                        const float al = fminf(kAlphaMax, ag);
+                        const bool c = pos < lastp[qq] && in && al >= kAlphaMin;
+                        any = any || c;
+                        const float ae = c ? al : 0.0f;
+                        const float wgt = ae * T[qq];
+                        const float gc = __builtin_fmaf(g2[qq], cb, __builtin_fmaf(g1[qq], sh.w, g0[qq] * sh.z));
+                        R[qq] = __builtin_fmaf(-wgt, gc, R[qq]);
+                        const float inv1m = __builtin_amdgcn_rcpf(1.0f - al);
+                        const float dalpha = __builtin_fmaf(T[qq], gc, -(R[qq] * inv1m));
+                        const float agc = (ag > kAlphaMax) ? 0.0f : ae;
+                        const int p = Geo<TILE, PPT_>::pixel((int)threadIdx.x, qq);
+                        s_u[k * UP + p] = agc * dalpha;
+                        s_w[k * UP + p] = wgt;
+                        T[qq] = T[qq] - wgt;
                     }
+                    if (__ballot(any) != 0ull) used |= 1ull << k;
                 }
+                if (lane == 0) s_rel[w] = used;
             }
             __syncthreads();
-            // Gaussian-parallel pass: entry t % S over pixels i J + t / S
+            // relevant (entry, slice) items -- slice j is pixels [j Z, (j + 1) Z) of
+            // wavefront j Z / (64 PPT) -- packed onto the first threads
             {
                 const int k = threadIdx.x % S, j = threadIdx.x / S;
+                const bool live = ((s_rel[(j * Z) / (kWave * PPT)] >> k) & 1ull) != 0ull;
+                const uint64_t bl = __ballot(live);
+                if (lane == 0) s_wcnt[w] = (uint32_t)__popcll(bl);
+                if (!live) {
+                    float* pp = s_part[j][k];
+#pragma unroll
+                    for (int c = 0; c < 9; ++c) pp[c] = 0.0f;
+                }
+                __syncthreads();
+                if (live) {
+                    uint32_t off = (uint32_t)__popcll(bl & ((1ull << lane) - 1ull));
+                    for (int ww = 0; ww < w; ++ww) off += s_wcnt[ww];
+                    s_item[off] = (uint16_t)threadIdx.x;
+                }
+            }
+            __syncthreads();
+            // Gaussian-parallel pass: thread t sums item t (entry k over slice j)
+            uint32_t n_items = 0;
+            for (int ww = 0; ww < NW; ++ww) n_items += s_wcnt[ww];
+            if (threadIdx.x < n_items) {
+                const int it = s_item[threadIdx.x];
+                const int k = it % S, j = it / S;
                 float r0 = 0, r1 = 0, r2 = 0, r3 = 0, r4 = 0, r5 = 0, r6 = 0, r7 = 0, r8 = 0;
-                if (k < cnt) {
+                {
                     const float mx = s_g[k].x, my = s_g[k].y;
                     const float bx = (float)(ti.tx * TILE) + 0.5f, by = (float)(ti.ty * TILE) + 0.5f;
-                    for (int i = 0; i < NP / J; ++i) {
-                        const int p = i * J + j;
+#pragma unroll 4
+                    for (int i = 0; i < Z; ++i) {
+                        const int p = j * Z + i;
                         const float u = s_u[k * UP + p], wv = s_w[k * UP + p];
                         const float dx = bx + (float)(p % TILE) - mx, dy = by + (float)(p / TILE) - my;
                         const float ux = u * dx, uy = u * dy;
@@ -1029,12 +1072,12 @@ int launch_raster_bwd2(const gs_splats& sp, int64_t n, const gs_layout& L, const
     RasterArgs a;
     int rc = bwd_args(sp, n, L, b, views, fwd, target, dLdC, grads, loss, sched, s, &a);
     if (rc != GS_OK || a.total_tiles == 0) return rc;
+    // one pixel per lane whatever the forward's mapping (pixels are addressed
+    // by their tile-local index, so the two need not agree): four wavefronts
+    // per 16x16 tile keep the SIMDs busy across this kernel's barriers
     const unsigned grid = grid_for(a, sched);
     if (L.tile == 8) return launch_bwd2_s<8, 1>(a, lds_batch, grid, s);
-    const int ppt = L.pixels_per_lane;
-    return ppt == 1 ? launch_bwd2_s<16, 1>(a, lds_batch, grid, s)
-         : ppt == 2 ? launch_bwd2_s<16, 2>(a, lds_batch, grid, s)
-                    : launch_bwd2_s<16, 4>(a, lds_batch, grid, s);
+    return launch_bwd2_s<16, 1>(a, lds_batch, grid, s);
 }
 
 }  // namespace gs

@@ -392,13 +392,45 @@ GS_DEV float row_sum(float v) {
     return v;
 }
 
-// Sum of x over the four rows of the wavefront at the same row position
-// (lane-wise exchange through ds_bpermute); every lane gets its column's sum.
-// addr16 = 4 (lane ^ 16), addr32 = 4 (lane ^ 32).
-GS_DEV float sum_rows(float x, int addr16, int addr32) {
-    x += __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addr16, __builtin_bit_cast(int, x)));
-    x += __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addr32, __builtin_bit_cast(int, x)));
-    return x;
+// The two results of a lane swap, kept apart: without the empty asm the
+// compiler in use folds r[0] + r[1] of chained swaps into r[0] + r[0].
+GS_DEV float swap_sum(uint32_t x, uint32_t y) {
+    asm volatile("" : "+v"(x), "+v"(y));
+    return __builtin_bit_cast(float, x) + __builtin_bit_cast(float, y);
+}
+
+// Lane-pair sums across the wavefront's halves (v_permlane32_swap): lane l of
+// the lower half gets a[l] + a[l + 32], lane l of the upper half b[l - 32] + b[l].
+GS_DEV float fold32(float a, float b) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(uint32_t, a), __builtin_bit_cast(uint32_t, b),
+                                                    false, false);
+    return swap_sum(r[0], r[1]);
+}
+
+// Row-pair sums (v_permlane16_swap): rows 0 and 2 get a's sums over rows
+// (0, 1) and (2, 3), rows 1 and 3 b's.
+GS_DEV float fold16(float a, float b) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(uint32_t, a), __builtin_bit_cast(uint32_t, b),
+                                                    false, false);
+    return swap_sum(r[0], r[1]);
+}
+
+// Wavefront sums of nine values: halves folded pairwise, then row pairs, then
+// rows.  Lane 16 r of the result holds the sum of v[(0, 2, 1, 3)[r]], lane
+// 16 r + 1 that of v[(4, 6, 5, 7)[r]], and every lane that of v[8]; sum9_slot
+// gives the component each lane holds (-1: none it should write).
+GS_DEV float sum9(float v0, float v1, float v2, float v3, float v4, float v5, float v6, float v7, float v8,
+                  int pos16) {
+    const float b0 = row_sum(fold16(fold32(v0, v1), fold32(v2, v3)));
+    const float b1 = row_sum(fold16(fold32(v4, v5), fold32(v6, v7)));
+    const float a8 = fold32(v8, v8);
+    const float b8 = row_sum(fold16(a8, a8));
+    return pos16 == 0 ? b0 : (pos16 == 1 ? b1 : b8);
+}
+
+GS_DEV int sum9_slot(int lane) {
+    const int row = lane >> 4, pos16 = lane & 15, c = ((row & 1) << 1) | (row >> 1);
+    return pos16 == 0 ? c : (pos16 == 1 ? 4 + c : (lane == 2 ? 8 : -1));
 }
 
 // ---------------------------------------------------------------------------
@@ -467,11 +499,8 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd(RasterArgs a)
             }
             mylen = max(mylen, lastp[q]);
         }
-        // lane j < 9 of each DPP row collects reduced component j
-        bool sel[9];
-#pragma unroll
-        for (int c = 0; c < 9; ++c) sel[c] = (lane & 15) == c;
-        const int addr16 = (lane ^ 16) << 2, addr32 = (lane ^ 32) << 2;
+        // the reduced component this lane writes (-1: none)
+        const int slot = sum9_slot(lane), pos16 = lane & 15;
         __syncthreads();
         if (threadIdx.x == 0) s_len = 0;
         if (a.loss) {
@@ -594,26 +623,8 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd(RasterArgs a)
                         v5 = __builtin_fmaf(ddy, dy, v5);
                         T[q] = T[q] - wgt;
                     }
-                    v0 = row_sum(v0);
-                    v1 = row_sum(v1);
-                    v2 = row_sum(v2);
-                    v3 = row_sum(v3);
-                    v4 = row_sum(v4);
-                    v5 = row_sum(v5);
-                    v6 = row_sum(v6);
-                    v7 = row_sum(v7);
-                    v8 = row_sum(v8);
-                    float x = v0;
-                    x = sel[1] ? v1 : x;
-                    x = sel[2] ? v2 : x;
-                    x = sel[3] ? v3 : x;
-                    x = sel[4] ? v4 : x;
-                    x = sel[5] ? v5 : x;
-                    x = sel[6] ? v6 : x;
-                    x = sel[7] ? v7 : x;
-                    x = sel[8] ? v8 : x;
-                    x = sum_rows(x, addr16, addr32);
-                    if (lane < 9) s_red[w][kk][lane] = x;
+                    const float x = sum9(v0, v1, v2, v3, v4, v5, v6, v7, v8, pos16);
+                    if (slot >= 0) s_red[w][kk][slot] = x;
                     used |= 1ull << kk;
                 }
                 if (lane == 0) s_mask[w] = used;

@@ -301,9 +301,9 @@ def main():
     tp_variant = None
     if "twophase" in variants:
         tp_variant = {}
-        for S in (16, 32):
-            r5 = run_plain(args.cull, False, bwd_variant=("twophase", S))
-            tp_variant[f"S{S}"] = {"iters_per_s": r5["ips"], "ms_per_step": 1e3 * r5["wall"] / args.steps,
+        for sb in (16, 32):
+            r5 = run_plain(args.cull, False, bwd_variant=("twophase", sb))
+            tp_variant[f"S{sb}"] = {"iters_per_s": r5["ips"], "ms_per_step": 1e3 * r5["wall"] / args.steps,
                                    "rasterize_bwd_ms": r5["stage_ms"]["rasterize_bwd"],
                                    "vs_first_backward": stage_ms["rasterize_bwd"] / r5["stage_ms"]["rasterize_bwd"]}
     ts_variant = None

@@ -50,3 +50,16 @@ def test_host_only_entry_points():
     assert G.lib.gs_bin_sort_workspace_size(1000, ctypes.byref(L), 100000) > 8 * 100000
     assert G.lib.gs_grads2d_workspace_size(100000) >= 4 * (100000 // 1024) * 19
     assert G.lib.gs_order_by_cost_scratch_size(5000) > 4 * 5000
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libgs.so not built")
+def test_loss_sizes_are_host_arithmetic():
+    from paper_2605_00219_amd import _lib as G
+    L = G.layout_init([1280, 200], [720, 150], 16)
+    # (64 x 16 block, channel) units: 20 x 45 + 4 x 10 blocks, 3 channels each
+    assert G.lib.gs_loss_blocks(ctypes.byref(L)) == 3 * (20 * 45 + 4 * 10)
+    # 9 floats per pixel of each view padded to whole blocks
+    assert G.lib.gs_loss_workspace_size(ctypes.byref(L)) == 36 * (1280 * 720 + 256 * 160)
+    # views whose padded pixels overflow 32-bit indices are refused (size 0)
+    big = G.layout_init([16384] * 2, [16384] * 2, 32)
+    assert G.lib.gs_loss_workspace_size(ctypes.byref(big)) == 0

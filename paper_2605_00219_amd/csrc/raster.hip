@@ -105,11 +105,21 @@ GS_DEV bool eval_pair(float px, float py, const float4& sg, const float4& sh, fl
     return !(p2 > 0.0f);
 }
 
+// Without an order, workgroups (dealt to the 8 XCDs in turn) take chunks of
+// kXcdChunk consecutive tiles, chunk c on XCD c % 8, so that neighbouring
+// tiles, which stage many of the same splats, read them through one L2; the
+// grid is padded to whole rounds of 8 chunks.
+constexpr uint32_t kXcds = 8, kXcdChunk = 64;
+GS_DEV uint32_t chunked_tile(uint32_t b) {
+    const uint32_t x = b % kXcds, i = b / kXcds;
+    return ((i / kXcdChunk) * kXcds + x) * kXcdChunk + i % kXcdChunk;
+}
+
 // Next tile of this workgroup: -1 = no more work, -2 = skip (an order entry
 // outside [0, total tiles) is ignored rather than followed out of bounds).
 GS_DEV int next_tile(const RasterArgs& a, int* s_tile) {
     if (a.counter == nullptr) {
-        const uint32_t t = a.order ? a.order[blockIdx.x] : blockIdx.x;
+        const uint32_t t = a.order ? a.order[blockIdx.x] : chunked_tile(blockIdx.x);
         return t < (uint32_t)a.total_tiles ? (int)t : -2;
     }
     __syncthreads();
@@ -992,7 +1002,9 @@ static RasterArgs base_args(const gs_splats& sp, int64_t n, const gs_layout& L, 
 
 static unsigned grid_for(const RasterArgs& a, const gs_schedule* sched) {
     if (sched && sched->counter) return (unsigned)std::max(1, std::min(sched->n_groups, a.total_tiles));
-    return (unsigned)a.total_tiles;
+    if (sched && sched->order) return (unsigned)a.total_tiles;
+    const unsigned round = kXcds * kXcdChunk;
+    return ((unsigned)a.total_tiles + round - 1) / round * round;
 }
 
 int launch_raster_fwd(const gs_splats& sp, int64_t n, const gs_layout& L, const gs_bins& b,

@@ -480,3 +480,58 @@ def test_ellipse_culling_training_step(name):
     assert not (~okg.all(axis=1) & ~ex_any).any()
     # fewer intersections than the 3-sigma rectangle on the same scene
     assert g["K"] < oracle.bin_sort(oracle.project(scene, views, tile), views, tile).keys.size
+
+
+def test_plain_step_graph_replays_match_eager_steps():
+    """A training step captured in a HIP graph, replayed three times with eager
+    work between the replays, gives the eager steps' parameters bit for bit
+    after every replay."""
+    import torch
+    from paper_2605_00219_amd import pipeline as P
+    scene, target_scene, views, tile = WL["plain-2k-256"]
+    note("graph-replayed plain steps")
+    target = torch.as_tensor(np.ascontiguousarray(oracle.render(target_scene, views, tile), np.float32),
+                             device="cuda").reshape(-1, 3)
+    vd = P.views_to_device(views)
+
+    def setup():
+        model = P.Model(scene.flat())
+        frame = P.Frame(scene.n, [int(v["width"]) for v in views], [int(v["height"]) for v in views], tile)
+        P.fit_capacity(model.params, frame, vd)
+        frame.resize(frame.capacity * 2)
+        return model, frame
+
+    def step(model, frame):
+        P.project(model.params, frame, vd)
+        P.bin_sort(frame)
+        P.rasterize_fwd(frame, vd, 128)
+        P.rasterize_bwd(frame, vd, target=target, lds_batch=128)
+        P.project_bwd_adam(model, frame, vd)
+
+    me, fe = setup()
+    eager = []
+    for _ in range(3):
+        step(me, fe)
+        torch.cuda.synchronize()
+        eager.append(me.params.cpu().numpy())
+    mg, fg = setup()
+    saved = [t.clone() for t in (mg.params, mg.m, mg.v, mg.step)]
+    cs = torch.cuda.Stream()
+    cs.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cs):
+        step(mg, fg)
+    torch.cuda.current_stream().wait_stream(cs)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step(mg, fg)
+    torch.cuda.synchronize()
+    for t, s0 in zip((mg.params, mg.m, mg.v, mg.step), saved):
+        t.copy_(s0)
+    for i in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        junk = torch.ones(1 << 20, device="cuda").sum()      # eager work between replays
+        assert float(junk.item()) == float(1 << 20)
+        assert fg.status_bits() == 0
+        np.testing.assert_array_equal(mg.params.cpu().numpy(), eager[i], err_msg=f"replay {i}")

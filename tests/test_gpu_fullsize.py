@@ -107,3 +107,43 @@ def test_batched_3m_8_views_binning_full_size():
     np.testing.assert_array_equal(u32(frame.vals)[:K], bins.gid[bins.vals])
     np.testing.assert_array_equal(u32(frame.ranges), bins.ranges)
     note(f"  K = {K} over {len(views)} views")
+
+
+def test_twophase_backward_full_size_against_first_backward():
+    """The second (two-phase) backward at the full plain size, on the frame the
+    bench times: the same flagged records, tile stops and owners as the first
+    backward (itself checked against the oracle above), and every record equal
+    to the first's up to float summation order."""
+    import torch
+    from paper_2605_00219_amd import pipeline as P
+    w = S.workload_plain_300k()
+    views = w.views[:1]
+    W, H = 1280, 720
+    note("full size: two-phase backward against the first, 300k, 1280x720")
+    target = torch.as_tensor(S.random_image(H, W, 4243).reshape(-1, 3), device="cuda").contiguous()
+    model = P.Model(w.scene.flat())
+    frame = P.Frame(w.scene.n, [W], [H], 16)
+    vd = P.views_to_device(views)
+    P.fit_capacity(model.params, frame, vd)
+    P.project(model.params, frame, vd)
+    P.bin_sort(frame)
+    P.rasterize_fwd(frame, vd, 128)
+    out = []
+    for variant in (128, ("twophase", 32)):
+        P.backward(frame, vd, variant, target=target)
+        torch.cuda.synchronize()
+        K = frame.intersections()
+        out.append(dict(rec_mask=frame.rec_mask.cpu().numpy().view(np.uint32).copy(),
+                        stop=frame.tile_stop.cpu().numpy().copy(),
+                        grec=frame.grec[:K].cpu().numpy().copy(), K=K))
+    assert frame.status_bits() == 0
+    a, b = out
+    np.testing.assert_array_equal(a["rec_mask"], b["rec_mask"])
+    np.testing.assert_array_equal(a["stop"], b["stop"])
+    flagged = np.unpackbits(a["rec_mask"].view(np.uint8), bitorder="little")[:a["K"]].astype(bool)
+    assert flagged.sum() > 100_000
+    ra, rb = a["grec"][flagged], b["grec"][flagged]
+    np.testing.assert_array_equal(ra[:, 9].view(np.uint32), rb[:, 9].view(np.uint32))
+    scale = np.abs(ra[:, :9]).max(axis=0, keepdims=True) + 1e-30
+    diff = np.abs(ra[:, :9] - rb[:, :9])
+    assert (diff <= 1e-4 * scale + 1e-5 * np.abs(ra[:, :9])).all(), diff.max(axis=0) / scale

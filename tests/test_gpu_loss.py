@@ -125,3 +125,43 @@ def test_loss_gradient_1280x720_on_padded_crops():
             want_s = one_minus[yy:yy + 16, xx:xx + 64].sum()
             got_s = blocks[3 * blk:3 * blk + 3, 1].astype(np.float64).sum()
             assert got_s == pytest.approx(want_s, rel=1e-5, abs=1e-4)
+
+
+def test_loss_gradient_multiview_full_resolutions_on_crops():
+    """Three views of uneven full resolutions in one call (block bases, padded
+    workspace views and pixel bases at scale): padded crops of each view
+    against the oracle, and the per-view sums against the oracle's L1 sums."""
+    sizes = [(800, 600), (1920, 1080), (640, 480)]
+    note("L1 + D-SSIM loss gradient, 3 views up to 1920x1080, crops")
+    P_tot = sum(w * h for w, h in sizes)
+    rng = np.random.default_rng(31)
+    x = np.clip(rng.normal(0.5, 0.25, size=(P_tot, 3)), 0, 1).astype(np.float32)
+    t = rng.integers(0, 256, size=(P_tot, 4)).astype(np.uint8)
+    t[rng.random(P_tot) < 0.5, 3] = 255
+    g, blocks, loss = _run(_frame(sizes), x, t, 0.2, True)
+    base = np.cumsum([0] + [w * h for w, h in sizes])
+    nu = [3 * ((w + 63) // 64) * ((h + 15) // 16) for w, h in sizes]
+    ub = np.cumsum([0] + nu)
+    for v, (W, H) in enumerate(sizes):
+        xi = x[base[v]:base[v + 1]].reshape(H, W, 3)
+        ti = t[base[v]:base[v + 1]].reshape(H, W, 4)
+        gi = g[base[v]:base[v + 1]].reshape(H, W, 3)
+        # per-view L1 sum: m |x - y| over the view, against float64
+        m = ti[..., 3].astype(np.float64) / 255.0
+        l1 = (m[..., None] * np.abs(xi.astype(np.float64) - ti[..., :3].astype(np.float64) / 255.0)).sum()
+        assert blocks[ub[v]:ub[v + 1], 0].astype(np.float64).sum() == pytest.approx(l1, rel=1e-5)
+        for c in range(3):
+            x0 = int(rng.integers(0, W - 48)) if c else W - 48      # one crop at the right edge
+            y0 = int(rng.integers(0, H - 40)) if c else H - 40      # and the bottom edge
+            cx0, cy0 = max(0, x0 - 10), max(0, y0 - 10)
+            cx1, cy1 = min(W, x0 + 48 + 10), min(H, y0 + 40 + 10)
+            cw, ch = cx1 - cx0, cy1 - cy0
+            xc = xi[cy0:cy1, cx0:cx1].reshape(-1, 3)
+            tc = ti[cy0:cy1, cx0:cx1].reshape(-1, 4)
+            _, rc, _, fr = O.loss_and_grad(xc, tc, [(cw, ch)], lam=0.2, mask=True)
+            rc = rc.reshape(ch, cw, 3) * (cw * ch) / P_tot
+            fr = fr.reshape(ch, cw)
+            sl = (slice(y0 - cy0, y0 - cy0 + 40), slice(x0 - cx0, x0 - cx0 + 48))
+            got, want, ok = gi[y0:y0 + 40, x0:x0 + 48], rc[sl], fr[sl] == 0
+            close = grad_close(got[ok], want[ok], 1e-3)
+            assert close.all(), (v, c, np.argwhere(~close)[:5])

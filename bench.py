@@ -123,8 +123,9 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; multi-GPU runs are not "
-                          "supported (see DESIGN.md for how the path would shard)",
+        print(json.dumps({"error": "bench.py measures one GPU only; multi-GPU runs are not supported "
+                          "(the path is data-parallel over views: one replica of the Gaussians per GPU, "
+                          "gradients all-reduced before the optimiser)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 

@@ -333,7 +333,9 @@ def test_thompson_scheduled_backward_trains_the_same_bits():
         outs.append(model.params.cpu().numpy())
         if sbwd is not None:
             sbwd.harvest(block=True)
-            assert sum(sbwd.ts.counts()) == 6 and len(set(sbwd.history)) > 1
+            # every step's latency was folded in; which arms were tried depends on
+            # timing (each arm's bits are checked directly in the batch test above)
+            assert sum(sbwd.ts.counts()) == 6 and len(sbwd.history) == 6
     np.testing.assert_array_equal(outs[0], outs[1])
 
 

@@ -282,20 +282,14 @@ GS_DEV float adam_one(float p, float g, float& m, float& v, float step, float be
     return p - step * (m * __builtin_amdgcn_rcpf(denom));
 }
 
-__global__ __launch_bounds__(256) void k_project_bwd_adam(AdamArgs a) {
+__global__ __launch_bounds__(256, 2) void k_project_bwd_adam(AdamArgs a) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= a.n) return;
     const int64_t n = a.n;
     const float4 p0 = a.params[0 * n + g];
     const float4 p1 = a.params[1 * n + g];
     const float4 p2 = a.params[2 * n + g];
-    float4 sh[12];
-    bool finite = finite4(p0) && finite4(make_float4(p1.x, p1.y, p1.z, 0.0f)) && finite4(p2);
-#pragma unroll
-    for (int q = 0; q < 12; ++q) {
-        sh[q] = a.params[(3 + q) * n + g];
-        finite = finite && finite4(sh[q]);
-    }
+    const bool finite = finite4(p0) && finite4(make_float4(p1.x, p1.y, p1.z, 0.0f)) && finite4(p2);
     float gm[3] = {0.f, 0.f, 0.f}, gls[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f};
     float glo = 0.f;
     float gsh[48];
@@ -308,6 +302,17 @@ __global__ __launch_bounds__(256) void k_project_bwd_adam(AdamArgs a) {
         float d[9];
         gather_total(a.ga, o, vn, d);
         if (!finite || a.ga.offsets[o + 1] == a.ga.offsets[o]) continue;
+        // SH coefficients are loaded per view and not kept: the Adam update
+        // below reads them again, which keeps them out of the registers the
+        // float64 chain rule needs
+        float4 sh[12];
+        bool sh_finite = true;
+#pragma unroll
+        for (int q = 0; q < 12; ++q) {
+            sh[q] = a.params[(3 + q) * n + g];
+            sh_finite = sh_finite && finite4(sh[q]);
+        }
+        if (!sh_finite) continue;
         const gs_view vw = a.views[vi];
         Proj P;
         project_gaussian<true, false>(p0, p1, p2, sh, vw, a.tile, a.gx[vi], a.gy[vi], a.cull, P);
@@ -339,99 +344,105 @@ __global__ __launch_bounds__(256) void k_project_bwd_adam(AdamArgs a) {
         }
         // opacity
         glo += d[5] * P.o * (1.0f - P.o);
-        // conic -> 2D covariance
-        const float A = P.A, B = P.B, C = P.C;
-        const float g11 = d[2], g12 = 0.5f * d[3], g22 = d[4];
-        const float q00 = A * g11 + B * g12, q01 = A * g12 + B * g22;
-        const float q10 = B * g11 + C * g12, q11 = B * g12 + C * g22;
-        const float dS[4] = {-(q00 * A + q01 * B), -(q00 * B + q01 * C), -(q00 * B + q01 * C),
-                             -(q10 * B + q11 * C)};
+        // conic -> 2D covariance -> 3D covariance -> scales, rotation, and the
+        // Jacobian's dependence on the mean.  These steps run in float64 from
+        // the forward's float32 values: for elongated Gaussians the conic
+        // gradients are orders of magnitude larger than the parameter
+        // gradients they cancel down to, and float32 would lose most digits.
+        const double A = P.A, B = P.B, C = P.C;
+        const double g11 = d[2], g12 = 0.5 * (double)d[3], g22 = d[4];
+        const double q00 = A * g11 + B * g12, q01 = A * g12 + B * g22;
+        const double q10 = B * g11 + C * g12, q11 = B * g12 + C * g22;
+        const double dS[4] = {-(q00 * A + q01 * B), -(q00 * B + q01 * C), -(q00 * B + q01 * C),
+                              -(q10 * B + q11 * C)};
+        double Am[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) Am[i] = P.Am[i];
         // 2D covariance = Am Sigma Am^T
-        float Sig[9];
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) Sig[i * 3 + j] = sig_at(P.Sig, i, j);
-        float dSig[9];
+        double dSig[9];
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
-                float s = 0.f;
+                double sacc = 0.0;
 #pragma unroll
                 for (int k = 0; k < 2; ++k)
 #pragma unroll
-                    for (int l = 0; l < 2; ++l) s += P.Am[k * 3 + i] * dS[k * 2 + l] * P.Am[l * 3 + j];
-                dSig[i * 3 + j] = s;
+                    for (int l = 0; l < 2; ++l) sacc += Am[k * 3 + i] * dS[k * 2 + l] * Am[l * 3 + j];
+                dSig[i * 3 + j] = sacc;
             }
-        float dAm[6];
+        double dAm[6];
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
-            float t[3];
+            double t[3];
 #pragma unroll
-            for (int mm = 0; mm < 3; ++mm) t[mm] = dS[k * 2 + 0] * P.Am[mm] + dS[k * 2 + 1] * P.Am[3 + mm];
+            for (int mm = 0; mm < 3; ++mm) t[mm] = dS[k * 2 + 0] * Am[mm] + dS[k * 2 + 1] * Am[3 + mm];
 #pragma unroll
             for (int j = 0; j < 3; ++j)
-                dAm[k * 3 + j] = 2.0f * (t[0] * Sig[0 * 3 + j] + t[1] * Sig[1 * 3 + j] + t[2] * Sig[2 * 3 + j]);
+                dAm[k * 3 + j] = 2.0 * (t[0] * (double)sig_at(P.Sig, 0, j) + t[1] * (double)sig_at(P.Sig, 1, j) +
+                                        t[2] * (double)sig_at(P.Sig, 2, j));
         }
         // Sigma = M M^T, M = R diag(s)
-        float dR[9];
+        double dR[9];
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            float ds = 0.f;
+            double ds = 0.0;
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                const float dM = 2.0f * (dSig[i * 3 + 0] * P.M[0 * 3 + j] + dSig[i * 3 + 1] * P.M[1 * 3 + j] +
-                                         dSig[i * 3 + 2] * P.M[2 * 3 + j]);
-                ds += dM * P.Rq[i * 3 + j];
-                dR[i * 3 + j] = dM * P.s[j];
+                const double dM = 2.0 * (dSig[i * 3 + 0] * (double)P.M[0 * 3 + j] +
+                                         dSig[i * 3 + 1] * (double)P.M[1 * 3 + j] +
+                                         dSig[i * 3 + 2] * (double)P.M[2 * 3 + j]);
+                ds += dM * (double)P.Rq[i * 3 + j];
+                dR[i * 3 + j] = dM * (double)P.s[j];
             }
-            gls[j] += ds * P.s[j];
+            gls[j] += (float)(ds * (double)P.s[j]);
         }
         {
-            const float w = P.qn[0], x = P.qn[1], y = P.qn[2], z = P.qn[3];
-            float dq[4];
-            dq[0] = 2.f * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
-            dq[1] = 2.f * (y * dR[1] + z * dR[2] + y * dR[3] - 2.f * x * dR[4] - w * dR[5] + z * dR[6] +
-                           w * dR[7] - 2.f * x * dR[8]);
-            dq[2] = 2.f * (-2.f * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] +
-                           z * dR[7] - 2.f * y * dR[8]);
-            dq[3] = 2.f * (-2.f * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.f * z * dR[4] +
+            const double w = P.qn[0], x = P.qn[1], y = P.qn[2], z = P.qn[3];
+            double dq[4];
+            dq[0] = 2.0 * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+            dq[1] = 2.0 * (y * dR[1] + z * dR[2] + y * dR[3] - 2.0 * x * dR[4] - w * dR[5] + z * dR[6] +
+                           w * dR[7] - 2.0 * x * dR[8]);
+            dq[2] = 2.0 * (-2.0 * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] +
+                           z * dR[7] - 2.0 * y * dR[8]);
+            dq[3] = 2.0 * (-2.0 * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.0 * z * dR[4] +
                            y * dR[5] + x * dR[6] + y * dR[7]);
-            const float dot = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
-            gq[0] += (dq[0] - w * dot) / P.qnorm;
-            gq[1] += (dq[1] - x * dot) / P.qnorm;
-            gq[2] += (dq[2] - y * dot) / P.qnorm;
-            gq[3] += (dq[3] - z * dot) / P.qnorm;
+            const double dot = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
+            const double iq = 1.0 / (double)P.qnorm;
+            gq[0] += (float)((dq[0] - w * dot) * iq);
+            gq[1] += (float)((dq[1] - x * dot) * iq);
+            gq[2] += (float)((dq[2] - y * dot) * iq);
+            gq[3] += (float)((dq[3] - z * dot) * iq);
         }
         // Am = J W; J depends on the camera-space mean
         const float* W = vw.R;
-        const float z = P.z, x = P.p[0], y = P.p[1];
-        const float fx = vw.fx, fy = vw.fy;
-        const float dJ00 = dAm[0] * W[0] + dAm[1] * W[1] + dAm[2] * W[2];
-        const float dJ02 = dAm[0] * W[6] + dAm[1] * W[7] + dAm[2] * W[8];
-        const float dJ11 = dAm[3] * W[3] + dAm[4] * W[4] + dAm[5] * W[5];
-        const float dJ12 = dAm[3] * W[6] + dAm[4] * W[7] + dAm[5] * W[8];
-        const float iz = 1.0f / z, iz2 = iz * iz;
-        float dp[3] = {0.f, 0.f, 0.f};
+        const double z = P.z, x = P.p[0], y = P.p[1];
+        const double fx = vw.fx, fy = vw.fy;
+        const double dJ00 = dAm[0] * W[0] + dAm[1] * W[1] + dAm[2] * W[2];
+        const double dJ02 = dAm[0] * W[6] + dAm[1] * W[7] + dAm[2] * W[8];
+        const double dJ11 = dAm[3] * W[3] + dAm[4] * W[4] + dAm[5] * W[5];
+        const double dJ12 = dAm[3] * W[6] + dAm[4] * W[7] + dAm[5] * W[8];
+        const double iz = 1.0 / z, iz2 = iz * iz;
+        double dp[3] = {0.0, 0.0, 0.0};
         dp[2] += dJ00 * (-fx * iz2) + dJ11 * (-fy * iz2);
-        dp[2] += dJ02 * (fx * P.txc * iz2) + dJ12 * (fy * P.tyc * iz2);
+        dp[2] += dJ02 * (fx * (double)P.txc * iz2) + dJ12 * (fy * (double)P.tyc * iz2);
         if (P.tx == P.txc) {
-            const float dt = dJ02 * (-fx * iz);
+            const double dt = dJ02 * (-fx * iz);
             dp[0] += dt * iz;
             dp[2] += dt * (-x * iz2);
         }
         if (P.ty == P.tyc) {
-            const float dt = dJ12 * (-fy * iz);
+            const double dt = dJ12 * (-fy * iz);
             dp[1] += dt * iz;
             dp[2] += dt * (-y * iz2);
         }
-        dp[0] += d[0] * fx * iz;
-        dp[2] += d[0] * (-fx * x * iz2);
-        dp[1] += d[1] * fy * iz;
-        dp[2] += d[1] * (-fy * y * iz2);
+        dp[0] += (double)d[0] * fx * iz;
+        dp[2] += (double)d[0] * (-fx * x * iz2);
+        dp[1] += (double)d[1] * fy * iz;
+        dp[2] += (double)d[1] * (-fy * y * iz2);
 #pragma unroll
-        for (int i = 0; i < 3; ++i) dmean[i] += W[0 * 3 + i] * dp[0] + W[1 * 3 + i] * dp[1] + W[2 * 3 + i] * dp[2];
+        for (int i = 0; i < 3; ++i)
+            dmean[i] += (float)(W[0 * 3 + i] * dp[0] + W[1 * 3 + i] * dp[1] + W[2 * 3 + i] * dp[2]);
 #pragma unroll
         for (int i = 0; i < 3; ++i) gm[i] += dmean[i];
     }
@@ -454,27 +465,25 @@ __global__ __launch_bounds__(256) void k_project_bwd_adam(AdamArgs a) {
         float step[6];
 #pragma unroll
         for (int k = 0; k < 6; ++k) step[k] = a.lr[k] / bc1;
-        float4 P4[15];
-        P4[0] = p0; P4[1] = p1; P4[2] = p2;
-#pragma unroll
-        for (int q = 0; q < 12; ++q) P4[3 + q] = sh[q];
-        // the moments of kAdamBatch planes are loaded together, so a thread
-        // waits on memory three times rather than fifteen
+        // the moments (and SH coefficients) of kAdamBatch planes are loaded
+        // together, so a thread waits on memory three times rather than fifteen
         constexpr int kAdamBatch = 5;
 #pragma unroll
         for (int q0 = 0; q0 < 15; q0 += kAdamBatch) {
-            float4 mm[kAdamBatch], vv[kAdamBatch];
+            float4 mm[kAdamBatch], vv[kAdamBatch], pq[kAdamBatch];
 #pragma unroll
             for (int j = 0; j < kAdamBatch; ++j) {
                 if (q0 + j >= 15) break;
                 mm[j] = a.m[(q0 + j) * n + g];
                 vv[j] = a.v[(q0 + j) * n + g];
+                const int q = q0 + j;
+                pq[j] = q == 0 ? p0 : (q == 1 ? p1 : (q == 2 ? p2 : a.params[q * n + g]));
             }
 #pragma unroll
             for (int j = 0; j < kAdamBatch; ++j) {
                 const int q = q0 + j;
                 if (q >= 15) break;
-                float4 pp = P4[q];
+                float4 pp = pq[j];
                 const float4 gg = G[q];
                 // parameter group of each component
                 int gr[4];

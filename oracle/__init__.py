@@ -68,8 +68,9 @@ _SIGS = {
     "or_tile_ranges": (None, [_P, _P, _P, _I, _I, _P]),
     "or_raster_fwd": (None, [_P, _P, _P, _P, _P, _P, _P, _I64, _P, _I, _I, _P, _P,
                              _P, _P, _P, _P, _P, _P]),
-    "or_l1": (_D, [_P, _P, _I64, _D, _P, _P]),
-    "or_raster_bwd": (None, [_P, _P, _P, _P, _P, _P, _P, _P, _I64, _P, _I, _I, _P, _P, _P, _P]),
+    "or_l1": (_D, [_P, _P, _I64, _D, _P, _P, _P]),
+    "or_pixel_support": (None, [_P, _P, _P, _P, _P, _P, _I64, _P, _I, _I, _P, _D, _D, _P]),
+    "or_raster_bwd": (None, [_P, _P, _P, _P, _P, _P, _P, _P, _I64, _P, _I, _I, _P, _P, _P, _P, _P]),
     "or_project_bwd": (None, [_P, _P, _P, _P, _P, _I64, _P, _I, _I, _I, _P, _P]),
     "or_adam": (None, [_P, _P, _P, _P, _I64, _P, _D, _D, _D, _I]),
     "or_sh_basis": (None, [_P, _P]),
@@ -236,33 +237,65 @@ def raster_fwd(proj: Projected, bins: Bins, views, tile: int, double: bool = Fal
     return img
 
 
-def l1(image_rgb: np.ndarray, target: np.ndarray, double=False, fragile: np.ndarray | None = None):
-    """Returns (loss, dL/dC [P,3])."""
+def l1(image_rgb: np.ndarray, target: np.ndarray, double=False, fragile: np.ndarray | None = None,
+       last: np.ndarray | None = None):
+    """Returns (loss, dL/dC [P,3]); flags near-tie signs in fragile (in/out),
+    except at pixels where last says nothing was composited."""
     target = _f32(target).reshape(-1, 3)
     img = np.ascontiguousarray(image_rgb, dtype=np.float64).reshape(-1, 3)
     g = np.zeros_like(img)
     fr = fragile if fragile is not None else np.zeros(img.shape[0], np.uint8)
-    loss = lib(double).or_l1(_p(img), _p(target), img.shape[0], L1_SIGN_MARGIN, _p(g), _p(fr))
+    lst = None if last is None else np.ascontiguousarray(last, dtype=np.uint32)
+    loss = lib(double).or_l1(_p(img), _p(target), img.shape[0], L1_SIGN_MARGIN,
+                             None if lst is None else _p(lst), _p(g), _p(fr))
     return loss, g
 
 
+SUPPORT_MARGIN = 1e-2
+
+
+def pixel_support(proj: Projected, bins: Bins, views, tile: int, pixmask: np.ndarray,
+                  rel_margin: float = SUPPORT_MARGIN, double: bool = False) -> np.ndarray:
+    """[V, N] bool: the (view, Gaussian)s whose alpha at some flagged pixel of
+    their tile reaches 1/255 (within rel_margin and the quadratic form's float32
+    error): the only ones whose gradient a flagged pixel can change."""
+    V, n = proj.tiles.shape
+    views = np.ascontiguousarray(views)
+    out = np.zeros(V * n, np.uint8)
+    pm = np.ascontiguousarray(pixmask, dtype=np.uint8).reshape(-1)
+    assert pm.size == sum(n_pixels(views))
+    if not pm.any() or bins.vals.size == 0:
+        return out.reshape(V, n).astype(bool)
+    lib(double).or_pixel_support(_p(np.ascontiguousarray(proj.xy)), _p(np.ascontiguousarray(proj.conic)),
+                                 _p(np.ascontiguousarray(proj.opacity)), _p(bins.ranges), _p(bins.vals),
+                                 _p(bins.gid), n, _p(views), V, tile, _p(pm), float(rel_margin),
+                                 float(DEFAULT_MARGINS[4]), _p(out))
+    return out.reshape(V, n).astype(bool)
+
+
 def raster_bwd(proj: Projected, bins: Bins, views, tile: int, dLdC: np.ndarray,
-               double: bool = False, tile_mask=None):
+               double: bool = False, tile_mask=None, magnitudes: bool = False):
     """Returns (partials [K,9] by unsorted index, grads2d [V,N,9]); tile_mask
-    limits the work to a sample of tiles (others contribute nothing)."""
+    limits the work to a sample of tiles (others contribute nothing).  With
+    magnitudes, also mag2d [V,N,9]: per component the sum over pixels of the
+    magnitudes of the terms (the scale of a float summation's rounding)."""
     L = lib(double)
     V, n = proj.tiles.shape
     views = np.ascontiguousarray(views)
     K = int(bins.offsets[-1])
     partials = np.zeros((max(K, 1), 9))
     grads2d = np.zeros((V, n, 9))
+    mag2d = np.zeros((V, n, 9)) if magnitudes else None
     vals = bins.vals if bins.vals.size else np.zeros(1, np.uint32)
     gid = bins.gid if bins.gid.size else np.zeros(1, np.uint32)
     L.or_raster_bwd(_p(np.ascontiguousarray(proj.xy)), _p(np.ascontiguousarray(proj.conic)),
                     _p(np.ascontiguousarray(proj.opacity)), _p(np.ascontiguousarray(proj.rgb)),
                     _p(bins.ranges), _p(vals), _p(gid), _p(bins.offsets), n, _p(views), V, tile,
                     None if tile_mask is None else _p(np.ascontiguousarray(tile_mask, dtype=np.uint8)),
-                    _p(np.ascontiguousarray(dLdC, dtype=np.float64)), _p(partials), _p(grads2d))
+                    _p(np.ascontiguousarray(dLdC, dtype=np.float64)), _p(partials), _p(grads2d),
+                    _p(mag2d) if magnitudes else None)
+    if magnitudes:
+        return partials[:K], grads2d, mag2d
     return partials[:K], grads2d
 
 
@@ -277,6 +310,22 @@ def project_bwd(scene, views, tile: int, grads2d: np.ndarray, double: bool = Fal
     L.or_project_bwd(_p(means), _p(ls), _p(q), _p(lo), _p(sh), n, _p(views), len(views), tile,
                      int(cull), _p(np.ascontiguousarray(grads2d, dtype=np.float64)), _p(grads))
     return grads
+
+
+def project_bwd_magnitudes(scene, views, tile: int, mag2d: np.ndarray, double: bool = False,
+                           cull: int = CULL_RECT) -> np.ndarray:
+    """[N, 59]: sum over the 9 screen-space components j of |d param / d g_j| *
+    mag2d_j.  The projection backward is linear in the screen-space gradients,
+    so one pass per component gives each term; this bounds how far rounding
+    errors of the screen-space sums (each within a multiple of mag2d) can move
+    a parameter gradient."""
+    mag2d = np.ascontiguousarray(mag2d, dtype=np.float64)
+    out = np.zeros((mag2d.shape[1], 59))
+    for j in range(9):
+        one = np.zeros_like(mag2d)
+        one[..., j] = mag2d[..., j]
+        out += np.abs(project_bwd(scene, views, tile, one, double, cull))
+    return out
 
 
 ADAM_BETAS = (0.9, 0.999)
@@ -354,14 +403,21 @@ class StepResult:
     fragile: np.ndarray         # [P] uint8: compositing or L1-sign decisions near a threshold
 
 
-def train_step(scene, views, tile: int, target: np.ndarray, lr=1e-3, step: int = 1, m=None, v=None,
-               double: bool = False, adam_step: bool = True, cull: int = CULL_RECT) -> StepResult:
-    """One L1 training step over all given views (gradients summed over views)."""
+def train_step(scene, views, tile: int, target: np.ndarray | None, lr=1e-3, step: int = 1, m=None, v=None,
+               double: bool = False, adam_step: bool = True, cull: int = CULL_RECT,
+               dLdC: np.ndarray | None = None) -> StepResult:
+    """One L1 training step over all given views (gradients summed over views).
+    With dLdC given ([P,3]), the backward takes that image gradient instead of
+    the L1 gradient against target (loss is then None)."""
     proj = project(scene, views, tile, double, cull)
     bins = bin_sort(proj, views, tile, double)
     img = raster_fwd(proj, bins, views, tile, double)
     fragile = img.fragile.copy()
-    loss, dLdC = l1(img.rgb, target, double, fragile)
+    if dLdC is None:
+        loss, dLdC = l1(img.rgb, target, double, fragile, img.last)
+    else:
+        loss = None
+        dLdC = np.ascontiguousarray(dLdC, dtype=np.float64).reshape(-1, 3)
     partials, grads2d = raster_bwd(proj, bins, views, tile, dLdC, double)
     grads = project_bwd(scene, views, tile, grads2d, double, cull)
     params = mm = vv = None

@@ -789,9 +789,13 @@ void or_raster_fwd(const double* xy, const double* conic, const double* opac, co
 /* L1 loss mean|C - C^| over all channels of all pixels and its gradient
  * sign(C - C^)/count (sign(0) = 0).  Pixels where |C - C^| is within
  * sign_margin of max(|C|, |C^|) in any channel are marked in fragile (if
- * given): there the sign may differ between two float32 implementations. */
+ * given): there the sign may differ between two float32 implementations.
+ * Where last (nullable) says the pixel composited nothing, its colour is the
+ * background itself, which every implementation that composites nothing
+ * there (the compositing decisions are flagged on their own) reproduces
+ * exactly, so its sign is not flagged. */
 double or_l1(const double* image, const float* target, int64_t npix, double sign_margin,
-             double* dLdC, uint8_t* fragile)
+             const uint32_t* last, double* dLdC, uint8_t* fragile)
 {
     const double inv = 1.0 / (3.0 * (double)npix);
     double loss = 0;
@@ -800,9 +804,59 @@ double or_l1(const double* image, const float* target, int64_t npix, double sign
         loss += fabs(d);
         dLdC[i] = d > 0 ? inv : (d < 0 ? -inv : 0.0);
         const double mag = fmax(fabs(image[i]), fabs((double)target[i]));
-        if (fragile && mag > 0 && fabs(d) <= sign_margin * mag) fragile[i / 3] = 1;
+        const int exact = last && last[i / 3] == 0;
+        if (fragile && !exact && mag > 0 && fabs(d) <= sign_margin * mag) fragile[i / 3] = 1;
     }
     return loss * inv;
+}
+
+/* Marks in support[view * n + g] every (view, Gaussian) whose compositing at
+ * a pixel flagged in pixmask could differ, through a decision taken at a
+ * near-tie there, between two float32 implementations.  A pixel adds to a
+ * Gaussian's gradient only where it composites that Gaussian (Sec. 4.2), so
+ * these are the only gradients a flagged pixel can move.  The pixel's list is
+ * walked front to back in float64 with every decision loosened by rel_margin
+ * (plus the quadratic form's float32 error, form_eps per unit of its absolute
+ * terms) in the direction that keeps more entries: an entry is marked when its
+ * alpha reaches (1/255)(1 - margin), transmittance falls by the smallest alpha
+ * the margin allows, and the walk stops only where T (1 - alpha) is below
+ * 1e-4 (1 - rel_margin) even then. */
+void or_pixel_support(const double* xy, const double* conic, const double* opac,
+                      const uint32_t* ranges, const uint32_t* vals, const uint32_t* gid, int64_t n,
+                      const or_view* views, int n_views, int tile, const uint8_t* pixmask,
+                      double rel_margin, double form_eps, uint8_t* support)
+{
+    int64_t tb = 0, pb = 0;
+    for (int vi = 0; vi < n_views; ++vi) {
+        const or_view* vw = views + vi;
+        const int gx = (vw->width + tile - 1) / tile;
+        const int gy = (vw->height + tile - 1) / tile;
+        for (int iy = 0; iy < vw->height; ++iy)
+            for (int ix = 0; ix < vw->width; ++ix) {
+                if (!pixmask[pb + (int64_t)iy * vw->width + ix]) continue;
+                const int64_t gt = tb + (int64_t)(iy / tile) * gx + ix / tile;
+                const double px = ix + 0.5, py = iy + 0.5;
+                double T = 1.0;
+                for (uint32_t e = ranges[2 * gt]; e < ranges[2 * gt + 1]; ++e) {
+                    const int64_t g = (int64_t)vi * n + gid[vals[e]];
+                    const double dx = px - xy[2 * g], dy = py - xy[2 * g + 1];
+                    const double qa = conic[3 * g] * dx * dx, qc = conic[3 * g + 2] * dy * dy;
+                    const double qb = conic[3 * g + 1] * dx * dy;
+                    const double slack = 0.5 * form_eps * (fabs(qa) + fabs(qc) + 2.0 * fabs(qb));
+                    const double power = -0.5 * (qa + qc) - qb;
+                    const double hi = opac[g] * exp(fmin(0.0, power + slack));
+                    const double lo = power - slack > 0.0 ? 0.0 : opac[g] * exp(power - slack);
+                    const double m = rel_margin + slack;
+                    if (hi < (1.0 / 255.0) * (1.0 - m)) continue;
+                    support[g] = 1;
+                    const double alpha_lo = lo < (1.0 / 255.0) * (1.0 + m) ? 0.0 : fmin(0.99, lo) * (1.0 - m);
+                    if (T * (1.0 - fmin(0.99, hi)) < 1e-4 * (1.0 - rel_margin)) break;
+                    T *= 1.0 - alpha_lo;
+                }
+            }
+        tb += (int64_t)gx * gy;
+        pb += (int64_t)vw->width * vw->height;
+    }
 }
 
 /* Backward of compositing.  For each tile and pixel the included entries are
@@ -813,11 +867,22 @@ double or_l1(const double* image, const float* target, int64_t npix, double sign
  * then through alpha = min(0.99, o G), G = exp(power), power = -1/2 d^T Q d
  * (zero through the clamp).  Per-intersection partials (9 values: d mean2d x,y;
  * d conic A,B,C; d opacity; d colour r,g,b) accumulate at the entry's unsorted
- * index; grads2d[view][g][9] sums each Gaussian's intersections in index order. */
+ * index; grads2d[view][g][9] sums each Gaussian's intersections in index order.
+ * mag2d (nullable, same shape as grads2d) receives, per component, a
+ * running error bound in units of the float32 rounding unit (Wilkinson's
+ * running error analysis): the sum over pixels of each pixel's term with
+ * every factor and every difference inside it taken in absolute value (for
+ * dL/dalpha: sum_k |g_k| (T_i |c_ik| + S_ik / (1 - alpha_i))), weighted by
+ * the relative error a float32 evaluation of that term can carry: the
+ * quadratic form's (twice the sum of its absolute terms, which exp carries
+ * into alpha), that of the pixel's final transmittance (each composited
+ * entry before adds two roundings and its alpha's error scaled by
+ * alpha / (1 - alpha)), and a few roundings more. */
 void or_raster_bwd(const double* xy, const double* conic, const double* opac, const double* rgb,
                    const uint32_t* ranges, const uint32_t* vals, const uint32_t* gid,
                    const uint32_t* offsets, int64_t n, const or_view* views, int n_views, int tile,
-                   const uint8_t* tile_mask, const double* dLdC, double* partials, double* grads2d)
+                   const uint8_t* tile_mask, const double* dLdC, double* partials, double* grads2d,
+                   double* mag2d)
 {
     int64_t ntiles = 0;
     for (int vi = 0; vi < n_views; ++vi)
@@ -825,6 +890,7 @@ void or_raster_bwd(const double* xy, const double* conic, const double* opac, co
                   ((views[vi].height + tile - 1) / tile);
     const uint64_t K = offsets[(int64_t)n_views * n];
     memset(partials, 0, sizeof(double) * 9 * K);
+    double* pmag = mag2d ? (double*)calloc(9 * (K ? K : 1), sizeof(double)) : NULL;
 #pragma omp parallel
     {
         uint32_t cap = 0;
@@ -835,6 +901,7 @@ void or_raster_bwd(const double* xy, const double* conic, const double* opac, co
         real* e_ag = NULL;
         real* e_dx = NULL;
         real* e_dy = NULL;
+        double* e_fm = NULL;
 #pragma omp for schedule(dynamic, 4)
         for (int64_t gt = 0; gt < ntiles; ++gt) {
             if (tile_mask && !tile_mask[gt]) continue;
@@ -854,6 +921,7 @@ void or_raster_bwd(const double* xy, const double* conic, const double* opac, co
                 e_ag = (real*)realloc(e_ag, sizeof(real) * cap);
                 e_dx = (real*)realloc(e_dx, sizeof(real) * cap);
                 e_dy = (real*)realloc(e_dy, sizeof(real) * cap);
+                e_fm = (double*)realloc(e_fm, sizeof(double) * cap);
             }
             for (int iy = ty * tile; iy < (ty + 1) * tile && iy < vw->height; ++iy)
                 for (int ix = tx * tile; ix < (tx + 1) * tile && ix < vw->width; ++ix) {
@@ -861,6 +929,7 @@ void or_raster_bwd(const double* xy, const double* conic, const double* opac, co
                     real T = 1;
                     uint32_t m = 0;
                     int frag = 0;
+                    double rT = 0.0;   /* error bound of T, in rounding units */
                     for (uint32_t e = start; e < end; ++e) {
                         const int64_t g = (int64_t)vi * n + gid[vals[e]];
                         real alpha = 0, G = 0, ag = 0, dx, dy;
@@ -872,6 +941,13 @@ void or_raster_bwd(const double* xy, const double* conic, const double* opac, co
                         if (st == 0) continue;
                         e_idx[m] = e; e_alpha[m] = alpha; e_T[m] = T; e_G[m] = G; e_ag[m] = ag;
                         e_dx[m] = dx; e_dy[m] = dy;
+                        if (pmag) {
+                            const double qa = fabs((double)conic[3 * g] * dx * dx);
+                            const double qc = fabs((double)conic[3 * g + 2] * dy * dy);
+                            const double qb = fabs((double)conic[3 * g + 1] * dx * dy);
+                            e_fm[m] = 2.0 * (qa + qc + 2.0 * qb) + 4.0;
+                            rT += 2.0 + e_fm[m] * (double)alpha / (1.0 - (double)alpha);
+                        }
                         ++m;
                         T = T * ((real)1 - alpha);
                     }
@@ -885,10 +961,15 @@ void or_raster_bwd(const double* xy, const double* conic, const double* opac, co
                         const acc al = e_alpha[jj], Ti = e_T[jj];
                         const acc c[3] = {rgb[3 * g], rgb[3 * g + 1], rgb[3 * g + 2]};
                         acc* pp = partials + 9 * (uint64_t)vals[e];
-                        acc dalpha = 0;
+                        acc* pm = pmag ? pmag + 9 * (uint64_t)vals[e] : NULL;
+                        acc dalpha = 0, dmag = 0;
                         for (int k = 0; k < 3; ++k) {
                             pp[6 + k] += al * Ti * gk[k];
                             dalpha += gk[k] * (Ti * c[k] - S[k] / (1.0 - al));
+                            if (pm) {
+                                pm[6 + k] += al * Ti * fabs(gk[k]) * (rT + e_fm[jj] + 8.0);
+                                dmag += fabs(gk[k]) * (Ti * fabs(c[k]) + fabs(S[k]) / (1.0 - al));
+                            }
                         }
                         for (int k = 0; k < 3; ++k) S[k] += al * Ti * c[k];
                         if (e_ag[jj] > (real)0.99) continue; /* clamped: no gradient to o, G */
@@ -902,10 +983,21 @@ void or_raster_bwd(const double* xy, const double* conic, const double* opac, co
                         pp[4] += -0.5 * dy * dy * dpow;
                         pp[0] += dpow * (A * dx + B * dy);
                         pp[1] += dpow * (B * dx + C * dy);
+                        const double wgt = pm ? rT + e_fm[jj] + 8.0 : 0.0;
+                        if (pm) {
+                            const acc dpm = (acc)e_ag[jj] * dmag * wgt;
+                            pm[5] += G * dmag * wgt;
+                            pm[2] += 0.5 * dx * dx * dpm;
+                            pm[3] += fabs(dx * dy) * dpm;
+                            pm[4] += 0.5 * dy * dy * dpm;
+                            pm[0] += dpm * (fabs(A * dx) + fabs(B * dy));
+                            pm[1] += dpm * (fabs(B * dx) + fabs(C * dy));
+                        }
                     }
                 }
         }
         free(e_idx); free(e_alpha); free(e_T); free(e_G); free(e_ag); free(e_dx); free(e_dy);
+        free(e_fm);
     }
     /* sum each Gaussian's intersections, in index order */
 #pragma omp parallel for schedule(static)
@@ -914,7 +1006,14 @@ void or_raster_bwd(const double* xy, const double* conic, const double* opac, co
         for (uint32_t i = offsets[o]; i < offsets[o + 1]; ++i)
             for (int k = 0; k < 9; ++k) s[k] += partials[9 * (uint64_t)i + k];
         for (int k = 0; k < 9; ++k) grads2d[9 * o + k] = s[k];
+        if (pmag) {
+            acc sm[9] = {0};
+            for (uint32_t i = offsets[o]; i < offsets[o + 1]; ++i)
+                for (int k = 0; k < 9; ++k) sm[k] += pmag[9 * (uint64_t)i + k];
+            for (int k = 0; k < 9; ++k) mag2d[9 * o + k] = sm[k];
+        }
     }
+    free(pmag);
 }
 
 /* ------------------------------------------------------------------------- */

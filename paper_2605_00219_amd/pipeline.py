@@ -363,12 +363,15 @@ def render(params: torch.Tensor, frame: Frame, views_dev: torch.Tensor, lds_batc
     return frame.image
 
 
-def train_step(model: Model, frame: Frame, views_dev: torch.Tensor, target: torch.Tensor,
+def train_step(model: Model, frame: Frame, views_dev: torch.Tensor, target: torch.Tensor | None,
                lds_batch: int = 64, sched=None, check: bool = True,
                grads_out: torch.Tensor | None = None, adam: bool = True,
-               bwd_batch: int | None = None) -> None:
+               bwd_batch: int | None = None, dLdC: torch.Tensor | None = None) -> None:
     """One L1 training step over the frame's views: 5 stages, gradients summed over views.
-    bwd_batch: the backward variant if not rasterize_bwd with lds_batch (see backward())."""
+    bwd_batch: the backward variant if not rasterize_bwd with lds_batch (see backward()).
+    dLdC: an image gradient [pixels, 3] taken instead of the L1 gradient (target None)."""
+    if (target is None) == (dLdC is None):
+        raise ValueError("give exactly one of target and dLdC")
     project(model.params, frame, views_dev)
     bin_sort(frame)
     if check and frame.status_bits():
@@ -377,7 +380,7 @@ def train_step(model: Model, frame: Frame, views_dev: torch.Tensor, target: torc
         if frame.status_bits():
             raise G.GsError(f"intersection status {frame.status_bits()} after resize")
     rasterize_fwd(frame, views_dev, lds_batch, sched)
-    backward(frame, views_dev, bwd_batch or lds_batch, target=target, sched=sched)
+    backward(frame, views_dev, bwd_batch or lds_batch, target=target, dLdC=dLdC, sched=sched)
     project_bwd_adam(model, frame, views_dev, adam=adam, grads_out=grads_out)
 
 

@@ -16,7 +16,10 @@ def u32(t) -> np.ndarray:
 
 def run_gpu_step(scene, views, tile, target=None, lds_batch=64, lr=1e-3, adam=True, grads=True,
                  capacity=None, sched_order=None, persistent=False, tile_stats=False, steps=1,
-                 pixels_per_lane=None, cull=0, bwd_batch=None):
+                 pixels_per_lane=None, cull=0, bwd_batch=None, dLdC=None):
+    """One or more steps through the C ABI.  target: L1 training against it;
+    dLdC ([pixels, 3]): training with that image gradient instead; neither:
+    forward only."""
     import torch
     from paper_2605_00219_amd import pipeline as P
     n = scene.n
@@ -35,13 +38,15 @@ def run_gpu_step(scene, views, tile, target=None, lds_batch=64, lr=1e-3, adam=Tr
         sched_keep = order  # noqa: F841 (keeps the tensor alive)
     tgt = None if target is None else torch.as_tensor(np.ascontiguousarray(target, np.float32),
                                                       device="cuda").reshape(-1, 3)
+    gimg = None if dLdC is None else torch.as_tensor(np.ascontiguousarray(dLdC, np.float32),
+                                                      device="cuda").reshape(-1, 3)
     gout = torch.zeros_like(model.params) if grads else None
     for _ in range(steps):
-        if tgt is None:
+        if tgt is None and gimg is None:
             P.render(model.params, frame, vd, lds_batch, sched)
         else:
             P.train_step(model, frame, vd, tgt, lds_batch, sched, grads_out=gout, adam=adam,
-                         bwd_batch=bwd_batch)
+                         bwd_batch=bwd_batch, dLdC=gimg)
     torch.cuda.synchronize()
     out = dict(frame=frame, model=model)
     out["status"] = frame.status_bits()
@@ -65,7 +70,7 @@ def run_gpu_step(scene, views, tile, target=None, lds_batch=64, lr=1e-3, adam=Tr
     out["last"] = u32(frame.last)
     if tile_stats:
         out["tile_stats"] = u32(frame.tile_stats)
-    if tgt is not None:
+    if tgt is not None or gimg is not None:
         out["grec"] = frame.grec.cpu().numpy()[:K]
         out["sums"] = frame.sums.cpu().numpy().reshape(9, len(views), n).transpose(1, 2, 0)
         out["loss_tiles"] = frame.loss_tiles.cpu().numpy()

@@ -15,7 +15,7 @@ import pytest
 import oracle
 import synthetic as S
 from gpu_common import note
-from helpers import exempt_gaussians, grad_close
+from helpers import grad_close
 
 pytestmark = pytest.mark.gpu
 
@@ -52,13 +52,8 @@ def test_autograd_matches_oracle_gradient_on_crop(diffcheck):
     W, H = d["W"], d["H"]
     note("autograd vs oracle, 1M Gaussians, 512x512 crop")
     mask = _crop_mask(W, H, w.extra["crop"])
-    wts = np.random.default_rng(3003).uniform(-1, 1, size=(W * H, 3)) * mask[:, None]
-    p = d["params"].clone().requires_grad_(True)
-    img = AG.render(p, d["frame"], d["vd"])
-    loss = (img.double() * torch.as_tensor(wts, device="cuda")).sum()
-    loss.backward()
-    g_gpu = P.unpack_flat(p.grad).cpu().numpy()
-    # oracle: same linear loss, only the crop's tiles carry gradient
+    # oracle forward on the crop's tiles first: its fragile pixels (decisions
+    # at a threshold) get weight 0 on both sides, so every Gaussian is checked
     pr = oracle.project(w.scene, w.views, 16)
     bins = oracle.bin_sort(pr, w.views, 16)
     gx, gy = (W + 15) // 16, (H + 15) // 16
@@ -67,21 +62,36 @@ def test_autograd_matches_oracle_gradient_on_crop(diffcheck):
     tmask[y0 // 16:(y0 + ch) // 16, x0 // 16:(x0 + cw) // 16] = 1
     tmask = tmask.reshape(-1)
     fwd = oracle.raster_fwd(pr, bins, w.views, 16, tile_mask=tmask)
-    _, g2 = oracle.raster_bwd(pr, bins, w.views, 16, wts, tile_mask=tmask)
+    wts = np.random.default_rng(3003).uniform(-1, 1, size=(W * H, 3)) * mask[:, None]
+    wts[fwd.fragile != 0] = 0.0
+    p = d["params"].clone().requires_grad_(True)
+    img = AG.render(p, d["frame"], d["vd"])
+    loss = (img.double() * torch.as_tensor(wts, device="cuda")).sum()
+    loss.backward()
+    g_gpu = P.unpack_flat(p.grad).cpu().numpy()
+    # oracle: same linear loss, only the crop's tiles carry gradient
+    _, g2, mag2d = oracle.raster_bwd(pr, bins, w.views, 16, wts, tile_mask=tmask, magnitudes=True)
     g_ref = oracle.project_bwd(w.scene, w.views, 16, g2)
     # pixel parity on the crop
     ok_px = mask & (fwd.fragile == 0)
     err = np.abs(img.detach().cpu().numpy() - fwd.rgb).max(axis=1)
     assert err[ok_px].max() <= 1e-4
-    ex = exempt_gaussians(bins.ranges, bins.vals, bins.gid, w.views, 16, fwd.fragile & mask, w.scene.n)[0]
     touched = np.abs(g_ref).max(axis=1) > 0
     assert touched.sum() > 10000
-    ok = grad_close(g_gpu, g_ref, 1e-3)
-    bad = ~ok.all(axis=1) & ~ex
-    note(f"  {touched.sum()} Gaussians with gradient, {ex.sum()} exempt (fragile tiles), "
-         f"{(~ok.all(axis=1)).sum()} outside tolerance")
-    assert not bad.any(), np.argwhere(~ok & ~ex[:, None])[:5]
-    assert np.all(g_gpu[~touched & ~ex] == 0)
+    # the bar, and the bar plus the float32 running error bound of the
+    # screen-space sums carried through the projection backward (needle-like
+    # Gaussians: terms cancel by orders of magnitude)
+    plain = grad_close(g_gpu, g_ref, 1e-3)
+    mag = np.zeros_like(g_ref)
+    mag[touched] = oracle.project_bwd_magnitudes(w.scene, w.views, 16, mag2d)[touched]
+    ok = grad_close(g_gpu, g_ref, 1e-3, mag=mag)
+    bound_only = int((ok & ~plain).sum())
+    note(f"  {touched.sum()} Gaussians with gradient, all checked; {int((fwd.fragile & mask).sum())} "
+         f"fragile crop pixels weighted 0; {(~plain.all(axis=1)).sum()} outside the plain bar "
+         f"({bound_only} elements within the rounding bound), {(~ok).sum()} outside both")
+    assert ok.all(), np.argwhere(~ok)[:5]
+    assert bound_only <= 1e-3 * touched.sum() * 59
+    assert np.all(g_gpu[~touched] == 0)
 
 
 def test_central_differences_on_64_parameters(diffcheck):
@@ -175,16 +185,16 @@ def test_autograd_small_scene_against_oracle_and_pack_gradients():
     vd = P.views_to_device(w.views)
     ts = [torch.tensor(a, device="cuda", requires_grad=True) for a in w.scene.arrays()]
     P.fit_capacity(AG.pack(*[t.detach() for t in ts]), frame, vd)
-    wts = np.random.default_rng(5).uniform(-1, 1, size=(256 * 256, 3))
-    img = AG.render_gaussians(*ts, frame, vd)
-    (img * torch.as_tensor(wts, device="cuda", dtype=torch.float32)).sum().backward()
-    got = np.concatenate([ts[0].grad.cpu().numpy(), ts[1].grad.cpu().numpy(), ts[2].grad.cpu().numpy(),
-                          ts[3].grad.cpu().numpy()[:, None], ts[4].grad.cpu().numpy().reshape(-1, 48)], 1)
     pr = oracle.project(w.scene, w.views, 16)
     bins = oracle.bin_sort(pr, w.views, 16)
     fwd = oracle.raster_fwd(pr, bins, w.views, 16)
+    wts = np.random.default_rng(5).uniform(-1, 1, size=(256 * 256, 3)).astype(np.float32)
+    wts[fwd.fragile != 0] = 0.0           # every Gaussian checked
+    img = AG.render_gaussians(*ts, frame, vd)
+    (img * torch.as_tensor(wts, device="cuda")).sum().backward()
+    got = np.concatenate([ts[0].grad.cpu().numpy(), ts[1].grad.cpu().numpy(), ts[2].grad.cpu().numpy(),
+                          ts[3].grad.cpu().numpy()[:, None], ts[4].grad.cpu().numpy().reshape(-1, 48)], 1)
     _, g2 = oracle.raster_bwd(pr, bins, w.views, 16, wts)
     ref = oracle.project_bwd(w.scene, w.views, 16, g2)
-    ex = exempt_gaussians(bins.ranges, bins.vals, bins.gid, w.views, 16, fwd.fragile, w.scene.n)[0]
     ok = grad_close(got, ref, 1e-3)
-    assert not (~ok.all(axis=1) & ~ex).any()
+    assert ok.all(), np.argwhere(~ok)[:5]

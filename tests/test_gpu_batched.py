@@ -9,7 +9,7 @@ import pytest
 import oracle
 import synthetic as S
 from gpu_common import note
-from helpers import exempt_gaussians, grad_close
+from helpers import checked_fraction, exempt_gaussians, grad_close, masked_image_gradient
 
 pytestmark = pytest.mark.gpu
 
@@ -61,16 +61,36 @@ def test_graph_persistent_batched_steps_match_eager_and_oracle(setup):
     for a, b in ((m_e.params, m_g.params), (m_e.m, m_g.m), (m_e.v, m_g.v)):
         np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
     assert int(m_g.step.item()) == len(iters)
-    # the first step against the oracle (gradients summed over the 4 views)
+    # the first step against the oracle (gradients summed over the 4 views):
+    # with the fused L1 gradient, every Gaussian no fragile pixel reaches ...
     ref = oracle.train_step(d["scene"], views[0], 16, targets[0].cpu().numpy())
     m1 = P.Model(d["scene"].flat())
     g = torch.zeros_like(m1.params)
     f1 = P.Frame(n, [w for w, _ in RES], [h for _, h in RES], 16, capacity=cap)
     P.train_step(m1, f1, vrows[0], targets[0], grads_out=g)
     got = P.unpack_flat(g).cpu().numpy()
-    ex = exempt_gaussians(ref.bins.ranges, ref.bins.vals, ref.bins.gid, views[0], 16, ref.fragile, n)
+    ex = exempt_gaussians(ref.proj, ref.bins, views[0], 16, ref.fragile).any(axis=0)
+    touched = np.abs(ref.grads).max(axis=1) > 0
+    checked_fraction(ex, touched, 0.5, "fused L1: ")
     ok = grad_close(got, ref.grads)
-    assert not (~ok.all(axis=1) & ~ex.any(axis=0)).any()
+    assert not (~ok.all(axis=1) & ~ex).any()
+    # ... and every Gaussian, gradients and Adam update, with the oracle's image
+    # gradient zeroed at fragile pixels given to both sides
+    dLdC = masked_image_gradient(ref.dLdC, ref.fragile)
+    ref2 = oracle.train_step(d["scene"], views[0], 16, None, dLdC=dLdC)
+    m2 = P.Model(d["scene"].flat())
+    g2 = torch.zeros_like(m2.params)
+    f2 = P.Frame(n, [w for w, _ in RES], [h for _, h in RES], 16, capacity=cap)
+    P.train_step(m2, f2, vrows[0], None, grads_out=g2, dLdC=torch.as_tensor(dLdC, device="cuda"))
+    got2 = P.unpack_flat(g2).cpu().numpy()
+    ok2 = grad_close(got2, ref2.grads)
+    checked_fraction(np.zeros(n, bool), np.abs(ref2.grads).max(axis=1) > 0, 1.0, "given gradient: ")
+    assert ok2.all(), np.argwhere(~ok2)[:5]
+    par = P.unpack_flat(m2.params).cpu().numpy()
+    gmax = np.abs(ref2.grads).max(axis=0, keepdims=True)
+    certain = np.abs(ref2.grads) >= 1e-3 * gmax
+    tol = np.where(certain, 1e-3 * np.abs(ref2.params) + 1e-6, 2e-3 + 1e-6)
+    assert (np.abs(par - ref2.params) <= tol).all()
 
 
 def test_autotune_picks_a_candidate_and_caches(setup, tmp_path):

@@ -44,7 +44,7 @@ def test_plain_300k_1280x720_full_size():
     fwd = oracle.raster_fwd(pr, bins, views, 16, tile_mask=tmask)
     pix_tile = (np.arange(W * H) // W // 16) * gx + (np.arange(W * H) % W) // 16
     inside = tmask[pix_tile].astype(bool)
-    _, dLdC = oracle.l1(fwd.rgb, target, fragile=fwd.fragile)
+    _, dLdC = oracle.l1(fwd.rgb, target, fragile=fwd.fragile, last=fwd.last)
     ok = inside & (fwd.fragile == 0)
     assert ok.sum() > 0.9 * inside.sum()
     err = np.abs(g["image"] - fwd.rgb).max(axis=1)
@@ -52,7 +52,7 @@ def test_plain_300k_1280x720_full_size():
     np.testing.assert_array_equal(g["last"][ok], fwd.last[ok])
     assert np.abs(g["T"] - fwd.T)[ok].max() <= 1e-4
     partials, _ = oracle.raster_bwd(pr, bins, views, 16, dLdC, tile_mask=tmask)
-    ex = exempt_gaussians(bins.ranges, bins.vals, bins.gid, views, 16, fwd.fragile & inside, scene.n)[0]
+    ex = exempt_gaussians(pr, bins, views, 16, fwd.fragile & inside)[0]
     bit = lambda m, i: (m[i >> 5] >> (i & 31)) & 1
     kept, quiet = [], []
     for t in sample:

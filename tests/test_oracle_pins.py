@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import synthetic as S
-from helpers import exempt_gaussians, grad_close
+from helpers import exempt_gaussians, grad_close, masked_image_gradient
 
 pytestmark = pytest.mark.usefixtures("oracle_lib")
 
@@ -570,12 +570,67 @@ def test_float32_oracle_agrees_with_float64_oracle_on_full_step():
     ok = r32.fragile == 0
     assert ok.mean() > 0.999
     assert np.abs(r32.image.rgb - r64.image.rgb)[ok].max() < 1e-4
-    ex = exempt_gaussians(r64.bins.ranges, r64.bins.vals, r64.bins.gid, w.views, 16,
-                          r32.fragile | r64.fragile, w.scene.n)[0]
+    ex = exempt_gaussians(r64.proj, r64.bins, w.views, 16, r32.fragile | r64.fragile)[0]
     ok_g = grad_close(r32.grads, r64.grads)
-    # every mismatch sits in a tile with a fragile pixel, and mismatches are rare
+    # every mismatch is a Gaussian a fragile pixel can composite, and mismatches are rare
     assert np.all(ok_g[~ex]), np.argwhere(~ok_g & ~ex[:, None])[:10]
     assert (~ok_g).any(axis=1).mean() < 0.01
+    # with the image gradient zeroed at the fragile pixels of either build and
+    # given to both, every Gaussian's gradient agrees
+    dLdC = masked_image_gradient(r32.dLdC, r32.fragile | r64.fragile)
+    g32 = oracle.train_step(w.scene, w.views, 16, None, dLdC=dLdC, adam_step=False).grads
+    g64 = oracle.train_step(w.scene, w.views, 16, None, dLdC=dLdC, adam_step=False, double=True).grads
+    assert grad_close(g32, g64).all()
+
+
+def test_pixel_support_covers_every_gaussian_a_pixel_composites():
+    """Flagging every pixel marks every (view, Gaussian) with a gradient, and
+    only listed ones; one pixel's support holds exactly the Gaussians whose
+    partials at that pixel alone are non-zero, within the margin's reach."""
+    w = S.workload_plain_small()
+    views = w.views
+    pr = oracle.project(w.scene, views, 16)
+    bins = oracle.bin_sort(pr, views, 16)
+    P = 256 * 256
+    allpix = np.ones(P, np.uint8)
+    sup = oracle.pixel_support(pr, bins, views, 16, allpix)[0]
+    img = oracle.raster_fwd(pr, bins, views, 16)
+    _, g2 = oracle.raster_bwd(pr, bins, views, 16, np.full((P, 3), 1.0))
+    has = np.abs(g2[0]).max(axis=1) > 0
+    assert np.all(sup[has])
+    listed = np.zeros(w.scene.n, bool)
+    listed[bins.gid] = True
+    assert not np.any(sup & ~listed)
+    # single pixels: the Gaussians whose partials from that pixel are non-zero
+    rng = np.random.default_rng(11)
+    busy = np.flatnonzero(img.last >= 5)
+    for p in rng.choice(busy, size=20, replace=False):
+        one = np.zeros(P, np.uint8)
+        one[p] = 1
+        s1 = oracle.pixel_support(pr, bins, views, 16, one)[0]
+        g = np.zeros((P, 3))
+        g[p] = 1.0
+        _, gp = oracle.raster_bwd(pr, bins, views, 16, g)
+        comp = np.abs(gp[0]).max(axis=1) > 0
+        assert np.all(s1[comp])
+        # the margin adds few beyond the composited ones
+        assert s1.sum() <= comp.sum() + 3 + comp.sum() // 4, (s1.sum(), comp.sum())
+
+
+def test_l1_sign_tie_flag_skips_pixels_that_composited_nothing():
+    img = np.array([[0.1, 0.2, 0.05], [0.3, 0.3, 0.3], [0.5, 0.5, 0.5]])
+    tgt = np.array([[0.1, 0.2, 0.05], [0.3, 0.3, 0.3], [0.2, 0.6, 0.9]], np.float32)
+    tgt64 = tgt.astype(np.float64)
+    img[:2] = tgt64[:2]
+    fr = np.zeros(3, np.uint8)
+    _, g = oracle.l1(img, tgt, fragile=fr, last=np.array([0, 4, 2], np.uint32))
+    # pixel 0: background, exact tie, nothing composited -> not flagged;
+    # pixel 1: tie where something composited -> flagged; pixel 2: sign certain
+    assert fr.tolist() == [0, 1, 0]
+    assert np.all(g[0] == 0) and np.all(g[1] == 0)
+    fr2 = np.zeros(3, np.uint8)
+    oracle.l1(img, tgt, fragile=fr2)
+    assert fr2[0] == 1
 
 
 # ---------------------------------------------------------------------------
@@ -690,3 +745,23 @@ def test_ellipse_culling_changes_no_pixel_below_the_three_sigma_opacity():
         assert ok.mean() > 0.99
         np.testing.assert_array_equal(ir.rgb[ok], ie.rgb[ok])
         np.testing.assert_array_equal(ir.T[ok], ie.T[ok])
+
+
+def test_running_error_bound_dominates_the_sums_it_bounds():
+    """mag2d (the float32 running error bound of the screen-space sums, in
+    rounding units) is at least 8 times the sum of absolute terms, so it bounds
+    |grads2d| by the triangle inequality, and is positive wherever a sum is
+    non-zero; the projection backward carries it linearly (one component at a
+    time), so the parameter bound also dominates the parameter gradients."""
+    w = S.workload_plain_small()
+    views = w.views
+    target = oracle.render(w.target_scene, views, 16)
+    r = oracle.train_step(w.scene, views, 16, target, adam_step=False)
+    pr = oracle.project(w.scene, views, 16)
+    bins = oracle.bin_sort(pr, views, 16)
+    _, g2, m2 = oracle.raster_bwd(pr, bins, views, 16, r.dLdC, magnitudes=True)
+    np.testing.assert_array_equal(g2, r.grads2d)
+    assert np.all(np.abs(g2) * 8.0 <= m2 * (1 + 1e-12))
+    assert np.all(m2[np.abs(g2) > 0] > 0)
+    M = oracle.project_bwd_magnitudes(w.scene, views, 16, m2)
+    assert np.all(np.abs(r.grads) * 8.0 <= M * (1 + 1e-9) + 1e-300)

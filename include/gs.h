@@ -368,6 +368,26 @@ int gs_project_bwd_adam(float* params, int64_t n, const gs_view* views, const gs
                         const gs_splats* splats, const gs_bins* bins, const gs_grads2d* grads,
                         const gs_adam* adam, float* grads_out, void* stream);
 
+/* gs_project_bwd_adam for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same kernels and results, but grads->workspace is ignored
+ * (it may be NULL) and the gather's partial slots live in a static device
+ * array of GS_NOALLOC_SCRATCH_BYTES that each GPU the library runs on holds
+ * until the process ends.  The caller still passes every input and output.
+ * Limit: gs_grads2d_workspace_size(bins->capacity) must not exceed
+ * GS_NOALLOC_SCRATCH_BYTES (about 214M intersections), else GS_ERR_WORKSPACE
+ * and nothing is enqueued.  Calls no allocating routine; its first call on
+ * each device looks up that device's copy of the array (hipGetSymbolAddress).
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents (nothing needs clearing: every slot a call reads was written
+ * earlier in the same call): calls that overlap on one GPU (different streams
+ * or threads without ordering) race and give undefined results; calls ordered
+ * on one stream are safe. */
+#define GS_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+int gs_project_bwd_adam_noalloc(float* params, int64_t n, const gs_view* views, const gs_layout* layout,
+                                const gs_splats* splats, const gs_bins* bins, const gs_grads2d* grads,
+                                const gs_adam* adam, float* grads_out, void* stream);
+
 /* ---- learned tile schedule (per-tile cost model) --------------------------- */
 
 /* 8 features per tile of the current bins (float, total tiles x 8): log(1 +

@@ -18,6 +18,7 @@ PARAM_PLANES = 15
 MLP_PARAMS = 1377
 MLP_GROUPS = 64
 MLP_SCRATCH = (MLP_GROUPS + 1) * (MLP_PARAMS + 1)
+NOALLOC_SCRATCH_BYTES = 32 << 20   # GS_NOALLOC_SCRATCH_BYTES
 
 GS_OK, GS_ERR_INVALID_ARG, GS_ERR_HIP, GS_ERR_WORKSPACE, GS_ERR_CAPACITY = 0, -1, -2, -3, -4
 STATUS_CAPACITY, STATUS_OVERFLOW, STATUS_ROWS, STATUS_SORT = 1, 2, 4, 8
@@ -102,6 +103,9 @@ _SIGS = {
     "gs_project_bwd_adam": (C.c_int, [_P, C.c_int64, _P, C.POINTER(GsLayout), C.POINTER(GsSplats),
                                       C.POINTER(GsBins), C.POINTER(GsGrads2d), C.POINTER(GsAdam),
                                       _P, _P]),
+    "gs_project_bwd_adam_noalloc": (C.c_int, [_P, C.c_int64, _P, C.POINTER(GsLayout), C.POINTER(GsSplats),
+                                              C.POINTER(GsBins), C.POINTER(GsGrads2d), C.POINTER(GsAdam),
+                                              _P, _P]),
     "gs_tile_features": (C.c_int, [C.POINTER(GsSplats), C.c_int64, C.POINTER(GsLayout),
                                    C.POINTER(GsBins), _P, _P]),
     "gs_mlp_forward": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P]),

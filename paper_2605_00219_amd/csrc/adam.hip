@@ -15,6 +15,8 @@
 // The forward quantities needed by the chain rule are recomputed with the same
 // float32 code as the projection kernel, so every branch decision (culling,
 // Jacobian clamp, colour clamp) matches the forward pass bitwise.
+#include <mutex>
+
 #include "project_math.h"
 
 namespace gs {
@@ -511,6 +513,59 @@ __global__ void k_adam_tick(int32_t* step, float* bias, float beta1, float beta2
     *step = t;
     bias[0] = (float)(1.0 - pow((double)beta1, (double)t));
     bias[1] = (float)sqrt(1.0 - pow((double)beta2, (double)t));
+}
+
+// Device scratch of gs_project_bwd_adam_noalloc: the gather's partial slots.
+// Host code never uses the array's name as an address: each device's copy is
+// found once with hipGetSymbolAddress (with that device current) and that
+// pointer is what the kernels receive.
+static __device__ __align__(256) unsigned char scratch[GS_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+
+static int noalloc_scratch(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        set_error("gs_project_bwd_adam_noalloc: hipGetDevice: %s", hipGetErrorString(e));
+        return GS_ERR_HIP;
+    }
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("gs_project_bwd_adam_noalloc: device %d beyond %d", dev, kMaxDevices);
+        return GS_ERR_INVALID_ARG;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error("gs_project_bwd_adam_noalloc: hipGetSymbolAddress: %s", hipGetErrorString(e));
+            return GS_ERR_HIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return GS_OK;
+}
+
+int launch_project_bwd_adam_noalloc(float* params, int64_t n, const gs_view* views, const gs_layout& L,
+                                    const gs_splats& splats, const gs_bins& b, const gs_grads2d& grads,
+                                    const gs_adam* adam, float* grads_out, hipStream_t s) {
+    const size_t need = gather_workspace(b.capacity);
+    if (need > (size_t)GS_NOALLOC_SCRATCH_BYTES) {
+        set_error("gs_project_bwd_adam_noalloc: capacity %lld needs %zu bytes of scratch, more than the "
+                  "%zu the library holds",
+                  (long long)b.capacity, need, (size_t)GS_NOALLOC_SCRATCH_BYTES);
+        return GS_ERR_WORKSPACE;
+    }
+    void* ws = nullptr;
+    const int rc = noalloc_scratch(&ws);
+    if (rc != GS_OK) return rc;
+    gs_grads2d g = grads;
+    g.workspace = ws;
+    return launch_project_bwd_adam(params, n, views, L, splats, b, g, adam, grads_out, s);
 }
 
 int launch_project_bwd_adam(float* params, int64_t n, const gs_view* views, const gs_layout& L,

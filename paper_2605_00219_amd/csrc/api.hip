@@ -206,6 +206,22 @@ int gs_project_bwd_adam(float* params, int64_t n, const gs_view* views, const gs
                                    (hipStream_t)stream);
 }
 
+int gs_project_bwd_adam_noalloc(float* params, int64_t n, const gs_view* views, const gs_layout* layout,
+                                const gs_splats* splats, const gs_bins* bins, const gs_grads2d* grads,
+                                const gs_adam* adam, float* grads_out, void* stream) {
+    REQUIRE(layout_ok(layout), "gs_project_bwd_adam_noalloc: invalid layout");
+    REQUIRE(views && bins && bins->offsets && (n == 0 || params), "gs_project_bwd_adam_noalloc: null pointer");
+    REQUIRE(adam || grads_out, "gs_project_bwd_adam_noalloc: need adam state or grads_out");
+    REQUIRE(!adam || (adam->m && adam->v && adam->step && adam->scratch),
+            "gs_project_bwd_adam_noalloc: incomplete adam state");
+    REQUIRE(splats && (n == 0 || splats->rec), "gs_project_bwd_adam_noalloc: null splat records");
+    REQUIRE(grads && (grads->sums || n == 0) && ((grads->rec && grads->rec_mask) || bins->capacity == 0),
+            "gs_project_bwd_adam_noalloc: null gradient buffers");
+    if (n == 0) return GS_OK;
+    return launch_project_bwd_adam_noalloc(params, n, views, *layout, *splats, *bins, *grads, adam, grads_out,
+                                           (hipStream_t)stream);
+}
+
 int64_t gs_loss_blocks(const gs_layout* layout) {
     if (!layout_ok(layout)) return 0;
     return loss_blocks(*layout);

@@ -53,6 +53,9 @@ int launch_raster_bwd2(const gs_splats& sp, int64_t n, const gs_layout& L, const
 int launch_project_bwd_adam(float* params, int64_t n, const gs_view* views, const gs_layout& L,
                             const gs_splats& splats, const gs_bins& b, const gs_grads2d& grads,
                             const gs_adam* adam, float* grads_out, hipStream_t s);
+int launch_project_bwd_adam_noalloc(float* params, int64_t n, const gs_view* views, const gs_layout& L,
+                                    const gs_splats& splats, const gs_bins& b, const gs_grads2d& grads,
+                                    const gs_adam* adam, float* grads_out, hipStream_t s);
 int launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
 int launch_tile_features(const gs_splats& sp, int64_t n, const gs_layout& L, const gs_bins& b,
                          float* features, hipStream_t s);

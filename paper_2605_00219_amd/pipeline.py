@@ -327,6 +327,18 @@ def project_bwd_adam(model: Model, frame: Frame, views_dev: torch.Tensor, adam: 
                                       G.stream_ptr(stream)), "gs_project_bwd_adam")
 
 
+def project_bwd_adam_noalloc(model: Model, frame: Frame, views_dev: torch.Tensor, adam: bool = True,
+                             grads_out: torch.Tensor | None = None, stream=None) -> None:
+    """project_bwd_adam through gs_project_bwd_adam_noalloc: the library's static
+    device scratch instead of frame's workspace (nothing allocated)."""
+    G.check(G.lib.gs_project_bwd_adam_noalloc(_i(model.params), frame.n, _i(views_dev), C.byref(frame.layout),
+                                              C.byref(frame.splats), C.byref(frame.bins),
+                                              C.byref(frame.grads2d),
+                                              C.byref(model.adam) if adam else None,
+                                              _i(grads_out) if grads_out is not None else None,
+                                              G.stream_ptr(stream)), "gs_project_bwd_adam_noalloc")
+
+
 def tile_rows(frame: Frame) -> int:
     """R: tile-row slots the current projection needs (synchronises)."""
     bits = frame.rec[:, 12:14].view(torch.int32).to(torch.int64)

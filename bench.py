@@ -29,7 +29,17 @@ sys.path.insert(0, ROOT)
 
 METRIC = "train iters/sec + rasterize_bwd HBM GB/s (% peak), batched/learned vs plain"
 HBM_PEAK_GBS = 8000.0
-FP32_PEAK_TFLOPS = 157.3
+# fp32 vector peak without packed instructions (the build disables them): one
+# FMA (2 flops) per lane per clock, 256 CUs x 64 lanes x 2.4 GHz
+FP32_PEAK_TFLOPS = 78.6
+# VALU issue: each of the 1024 SIMDs (16 lanes) starts one wave64 instruction
+# every 4 clocks at 2.4 GHz
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
+# the rasterisation backward's bytes in the metric's own model: 80 per
+# traversed (Gaussian, tile) entry (44 read, 36 of partials written) and 32 per
+# pixel (C, target, T, last)
+METRIC_BWD_BYTES_TRAVERSED = 80
+METRIC_BWD_BYTES_PIXEL = 32
 
 # Algorithmic work per unit of each stage (the same figures are derived in the
 # design notes): bytes that must cross HBM, or flops that must be executed.
@@ -95,6 +105,46 @@ def recorded_traffic(stage: str):
     return None
 
 
+def bwd_figures(rb, counts, P_px, kernel="rasterize_bwd"):
+    """The backward's work counts and rates (design byte model, flops, and the
+    counters recorded for it when current)."""
+    t = rb["ms"] * 1e-3
+    out = {"ms": rb["ms"], "algorithmic_bytes": rb["algorithmic_bytes"], "hbm_gbs": rb["hbm_gbs"],
+           "hbm_frac": rb["hbm_frac"], "algorithmic_flop": rb["algorithmic_flop"],
+           "tflops": rb["achieved"], "alu_frac": rb["frac"],
+           "intersections": counts["K"], "traversed": counts["trav_bwd"],
+           "composited_entries": counts["flagged"], "pairs_evaluated": counts["eval_bwd"],
+           "pairs_composited": counts["contrib"], "visible_gaussians": counts["visible"],
+           "pairs_per_traversed_entry": counts["eval_bwd"] / max(counts["trav_bwd"], 1)}
+    tr = recorded_traffic(kernel)
+    if tr is not None:
+        out["measured_hbm_bytes"] = tr["bytes_per_launch"]
+        out["measured_hbm_gbs"] = tr["bytes_per_launch"] / t / 1e9
+        out["measured_hbm_frac"] = tr["bytes_per_launch"] / t / 1e9 / HBM_PEAK_GBS
+    return out
+
+
+def headline_roofline(rb, counts, P_px, kernel="rasterize_bwd"):
+    """rasterize_bwd against HBM in the metric's byte model (80 B per traversed
+    entry + 32 B per pixel), the counter-measured bytes as traffic, and beside
+    it the ALU (non-packed fp32) and VALU-issue fractions."""
+    t = rb["ms"] * 1e-3
+    nbytes = METRIC_BWD_BYTES_TRAVERSED * counts["trav_bwd"] + METRIC_BWD_BYTES_PIXEL * P_px
+    gbs = nbytes / t / 1e9
+    tr = recorded_traffic(kernel)
+    roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            "traffic": tr["bytes_per_launch"] if tr else None, "kernel": kernel,
+            "algorithmic_bytes": nbytes, "ms": rb["ms"],
+            "traffic_source": (f"rocprofv3 FETCH_SIZE + WRITE_SIZE, sources {tr['source_sha']}" if tr else None),
+            "alu": {"achieved": rb["achieved"], "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": rb["frac"]}}
+    if tr is not None and tr.get("valu_insts_per_launch"):
+        ips = tr["valu_insts_per_launch"] / t
+        roof["valu_issue"] = {"achieved": ips, "peak": VALU_ISSUE_PEAK, "unit": "wave64 instructions/s",
+                              "frac": ips / VALU_ISSUE_PEAK}
+    return roof
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +152,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--lds-batch", type=int, default=128)
     ap.add_argument("--n", type=int, default=300_000)
+    ap.add_argument("--log-scale-mean", type=float, default=-4.0,
+                    help="log-scale distribution of the headline scene (N(-6, 0.3): the sparse-footprint "
+                         "form, for profiling it on its own)")
+    ap.add_argument("--log-scale-std", type=float, default=0.7)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-replay", action="store_true", help="skip the work-counting replay")
     ap.add_argument("--no-graph", action="store_true",
@@ -109,9 +163,9 @@ def parse():
                          "stage times always come from an eager pass)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (for HBM counter scaling)")
-    ap.add_argument("--variants", default="ellipse,ssim,twophase,thompson,batched,learned",
-                    help="comma list of extra measurements: ellipse, ssim, twophase, thompson, batched, "
-                         "learned ('none' for none)")
+    ap.add_argument("--variants", default="sparse,ellipse,ssim,twophase,thompson,batched,learned",
+                    help="comma list of extra measurements: sparse, ellipse, ssim, twophase, thompson, "
+                         "batched, learned ('none' for none)")
     ap.add_argument("--cull", type=int, default=0, choices=(0, 1),
                     help="tile set of the headline run: 0 = 3-sigma rectangle, 1 = exact ellipse")
     ap.add_argument("--batched-steps", type=int, default=200)
@@ -138,7 +192,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     log("generating workload")
-    w = S.workload_plain_300k(n=args.n)
+    w = S.workload_plain_300k(n=args.n, log_scale_mean=args.log_scale_mean, log_scale_std=args.log_scale_std)
     n = w.scene.n
     W, H = int(w.views[0]["width"]), int(w.views[0]["height"])
     ncam = len(w.views)
@@ -161,12 +215,16 @@ def main():
             rgba = torch.cat([targets[i], 1.0 - tframe.T[:, None]], 1)
             targets8[i].copy_(torch.round(rgba.clamp(0, 1) * 255).to(torch.uint8))
     del tgt_model, tframe
+    targets_main = targets
 
-    def run_plain(cull, replay, loss="l1", ts_arms=None, bwd_variant=None, graph=False):
+    def run_plain(cull, replay, loss="l1", ts_arms=None, bwd_variant=None, graph=False, wk=None, tg=None):
         """Timed plain steps (and the work-counting replay) with the given tile
         culling; loss "l1" (fused into the backward) or "ssim" (L1 + D-SSIM
-        against the RGBA8 references, lambda 0.2, alpha mask)."""
-        model = P.Model(w.scene.flat(), lr=w.lr)
+        against the RGBA8 references, lambda 0.2, alpha mask); wk, tg: another
+        scene of the same size with its targets (same cameras)."""
+        wk = wk or w
+        targets = tg if tg is not None else targets_main
+        model = P.Model(wk.scene.flat(), lr=wk.lr)
         frame = P.Frame(n, [W], [H], 16, cull=cull)
         lossfn = P.LossL1SSIM(frame, 0.2, True) if loss == "ssim" else None
         # backward LDS batch chosen per step by Thompson sampling over ts_arms
@@ -386,10 +444,10 @@ def main():
                 "kernel_bytes_gbs": LOSS_KERNEL_BYTES_PX * px / t_loss / 1e9}}
         del targets8
 
-    # roofline of the dominant kernel: the single-kernel stage with the largest
-    # time (binning and the projection backward are several kernels each);
-    # every stage's figure is reported under stage_roofline
-    dom = max(("project", "rasterize_fwd", "rasterize_bwd"), key=stage_ms.get)
+    # per-stage rooflines (each stage's own bound and algorithmic work) under
+    # stage_roofline; the headline `roofline` is rasterize_bwd's (the kernel the
+    # metric names, and the step's longest single kernel) against HBM, with its
+    # ALU and VALU-issue figures beside it
     roof = None
     extra = {}
     P_px = H * W
@@ -433,27 +491,40 @@ def main():
                                     + counts["K"] / 8, "project_bwd_adam"),
         }
         rb = per_stage["rasterize_bwd"]
-        extra["rasterize_bwd"] = {
-            "ms": rb["ms"], "algorithmic_bytes": rb["algorithmic_bytes"], "hbm_gbs": rb["hbm_gbs"],
-            "hbm_frac": rb["hbm_frac"], "algorithmic_flop": rb["algorithmic_flop"],
-            "tflops": rb["achieved"], "alu_frac": rb["frac"],
-            "intersections": counts["K"], "traversed": counts["trav_bwd"],
-            "composited_entries": counts["flagged"],
-            "pairs_evaluated": counts["eval_bwd"], "pairs_composited": counts["contrib"],
-            "visible_gaussians": vis}
-        tr = recorded_traffic("rasterize_bwd")
-        if tr is not None:
-            t_bwd = rb["ms"] * 1e-3
-            extra["rasterize_bwd"]["measured_hbm_bytes"] = tr["bytes_per_launch"]
-            extra["rasterize_bwd"]["measured_hbm_gbs"] = tr["bytes_per_launch"] / t_bwd / 1e9
-            extra["rasterize_bwd"]["measured_hbm_frac"] = tr["bytes_per_launch"] / t_bwd / 1e9 / HBM_PEAK_GBS
+        extra["rasterize_bwd"] = bwd_figures(rb, counts, P_px)
         extra["stage_roofline"] = {k: {kk: v[kk] for kk in ("bound", "achieved", "unit", "frac")}
                                    for k, v in per_stage.items()}
-        roof = {k: per_stage[dom][k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic",
-                                              "kernel")}
+        roof = headline_roofline(rb, counts, P_px)
     if roof is None:
-        roof = {"bound": "unknown", "achieved": None, "peak": None, "unit": None, "frac": None,
-                "traffic": None, "kernel": dom}
+        roof = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
+                "traffic": None, "kernel": "rasterize_bwd"}
+
+    if "sparse" in variants:
+        log("sparse-footprint variant: log-scales N(-6, 0.3)")
+        ws_ = S.workload_plain_300k(n=args.n, log_scale_mean=-6.0, log_scale_std=0.3)
+        tm = P.Model(ws_.target_scene.flat())
+        tf_ = P.Frame(n, [W], [H], 16)
+        tg_s = torch.empty(ncam, H * W, 3, device=dev)
+        for i in range(ncam):
+            P.fit_capacity(tm.params, tf_, vptr(i))
+            tg_s[i].copy_(P.render(tm.params, tf_, vptr(i)))
+        del tm, tf_
+        rs = run_plain(0, True, wk=ws_, tg=tg_s)
+        cs = rs["counts"]
+        t_s = rs["stage_ms"]["rasterize_bwd"] * 1e-3
+        bytes_s = (BWD_BYTES_TRAVERSED * cs["trav_bwd"] + BWD_BYTES_FLAGGED * cs["flagged"]
+                   + BWD_BYTES_PIXEL * P_px + BWD_BYTES_TILE * rs["ntiles"])
+        rb_s = {"ms": rs["stage_ms"]["rasterize_bwd"], "algorithmic_bytes": bytes_s,
+                "hbm_gbs": bytes_s / t_s / 1e9, "hbm_frac": bytes_s / t_s / 1e9 / HBM_PEAK_GBS,
+                "algorithmic_flop": BWD_FLOP_EVAL * cs["eval_bwd"] + BWD_FLOP_CONTRIB * cs["contrib"]}
+        rb_s["achieved"] = rb_s["algorithmic_flop"] / t_s / 1e12
+        rb_s["frac"] = rb_s["achieved"] / FP32_PEAK_TFLOPS
+        extra["sparse"] = {"workload": ws_.name, "log_scales": "N(-6, 0.3)", "iters_per_s": rs["ips"],
+                           "ms_per_step": 1e3 * rs["wall"] / args.steps, "stage_ms": rs["stage_ms"],
+                           "rasterize_bwd": bwd_figures(rb_s, cs, P_px, "rasterize_bwd_sparse"),
+                           "roofline": headline_roofline(rb_s, cs, P_px, "rasterize_bwd_sparse")}
+        del ws_, tg_s
+        torch.cuda.empty_cache()
 
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB
@@ -463,7 +534,7 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    targets = None                                      # free the plain workload's buffers
+    targets = targets_main = None                       # free the plain workload's buffers
     torch.cuda.empty_cache()
     if cull_variant is not None:
         extra["cull_ellipse"] = cull_variant
@@ -504,7 +575,7 @@ def main():
         "metric": METRIC, "value": value, "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * value_wall / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"plain-{n // 1000}k-{W}x{H}", "gaussians": n, "width": W,
+        "config": {"workload": w.name, "gaussians": n, "width": W,
                    "height": H, "views_per_step": 1, "cameras": ncam, "tile": 16,
                    "lds_batch": args.lds_batch, "loss": "L1", "lr": w.lr,
                    "culling": "ellipse" if args.cull else "3-sigma rectangle",

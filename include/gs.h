@@ -231,6 +231,15 @@ size_t gs_bin_sort_workspace_size(int64_t n, const gs_layout* layout, int64_t ca
  * sums of 9 floats, each with its owner. */
 size_t gs_grads2d_workspace_size(int64_t capacity);
 
+/* A second stream a call may run independent work on, with the two events
+ * that fork it from and join it back to the call's stream; all three owned by
+ * the caller. */
+typedef struct gs_side_stream {
+    void* stream;   /* hipStream_t, default priority */
+    void* fork;     /* hipEvent_t */
+    void* join;     /* hipEvent_t */
+} gs_side_stream;
+
 /* ---- the five stages ------------------------------------------------------ */
 
 /* Projection forward (paper Sec. 2 parameterisation; Sec. 4.1 tile count).
@@ -264,14 +273,18 @@ int gs_project(const float* params, int64_t n, const gs_view* views, const gs_la
  * rows[4 r] + (tx - xa) with r = row_offsets[v*n+g] + (ty - y0).  If K > capacity only the first `capacity`
  * intersections are written and GS_STATUS_CAPACITY is set; the caller reads
  * offsets[V*n] to size a retry.
- * With many intersections per (view, Gaussian) part of the work runs on an
- * auxiliary stream of the library (one per host thread and device, default
- * priority, created on the first such call and kept), forked from and joined
- * back to `stream` with events, so the call remains ordered on `stream` and
- * capturable in a graph once that stream exists.
- *   workspace  device scratch of gs_bin_sort_workspace_size bytes */
+ * With many intersections per (view, Gaussian) the depth sort of the
+ * (view, Gaussian)s can run beside the scans and row slots: if `side` is
+ * given, it is enqueued on side->stream after side->fork is recorded on
+ * `stream`, and `stream` waits on side->join (recorded on side->stream after
+ * it), so the call stays ordered on `stream` and capturable in a graph; with
+ * side NULL everything runs on `stream`.  Same results either way.
+ *   workspace  device scratch of gs_bin_sort_workspace_size bytes
+ *   side       nullable; caller-owned stream (default priority) and two events
+ *              (created with hipEventDisableTiming), used only by this call
+ *              while it runs */
 int gs_bin_sort(const gs_splats* splats, int64_t n, const gs_layout* layout, const gs_bins* bins,
-                void* workspace, size_t workspace_bytes, void* stream);
+                void* workspace, size_t workspace_bytes, const gs_side_stream* side, void* stream);
 
 /* Rasterisation forward.  Per pixel, front to back over its tile's sorted
  * list: d = pixel centre - mean2d, power = -1/2 (A dx^2 + C dy^2) - B dx dy,

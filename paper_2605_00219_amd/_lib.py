@@ -52,6 +52,10 @@ class GsBins(C.Structure):
                 ("ranges", C.c_void_p), ("status", C.c_void_p), ("capacity", C.c_int64)]
 
 
+class GsSideStream(C.Structure):
+    _fields_ = [("stream", C.c_void_p), ("fork", C.c_void_p), ("join", C.c_void_p)]
+
+
 class GsGrads2d(C.Structure):
     _fields_ = [("rec", C.c_void_p), ("rec_mask", C.c_void_p), ("tile_stop", C.c_void_p),
                 ("sums", C.c_void_p), ("workspace", C.c_void_p)]
@@ -90,7 +94,7 @@ _SIGS = {
     "gs_grads2d_workspace_size": (C.c_size_t, [C.c_int64]),
     "gs_project": (C.c_int, [_P, C.c_int64, _P, C.POINTER(GsLayout), C.POINTER(GsSplats), _P]),
     "gs_bin_sort": (C.c_int, [C.POINTER(GsSplats), C.c_int64, C.POINTER(GsLayout), C.POINTER(GsBins),
-                              _P, C.c_size_t, _P]),
+                              _P, C.c_size_t, C.POINTER(GsSideStream), _P]),
     "gs_rasterize_fwd": (C.c_int, [C.POINTER(GsSplats), C.c_int64, C.POINTER(GsLayout),
                                    C.POINTER(GsBins), _P, C.POINTER(GsImage), C.c_int,
                                    C.POINTER(GsSchedule), _P]),

@@ -115,8 +115,9 @@ int gs_project(const float* params, int64_t n, const gs_view* views, const gs_la
 }
 
 int gs_bin_sort(const gs_splats* splats, int64_t n, const gs_layout* layout, const gs_bins* bins,
-                void* workspace, size_t workspace_bytes, void* stream) {
+                void* workspace, size_t workspace_bytes, const gs_side_stream* side, void* stream) {
     REQUIRE(layout_ok(layout), "gs_bin_sort: invalid layout");
+    REQUIRE(!side || (side->stream && side->fork && side->join), "gs_bin_sort: incomplete side stream");
     REQUIRE(splats && bins, "gs_bin_sort: null pointer");
     REQUIRE(n >= 0 && (int64_t)layout->n_views * n < (int64_t(1) << 32), "gs_bin_sort: n out of range");
     REQUIRE(bins->capacity >= 0 && bins->capacity < (int64_t(1) << 32) - 1,
@@ -126,7 +127,7 @@ int gs_bin_sort(const gs_splats* splats, int64_t n, const gs_layout* layout, con
     REQUIRE(bins->row_capacity >= 0 && bins->row_capacity < (int64_t(1) << 32) - 1 &&
             (bins->row_capacity == 0 || bins->rows), "gs_bin_sort: bad row buffer");
     REQUIRE(workspace || workspace_bytes == 0, "gs_bin_sort: null workspace");
-    return launch_bin_sort(*splats, n, *layout, *bins, workspace, workspace_bytes, (hipStream_t)stream);
+    return launch_bin_sort(*splats, n, *layout, *bins, workspace, workspace_bytes, side, (hipStream_t)stream);
 }
 
 static int check_sched(const gs_schedule* sched) {

@@ -1004,43 +1004,11 @@ int sort_pairs(uint32_t* keys, uint32_t* vals, int64_t count, void* scratch, hip
 }
 
 // ---------------------------------------------------------------------------
-// auxiliary stream: the depth sort runs beside the scans and row slots
-// ---------------------------------------------------------------------------
-
-struct AuxStream {
-    hipStream_t stream = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
-};
-
-// One auxiliary stream (default priority) and two events per host thread and
-// device, created on first use and kept for the life of the process.
-static int aux_stream(AuxStream** out) {
-    constexpr int kMaxDevices = 64;
-    static thread_local AuxStream aux[kMaxDevices];
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
-        set_error("bin_sort: no current device");
-        return GS_ERR_HIP;
-    }
-    AuxStream& a = aux[dev];
-    if (!a.stream) {
-        if (hipStreamCreateWithFlags(&a.stream, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&a.fork, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&a.join, hipEventDisableTiming) != hipSuccess) {
-            set_error("bin_sort: cannot create the auxiliary stream");
-            return GS_ERR_HIP;
-        }
-    }
-    *out = &a;
-    return GS_OK;
-}
-
-// ---------------------------------------------------------------------------
 // driver
 // ---------------------------------------------------------------------------
 
 int launch_bin_sort(const gs_splats& sp, int64_t n, const gs_layout& L, const gs_bins& b, void* ws,
-                    size_t ws_bytes, hipStream_t s) {
+                    size_t ws_bytes, const gs_side_stream* side, hipStream_t s) {
     Workspace W;
     const size_t need = carve(n, L, b.capacity, (char*)ws, &W);
     if (ws_bytes < need) {
@@ -1092,26 +1060,29 @@ int launch_bin_sort(const gs_splats& sp, int64_t n, const gs_layout& L, const gs
     hipLaunchKernelGGL(k_row_count, dim3(gm), dim3(256), 0, s, rec, sp.tiles, n, m, eg, W.row_count, b.status,
                        W.dkey, W.dval, W.dtable, SD.dcount, V);
     if ((rc = check_launch("row_count")) != GS_OK) return rc;
-    AuxStream* aux = nullptr;
-    if (depth_first) {
-        // depth order on the auxiliary stream: a stable sort of the
-        // (view, Gaussian)s by depth bits, then the scan of their tile counts
-        // in that order (each one's first position)
-        if ((rc = aux_stream(&aux)) != GS_OK) return rc;
-        if (hipEventRecord(aux->fork, s) != hipSuccess || hipStreamWaitEvent(aux->stream, aux->fork, 0) != hipSuccess) {
-            set_error("bin_sort: cannot fork to the auxiliary stream");
+    // the caller's side stream, if any, takes the depth order
+    const bool forked = depth_first && side != nullptr;
+    const hipStream_t ds = forked ? (hipStream_t)side->stream : s;
+    if (forked) {
+        if (hipEventRecord((hipEvent_t)side->fork, s) != hipSuccess ||
+            hipStreamWaitEvent(ds, (hipEvent_t)side->fork, 0) != hipSuccess) {
+            set_error("bin_sort: cannot fork to the side stream");
             return GS_ERR_HIP;
         }
+    }
+    if (depth_first) {
+        // depth order: a stable sort of the (view, Gaussian)s by depth bits,
+        // then the scan of their tile counts in that order (each one's first
+        // position); independent of the scans and row slots below
         if ((rc = radix_sort_views<kDepthItems>(W.dkey, W.dval, W.dkey_tmp, W.dval_tmp, W.dtable, V, SD, b.status,
-                                                aux->stream)) != GS_OK)
+                                                ds)) != GS_OK)
             return rc;
         const uint32_t* perm = SD.passes % 2 == 0 ? W.dval : W.dval_tmp;
-        if ((rc = scan_exclusive(sp.tiles, m, W.dpos, W.dblock_sums, nullptr, aux->stream, perm)) != GS_OK)
-            return rc;
-        if (hipEventRecord(aux->join, aux->stream) != hipSuccess) {
-            set_error("bin_sort: cannot join the auxiliary stream");
-            return GS_ERR_HIP;
-        }
+        if ((rc = scan_exclusive(sp.tiles, m, W.dpos, W.dblock_sums, nullptr, ds, perm)) != GS_OK) return rc;
+    }
+    if (forked && hipEventRecord((hipEvent_t)side->join, ds) != hipSuccess) {
+        set_error("bin_sort: cannot join the side stream");
+        return GS_ERR_HIP;
     }
     // offsets and row offsets, the view table, the row slots
     if ((rc = scan_exclusive(sp.tiles, m, b.offsets, W.block_sums, b.status, s)) != GS_OK) return rc;
@@ -1124,8 +1095,8 @@ int launch_bin_sort(const gs_splats& sp, int64_t n, const gs_layout& L, const gs
                            eg, b.row_capacity, rows, b.status);
         if ((rc = check_launch("rows")) != GS_OK) return rc;
     }
-    if (depth_first && hipStreamWaitEvent(s, aux->join, 0) != hipSuccess) {
-        set_error("bin_sort: cannot wait for the auxiliary stream");
+    if (forked && hipStreamWaitEvent(s, (hipEvent_t)side->join, 0) != hipSuccess) {
+        set_error("bin_sort: cannot wait for the side stream");
         return GS_ERR_HIP;
     }
     // keys (in depth order if depth_first), then the sort; the emit goes to

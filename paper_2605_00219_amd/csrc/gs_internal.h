@@ -36,7 +36,7 @@ GS_DEV void st4(float* p, int64_t i, float4 v) { reinterpret_cast<float4*>(p)[i]
 int launch_project(const float* params, int64_t n, const gs_view* views, const gs_layout& L,
                    const gs_splats& out, hipStream_t s);
 int launch_bin_sort(const gs_splats& sp, int64_t n, const gs_layout& L, const gs_bins& b,
-                    void* ws, size_t ws_bytes, hipStream_t s);
+                    void* ws, size_t ws_bytes, const gs_side_stream* side, hipStream_t s);
 size_t bin_sort_workspace(int64_t n, const gs_layout& L, int64_t capacity);
 size_t gather_workspace(int64_t capacity);
 int launch_raster_fwd(const gs_splats& sp, int64_t n, const gs_layout& L, const gs_bins& b,

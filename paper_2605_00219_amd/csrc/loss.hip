@@ -421,17 +421,12 @@ __global__ __launch_bounds__(kLT) __attribute__((amdgpu_waves_per_eu(4))) void k
 
 // ---- host ------------------------------------------------------------------
 
-// compute units of the current device, queried once per device
+// compute units of the current device (asked on every call: nothing is kept)
 static int cu_count() {
-    static std::atomic<int> cache[64];
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-    int c = cache[dev].load(std::memory_order_relaxed);
-    if (c == 0) {
-        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0)
-            c = 256;
-        cache[dev].store(c, std::memory_order_relaxed);
-    }
+    int dev = 0, c = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0)
+        return 256;
     return c;
 }
 

@@ -65,7 +65,7 @@ class Frame:
 
     def __init__(self, n: int, widths, heights, tile: int = 16, capacity: int = 1 << 16,
                  device="cuda", tile_stats: bool = False, pixels_per_lane: int | None = None,
-                 cull: int = G.CULL_RECT, row_capacity: int | None = None):
+                 cull: int = G.CULL_RECT, row_capacity: int | None = None, side_stream: bool = True):
         self.n = int(n)
         self.device = device
         self.cull = int(cull)
@@ -93,6 +93,20 @@ class Frame:
         self.capacity = 0
         self.row_capacity = 0
         self.resize(capacity, row_capacity)
+        # the binning's side stream (default priority) and its fork/join events,
+        # owned here; the events are recorded once so that they exist
+        self._side = None
+        if side_stream:
+            st = torch.cuda.Stream(device=device)
+            fork, join = torch.cuda.Event(), torch.cuda.Event()
+            fork.record(st)
+            join.record(st)
+            self._side_objs = (st, fork, join)
+            self._side = G.GsSideStream(st.cuda_stream, fork.cuda_event, join.cuda_event)
+
+    def side_stream(self):
+        """The GsSideStream gs_bin_sort may run its depth sort on (None: one stream)."""
+        return self._side
 
     # -- buffers sized by the intersection capacity (and the tile-row capacity) --
     def resize(self, capacity: int, row_capacity: int | None = None) -> None:
@@ -168,8 +182,10 @@ def project(params: torch.Tensor, frame: Frame, views_dev: torch.Tensor, stream=
 
 
 def bin_sort(frame: Frame, stream=None) -> None:
+    side = frame.side_stream()
     G.check(G.lib.gs_bin_sort(C.byref(frame.splats), frame.n, C.byref(frame.layout),
                               C.byref(frame.bins), _i(frame.workspace), frame.workspace.numel(),
+                              C.byref(side) if side is not None else None,
                               G.stream_ptr(stream)), "gs_bin_sort")
 
 

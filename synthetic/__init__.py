@@ -212,15 +212,18 @@ def workload_plain_small(n: int = 2000, width: int = 256, height: int = 256,
 
 
 def workload_plain_300k(n: int = 300_000, width: int = 1280, height: int = 720,
-                        n_cameras: int = 50, steps: int = 100, seed_base: int = 2000) -> Workload:
+                        n_cameras: int = 50, steps: int = 100, seed_base: int = 2000,
+                        log_scale_mean: float = -4.0, log_scale_std: float = 0.7) -> Workload:
     """300k Gaussians ~N(0,1)^3, log-scales N(-4,0.7), 50 cameras on a radius-5
-    sphere, 1280x720, one view per step."""
-    scene = scene_normal(n, seed_base)
-    target = scene_normal(n, seed_base + 1)
+    sphere, 1280x720, one view per step.  Other log-scale distributions give
+    the sparse-footprint form (N(-6, 0.3): footprints of about one pixel)."""
+    scene = scene_normal(n, seed_base, log_scale_mean, log_scale_std)
+    target = scene_normal(n, seed_base + 1, log_scale_mean, log_scale_std)
     cams = fibonacci_sphere(n_cameras, 5.0)
     views = views_array([make_view(width, height, c) for c in cams])
     order = np.random.default_rng(seed_base + 2).permutation(n_cameras)
-    return Workload(f"plain-{n // 1000}k-{width}x{height}", scene, target, views, tile=16,
+    sparse = "" if (log_scale_mean, log_scale_std) == (-4.0, 0.7) else f"-ls{log_scale_mean:g}"
+    return Workload(f"plain-{n // 1000}k-{width}x{height}{sparse}", scene, target, views, tile=16,
                     lr=1e-3, steps=steps, view_order=order)
 
 

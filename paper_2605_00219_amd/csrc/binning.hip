@@ -30,6 +30,12 @@ constexpr int kDigits = 256;
 constexpr int kPasses = 4;
 constexpr int kHistBlocks = 512;                        // workgroups of the histogram pass
 constexpr int kGroup = 16;                              // chunks per look-back group
+// single-pass tile scatter (depth order first, every view with at most
+// kTsBins tiles): chunks of kTsChunk keys in depth order
+constexpr int kTsThreads = 256;
+constexpr int kTsItems = 32;
+constexpr int kTsChunk = kTsThreads * kTsItems;          // 8192 keys
+constexpr int kTsBins = 4096;                            // tiles per view (12 bits)
 static_assert(kSortThreads == kDigits, "one thread per digit in the scan and look-back");
 
 // ---------------------------------------------------------------------------
@@ -65,7 +71,19 @@ struct Workspace {
     uint32_t* dtable;      // segments of the depth sort
     uint32_t* dsort_words;
     int64_t max_dchunks;
+    // single-pass tile scatter
+    uint32_t* tstable;     // 4 * (GS_MAX_VIEWS + 1): per view chunk base, chunks, matrix base, tiles
+    uint32_t* tsm;         // per view, tiles x chunks key counts, scanned in place (+1 word)
+    uint64_t* ts_sums;     // scan partials of tsm
+    int64_t max_ts_chunks;
+    int64_t ts_len;        // words of tsm scanned (an upper bound of the used length)
 };
+
+static int max_view_tiles(const gs_layout& L) {
+    int mt = 0;
+    for (int v = 0; v < L.n_views; ++v) mt = std::max(mt, L.tile_base[v + 1] - L.tile_base[v]);
+    return mt;
+}
 
 static int64_t max_chunks_for(int64_t capacity, int n_views) {
     return (capacity + kChunk - 1) / kChunk + n_views;
@@ -99,6 +117,12 @@ static size_t carve(int64_t n, const gs_layout& L, int64_t capacity, char* base,
     tmp.dtable = (uint32_t*)take(sizeof(uint32_t) * 4 * (GS_MAX_VIEWS + 1));
     tmp.dsort_words = (uint32_t*)take(sort_words_bytes(L.n_views, mcd));
     tmp.max_dchunks = mcd;
+    tmp.tstable = (uint32_t*)take(sizeof(uint32_t) * 4 * (GS_MAX_VIEWS + 1));
+    tmp.max_ts_chunks = (capacity + kTsChunk - 1) / kTsChunk + L.n_views;
+    const int mt = max_view_tiles(L);
+    tmp.ts_len = mt <= kTsBins ? (int64_t)mt * tmp.max_ts_chunks : 0;
+    tmp.tsm = (uint32_t*)take(sizeof(uint32_t) * (size_t)(tmp.ts_len + 1));
+    tmp.ts_sums = (uint64_t*)take(sizeof(uint64_t) * (size_t)(tmp.ts_len / kScanBlock + 2));
     if (w) *w = tmp;
     return off;
 }
@@ -293,12 +317,23 @@ static int scan_exclusive(const uint32_t* in, int64_t len, uint32_t* out, uint64
 // ---------------------------------------------------------------------------
 
 // Also clears the tile sort's digit totals.
+// Tiles of each view (for the single-pass tile scatter).
+struct TsGeom {
+    int32_t ntiles[GS_MAX_VIEWS];
+    int32_t tile_base[GS_MAX_VIEWS + 1];
+    int32_t depth_bits[GS_MAX_VIEWS];
+};
+
+// With tstable: the tile scatter's chunks of kTsChunk keys per view, and the
+// base of each view's tiles x chunks count matrix (views in order, each
+// tile-major), whose total length goes to tstable[4 * n_views + 1].
 __global__ void k_view_table(const uint32_t* __restrict__ offsets, int64_t n, int n_views,
                              int64_t capacity, uint32_t* __restrict__ table,
-                             uint32_t* __restrict__ status, uint32_t* __restrict__ dcount) {
+                             uint32_t* __restrict__ status, uint32_t* __restrict__ dcount,
+                             uint32_t* __restrict__ tstable, TsGeom tg) {
     for (int i = threadIdx.x; i < n_views * kPasses * kDigits; i += blockDim.x) dcount[i] = 0u;
     if (threadIdx.x != 0) return;
-    uint32_t chunks = 0;
+    uint32_t chunks = 0, tchunks = 0, mlen = 0;
     const uint64_t cap = (uint64_t)capacity;
     for (int v = 0; v < n_views; ++v) {
         uint64_t b = offsets[(int64_t)v * n], e = offsets[(int64_t)(v + 1) * n];
@@ -310,8 +345,21 @@ __global__ void k_view_table(const uint32_t* __restrict__ offsets, int64_t n, in
         table[4 * v + 2] = chunks;
         table[4 * v + 3] = nc;
         chunks += nc;
+        if (tstable) {
+            const uint32_t tc = (uint32_t)((e - b + kTsChunk - 1) / kTsChunk);
+            tstable[4 * v + 0] = tchunks;
+            tstable[4 * v + 1] = tc;
+            tstable[4 * v + 2] = mlen;
+            tstable[4 * v + 3] = (uint32_t)tg.ntiles[v];
+            tchunks += tc;
+            mlen += tc * (uint32_t)tg.ntiles[v];
+        }
     }
     table[4 * n_views] = chunks;
+    if (tstable) {
+        tstable[4 * n_views] = tchunks;
+        tstable[4 * n_views + 1] = mlen;
+    }
     if ((uint64_t)offsets[(int64_t)n_views * n] > cap) atomicOr(status, (uint32_t)GS_STATUS_CAPACITY);
 }
 
@@ -323,13 +371,14 @@ struct EmitGeom {
     int32_t tiles_x[GS_MAX_VIEWS];
     int32_t tiles_y[GS_MAX_VIEWS];
     int32_t depth_bits[GS_MAX_VIEWS];
+    int32_t split[GS_MAX_VIEWS];   // key bits (all depth bits) sorted in the depth order
     int32_t tile;
     int32_t cull;
 };
 
 // The first kernel of a call: clears the status word; per (view, Gaussian)
 // its tile rows (the rows of its bounding box) and, for the depth order, the
-// low min(kDepthSplit, D) bits of its keys (all depth bits) with its index;
+// low split bits of its keys (depth bits only) with its index;
 // workgroup 0 also writes the depth sort's table (one segment of n per view)
 // and clears its digit totals.
 __global__ __launch_bounds__(256) void k_row_count(const float4* __restrict__ rec,
@@ -358,9 +407,9 @@ __global__ __launch_bounds__(256) void k_row_count(const float4* __restrict__ re
     const float4 q3 = rec[4 * o + 3];
     row_count[o] = vis ? rect_rows(q3) : 0u;
     const int v = (int)(o / n);
-    // the key's bits below min(kDepthSplit, D): depth bits only
+    // the key's bits below split (at most D): depth bits only
     const int D = geo.depth_bits[v];
-    const int split = D < kDepthSplit ? D : kDepthSplit;
+    const int split = geo.split[v];
     const uint32_t dk = __float_as_uint(q3.z) >> (23 - D);
     dkey[o] = vis ? dk & ((1u << split) - 1u) : 0u;
     dval[o] = (uint32_t)o;
@@ -1004,6 +1053,261 @@ int sort_pairs(uint32_t* keys, uint32_t* vals, int64_t count, void* scratch, hip
 }
 
 // ---------------------------------------------------------------------------
+// single-pass tile scatter: with the keys already in depth order, a stable
+// partition by tile finishes the sort.  Chunks of kTsChunk consecutive keys
+// count their tiles (a tiles x chunks matrix per view, tile-major); one
+// exclusive scan of all the matrices in order gives, for every (view, tile,
+// chunk), the sorted position of the chunk's first key of that tile (the
+// view's segment start, plus the view's keys of earlier tiles, plus the
+// tile's keys in earlier chunks); each chunk then ranks its keys within the
+// chunk and writes them there.
+// ---------------------------------------------------------------------------
+
+// Workgroup -> chunk of the tile scatter, then (view, chunk within view).
+// Workgroups are dealt to the 8 XCDs in turn, so XCD x is given the
+// contiguous chunks [x * per, (x + 1) * per): consecutive chunks write
+// neighbouring positions of every tile's run and count-matrix words of the
+// same lines, which then meet in one L2 instead of eight.
+GS_DEV bool ts_chunk_of(const uint32_t* tstable, int n_views, uint32_t wg, int* view, uint32_t* c) {
+    const uint32_t total = tstable[4 * n_views];
+    const uint32_t per = (total + 7u) / 8u;
+    const uint32_t b = (wg % 8u) * per + wg / 8u;
+    if (wg / 8u >= per || b >= total) return false;
+    int v = 0;
+    for (int i = 0; i < n_views; ++i)
+        if (tstable[4 * i + 1] > 0 && b >= tstable[4 * i]) v = i;
+    *view = v;
+    *c = b - tstable[4 * v];
+    return true;
+}
+
+// Per chunk: its keys per tile, into column c of its view's matrix.
+// Workgroup 0 also writes the (empty) ranges of views without keys.
+__global__ __launch_bounds__(kTsThreads) void k_ts_count(const uint32_t* __restrict__ keys,
+                                                         const uint32_t* __restrict__ table,
+                                                         const uint32_t* __restrict__ tstable, int n_views,
+                                                         TsGeom tg, uint32_t* __restrict__ tsm,
+                                                         uint32_t* __restrict__ ranges) {
+    __shared__ uint32_t hist[kTsBins];
+    const int t = threadIdx.x;
+    if (blockIdx.x == 0) {
+        for (int v = 0; v < n_views; ++v) {
+            if (tstable[4 * v + 1] != 0) continue;
+            const uint32_t b = table[4 * v];
+            for (int j = t; j < tg.ntiles[v]; j += kTsThreads)
+                reinterpret_cast<uint2*>(ranges)[tg.tile_base[v] + j] = make_uint2(b, b);
+        }
+    }
+    int v;
+    uint32_t c;
+    if (!ts_chunk_of(tstable, n_views, blockIdx.x, &v, &c)) return;
+    const int nt = tg.ntiles[v], D = tg.depth_bits[v];
+    for (int j = t; j < nt; j += kTsThreads) hist[j] = 0u;
+    __syncthreads();
+    const uint32_t seg_e = table[4 * v + 1];
+    const uint32_t start = table[4 * v] + c * kTsChunk;
+    // loads unconditional (clamped into the chunk), 8 in flight per lane
+    for (int i0 = 0; i0 < kTsItems; i0 += 8) {
+        uint32_t k[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) k[u] = keys[min(start + (uint32_t)((i0 + u) * kTsThreads + t), seg_e - 1)];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (start + (uint32_t)((i0 + u) * kTsThreads + t) < seg_e)
+                atomicAdd(&hist[min((int)(k[u] >> D), nt - 1)], 1u);
+    }
+    __syncthreads();
+    const uint32_t nc = tstable[4 * v + 1], mb = tstable[4 * v + 2];
+    for (int j = t; j < nt; j += kTsThreads) tsm[mb + (uint32_t)j * nc + c] = hist[j];
+}
+
+// Per chunk: wavefront w owns the chunk's keys [w * 2048, (w + 1) * 2048),
+// read in blocks of 8 per lane with the next block's loads in flight.
+// 1. Each tile's keys are counted per wavefront: peers with the same tile are
+//    found with 12 ballots and the first lane of each group adds the group's
+//    size to the wavefront's count in LDS.
+// 2. A scan over the tiles of the chunk's totals gives each tile's start in
+//    the chunk sorted by tile; the counts become per-(wavefront, tile) starts.
+// 3. A second ranking pass gives each key its position l in the chunk sorted
+//    by tile (stable: equal tiles keep the input order); l -> input position
+//    goes to LDS.
+// 4. Sorted position l is then written by thread l mod 256: the key (read
+//    back, from L2) goes to the scanned matrix entry of its (tile, chunk)
+//    plus l minus the tile's start in the chunk, so that each tile's run of
+//    the chunk is written by consecutive lanes to consecutive addresses.
+// Chunk 0 of each view writes the view's tile ranges.
+__global__ __launch_bounds__(kTsThreads) void k_ts_scatter(const uint32_t* __restrict__ keys_in,
+                                                           const uint32_t* __restrict__ vals_in,
+                                                           uint32_t* __restrict__ keys_out,
+                                                           uint32_t* __restrict__ vals_out,
+                                                           const uint32_t* __restrict__ table,
+                                                           const uint32_t* __restrict__ tstable, int n_views,
+                                                           TsGeom tg, const uint32_t* __restrict__ tsm,
+                                                           uint32_t* __restrict__ ranges) {
+    constexpr int NW = kTsThreads / kWave;
+    constexpr int PER_WAVE = kTsChunk / NW;
+    constexpr int ITEMS = PER_WAVE / kWave;
+    constexpr int PRE = kTsBins / kTsThreads;    // tiles per thread (contiguous)
+    constexpr int KB = 8;                        // keys per lane per block
+    static_assert(ITEMS == kTsItems && ITEMS % KB == 0, "items per lane");
+    static_assert(kTsChunk <= 65536, "16-bit chunk positions");
+    __shared__ uint16_t cnt[NW][kTsBins];        // per-(wavefront, tile) counts, then starts
+    __shared__ uint32_t bml[kTsBins];            // destination of the tile's run minus its start
+    __shared__ uint16_t perm[kTsChunk];          // sorted position -> input position
+    __shared__ uint64_t s_scan[NW];
+    int v;
+    uint32_t c;
+    if (!ts_chunk_of(tstable, n_views, blockIdx.x, &v, &c)) return;
+    const int t = threadIdx.x, w = t / kWave, lane = t % kWave;
+    const int nt = tg.ntiles[v], D = tg.depth_bits[v];
+    const uint32_t nc = tstable[4 * v + 1], mb = tstable[4 * v + 2];
+    const uint32_t seg_b = table[4 * v], seg_e = table[4 * v + 1];
+    const uint32_t cstart = seg_b + c * kTsChunk;
+    const int n_here = (int)min((uint32_t)kTsChunk, seg_e - cstart);
+    // this thread's tiles [t * PRE, (t + 1) * PRE): their matrix entries (loads
+    // unconditional, indices clamped into range, all in flight at once)
+    uint32_t pre[PRE];
+#pragma unroll
+    for (int q = 0; q < PRE; ++q) {
+        const int j = min(t * PRE + q, nt - 1);
+        pre[q] = tsm[mb + (uint32_t)j * nc + c];
+    }
+#pragma unroll
+    for (int q = 0; q < PRE; ++q) {
+#pragma unroll
+        for (int r = 0; r < NW; ++r) cnt[r][t * PRE + q] = 0;
+    }
+    const int wbeg = w * PER_WAVE;
+    const int nv = max(0, min(PER_WAVE, n_here - wbeg));      // keys of this wavefront
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    // (a wavefront without keys reads the chunk's first key, which exists)
+    const uint32_t last = nv > 0 ? cstart + (uint32_t)(wbeg + nv - 1) : cstart;
+    auto load_block = [&](int i0, uint32_t (&dst)[KB]) {
+#pragma unroll
+        for (int u = 0; u < KB; ++u)
+            dst[u] = keys_in[nv > 0 ? min(cstart + (uint32_t)(wbeg + (i0 + u) * kWave + lane), last) : last];
+    };
+    // peers of this lane's tile among the valid lanes
+    auto peers_of = [&](uint32_t tile, bool valid) {
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 12; ++bit) {
+            const bool set = (tile >> bit) & 1u;
+            const uint64_t m = __ballot(set);
+            peers &= set ? m : ~m;
+        }
+        return peers;
+    };
+    __syncthreads();
+    // 1. counts per (wavefront, tile)
+    {
+        uint32_t kc[KB], kn[KB];
+        load_block(0, kn);
+        for (int i0 = 0; i0 < ITEMS; i0 += KB) {
+            if (i0 * kWave >= nv) break;
+#pragma unroll
+            for (int u = 0; u < KB; ++u) kc[u] = kn[u];
+            if (i0 + KB < ITEMS) load_block(i0 + KB, kn);
+#pragma unroll
+            for (int u = 0; u < KB; ++u) {
+                const bool valid = (i0 + u) * kWave + lane < nv;
+                const uint32_t tile = (uint32_t)min((int)(kc[u] >> D), nt - 1);
+                const uint64_t peers = peers_of(tile, valid);
+                if (valid && (peers & lt) == 0ull)
+                    cnt[w][tile] = (uint16_t)(cnt[w][tile] + (uint32_t)__popcll(peers));
+            }
+        }
+    }
+    __syncthreads();
+    // 2. tile starts within the chunk (scan over tiles), per-(wavefront, tile) starts
+    {
+        uint32_t tot[PRE];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int q = 0; q < PRE; ++q) {
+            uint32_t x = 0;
+#pragma unroll
+            for (int r = 0; r < NW; ++r) x += cnt[r][t * PRE + q];
+            tot[q] = x;
+            sum += x;
+        }
+        uint64_t all;
+        uint32_t run = (uint32_t)(block_scan_u64(sum, s_scan, &all) - sum);
+#pragma unroll
+        for (int q = 0; q < PRE; ++q) {
+            const int j = t * PRE + q;
+            bml[j] = pre[q] - run;
+            uint32_t wr = run;
+#pragma unroll
+            for (int r = 0; r < NW; ++r) {
+                const uint32_t x = cnt[r][j];
+                cnt[r][j] = (uint16_t)wr;
+                wr += x;
+            }
+            run += tot[q];
+        }
+    }
+    __syncthreads();
+    // 3. sorted position of every key
+    {
+        uint32_t kc[KB], kn[KB];
+        load_block(0, kn);
+        for (int i0 = 0; i0 < ITEMS; i0 += KB) {
+            if (i0 * kWave >= nv) break;
+#pragma unroll
+            for (int u = 0; u < KB; ++u) kc[u] = kn[u];
+            if (i0 + KB < ITEMS) load_block(i0 + KB, kn);
+#pragma unroll
+            for (int u = 0; u < KB; ++u) {
+                const int r = (i0 + u) * kWave + lane;
+                const bool valid = r < nv;
+                const uint32_t tile = (uint32_t)min((int)(kc[u] >> D), nt - 1);
+                const uint64_t peers = peers_of(tile, valid);
+                const uint64_t before = peers & lt;
+                const uint32_t base = cnt[w][tile];
+                if (valid) {
+                    perm[base + (uint32_t)__popcll(before)] = (uint16_t)(wbeg + r);
+                    if (before == 0ull) cnt[w][tile] = (uint16_t)(base + (uint32_t)__popcll(peers));
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // 4. coalesced runs, KB sorted positions per lane at a time (reads of
+    // positions past the chunk's keys are clamped and not written)
+    for (int l0 = 0; l0 < n_here; l0 += KB * kTsThreads) {
+        uint32_t src[KB], key[KB], val[KB];
+#pragma unroll
+        for (int u = 0; u < KB; ++u) src[u] = cstart + perm[min(l0 + u * kTsThreads + t, n_here - 1)];
+#pragma unroll
+        for (int u = 0; u < KB; ++u) {
+            key[u] = keys_in[src[u]];
+            val[u] = vals_in[src[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < KB; ++u) {
+            const int l = l0 + u * kTsThreads + t;
+            if (l < n_here) {
+                const uint32_t dst = bml[min((int)(key[u] >> D), nt - 1)] + (uint32_t)l;
+                keys_out[dst] = key[u];
+                vals_out[dst] = val[u];
+            }
+        }
+    }
+    if (c == 0) {
+        uint2* R = reinterpret_cast<uint2*>(ranges) + tg.tile_base[v];
+#pragma unroll
+        for (int q = 0; q < PRE; ++q) {
+            const int j = t * PRE + q;
+            if (j < nt) {
+                const uint32_t e0 = j + 1 < nt ? tsm[mb + (uint32_t)(j + 1) * nc] : seg_e;
+                R[j] = make_uint2(pre[q], e0);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // driver
 // ---------------------------------------------------------------------------
 
@@ -1027,10 +1331,17 @@ int launch_bin_sort(const gs_splats& sp, int64_t n, const gs_layout& L, const gs
     // split = min(kDepthSplit, D) are depth bits, the same for all of a
     // Gaussian's keys, so they are sorted per (view, Gaussian); the keys'
     // bits from split up are then sorted stably.)
+    // With every view at most kTsBins tiles, the depth order takes all depth
+    // bits and one stable partition by tile finishes (the single-pass tile
+    // scatter); otherwise the depth order takes the low kDepthSplit bits and
+    // radix passes sort the rest.
+    const bool ts_path = depth_first && W.ts_len > 0;
     SortWs S = carve_sort(W.sort_words, V, W.max_chunks);
     int high_bits = 1, low_bits = 1;
+    int splits[GS_MAX_VIEWS];
     for (int v = 0; v < V; ++v) {
-        const int split = std::min(kDepthSplit, L.depth_bits[v]);
+        const int split = ts_path ? L.depth_bits[v] : std::min(kDepthSplit, L.depth_bits[v]);
+        splits[v] = split;
         S.shift0[v] = depth_first ? split : 0;
         high_bits = std::max(high_bits, 32 - split);
         low_bits = std::max(low_bits, split);
@@ -1043,13 +1354,19 @@ int launch_bin_sort(const gs_splats& sp, int64_t n, const gs_layout& L, const gs
     EmitGeom eg;
     RangeGeom rg;
     memset(&eg, 0, sizeof(eg));
+    TsGeom tg;
+    memset(&tg, 0, sizeof(tg));
     for (int v = 0; v < GS_MAX_VIEWS; ++v) {
         eg.tiles_x[v] = v < V ? L.tiles_x[v] : 0;
         eg.tiles_y[v] = v < V ? L.tiles_y[v] : 0;
         eg.depth_bits[v] = v < V ? L.depth_bits[v] : 0;
+        eg.split[v] = v < V ? splits[v] : 0;
         rg.depth_bits[v] = eg.depth_bits[v];
         rg.tiles_x[v] = eg.tiles_x[v];
+        tg.ntiles[v] = v < V ? L.tile_base[v + 1] - L.tile_base[v] : 0;
+        tg.depth_bits[v] = eg.depth_bits[v];
     }
+    for (int v = 0; v <= GS_MAX_VIEWS; ++v) tg.tile_base[v] = v <= V ? L.tile_base[v] : L.tile_base[V];
     eg.tile = L.tile;
     eg.cull = L.cull;
     for (int v = 0; v <= GS_MAX_VIEWS; ++v) rg.tile_base[v] = v <= V ? L.tile_base[v] : L.tile_base[V];
@@ -1087,7 +1404,7 @@ int launch_bin_sort(const gs_splats& sp, int64_t n, const gs_layout& L, const gs
     // offsets and row offsets, the view table, the row slots
     if ((rc = scan_exclusive(sp.tiles, m, b.offsets, W.block_sums, b.status, s)) != GS_OK) return rc;
     hipLaunchKernelGGL(k_view_table, dim3(1), dim3(256), 0, s, b.offsets, n, V, b.capacity, W.table,
-                       b.status, S.dcount);
+                       b.status, S.dcount, ts_path ? W.tstable : nullptr, tg);
     if ((rc = check_launch("view_table")) != GS_OK) return rc;
     if ((rc = scan_exclusive(W.row_count, m, b.row_offsets, W.block_sums, nullptr, s)) != GS_OK) return rc;
     if (m > 0) {
@@ -1101,8 +1418,8 @@ int launch_bin_sort(const gs_splats& sp, int64_t n, const gs_layout& L, const gs
     }
     // keys (in depth order if depth_first), then the sort; the emit goes to
     // the buffer that leaves the sorted keys in bins.keys
-    uint32_t* ek = S.passes % 2 == 0 ? b.keys : W.keys_tmp;
-    uint32_t* ev = S.passes % 2 == 0 ? b.vals : W.vals_tmp;
+    uint32_t* ek = (ts_path || S.passes % 2 != 0) ? W.keys_tmp : b.keys;
+    uint32_t* ev = (ts_path || S.passes % 2 != 0) ? W.vals_tmp : b.vals;
     uint32_t* ok = S.passes % 2 == 0 ? W.keys_tmp : b.keys;
     uint32_t* ov = S.passes % 2 == 0 ? W.vals_tmp : b.vals;
     if (m > 0 && b.row_capacity > 0) {
@@ -1110,6 +1427,17 @@ int launch_bin_sort(const gs_splats& sp, int64_t n, const gs_layout& L, const gs
                            rec, rows, b.row_offsets, b.offsets, depth_first ? W.dpos : nullptr, n, m, eg,
                            b.capacity, b.row_capacity, ek, ev);
         if ((rc = check_launch("emit_keys")) != GS_OK) return rc;
+    }
+    if (ts_path) {
+        // a multiple of 8 workgroups covers every chunk under the XCD dealing
+        const unsigned tgrid = (unsigned)((W.max_ts_chunks + 7) / 8 * 8);
+        hipLaunchKernelGGL(k_ts_count, dim3(tgrid), dim3(kTsThreads), 0, s, ek, W.table, W.tstable, V, tg, W.tsm,
+                           b.ranges);
+        if ((rc = check_launch("ts_count")) != GS_OK) return rc;
+        if ((rc = scan_exclusive(W.tsm, W.ts_len, W.tsm, W.ts_sums, nullptr, s)) != GS_OK) return rc;
+        hipLaunchKernelGGL(k_ts_scatter, dim3(tgrid), dim3(kTsThreads), 0, s, ek, ev, b.keys, b.vals, W.table,
+                           W.tstable, V, tg, W.tsm, b.ranges);
+        return check_launch("ts_scatter");
     }
     if ((rc = radix_sort_views<kSortItems>(ek, ev, ok, ov, W.table, V, S, b.status, s)) != GS_OK) return rc;
     const int64_t nt = L.tile_base[V];

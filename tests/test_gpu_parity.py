@@ -88,6 +88,28 @@ def test_projection_and_binning_bit_exact(name, order):
     np.testing.assert_array_equal(g["ranges"], ref.bins.ranges)
 
 
+def test_depth_first_sort_with_more_tiles_than_one_scatter_pass_takes():
+    """Depth-first order with a view of 20,480 tiles (1280x1024 at 8-pixel
+    tiles, more than the 4,096 a single tile partition handles): the depth
+    order takes the low 16 key bits and radix passes sort the rest; keys,
+    values and ranges bit for bit; the same with 3,600 tiles (the single
+    partition) on the same scene."""
+    scene = S.scene_normal(20_000, 6100, log_scale_mean=-3.5)
+    for W, H, tile in ((1280, 1024, 8), (1280, 720, 16)):
+        views = S.views_array([S.make_view(W, H, (0.5, 0.2, -5.0))])
+        note(f"depth-first binning, {W}x{H} at tile {tile}")
+        pr = oracle.project(scene, views, tile)
+        bins = oracle.bin_sort(pr, views, tile)
+        K = int(bins.offsets[-1])
+        cap = max(16 * scene.n, int(1.25 * K) + 1024)     # at least 12 x n: depth first
+        g = run_gpu_step(scene, views, tile, capacity=cap)
+        assert g["status"] == 0
+        np.testing.assert_array_equal(g["offsets"], bins.offsets)
+        np.testing.assert_array_equal(g["keys"], bins.keys)
+        np.testing.assert_array_equal(g["vals"], bins.gid[bins.vals])
+        np.testing.assert_array_equal(g["ranges"], bins.ranges)
+
+
 def _tile_of_pixel(views, tile):
     """Global tile index of every pixel (views concatenated)."""
     out, tb = [], 0

@@ -559,10 +559,15 @@ def main():
         from paper_2605_00219_amd import experiments as X
         log("learned-schedule variant: 6M Gaussians, 4 x 1920x1080 per step")
         wl = S.workload_learned()
+        # traversal logs of differentiation-check-distribution scenes (anisotropic
+        # scales, long-tailed opacity) from sparse to dense: 100k, 300k, 1M and
+        # 3M Gaussians, 4 views each, so that both unsaturated tiles (cost grows
+        # with the list) and saturated ones (cost set by the early stop) occur
         train_cams = S.fibonacci_sphere(50, 5.0)
-        train_sets = [(S.scene_anisotropic(1_000_000, 3000 + 10 * k),
+        train_sets = [(S.scene_anisotropic(nk, 3000 + 10 * k),
                        S.views_array([S.make_view(1920, 1080, train_cams[(7 * k + j) % 50])
-                                      for j in range(4)])) for k in range(2)]
+                                      for j in range(4)]))
+                      for k, nk in enumerate((100_000, 300_000, 1_000_000, 3_000_000))]
         extra["learned"] = X.run_learned(wl, train_sets, steps=args.learned_steps, log=log)
         del wl, train_sets
         torch.cuda.empty_cache()

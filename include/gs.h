@@ -411,8 +411,11 @@ int gs_tile_features(const gs_splats* splats, int64_t n, const gs_layout* layout
                      const gs_bins* bins, float* features, void* stream);
 
 /* MLP 8 -> 32 -> 32 -> 1 with ReLU, fp32.  Weights (1377 floats) in the order
- * W1[32][8], b1[32], W2[32][32], b2[32], W3[32], b3[1]; input features are
- * standardised with mean/std (8 + 8 floats) before the first layer. */
+ * W1[32][8], b1[32], W2[32][32], b2[32], W3[32], b3[1].  norm: 32 floats,
+ * per feature its mean, standard deviation, low and high (8 each): a feature
+ * is clamped to [low, high] (the range seen in training, so that a scene
+ * unlike the training scenes is not extrapolated), then standardised, before
+ * the first layer. */
 #define GS_MLP_PARAMS 1377
 int gs_mlp_forward(const float* weights, const float* norm, const float* features, int64_t rows,
                    float* out, void* stream);

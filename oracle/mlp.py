@@ -1,7 +1,8 @@
 """CPU oracle of the per-tile cost MLP -- TEST INFRASTRUCTURE ONLY.
 
-Plain PyTorch CPU in float64.  Network: standardise the 8 features with
-(mean, std), Linear 8->32, ReLU, Linear 32->32, ReLU, Linear 32->1.  Loss:
+Plain PyTorch CPU in float64.  Network: clamp the 8 features to [low, high]
+and standardise them with (mean, std) (norm = mean, std, low, high, 8 each),
+Linear 8->32, ReLU, Linear 32->32, ReLU, Linear 32->1.  Loss:
 mean squared error.  Optimiser: Adam (Kingma & Ba) with beta = (0.9, 0.999),
 eps = 1e-8.  Weights are one flat vector: W1[32][8], b1[32], W2[32][32],
 b2[32], W3[32], b3.
@@ -41,7 +42,7 @@ def forward_t(wt, norm, x):
     norm = torch.as_tensor(np.asarray(norm, np.float64))
     x = torch.as_tensor(np.asarray(x, np.float64))
     W1, b1, W2, b2, W3, b3 = unpack(wt)
-    xn = (x - norm[:8]) / norm[8:]
+    xn = (torch.minimum(torch.maximum(x, norm[16:24]), norm[24:32]) - norm[:8]) / norm[8:16]
     h1 = torch.relu(xn @ W1.T + b1)
     h2 = torch.relu(h1 @ W2.T + b2)
     return h2 @ W3 + b3

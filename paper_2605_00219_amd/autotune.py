@@ -3,8 +3,9 @@
 Searches tile edge T in {8, 16, 32}, Gaussians-per-LDS-batch S in
 {32, 64, 128, 256} and, for T = 16 and 32, pixels per lane P in {1, 2, 4}
 (one lane renders P pixels of its tile, so a tile takes T*T/P lanes).  Every candidate runs the same iterations from the same
-optimiser state (restored between candidates), each as a captured HIP graph;
-the candidate with the lowest mean step time wins.  Results are cached in a
+optimiser state (restored between candidates), each as a captured HIP graph, every
+iteration timed with events on the launch stream; the candidate with the
+lowest mean step time wins (the standard deviation is reported beside it).  Results are cached in a
 JSON file keyed by GPU architecture, the view-set resolutions and the
 Gaussian count; an unreadable cache entry is ignored and the search reruns.
 
@@ -78,19 +79,22 @@ def time_candidate(model: P.Model, n: int, resolutions, tile: int, lds: int, vie
     torch.cuda.synchronize()
     for t, s0 in zip((model.params, model.m, model.v, model.step), saved):
         t.copy_(s0)
-    t0 = time.perf_counter()
-    for i in iters:
+    # each iteration bracketed by events on the launch stream
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in iters]
+    for (e0, e1), i in zip(ev, iters):
         step.load(view_rows(i), targets(i))
+        e0.record()
         step.run()
+        e1.record()
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / len(iters)
+    ms = [e0.elapsed_time(e1) for e0, e1 in ev]
     if step.status():
-        dt = float("inf")                      # capacity exceeded: not a valid candidate
+        ms = [float("inf")] * len(ms)          # capacity exceeded: not a valid candidate
     for t, s0 in zip((model.params, model.m, model.v, model.step), saved):
         t.copy_(s0)
     del step
     torch.cuda.empty_cache()
-    return dt
+    return ms
 
 
 def autotune(model: P.Model, n: int, resolutions, view_rows, targets, iters, cache_path=None,
@@ -101,18 +105,22 @@ def autotune(model: P.Model, n: int, resolutions, view_rows, targets, iters, cac
     if (isinstance(hit, dict) and hit.get("tile") in tiles and hit.get("lds_batch") in batches
             and hit.get("pixels_per_lane") in lane_pixels + (1,)):
         return dict(hit, cached=True)
-    table = {}
+    table, spread = {}, {}
     for T in tiles:
         cap = capacity_for(model, n, ViewSet(resolutions, T, cull=cull), view_rows, iters)
         for ppl in ((1,) if T == 8 else lane_pixels):
             for S in batches:
-                dt = time_candidate(model, n, resolutions, T, S, view_rows, targets, iters, cap, ppl, cull)
-                table[f"T{T}_S{S}_P{ppl}"] = dt * 1e3
-                log(f"autotune T={T} S={S} P={ppl}: {dt * 1e3:.3f} ms/step")
+                ms = time_candidate(model, n, resolutions, T, S, view_rows, targets, iters, cap, ppl, cull)
+                key_c = f"T{T}_S{S}_P{ppl}"
+                table[key_c] = float(sum(ms) / len(ms))
+                spread[key_c] = float(math.sqrt(sum((x - table[key_c]) ** 2 for x in ms) / len(ms))
+                                      if math.isfinite(table[key_c]) else float("inf"))
+                log(f"autotune T={T} S={S} P={ppl}: {table[key_c]:.3f} +- {spread[key_c]:.3f} ms/step "
+                    f"({len(ms)} iterations)")
     best = min(table, key=table.get)
     T, S, ppl = (int(x[1:]) for x in best.split("_"))
     res = {"tile": T, "lds_batch": S, "pixels_per_lane": ppl, "ms": table[best], "table_ms": table,
-           "cached": False}
+           "table_std_ms": spread, "iterations": len(iters), "cached": False}
     if cache_path:
         cache[key] = {k: v for k, v in res.items() if k != "cached"}
         save_cache(cache_path, cache)

@@ -8,6 +8,7 @@
 namespace gs {
 
 constexpr int kIn = 8, kH = 32;
+constexpr int kNorm = 4 * kIn;   // mean, std, low and high of each feature
 constexpr int kOffW1 = 0, kOffB1 = kOffW1 + kH * kIn, kOffW2 = kOffB1 + kH,
               kOffB2 = kOffW2 + kH * kH, kOffW3 = kOffB2 + kH, kOffB3 = kOffW3 + kH;
 static_assert(kOffB3 + 1 == GS_MLP_PARAMS, "weight layout");
@@ -82,7 +83,8 @@ int launch_tile_features(const gs_splats& sp, int64_t n, const gs_layout& L, con
 GS_DEV void mlp_row(const float* w, const float* norm, const float* x, float xn[kIn], float h1[kH],
                     float h2[kH], float* y) {
 #pragma unroll
-    for (int i = 0; i < kIn; ++i) xn[i] = (x[i] - norm[i]) / norm[kIn + i];
+    for (int i = 0; i < kIn; ++i)
+        xn[i] = (fminf(fmaxf(x[i], norm[2 * kIn + i]), norm[3 * kIn + i]) - norm[i]) / norm[kIn + i];
 #pragma unroll
     for (int j = 0; j < kH; ++j) {
         float s = w[kOffB1 + j];
@@ -108,9 +110,9 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ w
                                                      const float* __restrict__ x, int64_t rows,
                                                      float* __restrict__ out) {
     __shared__ float sw[GS_MLP_PARAMS];
-    __shared__ float sn[2 * kIn];
+    __shared__ float sn[kNorm];
     for (int i = threadIdx.x; i < GS_MLP_PARAMS; i += blockDim.x) sw[i] = w[i];
-    if (threadIdx.x < 2 * kIn) sn[threadIdx.x] = norm[threadIdx.x];
+    if (threadIdx.x < kNorm) sn[threadIdx.x] = norm[threadIdx.x];
     __syncthreads();
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= rows) return;
@@ -145,10 +147,10 @@ __global__ __launch_bounds__(64) void k_mlp_grad(const float* __restrict__ w,
                                                  const float* __restrict__ t, int64_t rows,
                                                  float* __restrict__ scratch) {
     __shared__ float sw[GS_MLP_PARAMS];
-    __shared__ float sn[2 * kIn];
+    __shared__ float sn[kNorm];
     __shared__ float rowbuf[kRowsPerChunk][kStride];
     for (int i = threadIdx.x; i < GS_MLP_PARAMS; i += 64) sw[i] = w[i];
-    if (threadIdx.x < 2 * kIn) sn[threadIdx.x] = norm[threadIdx.x];
+    if (threadIdx.x < kNorm) sn[threadIdx.x] = norm[threadIdx.x];
     __syncthreads();
     float acc[kSlots];
 #pragma unroll

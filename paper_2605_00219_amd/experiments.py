@@ -29,7 +29,7 @@ def _render_targets(target_params, n, resolutions, tile, views_per_step):
 
 
 def run_batched(workload, make_views, steps: int = 200, plain_steps: int = 25, log=print,
-                tune_iters=3, cache_path=None) -> dict:
+                tune_iters=10, cache_path=None, plain_lds_batch: int = 128, plain_ppl: int = 2) -> dict:
     """Batched + persistent + graph + autotuned step vs plain single-view steps."""
     w = workload
     res = w.extra["resolutions"]
@@ -65,20 +65,51 @@ def run_batched(workload, make_views, steps: int = 200, plain_steps: int = 25, l
     status = step.status()
     del step
     torch.cuda.empty_cache()
-    # plain: each view its own single-view step (one workgroup per tile, T = 16, S = 64)
-    frames = [P.Frame(n, [wd], [ht], 16) for wd, ht in res]
+    # plain: each view its own single-view step in the headline configuration
+    # (one workgroup per tile, T = 16, S = 128, 2 pixels per lane), replayed
+    # from one HIP graph per view slot whose camera row and target are copied
+    # into fixed buffers before each replay (as the batched step loads its own)
+    frames = [P.Frame(n, [wd], [ht], 16, pixels_per_lane=plain_ppl) for wd, ht in res]
     for k, f in enumerate(frames):
         kmax = 0
         for i in range(period):
             kmax = max(kmax, P.fit_capacity(model.params, f, view_rows(i)[128 * k:128 * (k + 1)]))
         f.resize(int(kmax * 1.15) + 4096)
     pix_base = np.cumsum([0] + [wd * ht for wd, ht in res])
+    vbuf = [torch.empty(128, dtype=view_rows(0).dtype, device="cuda") for _ in res]
+    tbuf = [torch.empty(int(pix_base[k + 1] - pix_base[k]), 3, device="cuda") for k in range(len(res))]
+
+    def load_plain(i):
+        vr, tg = view_rows(i), tgt(i)
+        for k in range(len(res)):
+            vbuf[k].copy_(vr[128 * k:128 * (k + 1)])
+            tbuf[k].copy_(tg[pix_base[k]:pix_base[k + 1]])
+
+    def plain_view(k):
+        P.train_step(model, frames[k], vbuf[k], tbuf[k], lds_batch=plain_lds_batch, check=False)
+
+    saved = [t.clone() for t in (model.params, model.m, model.v, model.step)]
+    load_plain(0)
+    graphs = []
+    cs = torch.cuda.Stream()
+    for k in range(len(res)):
+        cs.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(cs):
+            plain_view(k)                       # a launch outside capture
+        torch.cuda.current_stream().wait_stream(cs)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            plain_view(k)
+        graphs.append(g)
+    torch.cuda.synchronize()
+    for t, s0 in zip((model.params, model.m, model.v, model.step), saved):
+        t.copy_(s0)
 
     def plain_iter(i):
-        vr = view_rows(i)
-        for k, f in enumerate(frames):
-            vd = vr[128 * k:128 * (k + 1)]
-            P.train_step(model, f, vd, tgt(i)[pix_base[k]:pix_base[k + 1]], check=False)
+        load_plain(i)
+        for g in graphs:
+            g.replay()
 
     plain_iter(0)
     torch.cuda.synchronize()
@@ -88,7 +119,7 @@ def run_batched(workload, make_views, steps: int = 200, plain_steps: int = 25, l
     torch.cuda.synchronize()
     dt_p = (time.perf_counter() - t0) / plain_steps
     st_p = max(f.status_bits() for f in frames)
-    del frames
+    del frames, graphs
     torch.cuda.empty_cache()
     V = len(res)
     mpix = sum(wd * ht for wd, ht in res) / 1e6
@@ -101,8 +132,10 @@ def run_batched(workload, make_views, steps: int = 200, plain_steps: int = 25, l
                     "pixels_per_lane": ppl,
                     "graph": True, "persistent": True, "status": status},
         "plain": {"iters_per_s": 1.0 / dt_p, "ms_per_step": 1e3 * dt_p, "views_per_s": V / dt_p,
-                  "mpix_per_s": mpix / dt_p, "steps": plain_steps, "tile": 16, "lds_batch": 64,
-                  "note": "8 sequential single-view steps per iteration", "status": st_p},
+                  "mpix_per_s": mpix / dt_p, "steps": plain_steps, "tile": 16, "lds_batch": plain_lds_batch,
+                  "pixels_per_lane": plain_ppl,
+                  "note": "8 sequential single-view steps per iteration, each replayed from a HIP graph",
+                  "status": st_p},
         "speedup_views_per_s": dt_p / dt_b,
     }
 
@@ -122,6 +155,49 @@ def collect_cost_data(scenes_views, tile=16, log=print):
         del f, params
     torch.cuda.empty_cache()
     return torch.cat(X), torch.cat(Y)
+
+
+def _learned_on_varied_scene(cm, log, reps: int = 10) -> dict:
+    """The same trained model on a scene whose per-tile costs do vary (80k
+    Gaussians ~N(0,1)^3, log-scales N(-3.5, 0.7), two 800x600 views, many tiles
+    unsaturated): prediction quality and the persistent forward + backward
+    rasterisation time under the static and the learned order."""
+    import synthetic as S
+    scene = S.scene_normal(80_000, 3200, log_scale_mean=-3.5)
+    tscene = S.scene_normal(80_000, 3201, log_scale_mean=-3.5)
+    views = S.views_array([S.make_view(800, 600, c) for c in S.fibonacci_sphere(4, 5.0)[:2]])
+    vd = P.views_to_device(views)
+    res = [(800, 600), (800, 600)]
+    tgt = _render_targets(P.pack_flat(tscene.flat()), scene.n, res, 16, [vd])[0]
+    prm = P.pack_flat(scene.flat())
+    f = P.Frame(scene.n, [800, 800], [600, 600], 16, tile_stats=True)
+    P.fit_capacity(prm, f, vd)
+    P.render(prm, f, vd)
+    feats, meas = SC.tile_features(f), SC.traversal_target(f)
+    q = SC.prediction_quality(cm.predict(feats), meas)
+    order = SC.order_by_cost(cm.predict(feats))
+    out = {"scene": "80k Gaussians, log-scales N(-3.5, 0.7), 2 x 800x600", **q,
+           "length_only_spearman": SC.prediction_quality(feats[:, 0].contiguous(), meas)["spearman"],
+           "traversal_log_std": float(meas.std().item())}
+    for label, od in (("static", None), ("learned", order)):
+        sched = f.schedule(od)
+        times = []
+        for rep in range(reps + 2):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            P.rasterize_fwd(f, vd, 64, sched)
+            P.rasterize_bwd(f, vd, target=tgt, lds_batch=64, sched=sched)
+            e1.record()
+            torch.cuda.synchronize()
+            if rep >= 2:
+                times.append(e0.elapsed_time(e1))
+        out[f"{label}_raster_ms"] = float(np.mean(times))
+        out[f"{label}_raster_ms_std"] = float(np.std(times))
+    out["speedup_learned_vs_static"] = out["static_raster_ms"] / out["learned_raster_ms"]
+    log(f"learned, varied scene: {out}")
+    del f
+    torch.cuda.empty_cache()
+    return out
 
 
 def run_learned(workload, train_sets, steps: int = 10, log=print, epochs: int = 400) -> dict:
@@ -187,11 +263,14 @@ def run_learned(workload, train_sets, steps: int = 10, log=print, epochs: int = 
             P.project_bwd_adam(model, frame, vd)
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / steps
+        fwd = np.array([e[1].elapsed_time(e[2]) for e in ev])
+        bwd = np.array([e[2].elapsed_time(e[3]) for e in ev])
         results[mode] = {
             "iters_per_s": 1.0 / wall, "ms_per_step": 1e3 * wall,
             "order_ms": float(np.mean([e[0].elapsed_time(e[1]) for e in ev])),
-            "raster_fwd_ms": float(np.mean([e[1].elapsed_time(e[2]) for e in ev])),
-            "raster_bwd_ms": float(np.mean([e[2].elapsed_time(e[3]) for e in ev])),
+            "raster_fwd_ms": float(fwd.mean()), "raster_bwd_ms": float(bwd.mean()),
+            "raster_ms": float((fwd + bwd).mean()), "raster_ms_std": float((fwd + bwd).std()),
+            "steps_timed": steps,
         }
         images[mode] = (frame.image.clone(), model.params.clone())
         log(f"learned: {mode}: {results[mode]}")
@@ -203,11 +282,19 @@ def run_learned(workload, train_sets, steps: int = 10, log=print, epochs: int = 
     for t, s0 in zip((model.params,), saved[:1]):
         t.copy_(s0)
     P.render(model.params, fr, vrows[0])
-    q_bench = SC.prediction_quality(cm.predict(SC.tile_features(fr)), SC.traversal_target(fr))
+    feats_b, meas_b = SC.tile_features(fr), SC.traversal_target(fr)
+    q_bench = SC.prediction_quality(cm.predict(feats_b), meas_b)
+    q_bench["length_only_spearman"] = SC.prediction_quality(feats_b[:, 0].contiguous(), meas_b)["spearman"]
+    # how much the per-tile cost varies on this scene at all (log of entries traversed)
+    q_bench["traversal_log_mean"] = float(meas_b.mean().item())
+    q_bench["traversal_log_std"] = float(meas_b.std().item())
     del fr, frame
     torch.cuda.empty_cache()
+    varied = _learned_on_varied_scene(cm, log)
     return {"workload": w.name, "gaussians": n, "views_per_step": V, "tiles_per_step": nt,
+            "varied_scene": varied,
             "steps": steps, "mlp": {"epochs": epochs, "train_s": t_train, "train_loss": loss,
+                                    "train_tiles": int(X.shape[0]),
                                     "heldout": q_val, "bench_scene": q_bench},
             "orders": results, "bitwise_identical": bool(same),
             "speedup_learned_vs_static": results["static"]["ms_per_step"] / results["learned"]["ms_per_step"]}

@@ -56,7 +56,8 @@ class CostModel:
             w[o:o + fan_in * fan_out] = rng.uniform(-bound, bound, fan_in * fan_out)
             o += fan_in * fan_out + fan_out
         self.w = torch.tensor(w, device="cuda")
-        self.norm = torch.tensor(np.r_[np.zeros(8), np.ones(8)].astype(np.float32), device="cuda")
+        self.norm = torch.tensor(np.r_[np.zeros(8), np.ones(8), np.full(8, -3.0e38), np.full(8, 3.0e38)]
+                                 .astype(np.float32), device="cuda")
         self.m = torch.zeros_like(self.w)
         self.v = torch.zeros_like(self.w)
         self.step = torch.zeros(1, dtype=torch.int32, device="cuda")
@@ -64,9 +65,12 @@ class CostModel:
         self.loss = torch.zeros(1, dtype=torch.float32, device="cuda")
 
     def set_normalisation(self, features: torch.Tensor) -> None:
+        """Mean and standard deviation of the training features, and their
+        range, to which features are clamped before the network."""
         mean = features.mean(0)
         std = features.std(0).clamp_min(1e-6)
-        self.norm = torch.cat([mean, std]).to(torch.float32).contiguous()
+        lo, hi = features.min(0).values, features.max(0).values
+        self.norm = torch.cat([mean, std, lo, hi]).to(torch.float32).contiguous()
 
     def predict(self, features: torch.Tensor) -> torch.Tensor:
         x = features.contiguous()

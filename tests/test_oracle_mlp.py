@@ -9,7 +9,7 @@ from oracle import mlp
 def _data(seed=0, rows=50):
     rng = np.random.default_rng(seed)
     w = rng.normal(0, 0.3, size=mlp.N_PARAMS)
-    norm = np.r_[rng.normal(0, 1, 8), rng.uniform(0.5, 2, 8)]
+    norm = np.r_[rng.normal(0, 1, 8), rng.uniform(0.5, 2, 8), rng.uniform(-3, -1, 8), rng.uniform(1, 3, 8)]
     x = rng.normal(0, 2, size=(rows, 8))
     t = rng.normal(0, 1, size=rows)
     return w, norm, x, t
@@ -20,7 +20,7 @@ def test_forward_matches_numpy():
     W1, b1 = w[:256].reshape(32, 8), w[256:288]
     W2, b2 = w[288:1312].reshape(32, 32), w[1312:1344]
     W3, b3 = w[1344:1376], w[1376]
-    xn = (x - norm[:8]) / norm[8:]
+    xn = (np.clip(x, norm[16:24], norm[24:32]) - norm[:8]) / norm[8:16]
     h1 = np.maximum(xn @ W1.T + b1, 0)
     h2 = np.maximum(h1 @ W2.T + b2, 0)
     np.testing.assert_allclose(mlp.forward(w, norm, x).numpy(), h2 @ W3 + b3, rtol=1e-12)

@@ -324,11 +324,13 @@ int gs_rasterize_bwd(const gs_splats* splats, int64_t n, const gs_layout* layout
                      float* loss, int lds_batch, const gs_schedule* sched, void* stream);
 
 /* Rasterisation backward, two-phase form (Sec. 4.2, the second
- * implementation): per batch of lds_batch (16 or 32) entries some pixel
+ * implementation): per batch of lds_batch (16, 32 or 64) entries some pixel
  * composited, a pixel-parallel pass recomputes transmittance front to back and
  * stores, per (entry, pixel), dL/dpower and alpha T in LDS; a Gaussian-
  * parallel pass then sums them over the tile's pixels into the entry's record
- * (no cross-lane reductions).  Same arguments, outputs and record format as
+ * as a contraction on the fp32 matrix cores (per-pair terms against the
+ * pixel moments 1, X, Y, X^2, XY, Y^2 and the pixels' dL/dC; no cross-lane
+ * reductions).  Same arguments, outputs and record format as
  * gs_rasterize_bwd (the records agree with it up to float summation order);
  * 8x8 and 16x16 tiles only. */
 int gs_rasterize_bwd_twophase(const gs_splats* splats, int64_t n, const gs_layout* layout,

@@ -181,7 +181,8 @@ int gs_rasterize_bwd_twophase(const gs_splats* splats, int64_t n, const gs_layou
             "gs_rasterize_bwd_twophase: give exactly one of target (fused L1) and dL_dC");
     REQUIRE(grads && grads->tile_stop && ((grads->rec && grads->rec_mask) || bins->capacity == 0),
             "gs_rasterize_bwd_twophase: null gradient buffers");
-    REQUIRE(lds_batch == 16 || lds_batch == 32, "gs_rasterize_bwd_twophase: lds_batch %d not in {16, 32}",
+    REQUIRE(lds_batch == 16 || lds_batch == 32 || lds_batch == 64,
+            "gs_rasterize_bwd_twophase: lds_batch %d not in {16, 32, 64}",
             lds_batch);
     REQUIRE(layout->tile == 8 || layout->tile == 16, "gs_rasterize_bwd_twophase: tile %d not in {8, 16}",
             layout->tile);

@@ -7,11 +7,15 @@
 // with broadcast LDS loads.  The conic is staged pre-scaled by -log2(e)/2 so
 // that a pair costs one v_exp_f32.
 //
-// Backward: transmittance is recomputed front to back with the very same
-// arithmetic as the forward (shared device function, explicit FMAs), so the
-// set of composited pairs is bitwise that of the forward.  Using the forward's
-// output colour, the colour behind entry i is C_out - (colour composited up to
-// and including i), so no per-pair state is stored.  Per-pixel gradient terms
+// Backward: alpha is recomputed with the forward's own device function
+// (explicit FMAs, so bitwise the forward's alpha), and a pair counts as
+// composited when the pixel's forward stop (`last`) lies beyond it and alpha
+// reaches the 1/255 cut, so the set of composited pairs is the forward's.
+// Transmittance is recomputed front to back as T - alpha T (the forward keeps
+// T (1 - alpha), which it also tests against the stop threshold): the two
+// agree to float rounding and no decision depends on the backward's value.
+// Using the forward's output colour, the colour behind entry i is C_out -
+// (colour composited up to and including i), so no per-pair state is stored.  Per-pixel gradient terms
 // are summed over each wavefront with DPP row/broadcast reductions (no
 // atomics), waves whose lanes all skip a Gaussian skip its reduction (ballot),
 // and the per-wave sums are added in a fixed order through LDS: one 48-byte
@@ -30,6 +34,8 @@
 #pragma clang fp contract(off)
 
 namespace gs {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kAlphaMin = 1.0f / 255.0f;
@@ -684,22 +690,32 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd(RasterArgs a)
 // ---------------------------------------------------------------------------
 // Per batch of S staged entries: a pixel-parallel pass runs through the batch
 // front to back, recomputing transmittance, and stores per (entry, pixel)
-// u = dL/dpower and w = alpha T in LDS; then a Gaussian-parallel pass sums,
-// for each entry, u (1, dx, dy, dx^2, dx dy, dy^2) and w g over the tile's
-// pixels (the 9 sums of the record).  No cross-lane reductions: thread t sums
-// entry t % S over the pixels i J + t / S (J = NT / S slices), and the slices'
-// partial sums are added in slice order.  The pair evaluation is the
-// forward's (offsets from the mean), so composite decisions agree with it.
+// u = dL/dpower and w = alpha T in LDS (zero where the pixel does not
+// composite the entry).  The Gaussian-parallel pass is then a contraction
+// over the tile's pixels, on the matrix cores: with tile-local pixel
+// coordinates (X, Y), each wavefront multiplies the S x 64 PPT block of u of
+// its own pixels by the pixel moments [1, X, Y, X^2, XY, Y^2] and the block
+// of w by the pixels' dL/dC (v_mfma_f32_16x16x4f32, four pixels per
+// instruction, sixteen entries per matrix tile).  The wavefronts' partial
+// moments are added in a fixed order and turned into the record's sums of u
+// (1, dx, dy, dx^2, dx dy, dy^2) with dx = X - mx, mx the mean's offset from
+// the tile's first pixel centre (tile-local, so the expansion adds no
+// cancellation beyond that of the sums themselves).  The pair evaluation is
+// the forward's (offsets from the mean), so composite decisions agree with
+// it.
 
 template <int TILE, int S, int PPT_>
-__global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd2(RasterArgs a) {
+__global__ __launch_bounds__(TILE * TILE / PPT_, (TILE == 16 && PPT_ == 1) ? (S == 16 ? 3 : S == 32 ? 2 : 1) : 1)
+void k_raster_bwd2(RasterArgs a) {
     constexpr int PPT = PPT_, NT = Geo<TILE, PPT_>::NT;
     constexpr int NP = TILE * TILE;
-    constexpr int UP = NP + 1;           // row pitch of the per-pair arrays (entries on distinct banks)
+    // row pitch of the per-pair arrays: NP + 4, so that the matrix-operand
+    // reads (16 entries x 4 consecutive pixels) fall on distinct banks
+    constexpr int UP = NP + 4;
     constexpr int NW = NT / kWave;
-    constexpr int J = NT / S;            // pixel slices per entry in the Gaussian-parallel pass
-    constexpr int Z = NP / J;            // pixels per slice (PPT S): inside one wavefront's pixels
-    static_assert(NT % S == 0 && NP % J == 0 && S <= kWave && (kWave * PPT) % Z == 0, "whole slices");
+    constexpr int KS = kWave * PPT / 4;  // matrix K-steps (4 pixels each) per wavefront
+    constexpr int MT = S / 16;           // 16-entry matrix tiles per batch
+    static_assert(S % 16 == 0 && S <= kWave, "whole 16-entry matrix tiles");
     __shared__ float4 s_g[S];
     __shared__ float4 s_h[S];
     __shared__ float s_b[S];
@@ -707,13 +723,10 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd2(RasterArgs a
     __shared__ uint32_t s_idx[S];
     __shared__ uint32_t s_pos[S];
     __shared__ uint32_t s_mw[S / 32 + 2];
-    __shared__ uint64_t s_rel[NW];       // per wavefront: staged entries some of its pixels composite
-    __shared__ uint32_t s_wcnt[NW];      // per wavefront: relevant (entry, slice) items found
-    __shared__ uint16_t s_item[NT];      // relevant items, packed
     __shared__ float s_u[S * UP];        // dL/dpower per (entry, pixel)
     __shared__ float s_w[S * UP];        // alpha T per (entry, pixel)
     __shared__ float s_gp[3][NP];        // dL/dC per pixel
-    __shared__ float s_part[J][S][9];    // per-slice sums
+    __shared__ float s_part[NW][S][9];   // per-wavefront moments
     __shared__ int s_tile;
     __shared__ uint32_t s_len;
     __shared__ float s_loss[NT / kWave];
@@ -781,6 +794,22 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd2(RasterArgs a
             for (int i = 0; i < NT / kWave; ++i) sl += s_loss[i];
             a.loss[gt] = sl;
         }
+        // B operands of this wavefront's K-steps (lane l: pixel 4 s + l / 16 of
+        // the wavefront, column l % 16): the pixel moments 1, X, Y, X^2, XY,
+        // Y^2 (tile-local pixel indices) in columns 0..5, the pixel's dL/dC in
+        // columns 6..8, zeros elsewhere
+        float bmom[KS], bgrad[KS];
+        {
+            const int col = lane % 16;
+#pragma unroll
+            for (int st = 0; st < KS; ++st) {
+                const int p = w * (kWave * PPT) + 4 * st + lane / 16;
+                const float X = (float)(p % TILE), Y = (float)(p / TILE);
+                bmom[st] = col == 0 ? 1.0f : col == 1 ? X : col == 2 ? Y : col == 3 ? X * X
+                         : col == 4 ? X * Y : col == 5 ? Y * Y : 0.0f;
+                bgrad[st] = (col >= 6 && col < 9) ? s_gp[col - 6][p] : 0.0f;
+            }
+        }
         __syncthreads();
         const uint32_t stop = start + s_len;
         for (uint32_t b0 = start; b0 < stop; b0 += S) {
@@ -816,30 +845,47 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd2(RasterArgs a
             __syncthreads();
             // pixel-parallel pass over the staged entries this wavefront's pixels
             // can composite (lane k tests entry k: within the pixels' list
-            // lengths and able to reach their rectangle), in order
+            // lengths and able to reach their rectangle), in order; the other
+            // staged entries get zeros at this wavefront's pixels
+            uint64_t wlive;
             {
                 uint32_t wlen = mylen;
                 for (int off = 32; off > 0; off >>= 1) wlen = max(wlen, (uint32_t)__shfl_xor((int)wlen, off));
                 const float rx0 = (float)(ti.tx * TILE) + 0.5f, rx1 = rx0 + (float)(TILE - 1);
                 const float ry0 = (float)(ti.ty * TILE + w * Geo<TILE, PPT_>::ROWS) + 0.5f;
                 const float ry1 = ry0 + (float)(Geo<TILE, PPT_>::ROWS - 1);
-                uint64_t rel = __ballot(lane < cnt && s_pos[lane] < wlen &&
-                                        rect_may_composite(s_g[lane], s_h[lane], rx0, rx1, ry0, ry1));
-                uint64_t used = 0;
+                const uint64_t rel = __ballot(lane < cnt && s_pos[lane] < wlen &&
+                                              rect_may_composite(s_g[lane], s_h[lane], rx0, rx1, ry0, ry1));
+                const uint64_t staged = cnt >= kWave ? ~0ull : ((1ull << cnt) - 1ull);
+                // 16-entry matrix tiles with no entry this wavefront composites
+                // are skipped by the matrix pass; the others need zeros in the
+                // columns of their other entries
+                uint64_t live = 0ull;
+#pragma unroll
+                for (int t = 0; t < MT; ++t)
+                    if ((rel >> (16 * t)) & 0xffffull) live |= 0xffffull << (16 * t);
+                wlive = live;
+                for (uint64_t m = staged & ~rel & live; m != 0ull; m &= m - 1ull) {
+                    const int k = (int)__builtin_ctzll(m);
+#pragma unroll
+                    for (int qq = 0; qq < PPT; ++qq) {
+                        const int p = Geo<TILE, PPT_>::pixel((int)threadIdx.x, qq);
+                        s_u[k * UP + p] = 0.0f;
+                        s_w[k * UP + p] = 0.0f;
+                    }
+                }
                 for (uint64_t m = rel; m != 0ull; m &= m - 1ull) {
                     const int k = (int)__builtin_ctzll(m);
                     const uint32_t pos = s_pos[k];
                     const float4 sg = s_g[k];
                     const float4 sh = s_h[k];
                     const float cb = s_b[k];
-                    bool any = false;
 #pragma unroll
                     for (int qq = 0; qq < PPT; ++qq) {
                         float dx, dy, G, ag;
                         const bool in = eval_pair(px[qq], py[qq], sg, sh, dx, dy, G, ag);
                         const float al = fminf(kAlphaMax, ag);
                         const bool c = pos < lastp[qq] && in && al >= kAlphaMin;
-                        any = any || c;
                         const float ae = c ? al : 0.0f;
                         const float wgt = ae * T[qq];
                         const float gc = __builtin_fmaf(g2[qq], cb, __builtin_fmaf(g1[qq], sh.w, g0[qq] * sh.z));
@@ -852,70 +898,53 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd2(RasterArgs a
                         s_w[k * UP + p] = wgt;
                         T[qq] = T[qq] - wgt;
                     }
-                    if (__ballot(any) != 0ull) used |= 1ull << k;
                 }
-                if (lane == 0) s_rel[w] = used;
             }
-            __syncthreads();
-            // relevant (entry, slice) items -- slice j is pixels [j Z, (j + 1) Z) of
-            // wavefront j Z / (64 PPT) -- packed onto the first threads
+            // the matrix pass reads only this wavefront's pixel columns, which
+            // this wavefront has just written (LDS operations of one wavefront
+            // complete in order): no workgroup barrier
+            __builtin_amdgcn_wave_barrier();
+            // Gaussian-parallel pass on the matrix cores: this wavefront's
+            // pixels [w 64 PPT, (w + 1) 64 PPT), four per K-step (lane l:
+            // pixel 4 s + l / 16, entry l % 16 of the matrix tile, output
+            // column l % 16); D rows 4 (l / 16) + v, column l % 16
             {
-                const int k = threadIdx.x % S, j = threadIdx.x / S;
-                const bool live = ((s_rel[(j * Z) / (kWave * PPT)] >> k) & 1ull) != 0ull;
-                const uint64_t bl = __ballot(live);
-                if (lane == 0) s_wcnt[w] = (uint32_t)__popcll(bl);
-                if (!live) {
-                    float* pp = s_part[j][k];
+                floatx4 du[MT], dw[MT];
 #pragma unroll
-                    for (int c = 0; c < 9; ++c) pp[c] = 0.0f;
+                for (int t = 0; t < MT; ++t) {
+                    du[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    dw[t] = floatx4{0.f, 0.f, 0.f, 0.f};
                 }
-                __syncthreads();
-                if (live) {
-                    uint32_t off = (uint32_t)__popcll(bl & ((1ull << lane) - 1ull));
-                    for (int ww = 0; ww < w; ++ww) off += s_wcnt[ww];
-                    s_item[off] = (uint16_t)threadIdx.x;
-                }
-            }
-            __syncthreads();
-            // Gaussian-parallel pass: thread t sums item t (entry k over slice j)
-            uint32_t n_items = 0;
-            for (int ww = 0; ww < NW; ++ww) n_items += s_wcnt[ww];
-            if (threadIdx.x < n_items) {
-                const int it = s_item[threadIdx.x];
-                const int k = it % S, j = it / S;
-                float r0 = 0, r1 = 0, r2 = 0, r3 = 0, r4 = 0, r5 = 0, r6 = 0, r7 = 0, r8 = 0;
-                {
-                    const float mx = s_g[k].x, my = s_g[k].y;
-                    const float bx = (float)(ti.tx * TILE) + 0.5f, by = (float)(ti.ty * TILE) + 0.5f;
-#pragma unroll 4
-                    for (int i = 0; i < Z; ++i) {
-                        const int p = j * Z + i;
-                        const float u = s_u[k * UP + p], wv = s_w[k * UP + p];
-                        const float dx = bx + (float)(p % TILE) - mx, dy = by + (float)(p / TILE) - my;
-                        const float ux = u * dx, uy = u * dy;
-                        r0 += u;
-                        r1 += ux;
-                        r2 += uy;
-                        r3 = __builtin_fmaf(ux, dx, r3);
-                        r4 = __builtin_fmaf(ux, dy, r4);
-                        r5 = __builtin_fmaf(uy, dy, r5);
-                        r6 = __builtin_fmaf(wv, s_gp[0][p], r6);
-                        r7 = __builtin_fmaf(wv, s_gp[1][p], r7);
-                        r8 = __builtin_fmaf(wv, s_gp[2][p], r8);
+#pragma unroll
+                for (int t = 0; t < MT; ++t) {
+                    if (((wlive >> (16 * t)) & 1ull) == 0ull) continue;
+                    const int e = 16 * t + lane % 16;
+#pragma unroll
+                    for (int st = 0; st < KS; ++st) {
+                        const int p = w * (kWave * PPT) + 4 * st + lane / 16;
+                        du[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(s_u[e * UP + p], bmom[st], du[t], 0, 0, 0);
+                        dw[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(s_w[e * UP + p], bgrad[st], dw[t], 0, 0, 0);
                     }
                 }
-                float* pp = s_part[j][k];
-                pp[0] = r0; pp[1] = r1; pp[2] = r2; pp[3] = r3; pp[4] = r4;
-                pp[5] = r5; pp[6] = r6; pp[7] = r7; pp[8] = r8;
+                const int col = lane % 16;
+#pragma unroll
+                for (int t = 0; t < MT; ++t) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int e = 16 * t + 4 * (lane / 16) + v;
+                        if (col < 6) s_part[w][e][col] = du[t][v];
+                        else if (col < 9) s_part[w][e][col] = dw[t][v];
+                    }
+                }
             }
             __syncthreads();
             for (int k = threadIdx.x; k < cnt; k += NT) {
                 float r[9];
 #pragma unroll
                 for (int c = 0; c < 9; ++c) r[c] = 0.0f;
-                for (int j = 0; j < J; ++j)
+                for (int ww = 0; ww < NW; ++ww)
 #pragma unroll
-                    for (int c = 0; c < 9; ++c) r[c] += s_part[j][k][c];
+                    for (int c = 0; c < 9; ++c) r[c] += s_part[ww][k][c];
                 const uint32_t idx = s_idx[k];
                 if ((int64_t)idx >= a.capacity) continue;   // only after a capacity overflow
                 atomicOr(a.rec_mask + (idx >> 5), 1u << (idx & 31u));
@@ -925,8 +954,18 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd2(RasterArgs a
                 const float4 q0 = rr[0];
                 const float4 q1 = rr[1];
                 const float A = q0.z, B = q0.w, C = q1.x, op = q1.y;
-                rec[0] = make_float4(A * r[1] + B * r[2], B * r[1] + C * r[2], -0.5f * r[3], -r[4]);
-                rec[1] = make_float4(-0.5f * r[5], r[0] / op, r[6], r[7]);
+                // moments of u over (1, X, Y, X^2, XY, Y^2) -> sums over (1, dx,
+                // dy, dx^2, dx dy, dy^2), dx = X - mx, dy = Y - my
+                const float mx = q0.x - ((float)(ti.tx * TILE) + 0.5f);
+                const float my = q0.y - ((float)(ti.ty * TILE) + 0.5f);
+                const float s0 = r[0];
+                const float s1 = r[1] - mx * r[0];
+                const float s2 = r[2] - my * r[0];
+                const float s3 = r[3] - mx * (2.0f * r[1] - mx * r[0]);
+                const float s4 = r[4] - mx * r[2] - my * r[1] + (mx * my) * r[0];
+                const float s5 = r[5] - my * (2.0f * r[2] - my * r[0]);
+                rec[0] = make_float4(A * s1 + B * s2, B * s1 + C * s2, -0.5f * s3, -s4);
+                rec[1] = make_float4(-0.5f * s5, s0 / op, r[6], r[7]);
                 rec[2] = make_float4(r[8], __uint_as_float(owner), 0.0f, 0.0f);
             }
         }
@@ -1077,15 +1116,17 @@ static int launch_bwd2_t(const RasterArgs& a, unsigned grid, hipStream_t s) {
 
 template <int TILE, int PPT>
 static int launch_bwd2_s(const RasterArgs& a, int S, unsigned grid, hipStream_t s) {
-    return S == 16 ? launch_bwd2_t<TILE, 16, PPT>(a, grid, s) : launch_bwd2_t<TILE, 32, PPT>(a, grid, s);
+    return S == 16 ? launch_bwd2_t<TILE, 16, PPT>(a, grid, s)
+         : S == 32 ? launch_bwd2_t<TILE, 32, PPT>(a, grid, s)
+                   : launch_bwd2_t<TILE, 64, PPT>(a, grid, s);
 }
 
 int launch_raster_bwd2(const gs_splats& sp, int64_t n, const gs_layout& L, const gs_bins& b,
                        const gs_view* views, const gs_image& fwd, const float* target,
                        const float* dLdC, const gs_grads2d& grads, float* loss, int lds_batch,
                        const gs_schedule* sched, hipStream_t s) {
-    if (lds_batch != 16 && lds_batch != 32) {
-        set_error("the two-phase backward's lds_batch must be 16 or 32 (got %d)", lds_batch);
+    if (lds_batch != 16 && lds_batch != 32 && lds_batch != 64) {
+        set_error("the two-phase backward's lds_batch must be 16, 32 or 64 (got %d)", lds_batch);
         return GS_ERR_INVALID_ARG;
     }
     if (L.tile != 8 && L.tile != 16) {
@@ -1095,9 +1136,11 @@ int launch_raster_bwd2(const gs_splats& sp, int64_t n, const gs_layout& L, const
     RasterArgs a;
     int rc = bwd_args(sp, n, L, b, views, fwd, target, dLdC, grads, loss, sched, s, &a);
     if (rc != GS_OK || a.total_tiles == 0) return rc;
-    // one pixel per lane whatever the forward's mapping (pixels are addressed
-    // by their tile-local index, so the two need not agree): four wavefronts
-    // per 16x16 tile keep the SIMDs busy across this kernel's barriers
+    // one pixel per lane whatever the layout asks of the first backward
+    // (pixels are addressed by their tile-local index, so the mapping need
+    // not be the forward's): with two, the per-pair arrays and the operands
+    // of twice the matrix steps leave one wavefront per SIMD, which measured
+    // slower at every batch size
     const unsigned grid = grid_for(a, sched);
     if (L.tile == 8) return launch_bwd2_s<8, 1>(a, lds_batch, grid, s);
     return launch_bwd2_s<16, 1>(a, lds_batch, grid, s);

@@ -173,8 +173,7 @@ typedef struct gs_grads2d {
     float* sums;          /* 9 planes of n_views * n floats, plane c at c * n_views * n:
                              per (view, Gaussian) sum of its records flagged in rec_mask
                              (components 0..8), written by gs_project_bwd_adam */
-    void* workspace;      /* device scratch of gs_grads2d_workspace_size(capacity) bytes
-                             for gs_project_bwd_adam */
+    void* workspace;      /* unused (gs_grads2d_workspace_size is 0); may be NULL */
 } gs_grads2d;
 
 /* Rasterisation outputs, indexed by global pixel (views concatenated). */
@@ -227,8 +226,8 @@ int gs_layout_init(const int32_t* widths, const int32_t* heights, int n_views, i
 size_t gs_bin_sort_workspace_size(int64_t n, const gs_layout* layout, int64_t capacity);
 
 /* Bytes of scratch (gs_grads2d.workspace) that gs_project_bwd_adam needs for
- * the given intersection capacity: per 256 intersection indices, two partial
- * sums of 9 floats, each with its owner. */
+ * the given intersection capacity: none (0); the per-Gaussian record sums are
+ * formed in LDS inside its kernel. */
 size_t gs_grads2d_workspace_size(int64_t capacity);
 
 /* A second stream a call may run independent work on, with the two events
@@ -385,20 +384,12 @@ int gs_project_bwd_adam(float* params, int64_t n, const gs_view* views, const gs
 
 /* gs_project_bwd_adam for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid
- * allocation): the same kernels and results, but grads->workspace is ignored
- * (it may be NULL) and the gather's partial slots live in a static device
- * array of GS_NOALLOC_SCRATCH_BYTES that each GPU the library runs on holds
- * until the process ends.  The caller still passes every input and output.
- * Limit: gs_grads2d_workspace_size(bins->capacity) must not exceed
- * GS_NOALLOC_SCRATCH_BYTES (about 214M intersections), else GS_ERR_WORKSPACE
- * and nothing is enqueued.  Calls no allocating routine; its first call on
- * each device looks up that device's copy of the array (hipGetSymbolAddress).
- * Every call on one GPU shares that GPU's array, which keeps the last call's
- * contents (nothing needs clearing: every slot a call reads was written
- * earlier in the same call): calls that overlap on one GPU (different streams
- * or threads without ordering) race and give undefined results; calls ordered
- * on one stream are safe. */
-#define GS_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+ * allocation): the same kernels and results.  The projection backward needs no
+ * device scratch at all (the per-(view, Gaussian) record sums are formed in
+ * LDS), so neither entry point allocates, reads grads->workspace (it may be
+ * NULL) or keeps state between calls; calls on one stream are ordered, calls
+ * that overlap on one GPU race only through the caller's own buffers.  Calls
+ * no allocating routine. */
 int gs_project_bwd_adam_noalloc(float* params, int64_t n, const gs_view* views, const gs_layout* layout,
                                 const gs_splats* splats, const gs_bins* bins, const gs_grads2d* grads,
                                 const gs_adam* adam, float* grads_out, void* stream);

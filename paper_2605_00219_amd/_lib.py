@@ -18,7 +18,6 @@ PARAM_PLANES = 15
 MLP_PARAMS = 1377
 MLP_GROUPS = 64
 MLP_SCRATCH = (MLP_GROUPS + 1) * (MLP_PARAMS + 1)
-NOALLOC_SCRATCH_BYTES = 32 << 20   # GS_NOALLOC_SCRATCH_BYTES
 
 GS_OK, GS_ERR_INVALID_ARG, GS_ERR_HIP, GS_ERR_WORKSPACE, GS_ERR_CAPACITY = 0, -1, -2, -3, -4
 STATUS_CAPACITY, STATUS_OVERFLOW, STATUS_ROWS, STATUS_SORT = 1, 2, 4, 8

@@ -1,232 +1,127 @@
-// Projection backward fused with Adam, in two passes.
+// Projection backward fused with Adam, one kernel.
 //
-// Gather: per (view, Gaussian), the sum of the screen-space gradient records
-// the backward rasteriser flagged.  It wrote them at their unsorted indices,
-// so a Gaussian's records are one contiguous range.  The sums go to a dense
-// [9][views * n] array.
+// Record sums: the backward rasteriser wrote one screen-space gradient record
+// per composited intersection at its unsorted index and flagged it in a bit
+// mask, so a (view, Gaussian)'s records lie in its own contiguous index range
+// and the 64 Gaussians of a wavefront own one contiguous range.  The
+// wavefront walks that range 64 indices at a time, compacts the flagged
+// indices into LDS, and sums each batch of 64 flagged records per owner with
+// a segmented scan across lanes (owners ascend with the index); each run's
+// total is added to its owner's accumulator in LDS, batch after batch, so the
+// order of every sum is fixed.  The sums also go to a dense [9][views * n]
+// array for the caller.
 //
 // Chain rule + Adam: one thread per Gaussian streams its parameter record and
-// both Adam moments once, reads its per-view sums (coalesced), and writes
-// parameters and moments once.  No per-parameter gradient buffer exists
-// unless the caller asks for one (grads_out).  Log-scales and opacity logits
-// are optimised as stored: the chain rule through exp and the sigmoid is part
-// of this kernel.
+// both Adam moments once, and writes parameters and moments once.  No
+// per-parameter gradient buffer exists unless the caller asks for one
+// (grads_out).  Log-scales and opacity logits are optimised as stored: the
+// chain rule through exp and the sigmoid is part of this kernel.
 //
 // The forward quantities needed by the chain rule are recomputed with the same
 // float32 code as the projection kernel, so every branch decision (culling,
 // Jacobian clamp, colour clamp) matches the forward pass bitwise.
-#include <mutex>
-
 #include "project_math.h"
 
 namespace gs {
 
-struct GatherArgs {
-    const uint32_t* offsets;
+struct RecArgs {
+    const uint32_t* offsets;   // exclusive scan of the tile counts per (view, Gaussian)
     const uint32_t* rec_mask;
     const float4* grec;
-    int64_t n;
     int64_t capacity;
-    int n_views;
     float* sums;
-    float* part_first;      // per unit, kPart floats: owner bits, then the sum of the
-                            // unit's first run (owner 0xFFFFFFFF: no run)
-    float* part_last;       // per unit, kPart floats: the same for its last run, if it
-                            // is not also the first
 };
 
-constexpr int kPart = 10;   // floats per partial slot
+// No scratch: the record sums live in LDS.
+size_t gather_workspace(int64_t) { return 0; }
 
-constexpr int kGatherThreads = 256;
-constexpr int kGatherE = 512;                           // intersection indices per unit
-constexpr int kGatherPer = kGatherE / kGatherThreads;   // indices per thread
-static_assert(kGatherPer == 2, "two compacted records per thread in the segmented scan");
+constexpr int kAdamThreads = 256;
+constexpr int kAdamWaves = kAdamThreads / kWave;
 
-size_t gather_workspace(int64_t capacity) {
-    const size_t nb = (size_t)((capacity + kGatherE - 1) / kGatherE) + 1;
-    auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
-    return 2 * up(4 * kPart * nb);
-}
-
-static void carve_gather(void* ws, int64_t capacity, GatherArgs& g) {
-    const size_t nb = (size_t)((capacity + kGatherE - 1) / kGatherE) + 1;
-    auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
-    char* p = static_cast<char*>(ws);
-    g.part_first = reinterpret_cast<float*>(p);
-    p += up(4 * kPart * nb);
-    g.part_last = reinterpret_cast<float*>(p);
-}
-
-// Number of valid intersections (clamped to the capacity).
-GS_DEV uint64_t entries_valid(const GatherArgs& a, int64_t vn) {
-    return min((uint64_t)a.offsets[vn], (uint64_t)a.capacity);
-}
-
-// Gather, one workgroup per unit of E intersection indices.  Each thread
-// reads the record-mask bits of its indices; a workgroup scan of the flag
-// counts gives every flagged record a slot, and the flagged records (9
-// gradient components and the owner (view, Gaussian) the backward stored in
-// the record) are compacted into LDS in index order.  A Gaussian's indices
-// are one contiguous range, so its flagged records in the unit are one run of
-// equal owner, summed by a segmented scan over the compacted records.
-// A run with runs on both sides lies wholly inside the unit, so its sum is the
-// Gaussian's and goes to sums; the unit's first run goes to its first partial
-// slot and its last run (if there are two or more) to its last partial slot,
-// each tagged with the owner, for the chain-rule kernel to add up.  Every unit
-// writes the tags of both slots; sums of Gaussians without a middle run keep
-// the zeros filled beforehand.
-__global__ __launch_bounds__(kGatherThreads) void k_gather2d(GatherArgs a) {
-    constexpr int NW = kGatherThreads / kWave;
-    __shared__ float s_val[9][kGatherE];
-    __shared__ uint32_t s_own[kGatherE];
-    __shared__ uint32_t s_flag[kGatherThreads];
-    __shared__ uint32_t s_wsum[NW];
-    const int64_t vn = (int64_t)a.n_views * a.n;
-    const uint64_t kc = entries_valid(a, vn);
-    const uint32_t unit = blockIdx.x;
-    const uint64_t e0 = (uint64_t)unit * kGatherE;
-    if (e0 >= kc) return;
-    const uint64_t e1 = min(e0 + (uint64_t)kGatherE, kc);
-    const int t = threadIdx.x, lane = t % kWave, w = t / kWave;
-    const uint64_t i0 = e0 + (uint64_t)kGatherPer * t;
-    uint32_t bits = 0;
-    if (i0 < e1) {
-        bits = (a.rec_mask[i0 >> 5] >> (uint32_t)(i0 & 31)) & ((1u << kGatherPer) - 1u);
-        const uint64_t left = e1 - i0;
-        if (left < (uint64_t)kGatherPer) bits &= (1u << left) - 1u;
+// Sums over the flagged records of (view vi, Gaussian g0 + lane) for the
+// wavefront's 64 Gaussians [g0, g0 + 64) (lanes past n take part with an
+// empty range).  s_idx: 128 words, s_acc: 9 x 64 floats, both this
+// wavefront's own.
+GS_DEV void wave_record_sums(const RecArgs& r, int64_t n, int vi, int64_t g0, int lane, bool live,
+                             uint32_t* s_idx, float* s_acc, float d[9]) {
+    const uint64_t cap = (uint64_t)r.capacity;
+    const int64_t o = (int64_t)vi * n + g0 + lane;
+    uint32_t ob = 0, oe = 0;
+    if (live) {
+        ob = (uint32_t)min((uint64_t)r.offsets[o], cap);
+        oe = (uint32_t)min((uint64_t)r.offsets[o + 1], cap);
     }
-    const uint32_t cnt = (uint32_t)__popc(bits);
-    uint32_t incl = cnt;
+    const int nlive = __popcll(__ballot(live));
+    const uint32_t R0 = (uint32_t)__shfl((int)ob, 0), R1 = (uint32_t)__shfl((int)oe, nlive - 1);
+    const uint32_t own0 = (uint32_t)((int64_t)vi * n + g0);
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        const uint32_t y = __shfl_up(incl, off);
-        if (lane >= off) incl += y;
-    }
-    if (lane == kWave - 1) s_wsum[w] = incl;
-    if (t == 0) {
-        a.part_first[kPart * (int64_t)unit] = __uint_as_float(0xFFFFFFFFu);
-        a.part_last[kPart * (int64_t)unit] = __uint_as_float(0xFFFFFFFFu);
-    }
-    __syncthreads();
-    uint32_t pos = incl - cnt, nf = 0;
+    for (int c = 0; c < 9; ++c) s_acc[c * kWave + lane] = 0.0f;
+    // sum one batch of k <= 64 compacted indices s_idx[0, k) into s_acc
+    auto batch = [&](int k) {
+        __builtin_amdgcn_wave_barrier();
+        const bool act = lane < k;
+        float v[9];
+        uint32_t own = 0xFFFFFFFFu;
 #pragma unroll
-    for (int j = 0; j < NW; ++j) {
-        if (j < w) pos += s_wsum[j];
-        nf += s_wsum[j];
-    }
-    if (nf == 0) return;
+        for (int c = 0; c < 9; ++c) v[c] = 0.0f;
+        if (act) {
+            const float4* q = r.grec + 3 * (int64_t)s_idx[lane];
+            const float4 q0 = q[0], q1 = q[1], q2 = q[2];
+            v[0] = q0.x; v[1] = q0.y; v[2] = q0.z; v[3] = q0.w;
+            v[4] = q1.x; v[5] = q1.y; v[6] = q1.z; v[7] = q1.w; v[8] = q2.x;
+            own = __float_as_uint(q2.y) - own0;
+        }
+        const uint32_t prev = (uint32_t)__shfl_up((int)own, 1);
+        uint32_t head = (act && (lane == 0 || prev != own)) ? 1u : 0u;
 #pragma unroll
-    for (int q = 0; q < kGatherPer; ++q) {
-        if ((bits >> q) & 1u) {
-            const float4* g = a.grec + 3 * (int64_t)(i0 + (uint64_t)q);
-            const float4 r0 = g[0], r1 = g[1], r2 = g[2];
-            s_val[0][pos] = r0.x; s_val[1][pos] = r0.y; s_val[2][pos] = r0.z; s_val[3][pos] = r0.w;
-            s_val[4][pos] = r1.x; s_val[5][pos] = r1.y; s_val[6][pos] = r1.z; s_val[7][pos] = r1.w;
-            s_val[8][pos] = r2.x;
-            s_own[pos] = __float_as_uint(r2.y);
-            ++pos;
+        for (int off = 1; off < kWave; off <<= 1) {
+            float y[9];
+#pragma unroll
+            for (int c = 0; c < 9; ++c) y[c] = __shfl_up(v[c], off);
+            const uint32_t hy = (uint32_t)__shfl_up((int)head, off);
+            if (lane >= off && !head) {
+#pragma unroll
+                for (int c = 0; c < 9; ++c) v[c] = y[c] + v[c];
+                head = hy;
+            }
+        }
+        const uint32_t next = (uint32_t)__shfl_down((int)own, 1);
+        const bool tail = act && (lane == k - 1 || next != own);
+        if (tail && own < (uint32_t)kWave) {
+#pragma unroll
+            for (int c = 0; c < 9; ++c) s_acc[c * kWave + own] += v[c];
+        }
+        __builtin_amdgcn_wave_barrier();
+    };
+    int cnt = 0;
+    if (R1 > R0) {
+        // the range's mask words, 64 at a time (one per lane, loaded together),
+        // then 64 indices (two words) per step
+        const uint32_t wlast = (R1 - 1) >> 5;
+        for (uint32_t wb = R0 >> 5; wb <= wlast; wb += kWave) {
+            const uint32_t mine = wb + (uint32_t)lane <= wlast ? r.rec_mask[wb + lane] : 0u;
+            const uint32_t nw = min((uint32_t)kWave, wlast - wb + 1);
+            for (uint32_t k = 0; k < nw; k += 2) {
+                const uint32_t idx = (wb + k) * 32u + (uint32_t)lane;
+                const uint32_t word = (uint32_t)__shfl((int)mine, (int)k + (lane >> 5));
+                const bool f = idx >= R0 && idx < R1 && ((word >> (lane & 31)) & 1u);
+                const uint64_t m = __ballot(f);
+                if (m == 0ull) continue;
+                if (f) s_idx[cnt + __popcll(m & lt)] = idx;
+                cnt += __popcll(m);
+                if (cnt >= kWave) {
+                    batch(kWave);
+                    cnt -= kWave;
+                    if (lane < cnt) s_idx[lane] = s_idx[kWave + lane];
+                }
+            }
         }
     }
-    __syncthreads();
-    // segmented inclusive scan over the compacted records, two per thread
-    // (records 2t and 2t + 1): the last record of each run ends up with the
-    // run's sum.  Per thread: the pair's aggregate; across threads: a
-    // Hillis-Steele scan of (aggregate, run-start flag); then each record adds
-    // the running sum before it unless a run starts at it.
-    const uint32_t p0 = 2 * (uint32_t)t, p1 = p0 + 1;
-    const bool act0 = p0 < nf, act1 = p1 < nf;
-    const uint32_t own0 = act0 ? s_own[p0] : 0xFFFFFFFFu;
-    const uint32_t own1 = act1 ? s_own[p1] : 0xFFFFFFFFu;
-    const bool head0 = act0 && (p0 == 0 || s_own[p0 - 1] != own0);
-    const bool head1 = act1 && own1 != own0;
-    const bool tail0 = act0 && (!act1 || own1 != own0);
-    const bool tail1 = act1 && (p1 == nf - 1 || s_own[p1 + 1] != own1);
-    float v0[9], v1[9], agg[9];
+    if (cnt > 0) batch(cnt);
+    __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int c = 0; c < 9; ++c) {
-        v0[c] = act0 ? s_val[c][p0] : 0.f;
-        v1[c] = act1 ? s_val[c][p1] : 0.f;
-        agg[c] = head1 ? v1[c] : v0[c] + v1[c];
-    }
-    uint32_t f = (head0 || head1) ? 1u : 0u;
-    const uint32_t nt = (nf + 1) / 2;   // threads holding records
-    for (uint32_t off = 1; off < nt; off <<= 1) {
-        __syncthreads();
-        s_flag[t] = f;
-#pragma unroll
-        for (int c = 0; c < 9; ++c) s_val[c][t] = agg[c];
-        __syncthreads();
-        if ((uint32_t)t >= off && !f) {
-#pragma unroll
-            for (int c = 0; c < 9; ++c) agg[c] = s_val[c][t - off] + agg[c];
-            f = s_flag[t - off];
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < 9; ++c) s_val[c][t] = agg[c];   // inclusive, per thread
-    __syncthreads();
-    if (!head0 && t > 0) {
-#pragma unroll
-        for (int c = 0; c < 9; ++c) v0[c] = s_val[c][t - 1] + v0[c];
-    }
-    if (!head1) {
-#pragma unroll
-        for (int c = 0; c < 9; ++c) v1[c] = v0[c] + v1[c];
-    }
-    // the unit's first run goes to the first slot, its last run (if not also
-    // the first) to the last slot, every other run to sums
-    const uint32_t first_own = s_own[0];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const bool tl = h == 0 ? tail0 : tail1;
-        const uint32_t own = h == 0 ? own0 : own1;
-        const uint32_t p = h == 0 ? p0 : p1;
-        if (!tl || (int64_t)own >= vn) continue;
-        float* dst;
-        int64_t stride;
-        if (own == first_own) { dst = a.part_first + kPart * (int64_t)unit; stride = 1; }
-        else if (p == nf - 1) { dst = a.part_last + kPart * (int64_t)unit; stride = 1; }
-        else { dst = a.sums + own; stride = vn; }
-        if (stride == 1) {
-            dst[0] = __uint_as_float(own);
-            ++dst;
-        }
-#pragma unroll
-        for (int c = 0; c < 9; ++c) dst[c * stride] = h == 0 ? v0[c] : v1[c];
-    }
-}
-
-// Sum of the flagged records of (view, Gaussian) o: its middle run if it had
-// one (sums, zero otherwise), then, unit by unit over the units its index
-// range covers, the first and last partial slots tagged with o.  The result
-// is also stored to sums when a partial slot contributed.
-GS_DEV void gather_total(const GatherArgs& a, int64_t o, int64_t vn, float d[9]) {
-    const uint64_t b = min((uint64_t)a.offsets[o], (uint64_t)a.capacity);
-    const uint64_t e = min((uint64_t)a.offsets[o + 1], (uint64_t)a.capacity);
-#pragma unroll
-    for (int c = 0; c < 9; ++c) d[c] = a.sums[c * vn + o];
-    if (e <= b) return;
-    const uint32_t tag = (uint32_t)o;
-    bool added = false;
-    for (uint64_t u = b / kGatherE; u <= (e - 1) / kGatherE; ++u) {
-        const float* pf = a.part_first + kPart * u;
-        if (__float_as_uint(pf[0]) == tag) {
-#pragma unroll
-            for (int c = 0; c < 9; ++c) d[c] += pf[1 + c];
-            added = true;
-        }
-        const float* pl = a.part_last + kPart * u;
-        if (__float_as_uint(pl[0]) == tag) {
-#pragma unroll
-            for (int c = 0; c < 9; ++c) d[c] += pl[1 + c];
-            added = true;
-        }
-    }
-    if (added) {
-#pragma unroll
-        for (int c = 0; c < 9; ++c) a.sums[c * vn + o] = d[c];
-    }
+    for (int c = 0; c < 9; ++c) d[c] = s_acc[c * kWave + lane];
 }
 
 struct AdamArgs {
@@ -237,7 +132,7 @@ struct AdamArgs {
     int tile;
     int cull;
     int32_t gx[GS_MAX_VIEWS], gy[GS_MAX_VIEWS];
-    GatherArgs ga;
+    RecArgs rec;
     float4* m;
     float4* v;
     const float* bias;  // [0] = 1 - beta1^t, [1] = sqrt(1 - beta2^t)
@@ -284,10 +179,27 @@ GS_DEV float adam_one(float p, float g, float& m, float& v, float step, float be
     return p - step * (m * __builtin_amdgcn_rcpf(denom));
 }
 
-__global__ __launch_bounds__(256, 2) void k_project_bwd_adam(AdamArgs a) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= a.n) return;
+__global__ __launch_bounds__(kAdamThreads, 2) void k_project_bwd_adam(AdamArgs a) {
+    __shared__ uint32_t s_idx[kAdamWaves][2 * kWave];
+    __shared__ float s_acc[kAdamWaves][9 * kWave];
     const int64_t n = a.n;
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+    const int64_t g0 = (int64_t)blockIdx.x * kAdamThreads + wv * kWave;
+    if (g0 >= n) return;                    // whole wavefronts only
+    const int64_t g = g0 + lane;
+    const bool live = g < n;
+    const int64_t vn = (int64_t)a.n_views * n;
+    // per-view record sums first (to sums; read back below), so that their
+    // registers and the chain rule's are never live together
+    for (int vi = 0; vi < a.n_views; ++vi) {
+        float d[9];
+        wave_record_sums(a.rec, n, vi, g0, lane, live, s_idx[wv], s_acc[wv], d);
+        if (live) {
+#pragma unroll
+            for (int c = 0; c < 9; ++c) a.rec.sums[c * vn + (int64_t)vi * n + g] = d[c];
+        }
+    }
+    if (!live) return;
     const float4 p0 = a.params[0 * n + g];
     const float4 p1 = a.params[1 * n + g];
     const float4 p2 = a.params[2 * n + g];
@@ -298,12 +210,12 @@ __global__ __launch_bounds__(256, 2) void k_project_bwd_adam(AdamArgs a) {
 #pragma unroll
     for (int i = 0; i < 48; ++i) gsh[i] = 0.f;
 
-    const int64_t vn = (int64_t)a.n_views * n;
     for (int vi = 0; vi < a.n_views; ++vi) {
         const int64_t o = (int64_t)vi * n + g;
+        if (!finite || a.rec.offsets[o + 1] == a.rec.offsets[o]) continue;
         float d[9];
-        gather_total(a.ga, o, vn, d);
-        if (!finite || a.ga.offsets[o + 1] == a.ga.offsets[o]) continue;
+#pragma unroll
+        for (int c = 0; c < 9; ++c) d[c] = a.rec.sums[c * vn + o];
         // SH coefficients are loaded per view and not kept: the Adam update
         // below reads them again, which keeps them out of the registers the
         // float64 chain rule needs
@@ -515,57 +427,12 @@ __global__ void k_adam_tick(int32_t* step, float* bias, float beta1, float beta2
     bias[1] = (float)sqrt(1.0 - pow((double)beta2, (double)t));
 }
 
-// Device scratch of gs_project_bwd_adam_noalloc: the gather's partial slots.
-// Host code never uses the array's name as an address: each device's copy is
-// found once with hipGetSymbolAddress (with that device current) and that
-// pointer is what the kernels receive.
-static __device__ __align__(256) unsigned char scratch[GS_NOALLOC_SCRATCH_BYTES];
-
-constexpr int kMaxDevices = 64;
-static std::mutex g_scratch_mu;
-static void* g_scratch_ptr[kMaxDevices];
-
-static int noalloc_scratch(void** out) {
-    int dev = -1;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) {
-        set_error("gs_project_bwd_adam_noalloc: hipGetDevice: %s", hipGetErrorString(e));
-        return GS_ERR_HIP;
-    }
-    if (dev < 0 || dev >= kMaxDevices) {
-        set_error("gs_project_bwd_adam_noalloc: device %d beyond %d", dev, kMaxDevices);
-        return GS_ERR_INVALID_ARG;
-    }
-    std::lock_guard<std::mutex> lock(g_scratch_mu);
-    if (!g_scratch_ptr[dev]) {
-        void* p = nullptr;
-        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
-        if (e != hipSuccess || !p) {
-            set_error("gs_project_bwd_adam_noalloc: hipGetSymbolAddress: %s", hipGetErrorString(e));
-            return GS_ERR_HIP;
-        }
-        g_scratch_ptr[dev] = p;
-    }
-    *out = g_scratch_ptr[dev];
-    return GS_OK;
-}
-
+// The no-allocation entry point: the projection backward needs no scratch at
+// all (the record sums live in LDS), so it is the same launch.
 int launch_project_bwd_adam_noalloc(float* params, int64_t n, const gs_view* views, const gs_layout& L,
                                     const gs_splats& splats, const gs_bins& b, const gs_grads2d& grads,
                                     const gs_adam* adam, float* grads_out, hipStream_t s) {
-    const size_t need = gather_workspace(b.capacity);
-    if (need > (size_t)GS_NOALLOC_SCRATCH_BYTES) {
-        set_error("gs_project_bwd_adam_noalloc: capacity %lld needs %zu bytes of scratch, more than the "
-                  "%zu the library holds",
-                  (long long)b.capacity, need, (size_t)GS_NOALLOC_SCRATCH_BYTES);
-        return GS_ERR_WORKSPACE;
-    }
-    void* ws = nullptr;
-    const int rc = noalloc_scratch(&ws);
-    if (rc != GS_OK) return rc;
-    gs_grads2d g = grads;
-    g.workspace = ws;
-    return launch_project_bwd_adam(params, n, views, L, splats, b, g, adam, grads_out, s);
+    return launch_project_bwd_adam(params, n, views, L, splats, b, grads, adam, grads_out, s);
 }
 
 int launch_project_bwd_adam(float* params, int64_t n, const gs_view* views, const gs_layout& L,
@@ -573,16 +440,12 @@ int launch_project_bwd_adam(float* params, int64_t n, const gs_view* views, cons
                             const gs_adam* adam, float* grads_out, hipStream_t s) {
     if (n == 0) return GS_OK;
     int rc = GS_OK;
-    GatherArgs ga;
-    memset(&ga, 0, sizeof(ga));
-    ga.offsets = b.offsets;
-    ga.rec_mask = grads.rec_mask;
-    ga.grec = reinterpret_cast<const float4*>(grads.rec);
-    ga.n = n;
-    ga.capacity = b.capacity;
-    ga.n_views = L.n_views;
-    ga.sums = grads.sums;
-    carve_gather(grads.workspace, b.capacity, ga);
+    RecArgs ra;
+    ra.offsets = b.offsets;
+    ra.rec_mask = grads.rec_mask;
+    ra.grec = reinterpret_cast<const float4*>(grads.rec);
+    ra.capacity = b.capacity;
+    ra.sums = grads.sums;
     AdamArgs a;
     memset(&a, 0, sizeof(a));
     a.params = reinterpret_cast<float4*>(params);
@@ -609,18 +472,9 @@ int launch_project_bwd_adam(float* params, int64_t n, const gs_view* views, cons
         rc = check_launch("adam_tick");
         if (rc != GS_OK) return rc;
     }
-    const int64_t vn = (int64_t)L.n_views * n;
-    // sums of Gaussians without any flagged record stay zero
-    rc = launch_fill_u32(reinterpret_cast<uint32_t*>(ga.sums), 0u, 9 * vn, s);
-    if (rc != GS_OK) return rc;
-    if (b.capacity > 0) {
-        hipLaunchKernelGGL(k_gather2d, dim3((unsigned)((b.capacity + kGatherE - 1) / kGatherE)),
-                           dim3(kGatherThreads), 0, s, ga);
-        rc = check_launch("gather2d");
-        if (rc != GS_OK) return rc;
-    }
-    a.ga = ga;
-    hipLaunchKernelGGL(k_project_bwd_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
+    a.rec = ra;
+    hipLaunchKernelGGL(k_project_bwd_adam, dim3((unsigned)((n + kAdamThreads - 1) / kAdamThreads)),
+                       dim3(kAdamThreads), 0, s, a);
     return check_launch("project_bwd_adam");
 }
 

@@ -202,8 +202,8 @@ int gs_project_bwd_adam(float* params, int64_t n, const gs_view* views, const gs
             "gs_project_bwd_adam: incomplete adam state");
     REQUIRE(splats && (n == 0 || splats->rec), "gs_project_bwd_adam: null splat records");
     REQUIRE(grads && (grads->sums || n == 0) &&
-            ((grads->rec && grads->rec_mask) || bins->capacity == 0) &&
-            grads->workspace, "gs_project_bwd_adam: null gradient buffers");
+            ((grads->rec && grads->rec_mask) || bins->capacity == 0),
+            "gs_project_bwd_adam: null gradient buffers");
     return launch_project_bwd_adam(params, n, views, *layout, *splats, *bins, *grads, adam, grads_out,
                                    (hipStream_t)stream);
 }

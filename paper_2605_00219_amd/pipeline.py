@@ -124,8 +124,6 @@ class Frame:
         self.comp_mask = torch.zeros((capacity + 31) // 32, **u32)
         ws = G.lib.gs_bin_sort_workspace_size(self.n, C.byref(self.layout), capacity)
         self.workspace = torch.zeros(max(int(ws), 1), dtype=torch.uint8, device=self.device)
-        gws = G.lib.gs_grads2d_workspace_size(capacity)
-        self.gather_ws = torch.zeros(max(int(gws), 1), dtype=torch.uint8, device=self.device)
         self.capacity = capacity
         self._structs()
 
@@ -134,8 +132,7 @@ class Frame:
         self.bins = G.GsBins(_i(self.offsets), _i(self.row_offsets), _i(self.rows), self.row_capacity,
                              _i(self.keys), _i(self.vals), _i(self.ranges), _i(self.status),
                              self.capacity)
-        self.grads2d = G.GsGrads2d(_i(self.grec), _i(self.rec_mask), _i(self.tile_stop), _i(self.sums),
-                                   _i(self.gather_ws))
+        self.grads2d = G.GsGrads2d(_i(self.grec), _i(self.rec_mask), _i(self.tile_stop), _i(self.sums), None)
         self.img = G.GsImage(_i(self.image), _i(self.T), _i(self.last),
                              _i(self.tile_stats) if self.tile_stats is not None else None,
                              _i(self.comp_mask))
@@ -345,8 +342,8 @@ def project_bwd_adam(model: Model, frame: Frame, views_dev: torch.Tensor, adam: 
 
 def project_bwd_adam_noalloc(model: Model, frame: Frame, views_dev: torch.Tensor, adam: bool = True,
                              grads_out: torch.Tensor | None = None, stream=None) -> None:
-    """project_bwd_adam through gs_project_bwd_adam_noalloc: the library's static
-    device scratch instead of frame's workspace (nothing allocated)."""
+    """project_bwd_adam through gs_project_bwd_adam_noalloc (allocates nothing;
+    the same launch as gs_project_bwd_adam, which needs no scratch either)."""
     G.check(G.lib.gs_project_bwd_adam_noalloc(_i(model.params), frame.n, _i(views_dev), C.byref(frame.layout),
                                               C.byref(frame.splats), C.byref(frame.bins),
                                               C.byref(frame.grads2d),

@@ -48,7 +48,7 @@ def test_host_only_entry_points():
         G.layout_init([64] * 17, [64] * 17, 16)
     # workspace query is pure host arithmetic
     assert G.lib.gs_bin_sort_workspace_size(1000, ctypes.byref(L), 100000) > 8 * 100000
-    assert G.lib.gs_grads2d_workspace_size(100000) >= 4 * (100000 // 1024) * 19
+    assert G.lib.gs_grads2d_workspace_size(100000) == 0      # record sums are formed in LDS
     assert G.lib.gs_order_by_cost_scratch_size(5000) > 4 * 5000
 
 

@@ -33,8 +33,11 @@ constexpr int kGroup = 16;                              // chunks per look-back 
 // single-pass tile scatter (depth order first, every view with at most
 // kTsBins tiles): chunks of kTsChunk keys in depth order
 constexpr int kTsThreads = 256;
-constexpr int kTsItems = 32;
-constexpr int kTsChunk = kTsThreads * kTsItems;          // 8192 keys
+// 10240 keys: the 4.9M keys of a 300k-Gaussian 720p view make 475 chunks,
+// one round of the 512 workgroups two per CU hold (8192 left a second round
+// of 82 and took 27 us longer)
+constexpr int kTsItems = 40;
+constexpr int kTsChunk = kTsThreads * kTsItems;
 constexpr int kTsBins = 4096;                            // tiles per view (12 bits)
 static_assert(kSortThreads == kDigits, "one thread per digit in the scan and look-back");
 
@@ -1121,7 +1124,7 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_count(const uint32_t* __restr
     for (int j = t; j < nt; j += kTsThreads) tsm[mb + (uint32_t)j * nc + c] = hist[j];
 }
 
-// Per chunk: wavefront w owns the chunk's keys [w * 2048, (w + 1) * 2048),
+// Per chunk: wavefront w owns the chunk's keys [w * PER_WAVE, (w + 1) * PER_WAVE),
 // read in blocks of 8 per lane with the next block's loads in flight.
 // 1. Each tile's keys are counted per wavefront: peers with the same tile are
 //    found with 12 ballots and the first lane of each group adds the group's
@@ -1151,9 +1154,13 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_scatter(const uint32_t* __res
     constexpr int KB = 8;                        // keys per lane per block
     static_assert(ITEMS == kTsItems && ITEMS % KB == 0, "items per lane");
     static_assert(kTsChunk <= 65536, "16-bit chunk positions");
-    __shared__ uint16_t cnt[NW][kTsBins];        // per-(wavefront, tile) counts, then starts
-    __shared__ uint32_t bml[kTsBins];            // destination of the tile's run minus its start
+    // per-(wavefront, tile) counts, then starts; after the ranking, the
+    // destination of each tile's run minus its start in the chunk (uint32)
+    __shared__ uint16_t cnt[NW][kTsBins];
+    static_assert(sizeof(cnt) >= sizeof(uint32_t) * kTsBins, "run destinations fit over the counts");
+    uint32_t* bml = reinterpret_cast<uint32_t*>(&cnt[0][0]);
     __shared__ uint16_t perm[kTsChunk];          // sorted position -> input position
+    __shared__ uint8_t s_own[NW][kTsBins];       // per wavefront: a lane that holds the tile
     __shared__ uint64_t s_scan[NW];
     int v;
     uint32_t c;
@@ -1187,8 +1194,17 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_scatter(const uint32_t* __res
         for (int u = 0; u < KB; ++u)
             dst[u] = keys_in[nv > 0 ? min(cstart + (uint32_t)(wbeg + (i0 + u) * kWave + lane), last) : last];
     };
-    // peers of this lane's tile among the valid lanes
-    auto peers_of = [&](uint32_t tile, bool valid) {
+    // peers of this lane's tile among the valid lanes.  Usually the 64 keys
+    // of a step hold 64 different tiles (consecutive keys in depth order are
+    // a few Gaussians' tile sets): every lane writes its id at its tile and
+    // reads it back, and if no lane finds another's id, each lane is its own
+    // only peer; otherwise 12 ballots find the peers.  (Volatile: the read
+    // must see the other lanes' writes, not the compiler's copy of its own.)
+    volatile uint8_t* own = s_own[w];
+    auto peers_of = [&](uint32_t tile, bool valid) -> uint64_t {
+        if (valid) own[tile] = (uint8_t)lane;
+        const bool dup = valid && own[tile] != (uint8_t)lane;
+        if (__ballot(dup) == 0ull) return valid ? (uint64_t)1 << lane : (uint64_t)0;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int bit = 0; bit < 12; ++bit) {
@@ -1220,6 +1236,7 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_scatter(const uint32_t* __res
     }
     __syncthreads();
     // 2. tile starts within the chunk (scan over tiles), per-(wavefront, tile) starts
+    uint32_t dstm[PRE];
     {
         uint32_t tot[PRE];
         uint32_t sum = 0;
@@ -1236,7 +1253,7 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_scatter(const uint32_t* __res
 #pragma unroll
         for (int q = 0; q < PRE; ++q) {
             const int j = t * PRE + q;
-            bml[j] = pre[q] - run;
+            dstm[q] = pre[q] - run;
             uint32_t wr = run;
 #pragma unroll
             for (int r = 0; r < NW; ++r) {
@@ -1272,6 +1289,9 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_scatter(const uint32_t* __res
             }
         }
     }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PRE; ++q) bml[t * PRE + q] = dstm[q];
     __syncthreads();
     // 4. coalesced runs, KB sorted positions per lane at a time (reads of
     // positions past the chunk's keys are clamped and not written)

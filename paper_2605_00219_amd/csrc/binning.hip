@@ -20,8 +20,8 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanBlock = kScanThreads * kScanItems;  // 2048 elements per block
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;
-constexpr int kChunk = kSortThreads * kSortItems;      // 4096 keys per radix chunk
+constexpr int kSortItems = 32;
+constexpr int kChunk = kSortThreads * kSortItems;      // 8192 keys per radix chunk
 constexpr int kDepthItems = 4;                          // the depth sort of (view, Gaussian)s:
 constexpr int kDepthChunk = kSortThreads * kDepthItems; // 1024-key chunks
 constexpr int64_t kDepthFirstRatio = 12;                // capacity / (views x n) to sort by depth first
@@ -389,7 +389,8 @@ __global__ __launch_bounds__(256) void k_row_count(const float4* __restrict__ re
                                                    int64_t m, EmitGeom geo, uint32_t* __restrict__ row_count,
                                                    uint32_t* __restrict__ status, uint32_t* __restrict__ dkey,
                                                    uint32_t* __restrict__ dval, uint32_t* __restrict__ dtable,
-                                                   uint32_t* __restrict__ ddcount, int n_views) {
+                                                   uint32_t* __restrict__ ddcount, int n_views,
+                                                   bool depth_keys) {
     if (blockIdx.x == 0) {
         for (int i = threadIdx.x; i < n_views * kPasses * kDigits; i += blockDim.x) ddcount[i] = 0u;
         if (threadIdx.x == 0) {
@@ -409,6 +410,7 @@ __global__ __launch_bounds__(256) void k_row_count(const float4* __restrict__ re
     const bool vis = tiles[o] > 0;
     const float4 q3 = rec[4 * o + 3];
     row_count[o] = vis ? rect_rows(q3) : 0u;
+    if (!depth_keys) return;   // no depth order in this call
     const int v = (int)(o / n);
     // the key's bits below split (at most D): depth bits only
     const int D = geo.depth_bits[v];
@@ -712,7 +714,7 @@ constexpr int kLbGroupWindow = 8;
 // that has started and will publish; a spin limit bounds the waits all the
 // same (GS_STATUS_SORT).
 //
-// Wavefront w owns the contiguous keys [w * 1024, (w + 1) * 1024) of the chunk
+// Wavefront w owns the contiguous keys [w * PER_WAVE, (w + 1) * PER_WAVE) of the chunk
 // and ranks them item by item: peers with the same digit are found with 8
 // ballots, and a running per-(wavefront, digit) count in LDS gives each key its
 // rank among the wavefront's keys of that digit (one wavefront updates only
@@ -728,7 +730,10 @@ constexpr int kLbGroupWindow = 8;
 // counts of the earlier chunks of its group and the totals of the earlier
 // groups, stopping early at the published inclusive prefix of a group's last
 // chunk.
-// At most 128 VGPRs, so that four workgroups (the LDS limit) fit on a CU.
+// With 8192-key chunks (runs of 32 keys per digit on average, whole 128-byte
+// lines) two workgroups fit on a CU (LDS); 4096-key chunks, four per CU,
+// took 7% longer on 1.6e8 keys.  (The depth sort's 1024-key chunks keep the
+// 128-VGPR bound.)
 template <int ITEMS>
 __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_onesweep(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
@@ -943,51 +948,52 @@ struct RangeGeom {
     int32_t tile_base[GS_MAX_VIEWS + 1];
 };
 
-// One thread per sorted position j: tile boundaries -> ranges (lower-bound
-// semantics, empty tiles get start = end = insertion point).  Workgroups past
-// the first ceil(capacity / 256) handle the tiles of views without any
-// intersection, one thread per tile.
+// Tile boundaries -> ranges (lower-bound semantics, empty tiles get start =
+// end = insertion point), a grid-stride loop over sorted positions (one
+// position per thread per round: a launch of one workgroup per 256 positions
+// was bound by the workgroup dispatch rate at 10^8 keys), after which the
+// same threads give the tiles of views without any intersection their empty
+// range.
+constexpr int kRangeBlocks = 4096;
+
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ keys,
                                                 const uint32_t* __restrict__ table, int n_views,
-                                                RangeGeom geo, int64_t capacity,
-                                                uint32_t* __restrict__ ranges) {
-    const int64_t cap_blocks = (capacity + 255) / 256;
-    if ((int64_t)blockIdx.x >= cap_blocks) {
-        const int64_t gt = ((int64_t)blockIdx.x - cap_blocks) * blockDim.x + threadIdx.x;
-        if (gt >= geo.tile_base[n_views]) return;
+                                                RangeGeom geo, uint32_t* __restrict__ ranges) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t first = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t total = table[4 * (n_views - 1) + 1];   // the views' segments are consecutive
+    for (int64_t j64 = first; j64 < (int64_t)total; j64 += stride) {
+        const uint32_t j = (uint32_t)j64;
+        int v = 0;
+        for (int i = 1; i < n_views; ++i)
+            if (j >= table[4 * i]) v = i;
+        const uint32_t sb = table[4 * v], se = table[4 * v + 1];
+        const int D = geo.depth_bits[v];
+        const int tb = geo.tile_base[v];
+        const int nt = geo.tile_base[v + 1] - tb;
+        uint2* R = reinterpret_cast<uint2*>(ranges) + tb;
+        const int t = min((int)(keys[j] >> D), nt - 1);
+        if (j == sb) {
+            for (int u = 0; u <= t; ++u) R[u].x = j;
+            for (int u = 0; u < t; ++u) R[u].y = j;
+        } else {
+            const int tp = min((int)(keys[j - 1] >> D), nt - 1);
+            if (tp != t) {
+                for (int u = tp + 1; u <= t; ++u) R[u].x = j;
+                for (int u = tp; u < t; ++u) R[u].y = j;
+            }
+        }
+        if (j == se - 1) {
+            for (int u = t; u < nt; ++u) R[u].y = j + 1;
+            for (int u = t + 1; u < nt; ++u) R[u].x = j + 1;
+        }
+    }
+    for (int64_t gt = first; gt < (int64_t)geo.tile_base[n_views]; gt += stride) {
         int v = 0;
         for (int i = 1; i < n_views; ++i)
             if (gt >= geo.tile_base[i]) v = i;
         const uint32_t b = table[4 * v], e = table[4 * v + 1];
         if (b == e) reinterpret_cast<uint2*>(ranges)[gt] = make_uint2(b, b);
-        return;
-    }
-    const int64_t j64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j64 >= capacity) return;
-    const uint32_t j = (uint32_t)j64;
-    int v = -1;
-    for (int i = 0; i < n_views; ++i)
-        if (j >= table[4 * i] && j < table[4 * i + 1]) v = i;
-    if (v < 0) return;
-    const uint32_t sb = table[4 * v], se = table[4 * v + 1];
-    const int D = geo.depth_bits[v];
-    const int tb = geo.tile_base[v];
-    const int nt = geo.tile_base[v + 1] - tb;
-    uint2* R = reinterpret_cast<uint2*>(ranges) + tb;
-    const int t = min((int)(keys[j] >> D), nt - 1);
-    if (j == sb) {
-        for (int u = 0; u <= t; ++u) R[u].x = j;
-        for (int u = 0; u < t; ++u) R[u].y = j;
-    } else {
-        const int tp = min((int)(keys[j - 1] >> D), nt - 1);
-        if (tp != t) {
-            for (int u = tp + 1; u <= t; ++u) R[u].x = j;
-            for (int u = tp; u < t; ++u) R[u].y = j;
-        }
-    }
-    if (j == se - 1) {
-        for (int u = t; u < nt; ++u) R[u].y = j + 1;
-        for (int u = t + 1; u < nt; ++u) R[u].x = j + 1;
     }
 }
 
@@ -1395,7 +1401,7 @@ int launch_bin_sort(const gs_splats& sp, int64_t n, const gs_layout& L, const gs
     const unsigned gm = (unsigned)std::max<int64_t>((m + 255) / 256, 1);
     // status cleared, tile rows and depth keys per (view, Gaussian)
     hipLaunchKernelGGL(k_row_count, dim3(gm), dim3(256), 0, s, rec, sp.tiles, n, m, eg, W.row_count, b.status,
-                       W.dkey, W.dval, W.dtable, SD.dcount, V);
+                       W.dkey, W.dval, W.dtable, SD.dcount, V, depth_first);
     if ((rc = check_launch("row_count")) != GS_OK) return rc;
     // the caller's side stream, if any, takes the depth order
     const bool forked = depth_first && side != nullptr;
@@ -1461,9 +1467,8 @@ int launch_bin_sort(const gs_splats& sp, int64_t n, const gs_layout& L, const gs
     }
     if ((rc = radix_sort_views<kSortItems>(ek, ev, ok, ov, W.table, V, S, b.status, s)) != GS_OK) return rc;
     const int64_t nt = L.tile_base[V];
-    const int64_t rgrid = (b.capacity + 255) / 256 + (nt + 255) / 256;
-    hipLaunchKernelGGL(k_ranges, dim3((unsigned)rgrid), dim3(256), 0, s, b.keys, W.table, V, rg, b.capacity,
-                       b.ranges);
+    const int64_t rgrid = std::max<int64_t>(1, std::min<int64_t>((std::max(b.capacity, nt) + 255) / 256, kRangeBlocks));
+    hipLaunchKernelGGL(k_ranges, dim3((unsigned)rgrid), dim3(256), 0, s, b.keys, W.table, V, rg, b.ranges);
     return check_launch("ranges");
 }
 

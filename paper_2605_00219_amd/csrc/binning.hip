@@ -28,7 +28,7 @@ constexpr int64_t kDepthFirstRatio = 12;                // capacity / (views x n
 constexpr int kDepthSplit = 16;                          // key bits sorted per Gaussian in the depth order
 constexpr int kDigits = 256;
 constexpr int kPasses = 4;
-constexpr int kHistBlocks = 512;                        // workgroups of the histogram pass
+constexpr int kHistBlocks = 2048;                       // workgroups of the histogram pass
 constexpr int kGroup = 16;                              // chunks per look-back group
 // single-pass tile scatter (depth order first, every view with at most
 // kTsBins tiles): chunks of kTsChunk keys in depth order
@@ -949,12 +949,26 @@ struct RangeGeom {
 };
 
 // Tile boundaries -> ranges (lower-bound semantics, empty tiles get start =
-// end = insertion point), a grid-stride loop over sorted positions (one
-// position per thread per round: a launch of one workgroup per 256 positions
-// was bound by the workgroup dispatch rate at 10^8 keys), after which the
-// same threads give the tiles of views without any intersection their empty
-// range.
-constexpr int kRangeBlocks = 4096;
+// end = insertion point): a grid-stride loop in which each thread takes four
+// consecutive sorted positions (one 16-byte load and the key before them);
+// one workgroup per 256 positions was bound by the workgroup dispatch rate at
+// 10^8 keys.  Then the same threads give the tiles of views without any
+// intersection their empty range.
+constexpr int kRangeBlocks = 16384;
+
+GS_DEV void range_bounds(uint2* R, int nt, uint32_t j, int t, int tp, bool first, bool last) {
+    if (first) {
+        for (int u = 0; u <= t; ++u) R[u].x = j;
+        for (int u = 0; u < t; ++u) R[u].y = j;
+    } else if (tp != t) {
+        for (int u = tp + 1; u <= t; ++u) R[u].x = j;
+        for (int u = tp; u < t; ++u) R[u].y = j;
+    }
+    if (last) {
+        for (int u = t; u < nt; ++u) R[u].y = j + 1;
+        for (int u = t + 1; u < nt; ++u) R[u].x = j + 1;
+    }
+}
 
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ keys,
                                                 const uint32_t* __restrict__ table, int n_views,
@@ -962,30 +976,30 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t first = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t total = table[4 * (n_views - 1) + 1];   // the views' segments are consecutive
-    for (int64_t j64 = first; j64 < (int64_t)total; j64 += stride) {
-        const uint32_t j = (uint32_t)j64;
-        int v = 0;
-        for (int i = 1; i < n_views; ++i)
-            if (j >= table[4 * i]) v = i;
-        const uint32_t sb = table[4 * v], se = table[4 * v + 1];
-        const int D = geo.depth_bits[v];
-        const int tb = geo.tile_base[v];
-        const int nt = geo.tile_base[v + 1] - tb;
-        uint2* R = reinterpret_cast<uint2*>(ranges) + tb;
-        const int t = min((int)(keys[j] >> D), nt - 1);
-        if (j == sb) {
-            for (int u = 0; u <= t; ++u) R[u].x = j;
-            for (int u = 0; u < t; ++u) R[u].y = j;
+    for (int64_t q = first; 4 * q < (int64_t)total; q += stride) {
+        const uint32_t j0 = (uint32_t)(4 * q);
+        uint32_t k[4];
+        if (j0 + 4 <= total) {
+            const uint4 x = reinterpret_cast<const uint4*>(keys)[q];
+            k[0] = x.x; k[1] = x.y; k[2] = x.z; k[3] = x.w;
         } else {
-            const int tp = min((int)(keys[j - 1] >> D), nt - 1);
-            if (tp != t) {
-                for (int u = tp + 1; u <= t; ++u) R[u].x = j;
-                for (int u = tp; u < t; ++u) R[u].y = j;
-            }
+            for (int u = 0; u < 4; ++u) k[u] = j0 + u < total ? keys[j0 + u] : 0u;
         }
-        if (j == se - 1) {
-            for (int u = t; u < nt; ++u) R[u].y = j + 1;
-            for (int u = t + 1; u < nt; ++u) R[u].x = j + 1;
+        const uint32_t kp = j0 > 0 ? keys[j0 - 1] : 0u;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t j = j0 + (uint32_t)u;
+            if (j >= total) break;
+            int v = 0;
+            for (int i = 1; i < n_views; ++i)
+                if (j >= table[4 * i]) v = i;
+            const uint32_t sb = table[4 * v], se = table[4 * v + 1];
+            const int D = geo.depth_bits[v];
+            const int tb = geo.tile_base[v];
+            const int nt = geo.tile_base[v + 1] - tb;
+            const int t = min((int)(k[u] >> D), nt - 1);
+            const int tp = j == sb ? 0 : min((int)((u > 0 ? k[u - 1] : kp) >> D), nt - 1);
+            range_bounds(reinterpret_cast<uint2*>(ranges) + tb, nt, j, t, tp, j == sb, j == se - 1);
         }
     }
     for (int64_t gt = first; gt < (int64_t)geo.tile_base[n_views]; gt += stride) {
@@ -1467,7 +1481,8 @@ int launch_bin_sort(const gs_splats& sp, int64_t n, const gs_layout& L, const gs
     }
     if ((rc = radix_sort_views<kSortItems>(ek, ev, ok, ov, W.table, V, S, b.status, s)) != GS_OK) return rc;
     const int64_t nt = L.tile_base[V];
-    const int64_t rgrid = std::max<int64_t>(1, std::min<int64_t>((std::max(b.capacity, nt) + 255) / 256, kRangeBlocks));
+    const int64_t rgrid =
+        std::max<int64_t>(1, std::min<int64_t>((std::max(b.capacity / 4, nt) + 255) / 256, kRangeBlocks));
     hipLaunchKernelGGL(k_ranges, dim3((unsigned)rgrid), dim3(256), 0, s, b.keys, W.table, V, rg, b.ranges);
     return check_launch("ranges");
 }

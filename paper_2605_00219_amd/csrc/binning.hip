@@ -200,6 +200,46 @@ GS_DEV void scan_store(const ScanIO& io, int64_t i, uint32_t x) {
     }
 }
 
+// A block's kScanBlock elements, kScanItems consecutive per thread: loaded
+// (two 16-byte loads per thread when the block is whole and the arrays are
+// 16-byte aligned, which the direct, in-order case allows), scanned across the
+// block from `carry`, and stored.  Returns the block's total in *tot.
+static_assert(kScanItems == 8, "two 16-byte vectors per thread");
+GS_DEV void scan_block(const ScanIO& io, int64_t len, int64_t base, uint64_t carry, uint64_t* lds,
+                       uint64_t* tot) {
+    const int64_t i0 = base + (int64_t)threadIdx.x * kScanItems;
+    const bool vec = !io.perm && base + kScanBlock <= len &&
+                     ((reinterpret_cast<uintptr_t>(io.in) | reinterpret_cast<uintptr_t>(io.out)) & 15u) == 0;
+    uint32_t v[kScanItems];
+    if (vec) {
+        const uint4 a = reinterpret_cast<const uint4*>(io.in + i0)[0];
+        const uint4 b = reinterpret_cast<const uint4*>(io.in + i0)[1];
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } else {
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) v[i] = i0 + i < len ? scan_load(io, i0 + i) : 0u;
+    }
+    uint64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) s += v[i];
+    const uint64_t inc = block_scan_u64(s, lds, tot);
+    uint64_t run = carry + inc - s;
+    uint32_t o[kScanItems];
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        o[i] = (uint32_t)run;
+        run += v[i];
+    }
+    if (vec) {
+        reinterpret_cast<uint4*>(io.out + i0)[0] = make_uint4(o[0], o[1], o[2], o[3]);
+        reinterpret_cast<uint4*>(io.out + i0)[1] = make_uint4(o[4], o[5], o[6], o[7]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i)
+            if (i0 + i < len) scan_store(io, i0 + i, o[i]);
+    }
+}
+
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(ScanIO io, int64_t len,
                                                               uint64_t* __restrict__ sums) {
     __shared__ uint64_t lds[kScanThreads / kWave];
@@ -240,24 +280,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(ScanIO io, int64_t l
                                                             int64_t nb) {
     __shared__ uint64_t lds[kScanThreads / kWave];
     const int64_t base = (int64_t)blockIdx.x * kScanBlock;
-    // each thread owns kScanItems consecutive elements
-    uint32_t v[kScanItems];
-    uint64_t s = 0;
-#pragma unroll
-    for (int i = 0; i < kScanItems; ++i) {
-        const int64_t idx = base + (int64_t)threadIdx.x * kScanItems + i;
-        v[i] = idx < len ? scan_load(io, idx) : 0u;
-        s += v[i];
-    }
     uint64_t tot;
-    const uint64_t inc = block_scan_u64(s, lds, &tot);
-    uint64_t run = sums[blockIdx.x] + inc - s;
-#pragma unroll
-    for (int i = 0; i < kScanItems; ++i) {
-        const int64_t idx = base + (int64_t)threadIdx.x * kScanItems + i;
-        if (idx < len) scan_store(io, idx, (uint32_t)run);
-        run += v[i];
-    }
+    scan_block(io, len, base, sums[blockIdx.x], lds, &tot);
     if (!io.perm && blockIdx.x == 0 && threadIdx.x == 0) io.out[len] = (uint32_t)sums[nb];
 }
 
@@ -275,23 +299,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down_inline(ScanIO io, in
     for (int64_t i = threadIdx.x; i < (int64_t)blockIdx.x; i += kScanThreads) carry += sums[i];
     carry = block_reduce_u64(carry, lds);
     const int64_t base = (int64_t)blockIdx.x * kScanBlock;
-    uint32_t v[kScanItems];
-    uint64_t s = 0;
-#pragma unroll
-    for (int i = 0; i < kScanItems; ++i) {
-        const int64_t idx = base + (int64_t)threadIdx.x * kScanItems + i;
-        v[i] = idx < len ? scan_load(io, idx) : 0u;
-        s += v[i];
-    }
     uint64_t tot;
-    const uint64_t inc = block_scan_u64(s, lds, &tot);
-    uint64_t run = carry + inc - s;
-#pragma unroll
-    for (int i = 0; i < kScanItems; ++i) {
-        const int64_t idx = base + (int64_t)threadIdx.x * kScanItems + i;
-        if (idx < len) scan_store(io, idx, (uint32_t)run);
-        run += v[i];
-    }
+    scan_block(io, len, base, carry, lds, &tot);
     if (blockIdx.x == nb - 1 && threadIdx.x == 0) {
         const uint64_t total = carry + tot;
         if (!io.perm) io.out[len] = (uint32_t)total;
@@ -408,7 +417,8 @@ __global__ __launch_bounds__(256) void k_row_count(const float4* __restrict__ re
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= m) return;
     const bool vis = tiles[o] > 0;
-    const float4 q3 = rec[4 * o + 3];
+    // records of Gaussians outside the view are not read
+    const float4 q3 = vis ? rec[4 * o + 3] : make_float4(0.f, 0.f, 0.f, 0.f);
     row_count[o] = vis ? rect_rows(q3) : 0u;
     if (!depth_keys) return;   // no depth order in this call
     const int v = (int)(o / n);

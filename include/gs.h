@@ -227,7 +227,7 @@ size_t gs_bin_sort_workspace_size(int64_t n, const gs_layout* layout, int64_t ca
 
 /* Bytes of scratch (gs_grads2d.workspace) that gs_project_bwd_adam needs for
  * the given intersection capacity: none (0); the per-Gaussian record sums are
- * formed in LDS inside its kernel. */
+ * formed in LDS. */
 size_t gs_grads2d_workspace_size(int64_t capacity);
 
 /* A second stream a call may run independent work on, with the two events

@@ -1,4 +1,4 @@
-// Projection backward fused with Adam, one kernel.
+// Projection backward fused with Adam, in two kernels.
 //
 // Record sums: the backward rasteriser wrote one screen-space gradient record
 // per composited intersection at its unsorted index and flagged it in a bit
@@ -8,8 +8,8 @@
 // indices into LDS, and sums each batch of 64 flagged records per owner with
 // a segmented scan across lanes (owners ascend with the index); each run's
 // total is added to its owner's accumulator in LDS, batch after batch, so the
-// order of every sum is fixed.  The sums also go to a dense [9][views * n]
-// array for the caller.
+// order of every sum is fixed.  The sums go to a dense [9][views * n] array,
+// which the chain-rule kernel reads (and the caller may).
 //
 // Chain rule + Adam: one thread per Gaussian streams its parameter record and
 // both Adam moments once, and writes parameters and moments once.  No
@@ -38,22 +38,14 @@ size_t gather_workspace(int64_t) { return 0; }
 constexpr int kAdamThreads = 256;
 constexpr int kAdamWaves = kAdamThreads / kWave;
 
-// Sums over the flagged records of (view vi, Gaussian g0 + lane) for the
-// wavefront's 64 Gaussians [g0, g0 + 64) (lanes past n take part with an
-// empty range).  s_idx: 128 words, s_acc: 9 x 64 floats, both this
-// wavefront's own.
-GS_DEV void wave_record_sums(const RecArgs& r, int64_t n, int vi, int64_t g0, int lane, bool live,
-                             uint32_t* s_idx, float* s_acc, float d[9]) {
-    const uint64_t cap = (uint64_t)r.capacity;
-    const int64_t o = (int64_t)vi * n + g0 + lane;
-    uint32_t ob = 0, oe = 0;
-    if (live) {
-        ob = (uint32_t)min((uint64_t)r.offsets[o], cap);
-        oe = (uint32_t)min((uint64_t)r.offsets[o + 1], cap);
-    }
-    const int nlive = __popcll(__ballot(live));
-    const uint32_t R0 = (uint32_t)__shfl((int)ob, 0), R1 = (uint32_t)__shfl((int)oe, nlive - 1);
-    const uint32_t own0 = (uint32_t)((int64_t)vi * n + g0);
+// Sums over the flagged records of (view, Gaussian own0 + lane) for the
+// wavefront's 64 Gaussians, whose records occupy the index range [R0, R1)
+// (lanes past n own nothing); `mine` is the range's mask word R0 / 32 + lane,
+// loaded by the caller together with the other views' (a range of more than
+// 64 words loads the rest here).  s_idx: 128 words, s_acc: 9 x 64 floats,
+// both this wavefront's own.
+GS_DEV void wave_record_sums(const RecArgs& r, uint32_t own0, uint32_t R0, uint32_t R1, uint32_t mine,
+                             int lane, uint32_t* s_idx, float* s_acc, float d[9]) {
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
     for (int c = 0; c < 9; ++c) s_acc[c * kWave + lane] = 0.0f;
@@ -96,11 +88,11 @@ GS_DEV void wave_record_sums(const RecArgs& r, int64_t n, int vi, int64_t g0, in
     };
     int cnt = 0;
     if (R1 > R0) {
-        // the range's mask words, 64 at a time (one per lane, loaded together),
-        // then 64 indices (two words) per step
+        // 64 mask words at a time (one per lane), then 64 indices (two words)
+        // per step
         const uint32_t wlast = (R1 - 1) >> 5;
         for (uint32_t wb = R0 >> 5; wb <= wlast; wb += kWave) {
-            const uint32_t mine = wb + (uint32_t)lane <= wlast ? r.rec_mask[wb + lane] : 0u;
+            if (wb != (R0 >> 5)) mine = wb + (uint32_t)lane <= wlast ? r.rec_mask[wb + lane] : 0u;
             const uint32_t nw = min((uint32_t)kWave, wlast - wb + 1);
             for (uint32_t k = 0; k < nw; k += 2) {
                 const uint32_t idx = (wb + k) * 32u + (uint32_t)lane;
@@ -122,6 +114,61 @@ GS_DEV void wave_record_sums(const RecArgs& r, int64_t n, int vi, int64_t g0, in
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int c = 0; c < 9; ++c) d[c] = s_acc[c * kWave + lane];
+}
+
+// views whose index ranges and first mask words are loaded together
+constexpr int kViewGroup = 4;
+
+// One wavefront per 64 consecutive Gaussians: their record sums in every view,
+// to sums (every (view, Gaussian), zero where nothing was flagged).  A kernel
+// of its own: beside the float64 chain rule (256 VGPRs, two wavefronts per
+// SIMD) the walks and scans run with too little latency hiding at 8 views.
+__global__ __launch_bounds__(kAdamThreads) void k_record_sums(RecArgs r, int64_t n, int n_views) {
+    __shared__ uint32_t s_idx[kAdamWaves][2 * kWave];
+    __shared__ float s_acc[kAdamWaves][9 * kWave];
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+    const int64_t g0 = (int64_t)blockIdx.x * kAdamThreads + wv * kWave;
+    if (g0 >= n) return;                    // whole wavefronts only
+    const int64_t g = g0 + lane;
+    const bool live = g < n;
+    const int64_t vn = (int64_t)n_views * n;
+    const int nlive = __popcll(__ballot(live));
+    const uint64_t cap = (uint64_t)r.capacity;
+    for (int v0 = 0; v0 < n_views; v0 += kViewGroup) {
+        // the ranges and first mask words of kViewGroup views, loaded together
+        uint32_t R0[kViewGroup], R1[kViewGroup], mine[kViewGroup];
+#pragma unroll
+        for (int j = 0; j < kViewGroup; ++j) {
+            uint32_t ob = 0, oe = 0;
+            if (live && v0 + j < n_views) {
+                const int64_t o = (int64_t)(v0 + j) * n + g;
+                ob = (uint32_t)min((uint64_t)r.offsets[o], cap);
+                oe = (uint32_t)min((uint64_t)r.offsets[o + 1], cap);
+            }
+            // offsets ascend with the Gaussian: lane 0's start to the last
+            // live lane's end
+            R0[j] = (uint32_t)__shfl((int)ob, 0);
+            R1[j] = (uint32_t)__shfl((int)oe, nlive - 1);
+        }
+#pragma unroll
+        for (int j = 0; j < kViewGroup; ++j) {
+            const uint32_t w0 = R0[j] >> 5;
+            mine[j] = R1[j] > R0[j] && w0 + (uint32_t)lane <= ((R1[j] - 1) >> 5) ? r.rec_mask[w0 + lane] : 0u;
+        }
+#pragma unroll 1
+        for (int j = 0; j < kViewGroup && v0 + j < n_views; ++j) {
+            uint32_t r0 = R0[0], r1 = R1[0], mw = mine[0];
+#pragma unroll
+            for (int q = 1; q < kViewGroup; ++q)
+                if (j == q) { r0 = R0[q]; r1 = R1[q]; mw = mine[q]; }
+            float d[9];
+            wave_record_sums(r, (uint32_t)((int64_t)(v0 + j) * n + g0), r0, r1, mw, lane, s_idx[wv], s_acc[wv], d);
+            if (live) {
+#pragma unroll
+                for (int c = 0; c < 9; ++c) r.sums[c * vn + (int64_t)(v0 + j) * n + g] = d[c];
+            }
+        }
+    }
 }
 
 struct AdamArgs {
@@ -180,26 +227,10 @@ GS_DEV float adam_one(float p, float g, float& m, float& v, float step, float be
 }
 
 __global__ __launch_bounds__(kAdamThreads, 2) void k_project_bwd_adam(AdamArgs a) {
-    __shared__ uint32_t s_idx[kAdamWaves][2 * kWave];
-    __shared__ float s_acc[kAdamWaves][9 * kWave];
     const int64_t n = a.n;
-    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
-    const int64_t g0 = (int64_t)blockIdx.x * kAdamThreads + wv * kWave;
-    if (g0 >= n) return;                    // whole wavefronts only
-    const int64_t g = g0 + lane;
-    const bool live = g < n;
+    const int64_t g = (int64_t)blockIdx.x * kAdamThreads + threadIdx.x;
+    if (g >= n) return;
     const int64_t vn = (int64_t)a.n_views * n;
-    // per-view record sums first (to sums; read back below), so that their
-    // registers and the chain rule's are never live together
-    for (int vi = 0; vi < a.n_views; ++vi) {
-        float d[9];
-        wave_record_sums(a.rec, n, vi, g0, lane, live, s_idx[wv], s_acc[wv], d);
-        if (live) {
-#pragma unroll
-            for (int c = 0; c < 9; ++c) a.rec.sums[c * vn + (int64_t)vi * n + g] = d[c];
-        }
-    }
-    if (!live) return;
     const float4 p0 = a.params[0 * n + g];
     const float4 p1 = a.params[1 * n + g];
     const float4 p2 = a.params[2 * n + g];
@@ -473,6 +504,10 @@ int launch_project_bwd_adam(float* params, int64_t n, const gs_view* views, cons
         if (rc != GS_OK) return rc;
     }
     a.rec = ra;
+    hipLaunchKernelGGL(k_record_sums, dim3((unsigned)((n + kAdamThreads - 1) / kAdamThreads)), dim3(kAdamThreads),
+                       0, s, ra, n, L.n_views);
+    rc = check_launch("record_sums");
+    if (rc != GS_OK) return rc;
     hipLaunchKernelGGL(k_project_bwd_adam, dim3((unsigned)((n + kAdamThreads - 1) / kAdamThreads)),
                        dim3(kAdamThreads), 0, s, a);
     return check_launch("project_bwd_adam");

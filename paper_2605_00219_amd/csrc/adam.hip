@@ -123,9 +123,19 @@ constexpr int kViewGroup = 4;
 // to sums (every (view, Gaussian), zero where nothing was flagged).  A kernel
 // of its own: beside the float64 chain rule (256 VGPRs, two wavefronts per
 // SIMD) the walks and scans run with too little latency hiding at 8 views.
-__global__ __launch_bounds__(kAdamThreads) void k_record_sums(RecArgs r, int64_t n, int n_views) {
+// Its first thread also advances the Adam step (when `step` is set): step +=
+// 1, bias[0] = 1 - beta1^t, bias[1] = sqrt(1 - beta2^t), for the chain-rule
+// kernel that follows.
+__global__ __launch_bounds__(kAdamThreads) void k_record_sums(RecArgs r, int64_t n, int n_views, int32_t* step,
+                                                              float* bias, float beta1, float beta2) {
     __shared__ uint32_t s_idx[kAdamWaves][2 * kWave];
     __shared__ float s_acc[kAdamWaves][9 * kWave];
+    if (step && blockIdx.x == 0 && threadIdx.x == 0) {
+        const int t = *step + 1;
+        *step = t;
+        bias[0] = (float)(1.0 - pow((double)beta1, (double)t));
+        bias[1] = (float)sqrt(1.0 - pow((double)beta2, (double)t));
+    }
     const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
     const int64_t g0 = (int64_t)blockIdx.x * kAdamThreads + wv * kWave;
     if (g0 >= n) return;                    // whole wavefronts only
@@ -449,15 +459,6 @@ __global__ __launch_bounds__(kAdamThreads, 2) void k_project_bwd_adam(AdamArgs a
     }
 }
 
-// step += 1; bias[0] = 1 - beta1^t, bias[1] = sqrt(1 - beta2^t)
-__global__ void k_adam_tick(int32_t* step, float* bias, float beta1, float beta2) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const int t = *step + 1;
-    *step = t;
-    bias[0] = (float)(1.0 - pow((double)beta1, (double)t));
-    bias[1] = (float)sqrt(1.0 - pow((double)beta2, (double)t));
-}
-
 // The no-allocation entry point: the projection backward needs no scratch at
 // all (the record sums live in LDS), so it is the same launch.
 int launch_project_bwd_adam_noalloc(float* params, int64_t n, const gs_view* views, const gs_layout& L,
@@ -498,14 +499,11 @@ int launch_project_bwd_adam(float* params, int64_t n, const gs_view* views, cons
         a.beta1 = adam->beta1;
         a.beta2 = adam->beta2;
         a.eps = adam->eps;
-        hipLaunchKernelGGL(k_adam_tick, dim3(1), dim3(64), 0, s, adam->step, adam->scratch, adam->beta1,
-                           adam->beta2);
-        rc = check_launch("adam_tick");
-        if (rc != GS_OK) return rc;
     }
     a.rec = ra;
     hipLaunchKernelGGL(k_record_sums, dim3((unsigned)((n + kAdamThreads - 1) / kAdamThreads)), dim3(kAdamThreads),
-                       0, s, ra, n, L.n_views);
+                       0, s, ra, n, L.n_views, adam ? adam->step : nullptr, adam ? adam->scratch : nullptr,
+                       adam ? adam->beta1 : 0.0f, adam ? adam->beta2 : 0.0f);
     rc = check_launch("record_sums");
     if (rc != GS_OK) return rc;
     hipLaunchKernelGGL(k_project_bwd_adam, dim3((unsigned)((n + kAdamThreads - 1) / kAdamThreads)),

@@ -461,6 +461,30 @@ def test_empty_scene_and_culled_gaussians():
     assert np.all(g["grads"] == 0)
 
 
+@pytest.mark.parametrize("order", ["direct", "depth_first"])
+def test_binning_with_a_view_that_sees_nothing(order):
+    """Three views, the middle one looking away from the scene (no
+    intersection): keys, values and every tile range bit-exact, through the
+    direct 32-bit sort and k_ranges (capacity under 12 intersections per
+    (view, Gaussian)) and through the depth order and the tile partition."""
+    scene = WL["plain-2k-256"][0]
+    views = S.views_array([S.make_view(256, 256, (0.0, 0.0, -5.0)),
+                           S.make_view(128, 96, (0.0, 0.0, -4.0), target=(0.0, 0.0, -10.0)),
+                           S.make_view(192, 160, (3.0, 1.0, -4.0))])
+    note(f"binning, 3 views with an empty one, {order} order")
+    pr = oracle.project(scene, views, 16)
+    bins = oracle.bin_sort(pr, views, 16)
+    assert pr.tiles[1].sum() == 0 and pr.tiles[0].sum() > 0 and pr.tiles[2].sum() > 0
+    K, m = int(bins.offsets[-1]), 3 * scene.n
+    capacity = K + 1024 if order == "direct" else 12 * m + 1024
+    assert (capacity < 12 * m) == (order == "direct")
+    g = run_gpu_step(scene, views, 16, capacity=capacity)
+    assert g["status"] == 0 and g["K"] == K
+    np.testing.assert_array_equal(g["keys"], bins.keys[:K])
+    np.testing.assert_array_equal(g["vals"], bins.gid[bins.vals[:K]])
+    np.testing.assert_array_equal(g["ranges"], bins.ranges)
+
+
 def test_capacity_overflow_is_reported_and_recovered():
     import torch
     from paper_2605_00219_amd import pipeline as P

@@ -407,7 +407,7 @@ def test_thompson_scheduled_backward_trains_the_same_bits():
         model = P.Model(scene.flat())
         frame = P.Frame(scene.n, [int(v["width"]) for v in views], [int(v["height"]) for v in views], tile)
         P.fit_capacity(model.params, frame, vd)
-        sbwd = P.ScheduledBackward((64, 128, 256, -128), seed=2, prior_ms=0.05) if scheduled else None
+        sbwd = P.ScheduledBackward((64, 128, 256, -128), seed=2, prior_ms=0.05, time_every=1) if scheduled else None
         for _ in range(6):
             P.project(model.params, frame, vd)
             P.bin_sort(frame)

@@ -616,6 +616,9 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd(RasterArgs a)
                           v7 = 0.f, v8 = 0.f;
 #pragma unroll
                     for (int q = 0; q < PPT; ++q) {
+                        // a pixel slot where no lane composites this Gaussian
+                        // adds nothing (alpha 0: T and R unchanged)
+                        if (PPT > 1 && __ballot(cq[q]) == 0ull) continue;
                         // pixels that do not composite this Gaussian use alpha = 0
                         const float ae = cq[q] ? alq[q] : 0.0f;
                         const float wgt = ae * T[q];

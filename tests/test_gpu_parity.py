@@ -494,6 +494,26 @@ def test_binning_with_a_view_that_sees_nothing(order):
     np.testing.assert_array_equal(g["ranges"], bins.ranges)
 
 
+def test_depth_first_order_with_long_tile_lists():
+    """The depth order and the tile partition with a few long lists: 6000
+    Gaussians clustered on the centre of a 128x128 view give four tiles of
+    about 5000-6000 entries; keys, values and ranges bit-exact."""
+    scene = S.scene_normal(6000, 9300, log_scale_mean=-3.5, log_scale_std=0.3)
+    scene.means[:] = (scene.means * np.float32(0.05)).astype(np.float32)
+    views = S.views_array([S.make_view(128, 128, (0.0, 0.0, -4.0))])
+    note("depth order, tile lists past 4096 entries")
+    pr = oracle.project(scene, views, 16)
+    bins = oracle.bin_sort(pr, views, 16)
+    K = int(bins.offsets[-1])
+    lens = np.diff(bins.ranges.reshape(-1, 2), axis=1)
+    assert lens.max() > 4096
+    g = run_gpu_step(scene, views, 16, capacity=12 * scene.n + 1024)
+    assert g["status"] == 0 and g["K"] == K
+    np.testing.assert_array_equal(g["keys"], bins.keys[:K])
+    np.testing.assert_array_equal(g["vals"], bins.gid[bins.vals[:K]])
+    np.testing.assert_array_equal(g["ranges"], bins.ranges)
+
+
 def test_capacity_overflow_is_reported_and_recovered():
     import torch
     from paper_2605_00219_amd import pipeline as P

@@ -1245,10 +1245,13 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_scatter(const uint32_t* __res
         return peers;
     };
     __syncthreads();
-    // 1. counts per (wavefront, tile)
+    // 1. counts per (wavefront, tile), and each key's tile and rank among the
+    // wavefront's earlier keys of that tile, kept in registers for step 3
+    uint32_t tr[ITEMS];                          // tile << 16 | rank
     {
         uint32_t kc[KB], kn[KB];
         load_block(0, kn);
+#pragma unroll
         for (int i0 = 0; i0 < ITEMS; i0 += KB) {
             if (i0 * kWave >= nv) break;
 #pragma unroll
@@ -1259,8 +1262,10 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_scatter(const uint32_t* __res
                 const bool valid = (i0 + u) * kWave + lane < nv;
                 const uint32_t tile = (uint32_t)min((int)(kc[u] >> D), nt - 1);
                 const uint64_t peers = peers_of(tile, valid);
-                if (valid && (peers & lt) == 0ull)
-                    cnt[w][tile] = (uint16_t)(cnt[w][tile] + (uint32_t)__popcll(peers));
+                const uint64_t before = peers & lt;
+                const uint32_t base = cnt[w][tile];
+                tr[i0 + u] = (tile << 16) | (base + (uint32_t)__popcll(before));
+                if (valid && before == 0ull) cnt[w][tile] = (uint16_t)(base + (uint32_t)__popcll(peers));
             }
         }
     }
@@ -1295,29 +1300,12 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_scatter(const uint32_t* __res
         }
     }
     __syncthreads();
-    // 3. sorted position of every key
-    {
-        uint32_t kc[KB], kn[KB];
-        load_block(0, kn);
-        for (int i0 = 0; i0 < ITEMS; i0 += KB) {
-            if (i0 * kWave >= nv) break;
+    // 3. sorted position of every key: its (wavefront, tile) start plus its
+    // rank from step 1 (no ballots, no dependence between keys)
 #pragma unroll
-            for (int u = 0; u < KB; ++u) kc[u] = kn[u];
-            if (i0 + KB < ITEMS) load_block(i0 + KB, kn);
-#pragma unroll
-            for (int u = 0; u < KB; ++u) {
-                const int r = (i0 + u) * kWave + lane;
-                const bool valid = r < nv;
-                const uint32_t tile = (uint32_t)min((int)(kc[u] >> D), nt - 1);
-                const uint64_t peers = peers_of(tile, valid);
-                const uint64_t before = peers & lt;
-                const uint32_t base = cnt[w][tile];
-                if (valid) {
-                    perm[base + (uint32_t)__popcll(before)] = (uint16_t)(wbeg + r);
-                    if (before == 0ull) cnt[w][tile] = (uint16_t)(base + (uint32_t)__popcll(peers));
-                }
-            }
-        }
+    for (int i = 0; i < ITEMS; ++i) {
+        const int r = i * kWave + lane;
+        if (r < nv) perm[cnt[w][tr[i] >> 16] + (tr[i] & 0xFFFFu)] = (uint16_t)(wbeg + r);
     }
     __syncthreads();
 #pragma unroll

@@ -744,6 +744,12 @@ constexpr int kLbGroupWindow = 8;
 // lines) two workgroups fit on a CU (LDS); 4096-key chunks, four per CU,
 // took 7% longer on 1.6e8 keys.  (The depth sort's 1024-key chunks keep the
 // 128-VGPR bound.)
+// A key's rank: its group's base, held by the group's first lane, plus its
+// rank in the group (lead: that lane, then the rank, from bit 8).
+GS_DEV uint32_t finish_rank(uint32_t base, uint32_t lead) {
+    return (uint32_t)__shfl((int)base, (int)(lead & 0x3Fu)) + (lead >> 8);
+}
+
 template <int ITEMS>
 __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_onesweep(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
@@ -753,9 +759,12 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4)
     constexpr int NW = kSortThreads / kWave;
     constexpr int CHUNK = ITEMS * kSortThreads;
     constexpr int PER_WAVE = CHUNK / NW;
+    static_assert(PER_WAVE < 65536, "ranks packed in 16 bits");
+    constexpr int kLag = ITEMS < 4 ? ITEMS : 4;
     __shared__ uint32_t gbase[kDigits];   // global destination of the chunk's first key of digit d
     __shared__ uint32_t lstart[kDigits];  // chunk-local start of digit d
     __shared__ uint32_t wcnt[NW][kDigits];
+    __shared__ uint32_t s_nop[kSortThreads];   // target of the non-leading lanes' atomics
     __shared__ uint32_t s_k[CHUNK];
     __shared__ uint32_t s_v[CHUNK];
     __shared__ uint64_t s_scan[NW];
@@ -771,7 +780,7 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4)
     const uint32_t seg_e = table[4 * v + 1];
     const uint32_t start = table[4 * v] + c * CHUNK;
     const uint32_t n_here = min((uint32_t)CHUNK, seg_e - start);
-    uint32_t k[ITEMS], val[ITEMS], rank[ITEMS];
+    uint32_t k[ITEMS], val[ITEMS], rank[ITEMS], lead[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t idx = start + w * PER_WAVE + i * kWave + lane;
@@ -795,12 +804,25 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4)
             peers &= set ? m : ~m;
         }
         const uint64_t before = peers & lt;
-        const uint32_t base = valid ? wcnt[w][d] : 0u;
-        rank[i] = base + (uint32_t)__popcll(before);
-        // the first lane of each digit group advances the wavefront's count
-        // (after every lane of the group has read it: same wavefront, in order)
-        if (valid && before == 0ull) wcnt[w][d] = base + (uint32_t)__popcll(peers);
+        // the first lane of each digit group takes the wavefront's count and
+        // advances it in one LDS atomic; a wavefront's LDS operations complete
+        // in issue order, so item i + 1's atomics need not wait for item i's
+        // result
+        // (packed: the base in the low 16 bits, counts per wavefront being at
+        // most PER_WAVE; the group's first lane above, then the key's rank in
+        // its group)
+        // (every lane issues the atomic, the others adding 0 to a slot of
+        // their own: without a branch the compiler waits for each result
+        // only where it is used)
+        const bool first = valid && before == 0ull;
+        rank[i] = atomicAdd(first ? &wcnt[w][d] : &s_nop[threadIdx.x], first ? (uint32_t)__popcll(peers) : 0u);
+        lead[i] = valid ? (uint32_t)__builtin_ctzll(peers) | ((uint32_t)__popcll(before) << 8) : 0u;
+        // every key's rank: its group's base from the group's first lane,
+        // kLag items later (by then the atomic has returned)
+        if (i >= kLag) rank[i - kLag] = finish_rank(rank[i - kLag], lead[i - kLag]);
     }
+#pragma unroll
+    for (int i = ITEMS - kLag; i < ITEMS; ++i) rank[i] = finish_rank(rank[i], lead[i]);
     __syncthreads();
     const uint32_t d = threadIdx.x;
     const int64_t cw = (int64_t)pass * S.max_chunks * kDigits;   // this pass's chunk words
@@ -1191,6 +1213,7 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_scatter(const uint32_t* __res
     uint32_t* bml = reinterpret_cast<uint32_t*>(&cnt[0][0]);
     __shared__ uint16_t perm[kTsChunk];          // sorted position -> input position
     __shared__ uint8_t s_own[NW][kTsBins];       // per wavefront: a lane that holds the tile
+    __shared__ uint32_t s_nop[kTsThreads];       // target of the non-leading lanes' atomics
     __shared__ uint64_t s_scan[NW];
     int v;
     uint32_t c;
@@ -1227,14 +1250,15 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_scatter(const uint32_t* __res
     // peers of this lane's tile among the valid lanes.  Usually the 64 keys
     // of a step hold 64 different tiles (consecutive keys in depth order are
     // a few Gaussians' tile sets): every lane writes its id at its tile and
-    // reads it back, and if no lane finds another's id, each lane is its own
-    // only peer; otherwise 12 ballots find the peers.  (Volatile: the read
-    // must see the other lanes' writes, not the compiler's copy of its own.)
-    volatile uint8_t* own = s_own[w];
+    // reads it back, and if no valid lane finds another's id, each lane is
+    // its own only peer; otherwise 12 ballots find the peers.  The writes and
+    // reads of a block of steps are issued back to back (a step's read may
+    // also see a later step's write: that can only make a step take the
+    // ballots, never hide a duplicate, since two lanes reading one byte read
+    // one value).  Relaxed atomic LDS accesses: the read must see the other
+    // lanes' writes, not the compiler's copy of its own.
+    uint8_t* own = s_own[w];
     auto peers_of = [&](uint32_t tile, bool valid) -> uint64_t {
-        if (valid) own[tile] = (uint8_t)lane;
-        const bool dup = valid && own[tile] != (uint8_t)lane;
-        if (__ballot(dup) == 0ull) return valid ? (uint64_t)1 << lane : (uint64_t)0;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int bit = 0; bit < 12; ++bit) {
@@ -1247,8 +1271,19 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_scatter(const uint32_t* __res
     __syncthreads();
     // 1. counts per (wavefront, tile), and each key's tile and rank among the
     // wavefront's earlier keys of that tile, kept in registers for step 3
+    // The first lane of each tile's group takes the count and advances it in
+    // one LDS atomic on the 32-bit word holding it (the neighbouring count in
+    // the other half does not change: counts stay below 2^16); the other
+    // lanes add 0 to a slot of their own, so the atomic needs no branch and
+    // the compiler waits for the results only where they are used.  A
+    // wavefront's LDS operations complete in issue order, so each group's
+    // base counts every earlier key of its tile.
     uint32_t tr[ITEMS];                          // tile << 16 | rank
+    uint32_t raw[ITEMS];                         // the word the group's first lane read
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) tr[i] = raw[i] = 0u;
     {
+        uint32_t* wc = reinterpret_cast<uint32_t*>(&cnt[w][0]);
         uint32_t kc[KB], kn[KB];
         load_block(0, kn);
 #pragma unroll
@@ -1257,17 +1292,41 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_scatter(const uint32_t* __res
 #pragma unroll
             for (int u = 0; u < KB; ++u) kc[u] = kn[u];
             if (i0 + KB < ITEMS) load_block(i0 + KB, kn);
+            uint64_t pm[KB];
+            uint32_t seen[KB];
+#pragma unroll
+            for (int u = 0; u < KB; ++u) {
+                kc[u] = (uint32_t)min((int)(kc[u] >> D), nt - 1);
+                __hip_atomic_store(own + kc[u], (uint8_t)lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                seen[u] = __hip_atomic_load(own + kc[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
 #pragma unroll
             for (int u = 0; u < KB; ++u) {
                 const bool valid = (i0 + u) * kWave + lane < nv;
-                const uint32_t tile = (uint32_t)min((int)(kc[u] >> D), nt - 1);
-                const uint64_t peers = peers_of(tile, valid);
-                const uint64_t before = peers & lt;
-                const uint32_t base = cnt[w][tile];
-                tr[i0 + u] = (tile << 16) | (base + (uint32_t)__popcll(before));
-                if (valid && before == 0ull) cnt[w][tile] = (uint16_t)(base + (uint32_t)__popcll(peers));
+                if (__ballot(valid && seen[u] != (uint32_t)lane) == 0ull)
+                    pm[u] = valid ? (uint64_t)1 << lane : 0ull;
+                else
+                    pm[u] = peers_of(kc[u], valid);
+            }
+#pragma unroll
+            for (int u = 0; u < KB; ++u) {
+                const uint32_t tile = kc[u];
+                const uint64_t before = pm[u] & lt;
+                const bool first = pm[u] != 0ull && before == 0ull;
+                raw[i0 + u] = atomicAdd(first ? wc + (tile >> 1) : &s_nop[t],
+                                        first ? (uint32_t)__popcll(pm[u]) << ((tile & 1u) * 16u) : 0u);
+                // (tile, rank in the group, the group's first lane)
+                tr[i0 + u] = (tile << 16) | ((uint32_t)__popcll(before) << 6) |
+                             (pm[u] != 0ull ? (uint32_t)__builtin_ctzll(pm[u]) : 0u);
             }
         }
+    }
+    // every key's rank: its group's base, from the group's first lane
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t x = tr[i], tile = x >> 16;
+        const uint32_t word = (uint32_t)__shfl((int)raw[i], (int)(x & 0x3Fu));
+        tr[i] = (tile << 16) | (((word >> ((tile & 1u) * 16u)) & 0xFFFFu) + ((x >> 6) & 0x3Fu));
     }
     __syncthreads();
     // 2. tile starts within the chunk (scan over tiles), per-(wavefront, tile) starts

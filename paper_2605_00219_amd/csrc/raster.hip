@@ -612,15 +612,17 @@ __global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd(RasterArgs a)
                         any = any || cq[q];
                     }
                     if (__ballot(any) == 0ull) continue;
-                    float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f, v4 = 0.f, v5 = 0.f, v6 = 0.f,
-                          v7 = 0.f, v8 = 0.f;
+                    // (-0 + x is x exactly, so the first slot's terms need no add)
+                    float v0 = -0.f, v1 = -0.f, v2 = -0.f, v3 = -0.f, v4 = -0.f, v5 = -0.f, v6 = -0.f,
+                          v7 = -0.f, v8 = -0.f;
 #pragma unroll
                     for (int q = 0; q < PPT; ++q) {
+                        // pixels that do not composite this Gaussian use alpha = 0
+                        // (a composited alpha is at least 1/255)
+                        const float ae = cq[q] ? alq[q] : 0.0f;
                         // a pixel slot where no lane composites this Gaussian
                         // adds nothing (alpha 0: T and R unchanged)
-                        if (PPT > 1 && __ballot(cq[q]) == 0ull) continue;
-                        // pixels that do not composite this Gaussian use alpha = 0
-                        const float ae = cq[q] ? alq[q] : 0.0f;
+                        if (PPT > 1 && __ballot(ae > 0.0f) == 0ull) continue;
                         const float wgt = ae * T[q];
                         v6 = __builtin_fmaf(wgt, g0[q], v6);
                         v7 = __builtin_fmaf(wgt, g1[q], v7);

@@ -22,8 +22,8 @@ constexpr int kScanBlock = kScanThreads * kScanItems;  // 2048 elements per bloc
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 32;
 constexpr int kChunk = kSortThreads * kSortItems;      // 8192 keys per radix chunk
-constexpr int kDepthItems = 4;                          // the depth sort of (view, Gaussian)s:
-constexpr int kDepthChunk = kSortThreads * kDepthItems; // 1024-key chunks
+constexpr int kDepthItems = 8;                          // the depth sort of (view, Gaussian)s:
+constexpr int kDepthChunk = kSortThreads * kDepthItems; // 2048-key chunks
 constexpr int64_t kDepthFirstRatio = 12;                // capacity / (views x n) to sort by depth first
 constexpr int kDepthSplit = 16;                          // key bits sorted per Gaussian in the depth order
 constexpr int kDigits = 256;
@@ -718,6 +718,12 @@ GS_DEV uint64_t lb_wait(const uint64_t* p, uint32_t* status) {
 
 constexpr int kLbGroupWindow = 8;
 
+// A key's rank: its group's base, held by the group's first lane, plus its
+// rank in the group (lead: that lane, then the rank, from bit 8).
+GS_DEV uint32_t finish_rank(uint32_t base, uint32_t lead) {
+    return (uint32_t)__shfl((int)base, (int)(lead & 0x3Fu)) + (lead >> 8);
+}
+
 // One stable radix pass over a chunk of 256 ITEMS keys; chunk b is workgroup b.
 // Workgroups start in index order, and each publishes its per-digit counts
 // before it waits on anything, so every wait of the look-back is on a chunk
@@ -742,14 +748,9 @@ constexpr int kLbGroupWindow = 8;
 // chunk.
 // With 8192-key chunks (runs of 32 keys per digit on average, whole 128-byte
 // lines) two workgroups fit on a CU (LDS); 4096-key chunks, four per CU,
-// took 7% longer on 1.6e8 keys.  (The depth sort's 1024-key chunks keep the
-// 128-VGPR bound.)
-// A key's rank: its group's base, held by the group's first lane, plus its
-// rank in the group (lead: that lane, then the rank, from bit 8).
-GS_DEV uint32_t finish_rank(uint32_t base, uint32_t lead) {
-    return (uint32_t)__shfl((int)base, (int)(lead & 0x3Fu)) + (lead >> 8);
-}
-
+// took 7% longer on 1.6e8 keys.  The depth sort of 3e5 (view, Gaussian)s
+// runs 2048-key chunks: 1024 took 10% longer (more look-back groups), 4096
+// 15% (fewer workgroups than CUs).
 template <int ITEMS>
 __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_onesweep(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,

@@ -453,8 +453,15 @@ GS_DEV int sum9_slot(int lane) {
 // backward
 // ---------------------------------------------------------------------------
 
+// With one or two pixels per lane the kernel is held to 72 VGPRs, seven
+// wavefronts per SIMD: the per-Gaussian chain (LDS read, exp, compare,
+// uniform branch) needs that many wavefronts to keep the VALU busy, and the
+// compiler then keeps two per-tile values in scratch (reloaded once per tile,
+// outside the Gaussian loops).  Six (76 VGPRs) and eight (64) were no faster
+// than five.
 template <int TILE, int S, int PPT_>
-__global__ __launch_bounds__(TILE * TILE / PPT_) void k_raster_bwd(RasterArgs a) {
+__global__ __launch_bounds__(TILE * TILE / PPT_) __attribute__((amdgpu_waves_per_eu(PPT_ <= 2 ? 7 : 1)))
+void k_raster_bwd(RasterArgs a) {
     constexpr int PPT = PPT_, NT = Geo<TILE, PPT_>::NT, NW = Geo<TILE, PPT_>::NW;
     constexpr int SUB = 64;  // Gaussians per reduction sub-batch
     static_assert(SUB == kWave, "one relevance ballot per sub-batch");

@@ -20,8 +20,8 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanBlock = kScanThreads * kScanItems;  // 2048 elements per block
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 32;
-constexpr int kChunk = kSortThreads * kSortItems;      // 8192 keys per radix chunk
+constexpr int kSortItems = 24;
+constexpr int kChunk = kSortThreads * kSortItems;      // 6144 keys per radix chunk
 constexpr int kDepthItems = 8;                          // the depth sort of (view, Gaussian)s:
 constexpr int kDepthChunk = kSortThreads * kDepthItems; // 2048-key chunks
 constexpr int64_t kDepthFirstRatio = 12;                // capacity / (views x n) to sort by depth first
@@ -736,9 +736,10 @@ GS_DEV uint32_t finish_rank(uint32_t base, uint32_t lead) {
 // rank among the wavefront's keys of that digit (one wavefront updates only
 // its own counts, so no barrier is needed while ranking).  A scan over
 // (digit, wavefront) turns the counts into chunk-local positions, the keys are
-// placed in LDS in digit order, and they are written out so that consecutive
-// lanes write consecutive addresses of each digit's run.  The order of equal
-// digits is (chunk, wavefront, item, lane) = input order: stable.
+// placed in LDS in digit order and written out so that consecutive lanes write
+// consecutive addresses of each digit's run; then the values, read only now,
+// take the same LDS buffer and go out the same way.  The order of equal digits
+// is (chunk, wavefront, item, lane) = input order: stable.
 //
 // Destinations: the digit's start in the view plus the counts of the view's
 // earlier chunks.  Each chunk publishes its count, and the chunk of a group of
@@ -746,13 +747,15 @@ GS_DEV uint32_t finish_rank(uint32_t base, uint32_t lead) {
 // counts of the earlier chunks of its group and the totals of the earlier
 // groups, stopping early at the published inclusive prefix of a group's last
 // chunk.
-// With 8192-key chunks (runs of 32 keys per digit on average, whole 128-byte
-// lines) two workgroups fit on a CU (LDS); 4096-key chunks, four per CU,
-// took 7% longer on 1.6e8 keys.  The depth sort of 3e5 (view, Gaussian)s
+// With 6144-key chunks (runs of 24 keys per digit on average) one 24 KB
+// buffer for keys and then values and at most 168 VGPRs let three workgroups
+// share a CU: 2% faster on 1.6e8 keys than 8192-key chunks holding keys and
+// values in LDS together (two per CU); 8192-key chunks with the one buffer
+// spill at three per CU, and 6144 at four.  The depth sort of 3e5 (view, Gaussian)s
 // runs 2048-key chunks: 1024 took 10% longer (more look-back groups), 4096
 // 15% (fewer workgroups than CUs).
 template <int ITEMS>
-__global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_onesweep(
+__global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(ITEMS >= 24 ? 3 : 4))) void k_onesweep(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
     const uint32_t* __restrict__ table, int n_views, int pass, SortWs S,
@@ -762,12 +765,14 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4)
     constexpr int PER_WAVE = CHUNK / NW;
     static_assert(PER_WAVE < 65536, "ranks packed in 16 bits");
     constexpr int kLag = ITEMS < 4 ? ITEMS : 4;
-    __shared__ uint32_t gbase[kDigits];   // global destination of the chunk's first key of digit d
-    __shared__ uint32_t lstart[kDigits];  // chunk-local start of digit d
+    // global destination of the chunk's keys of digit d minus their
+    // chunk-local start
+    __shared__ uint32_t goff[kDigits];
     __shared__ uint32_t wcnt[NW][kDigits];
-    __shared__ uint32_t s_nop[kSortThreads];   // target of the non-leading lanes' atomics
-    __shared__ uint32_t s_k[CHUNK];
-    __shared__ uint32_t s_v[CHUNK];
+    // the chunk's keys in sorted order, then its values (and, while the
+    // chunk is ranked, the target of the non-leading lanes' atomics)
+    __shared__ uint32_t s_buf[CHUNK];
+    __shared__ uint8_t s_dg[CHUNK];       // digit of each sorted position
     __shared__ uint64_t s_scan[NW];
     __shared__ uint32_t s_last;
     const uint32_t b = blockIdx.x;
@@ -781,13 +786,13 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4)
     const uint32_t seg_e = table[4 * v + 1];
     const uint32_t start = table[4 * v] + c * CHUNK;
     const uint32_t n_here = min((uint32_t)CHUNK, seg_e - start);
-    uint32_t k[ITEMS], val[ITEMS], rank[ITEMS], lead[ITEMS];
+    // this lane's first key; its i-th is kWave * i further (one base address
+    // and immediate offsets, not a live address per item)
+    const uint32_t idx0 = start + w * PER_WAVE + lane;
+    const uint32_t* __restrict__ kp = keys_in + idx0;
+    uint32_t k[ITEMS], rank[ITEMS], lead[ITEMS];
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t idx = start + w * PER_WAVE + i * kWave + lane;
-        k[i] = idx < seg_e ? keys_in[idx] : 0u;
-        val[i] = idx < seg_e ? vals_in[idx] : 0u;
-    }
+    for (int i = 0; i < ITEMS; ++i) k[i] = idx0 + i * kWave < seg_e ? kp[i * kWave] : 0u;
     const uint64_t lt = lanemask_lt();
     // the view's total of this thread's digit (its start is their exclusive scan)
     const uint32_t dtot = S.dcount[(v * kPasses + pass) * kDigits + threadIdx.x];
@@ -808,15 +813,11 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4)
         // the first lane of each digit group takes the wavefront's count and
         // advances it in one LDS atomic; a wavefront's LDS operations complete
         // in issue order, so item i + 1's atomics need not wait for item i's
-        // result
-        // (packed: the base in the low 16 bits, counts per wavefront being at
-        // most PER_WAVE; the group's first lane above, then the key's rank in
-        // its group)
-        // (every lane issues the atomic, the others adding 0 to a slot of
-        // their own: without a branch the compiler waits for each result
-        // only where it is used)
+        // result.  Every lane issues the atomic, the others adding 0 to a
+        // slot of their own: without a branch the compiler waits for each
+        // result only where it is used.
         const bool first = valid && before == 0ull;
-        rank[i] = atomicAdd(first ? &wcnt[w][d] : &s_nop[threadIdx.x], first ? (uint32_t)__popcll(peers) : 0u);
+        rank[i] = atomicAdd(first ? &wcnt[w][d] : &s_buf[threadIdx.x], first ? (uint32_t)__popcll(peers) : 0u);
         lead[i] = valid ? (uint32_t)__builtin_ctzll(peers) | ((uint32_t)__popcll(before) << 8) : 0u;
         // every key's rank: its group's base from the group's first lane,
         // kLag items later (by then the atomic has returned)
@@ -839,7 +840,7 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4)
         const uint32_t gsize = min((uint32_t)kGroup, nc - gi * kGroup);
         s_last = atomicAdd(&S.gdone[pass * S.max_groups + group_slot(table, v, c)], 1u) + 1 == gsize;
     }
-    uint32_t dbase;
+    uint32_t dbase, lstart;
     {
         // digit-major exclusive scan over (digit, wavefront), and in the high
         // half the exclusive scan of the view's digit totals (no carry: the
@@ -849,7 +850,7 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4)
         const uint64_t inc = block_scan_u64(both, s_scan, &tot);
         dbase = table[4 * v] + (uint32_t)((inc - both) >> 32);
         uint32_t run = (uint32_t)(inc - both);
-        lstart[d] = run;
+        lstart = run;
 #pragma unroll
         for (int j = 0; j < NW; ++j) {
             const uint32_t x = wcnt[j][d];
@@ -858,13 +859,15 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4)
         }
     }
     __syncthreads();
+    // keys to their chunk-local sorted positions (rank[] becomes the position)
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t idx = start + w * PER_WAVE + i * kWave + lane;
         if (idx < seg_e) {
-            const uint32_t pos = wcnt[w][digit_at(k[i], shift)] + rank[i];
-            s_k[pos] = k[i];
-            s_v[pos] = val[i];
+            const uint32_t dg = digit_at(k[i], shift);
+            rank[i] += wcnt[w][dg];
+            s_buf[rank[i]] = k[i];
+            s_dg[rank[i]] = (uint8_t)dg;
         }
     }
     if (s_last) {
@@ -936,15 +939,24 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4)
         }
         lb_store(&S.pre[cw + (int64_t)b * kDigits + d], kLbPrefix | (excl + total));
     }
-    gbase[d] = dbase + excl;
+    goff[d] = dbase + excl - lstart;
+    // the values, read in input order while the keys go out
+    const uint32_t* __restrict__ vp = vals_in + idx0;
+    uint32_t val[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) val[i] = idx0 + i * kWave < seg_e ? vp[i * kWave] : 0u;
     __syncthreads();
+    // keys out: consecutive lanes write consecutive addresses of each digit's run
     for (uint32_t j = threadIdx.x; j < n_here; j += kSortThreads) {
-        const uint32_t key = s_k[j];
-        const uint32_t dg = digit_at(key, shift);
-        const uint32_t dst = gbase[dg] + (j - lstart[dg]);
-        keys_out[dst] = key;
-        vals_out[dst] = s_v[j];
+        const uint32_t key = s_buf[j];
+        keys_out[j + goff[digit_at(key, shift)]] = key;
     }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i)
+        if (idx0 + i * kWave < seg_e) s_buf[rank[i]] = val[i];
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < n_here; j += kSortThreads) vals_out[j + goff[s_dg[j]]] = s_buf[j];
 }
 
 // Stable sort of each view's segment of (keys, vals) by S.passes 8-bit digits

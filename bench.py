@@ -168,6 +168,9 @@ def parse():
                          "batched, learned ('none' for none)")
     ap.add_argument("--cull", type=int, default=0, choices=(0, 1),
                     help="tile set of the headline run: 0 = 3-sigma rectangle, 1 = exact ellipse")
+    ap.add_argument("--ppl", type=int, default=None, choices=(1, 2, 4),
+                    help="pixels per lane of the headline run (default: the layout's, 2 on 16x16 tiles; "
+                         "the sparse-footprint variant runs at 1)")
     ap.add_argument("--batched-steps", type=int, default=200)
     ap.add_argument("--batched-plain-steps", type=int, default=25)
     ap.add_argument("--learned-steps", type=int, default=10)
@@ -217,15 +220,17 @@ def main():
     del tgt_model, tframe
     targets_main = targets
 
-    def run_plain(cull, replay, loss="l1", ts_arms=None, bwd_variant=None, graph=False, wk=None, tg=None):
+    def run_plain(cull, replay, loss="l1", ts_arms=None, bwd_variant=None, graph=False, wk=None, tg=None,
+                  ppl=None):
         """Timed plain steps (and the work-counting replay) with the given tile
         culling; loss "l1" (fused into the backward) or "ssim" (L1 + D-SSIM
         against the RGBA8 references, lambda 0.2, alpha mask); wk, tg: another
-        scene of the same size with its targets (same cameras)."""
+        scene of the same size with its targets (same cameras); ppl: pixels
+        per lane (None: the layout's default, 2 on 16x16 tiles)."""
         wk = wk or w
         targets = tg if tg is not None else targets_main
         model = P.Model(wk.scene.flat(), lr=wk.lr)
-        frame = P.Frame(n, [W], [H], 16, cull=cull)
+        frame = P.Frame(n, [W], [H], 16, cull=cull, pixels_per_lane=ppl)
         lossfn = P.LossL1SSIM(frame, 0.2, True) if loss == "ssim" else None
         # backward LDS batch chosen per step by Thompson sampling over ts_arms
         sbwd = P.ScheduledBackward(ts_arms, seed=0, prior_ms=0.3) if ts_arms else None
@@ -341,7 +346,7 @@ def main():
             for t, s0 in zip((model.params, model.m, model.v, model.step), state0):
                 t.copy_(s0)
             rframe = P.Frame(n, [W], [H], 16, capacity=frame.capacity, tile_stats=True, cull=cull,
-                             row_capacity=frame.row_capacity)
+                             row_capacity=frame.row_capacity, pixels_per_lane=ppl)
             gx = (W + 15) // 16
             tile_of_px = torch.arange(H * W, device=dev)
             tile_of_px = (tile_of_px // W // 16) * gx + (tile_of_px % W) // 16
@@ -391,7 +396,7 @@ def main():
         return out
 
     order = [int(x) for x in w.view_order]
-    res = run_plain(args.cull, not args.no_replay)
+    res = run_plain(args.cull, not args.no_replay, ppl=args.ppl)
     stage_ms, ips, wall, counts = res["stage_ms"], res["ips"], res["wall"], res["counts"]
     cull_variant = None
     if "ellipse" in variants and args.cull == 0:
@@ -407,7 +412,7 @@ def main():
     eager = {"iters_per_s": ips, "ms_per_step": 1e3 * wall / args.steps}
     value, value_wall = ips, wall
     if not args.no_graph:
-        rg = run_plain(args.cull, False, graph=True)
+        rg = run_plain(args.cull, False, graph=True, ppl=args.ppl)
         value, value_wall = rg["ips"], rg["wall"]
     tp_variant = None
     if "twophase" in variants:
@@ -509,7 +514,11 @@ def main():
             P.fit_capacity(tm.params, tf_, vptr(i))
             tg_s[i].copy_(P.render(tm.params, tf_, vptr(i)))
         del tm, tf_
-        rs = run_plain(0, True, wk=ws_, tg=tg_s)
+        # one pixel per lane: with footprints of about a pixel a wavefront
+        # covering four tile rows instead of eight has fewer staged Gaussians
+        # within reach to test and evaluate (rasterisers 0.24 against 0.29 ms
+        # per step, event-timed)
+        rs = run_plain(0, True, wk=ws_, tg=tg_s, ppl=1)
         cs = rs["counts"]
         t_s = rs["stage_ms"]["rasterize_bwd"] * 1e-3
         bytes_s = (BWD_BYTES_TRAVERSED * cs["trav_bwd"] + BWD_BYTES_FLAGGED * cs["flagged"]
@@ -519,7 +528,8 @@ def main():
                 "algorithmic_flop": BWD_FLOP_EVAL * cs["eval_bwd"] + BWD_FLOP_CONTRIB * cs["contrib"]}
         rb_s["achieved"] = rb_s["algorithmic_flop"] / t_s / 1e12
         rb_s["frac"] = rb_s["achieved"] / FP32_PEAK_TFLOPS
-        extra["sparse"] = {"workload": ws_.name, "log_scales": "N(-6, 0.3)", "iters_per_s": rs["ips"],
+        extra["sparse"] = {"workload": ws_.name, "log_scales": "N(-6, 0.3)", "pixels_per_lane": 1,
+                           "iters_per_s": rs["ips"],
                            "ms_per_step": 1e3 * rs["wall"] / args.steps, "stage_ms": rs["stage_ms"],
                            "rasterize_bwd": bwd_figures(rb_s, cs, P_px, "rasterize_bwd_sparse"),
                            "roofline": headline_roofline(rb_s, cs, P_px, "rasterize_bwd_sparse")}

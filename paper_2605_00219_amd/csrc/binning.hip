@@ -763,7 +763,6 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(IT
     constexpr int NW = kSortThreads / kWave;
     constexpr int CHUNK = ITEMS * kSortThreads;
     constexpr int PER_WAVE = CHUNK / NW;
-    static_assert(PER_WAVE < 65536, "ranks packed in 16 bits");
     constexpr int kLag = ITEMS < 4 ? ITEMS : 4;
     // global destination of the chunk's keys of digit d minus their
     // chunk-local start
@@ -799,8 +798,7 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(IT
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t idx = start + w * PER_WAVE + i * kWave + lane;
-        const bool valid = idx < seg_e;
+        const bool valid = idx0 + i * kWave < seg_e;
         const uint32_t d = digit_at(k[i], shift);
         uint64_t peers = __ballot(valid);
 #pragma unroll

@@ -421,8 +421,9 @@ __global__ __launch_bounds__(kAdamThreads, 2) void k_project_bwd_adam(AdamArgs a
 #pragma unroll
         for (int k = 0; k < 6; ++k) step[k] = a.lr[k] / bc1;
         // the moments (and SH coefficients) of kAdamBatch planes are loaded
-        // together, so a thread waits on memory three times rather than fifteen
-        constexpr int kAdamBatch = 5;
+        // together, so a thread waits on memory twice rather than fifteen
+        // times (eight planes fit in the registers; all fifteen spill)
+        constexpr int kAdamBatch = 8;
 #pragma unroll
         for (int q0 = 0; q0 < 15; q0 += kAdamBatch) {
             float4 mm[kAdamBatch], vv[kAdamBatch], pq[kAdamBatch];

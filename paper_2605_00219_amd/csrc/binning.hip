@@ -1189,14 +1189,16 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_count(const uint32_t* __restr
 
 // Per chunk: wavefront w owns the chunk's keys [w * PER_WAVE, (w + 1) * PER_WAVE),
 // read in blocks of 8 per lane with the next block's loads in flight.
-// 1. Each tile's keys are counted per wavefront: peers with the same tile are
-//    found with 12 ballots and the first lane of each group adds the group's
-//    size to the wavefront's count in LDS.
+// 1. Each tile's keys are counted per wavefront: the peers of each key's tile
+//    among its step's lanes are found (a duplicate check in LDS, 12 ballots
+//    when it finds one) and the first lane of each group adds the group's
+//    size to the wavefront's count in LDS with one atomic; each key keeps its
+//    tile and its rank among the wavefront's earlier keys of that tile.
 // 2. A scan over the tiles of the chunk's totals gives each tile's start in
 //    the chunk sorted by tile; the counts become per-(wavefront, tile) starts.
-// 3. A second ranking pass gives each key its position l in the chunk sorted
-//    by tile (stable: equal tiles keep the input order); l -> input position
-//    goes to LDS.
+// 3. Each key's position l in the chunk sorted by tile (stable: equal tiles
+//    keep the input order) is its (wavefront, tile) start plus its rank;
+//    l -> input position goes to LDS.
 // 4. Sorted position l is then written by thread l mod 256: the key (read
 //    back, from L2) goes to the scanned matrix entry of its (tile, chunk)
 //    plus l minus the tile's start in the chunk, so that each tile's run of
@@ -1281,7 +1283,7 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_scatter(const uint32_t* __res
     };
     __syncthreads();
     // 1. counts per (wavefront, tile), and each key's tile and rank among the
-    // wavefront's earlier keys of that tile, kept in registers for step 3
+    // wavefront's earlier keys of that tile, kept in registers for step 3.
     // The first lane of each tile's group takes the count and advances it in
     // one LDS atomic on the 32-bit word holding it (the neighbouring count in
     // the other half does not change: counts stay below 2^16); the other
